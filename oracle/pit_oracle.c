@@ -1,0 +1,650 @@
+/*
+ * pit_oracle.c -- plain, slow, obviously correct CPU reference for PiTSBiCG
+ * (Riahi, "PiTSBiCG: Parallel in Time Stable Bi-Conjugate Gradient Algorithm").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the HIP
+ * path.  Everything is IEEE FP64, built without fast-math and without FMA
+ * contraction.
+ *
+ * What it computes, in the paper's terms:
+ *   - slice propagators: the fine solver F and the coarse solver G over one
+ *     slice of length DT = T/N (Sec. 2, eq. (Cauchyn) and the continuity
+ *     condition eq. (continuity)); here F = m implicit steps, G = c steps;
+ *   - the all-at-once operator  (F Lambda)_0 = lambda_0,
+ *     (F Lambda)_n = lambda_n - F(lambda_{n-1})  (Sec. 2, eq. (algebraiclinearsystem));
+ *   - the coarse preconditioner solve z = G^{-1} v by forward substitution
+ *     (Sec. 3, eq. (eqinverse) and the paragraph after Algorithm 1);
+ *   - the block inner product <U,V> = sum_n <u_n,v_n>_{L2(Omega)} (Sec. 3);
+ *   - Algorithm 1 (PiTSBiCG): left-preconditioned BiCGStab with the
+ *     shadow-residual restart (Sec. 3, Algorithm 1);
+ *   - parareal, both as the preconditioned Richardson iteration
+ *     (Sec. 2, eq. (pararealAlgebraic)) and as the predictor-corrector
+ *     recursion (Sec. 2, eq. (pararealscheme), read with the standard
+ *     superscripts);
+ *   - the serial fine trajectory lambda_{n+1} = F(lambda_n), the exact
+ *     solution of the all-at-once system (Sec. 2, eq. (continuity)).
+ *
+ * Discretisation (synthetic finite-difference stand-ins for the paper's FEM
+ * experiments): 1D Dirichlet-0 or periodic, 2D Dirichlet-0 on a rectangle,
+ * second-order central differences.
+ *   L u = nu*D2 u - a*D1c u - r*u                       (1D)
+ *   IE:  (I - dt L) u' = u
+ *   CN:  (I - dt/2 L) u' = (I + dt/2 L) u
+ *   PR-ADI (2D): (I - dt/2 Lx) u* = (I + dt/2 Ly) u,
+ *                (I - dt/2 Ly) u' = (I + dt/2 Lx) u*,
+ *       with Lx = nu*D2x - ax*D1x - r/2 and Ly = nu*D2y - ay*D1y - r/2.
+ * Tridiagonal systems: Thomas algorithm without pivoting.  Periodic (cyclic)
+ * systems: Sherman-Morrison rank-one correction.
+ *
+ * Layout: a block vector is N slices, each slice npts contiguous doubles;
+ * 2D slices are row-major u[j*Mx + i] with x (index i) fastest.  Dirichlet
+ * vectors hold interior points only; periodic vectors hold j = 0..M-1.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_DIRICHLET = 0, ORC_PERIODIC = 1 };
+enum { ORC_IE = 0, ORC_CN = 1, ORC_ADI = 2 };
+enum { ORC_ABS = 0, ORC_REL = 1 };
+enum { ORC_X0_ZERO = 0, ORC_X0_GIVEN = 1, ORC_X0_COARSE = 2 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOCONV = -4, ORC_EBREAKDOWN = -5 };
+
+typedef struct {
+    int dim, Mx, My, bc;
+    double Lx, Ly, nu, ax, ay, react, T;
+    int N, m, fine_scheme, c, coarse_scheme;
+    /* derived */
+    int npts;      /* points per slice */
+    double hx, hy; /* grid spacing */
+    double w;      /* L2 quadrature weight h^d */
+    double DT;     /* slice length T/N */
+} orc_ctx;
+
+static int g_threads = 1;
+
+void orc_set_threads(int n)
+{
+    g_threads = n > 0 ? n : 1;
+#ifdef _OPENMP
+    omp_set_num_threads(g_threads);
+#endif
+}
+int orc_get_threads(void) { return g_threads; }
+
+/* ------------------------------------------------------------------------- */
+/* Tridiagonal solves                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Solve the n x n tridiagonal system with sub-diagonal a[1..n-1], diagonal
+ * b[0..n-1], super-diagonal c[0..n-2] and right-hand side d; result in x.
+ * Thomas algorithm, no pivoting.  cp and dp are work arrays of length n. */
+static void thomas(int n, const double *a, const double *b, const double *c,
+                   const double *d, double *x, double *cp, double *dp)
+{
+    cp[0] = (n > 1) ? c[0] / b[0] : 0.0;
+    dp[0] = d[0] / b[0];
+    for (int i = 1; i < n; ++i) {
+        double den = b[i] - a[i] * cp[i - 1];
+        cp[i] = (i < n - 1) ? c[i] / den : 0.0;
+        dp[i] = (d[i] - a[i] * dp[i - 1]) / den;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+}
+
+/* Solve the cyclic tridiagonal system whose row i has a[i] on column i-1,
+ * b[i] on column i and c[i] on column i+1, columns taken modulo n (a[0] sits
+ * on column n-1, c[n-1] on column 0).  Sherman-Morrison: A = B + u v^T with
+ * u = (gam, 0, .., 0, c[n-1]), v = (1, 0, .., 0, a[0]/gam), gam = -b[0], so
+ * B is A without the corners and with its first and last diagonal entries
+ * shifted.  x = y - (v.y)/(1 + v.z) z where B y = d and B z = u.
+ * work: 6n doubles.  Requires n >= 3. */
+static void cyclic(int n, const double *a, const double *b, const double *c,
+                   const double *d, double *x, double *work)
+{
+    double *bb = work, *y = work + n, *z = work + 2 * n, *cp = work + 3 * n,
+           *dp = work + 4 * n, *u = work + 5 * n;
+    double gam = -b[0];
+    double alpha = c[n - 1]; /* A[n-1][0] */
+    double beta = a[0];      /* A[0][n-1] */
+    for (int i = 0; i < n; ++i) {
+        bb[i] = b[i];
+        u[i] = 0.0;
+    }
+    bb[0] = b[0] - gam;
+    bb[n - 1] = b[n - 1] - alpha * beta / gam;
+    u[0] = gam;
+    u[n - 1] = alpha;
+    thomas(n, a, bb, c, d, y, cp, dp);
+    thomas(n, a, bb, c, u, z, cp, dp);
+    double vy = y[0] + beta / gam * y[n - 1];
+    double vz = z[0] + beta / gam * z[n - 1];
+    double fac = vy / (1.0 + vz);
+    for (int i = 0; i < n; ++i) x[i] = y[i] - fac * z[i];
+}
+
+/* Exported for the brute-force pins against dense Gaussian elimination. */
+void orc_tridiag_solve(int n, const double *a, const double *b, const double *c,
+                       const double *d, double *x)
+{
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    thomas(n, a, b, c, d, x, w, w + n);
+    free(w);
+}
+
+void orc_cyclic_solve(int n, const double *a, const double *b, const double *c,
+                      const double *d, double *x)
+{
+    double *w = (double *)malloc(sizeof(double) * 6 * (size_t)n);
+    cyclic(n, a, b, c, d, x, w);
+    free(w);
+}
+
+/* ------------------------------------------------------------------------- */
+/* One implicit step of the 1D and 2D schemes                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Stencil of the 1D operator L along one axis:
+ *   (L u)_j = lo*u_{j-1} + di*u_j + up*u_{j+1}. */
+static void op1d(double nu, double a, double r, double h, double *lo, double *di, double *up)
+{
+    *lo = nu / (h * h) + a / (2.0 * h);
+    *di = -2.0 * nu / (h * h) - r;
+    *up = nu / (h * h) - a / (2.0 * h);
+}
+
+/* Solve (I - th*L) x = d along one line of n points, L given by (lo,di,up),
+ * Dirichlet-0 or periodic.  work: >= 9n doubles. */
+static void implicit_line(int n, int bc, double th, double lo, double di, double up,
+                          const double *d, double *x, double *work)
+{
+    double *a = work, *b = work + n, *c = work + 2 * n, *w = work + 3 * n;
+    for (int i = 0; i < n; ++i) {
+        a[i] = -th * lo;
+        b[i] = 1.0 - th * di;
+        c[i] = -th * up;
+    }
+    if (bc == ORC_PERIODIC)
+        cyclic(n, a, b, c, d, x, w);
+    else
+        thomas(n, a, b, c, d, x, w, w + n);
+}
+
+/* Work size in doubles needed by one_step. */
+static size_t step_work(const orc_ctx *C)
+{
+    int nmax = C->Mx > C->My ? C->Mx : C->My;
+    return (size_t)C->npts + 12 * (size_t)nmax;
+}
+
+/* out = one step of `scheme` with time step dt applied to u (no aliasing). */
+static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, double *out,
+                     double *work)
+{
+    if (C->dim == 1) {
+        int n = C->Mx;
+        double lo, di, up;
+        op1d(C->nu, C->ax, C->react, C->hx, &lo, &di, &up);
+        double *rhs = work, *lw = work + n;
+        if (scheme == ORC_IE) {
+            implicit_line(n, C->bc, dt, lo, di, up, u, out, lw);
+        } else { /* CN: rhs = (I + dt/2 L) u */
+            double th = 0.5 * dt;
+            for (int j = 0; j < n; ++j) {
+                double um, uq;
+                if (C->bc == ORC_PERIODIC) {
+                    um = u[(j - 1 + n) % n];
+                    uq = u[(j + 1) % n];
+                } else {
+                    um = (j > 0) ? u[j - 1] : 0.0;
+                    uq = (j < n - 1) ? u[j + 1] : 0.0;
+                }
+                rhs[j] = u[j] + th * (lo * um + di * u[j] + up * uq);
+            }
+            implicit_line(n, C->bc, th, lo, di, up, rhs, out, lw);
+        }
+        return;
+    }
+    /* 2D Peaceman-Rachford ADI, Dirichlet-0. */
+    int nx = C->Mx, ny = C->My;
+    double xlo, xdi, xup, ylo, ydi, yup;
+    op1d(C->nu, C->ax, 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
+    op1d(C->nu, C->ay, 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
+    int nmax = nx > ny ? nx : ny;
+    double *star = work;           /* npts */
+    double *line = work + C->npts; /* nmax */
+    double *sol = line + nmax;     /* nmax */
+    double *lw = sol + nmax;       /* 9*nmax */
+    double th = 0.5 * dt;
+    /* half-step 1: rhs = (I + th*Ly) u, then (I - th*Lx) u* = rhs row by row */
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            double c0 = u[j * nx + i];
+            double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
+            double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
+            line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
+        }
+        implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
+        for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
+    }
+    /* half-step 2: rhs = (I + th*Lx) u*, then (I - th*Ly) u' = rhs column by column */
+    for (int i = 0; i < nx; ++i) {
+        for (int j = 0; j < ny; ++j) {
+            double c0 = star[j * nx + i];
+            double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
+            double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
+            line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
+        }
+        implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
+        for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+    }
+}
+
+/* Apply `nsteps` steps of `scheme`, each of length span/nsteps:
+ * out = step^nsteps(in).  in and out may alias. */
+static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
+                      double *out)
+{
+    size_t np = (size_t)C->npts;
+    double dt = span / nsteps;
+    double *base = (double *)malloc(sizeof(double) * (2 * np + step_work(C)));
+    double *a = base, *b = base + np, *work = base + 2 * np;
+    memcpy(a, in, sizeof(double) * np);
+    for (int s = 0; s < nsteps; ++s) {
+        one_step(C, scheme, dt, a, b, work);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(out, a, sizeof(double) * np);
+    free(base);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, double nu, double ax,
+                    double ay, double react, double T, int N, int m, int fine_scheme, int c,
+                    int coarse_scheme)
+{
+    if (dim != 1 && dim != 2) return NULL;
+    if (Mx < 3 || N < 1 || m < 1 || c < 1) return NULL;
+    if (dim == 2 && (My < 3 || bc != ORC_DIRICHLET)) return NULL;
+    if (dim == 2 && (ax != 0.0 || ay != 0.0)) return NULL; /* 2D: diffusion-reaction only */
+    if (dim == 1 && (fine_scheme == ORC_ADI || coarse_scheme == ORC_ADI)) return NULL;
+    if (dim == 2 && (fine_scheme != ORC_ADI || coarse_scheme != ORC_ADI)) return NULL;
+    orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    C->dim = dim;
+    C->Mx = Mx;
+    C->My = (dim == 2) ? My : 1;
+    C->bc = bc;
+    C->Lx = Lx;
+    C->Ly = Ly;
+    C->nu = nu;
+    C->ax = ax;
+    C->ay = ay;
+    C->react = react;
+    C->T = T;
+    C->N = N;
+    C->m = m;
+    C->fine_scheme = fine_scheme;
+    C->c = c;
+    C->coarse_scheme = coarse_scheme;
+    C->npts = Mx * C->My;
+    /* Dirichlet: interior points x_j = (j+1) h, h = L/(M+1); periodic: x_j = j h, h = L/M */
+    C->hx = (bc == ORC_PERIODIC) ? Lx / Mx : Lx / (Mx + 1);
+    C->hy = (dim == 2) ? Ly / (My + 1) : 1.0;
+    C->w = (dim == 2) ? C->hx * C->hy : C->hx;
+    C->DT = T / N;
+    return C;
+}
+
+void orc_destroy(orc_ctx *C) { free(C); }
+int orc_npts(const orc_ctx *C) { return C->npts; }
+double orc_weight(const orc_ctx *C) { return C->w; }
+
+/* Fine propagator over one slice: m steps of dt = DT/m (Sec. 2). */
+void orc_F(const orc_ctx *C, const double *in, double *out)
+{
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out);
+}
+
+/* Coarse propagator over one slice: c steps of DT/c. */
+void orc_G(const orc_ctx *C, const double *in, double *out)
+{
+    propagate(C, C->coarse_scheme, C->c, C->DT, in, out);
+}
+
+/* One step of `scheme` with step dt (exported for the closed-form pins). */
+void orc_step(const orc_ctx *C, int scheme, double dt, const double *in, double *out)
+{
+    double *work = (double *)malloc(sizeof(double) * step_work(C));
+    one_step(C, scheme, dt, in, out, work);
+    free(work);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Block operators (Sec. 2 eq. (algebraiclinearsystem), Sec. 3 eq. (eqinverse)) */
+/* ------------------------------------------------------------------------- */
+
+/* y_0 = lam_0,  y_n = lam_n - F(lam_{n-1}),  n = 1..N-1.  y must not alias lam. */
+void orc_apply(const orc_ctx *C, const double *lam, double *y)
+{
+    size_t np = (size_t)C->npts;
+    memcpy(y, lam, sizeof(double) * np);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+    for (int n = 1; n < C->N; ++n) {
+        double *f = (double *)malloc(sizeof(double) * np);
+        orc_F(C, lam + (size_t)(n - 1) * np, f);
+        for (size_t j = 0; j < np; ++j) y[(size_t)n * np + j] = lam[(size_t)n * np + j] - f[j];
+        free(f);
+    }
+}
+
+/* y_n = F(lam_n) for n = 0..N-1 (the last row gives u(T) = F(lam_{N-1})). */
+void orc_apply_raw(const orc_ctx *C, const double *lam, double *y)
+{
+    size_t np = (size_t)C->npts;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+    for (int n = 0; n < C->N; ++n) orc_F(C, lam + (size_t)n * np, y + (size_t)n * np);
+}
+
+/* z = G^{-1} v by forward substitution: z_0 = v_0, z_n = v_n + G(z_{n-1}).
+ * In-place (v == z) is allowed. */
+void orc_sweep(const orc_ctx *C, const double *v, double *z)
+{
+    size_t np = (size_t)C->npts;
+    double *g = (double *)malloc(sizeof(double) * np);
+    if (z != v) memcpy(z, v, sizeof(double) * np);
+    for (int n = 1; n < C->N; ++n) {
+        orc_G(C, z + (size_t)(n - 1) * np, g);
+        for (size_t j = 0; j < np; ++j) z[(size_t)n * np + j] = v[(size_t)n * np + j] + g[j];
+    }
+    free(g);
+}
+
+/* Serial fine trajectory: lam_0 = u0, lam_{n+1} = F(lam_n); uT = F(lam_{N-1}) if non-NULL. */
+void orc_serial(const orc_ctx *C, const double *u0, double *lam, double *uT)
+{
+    size_t np = (size_t)C->npts;
+    memcpy(lam, u0, sizeof(double) * np);
+    for (int n = 1; n < C->N; ++n) orc_F(C, lam + (size_t)(n - 1) * np, lam + (size_t)n * np);
+    if (uT) orc_F(C, lam + (size_t)(C->N - 1) * np, uT);
+}
+
+/* Block inner product <U,V> = sum_n h^d sum_j u_{n,j} v_{n,j}, summed per
+ * slice in index order and then over slices in order (Sec. 3). */
+double orc_dot(const orc_ctx *C, const double *U, const double *V)
+{
+    size_t np = (size_t)C->npts;
+    double tot = 0.0;
+    for (int n = 0; n < C->N; ++n) {
+        double s = 0.0;
+        for (size_t j = 0; j < np; ++j) s += U[(size_t)n * np + j] * V[(size_t)n * np + j];
+        tot += C->w * s;
+    }
+    return tot;
+}
+
+/* ||U||_{N,inf} = max_n ( h^d sum_j u_{n,j}^2 )^{1/2}: the maximum over slices
+ * of the discrete L2(Omega) norm (the paper leaves this norm undefined). */
+double orc_norm(const orc_ctx *C, const double *U)
+{
+    size_t np = (size_t)C->npts;
+    double mx = 0.0;
+    for (int n = 0; n < C->N; ++n) {
+        double s = 0.0;
+        for (size_t j = 0; j < np; ++j) s += U[(size_t)n * np + j] * U[(size_t)n * np + j];
+        s = sqrt(C->w * s);
+        if (!(s <= mx)) mx = s; /* NaN propagates */
+    }
+    return mx;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 1: PiTSBiCG                                                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int status, iters, matvecs, restarts;
+    double res_norm;
+} orc_info;
+
+/* out = G^{-1} F in  (one "matrix-by-vector product" of the preconditioned system) */
+static void precond_apply(const orc_ctx *C, const double *in, double *out)
+{
+    orc_apply(C, in, out);
+    orc_sweep(C, out, out);
+}
+
+/*
+ * Solve G^{-1} F X = G^{-1} B with B = (u0, 0, .., 0) by Algorithm 1.
+ * X: initial guess on entry when x0_mode == ORC_X0_GIVEN, solution on exit.
+ * history (optional, capacity hist_cap): ||R^k|| for k = 0.. (the value tested
+ * at the head of the loop).  Returns the status; fills *info.
+ *
+ * Readings where the algorithm is silent:
+ *  - stopping test ||R^k||_{N,inf} > tol, absolute (norm_mode ORC_ABS) or
+ *    relative to ||R^0|| (ORC_REL);
+ *  - restart (lines 15-17) replaces both the shadow residual and the *new*
+ *    direction P^{k+1} by R^{k+1}; rho is then <R^{k+1}, R^{k+1}>;
+ *  - <D,Rt> == 0: restart with the current R and redo the direction;
+ *    <K,K> == 0 (then S = 0): X += alpha P, R = S, stop;
+ *    omega == 0 with K != 0: X += alpha P, R = S, then restart;
+ *    a NaN/Inf norm stops with ORC_EBREAKDOWN;
+ *  - half_step_check != 0 stops after line 8 when ||S|| <= tol;
+ *  - stall_window > 0: stop with ORC_ENOCONV when ||R|| has not halved over
+ *    the last stall_window iterations (used for reduced-precision fine solvers).
+ */
+int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, double eps0,
+                 int max_iter, int norm_mode, int x0_mode, int half_step_check, int stall_window,
+                 orc_info *info, double *history, int hist_cap, int *hist_len)
+{
+    size_t np = (size_t)C->npts, nt = (size_t)C->N * np;
+    double *B = (double *)calloc(nt, sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * nt);
+    double *Rt = (double *)malloc(sizeof(double) * nt);
+    double *P = (double *)malloc(sizeof(double) * nt);
+    double *D = (double *)malloc(sizeof(double) * nt);
+    double *S = (double *)malloc(sizeof(double) * nt);
+    double *K = (double *)malloc(sizeof(double) * nt);
+    double *Tm = (double *)malloc(sizeof(double) * nt);
+    int status = ORC_ENOCONV, k = 0, matvecs = 0, restarts = 0, hl = 0;
+    double nrm = 0.0;
+
+    memcpy(B, u0, sizeof(double) * np); /* B = (lambda_0, 0, ..., 0) */
+
+    /* line 1: R^0 = G^{-1}(B - F X^0) */
+    if (x0_mode == ORC_X0_ZERO) {
+        memset(X, 0, sizeof(double) * nt);
+        orc_sweep(C, B, R);
+    } else {
+        if (x0_mode == ORC_X0_COARSE) orc_sweep(C, B, X);
+        orc_apply(C, X, Tm);
+        for (size_t i = 0; i < nt; ++i) Tm[i] = B[i] - Tm[i];
+        orc_sweep(C, Tm, R);
+        matvecs++;
+    }
+    /* lines 2-4 */
+    memcpy(Rt, R, sizeof(double) * nt);
+    memcpy(P, R, sizeof(double) * nt);
+    double rho = orc_dot(C, R, Rt);
+    double nrm0 = orc_norm(C, R);
+    double scale = (norm_mode == ORC_REL && nrm0 > 0.0) ? nrm0 : 1.0;
+    double best = nrm0, best_at = 0;
+
+    for (;;) {
+        nrm = orc_norm(C, R);
+        if (history && hl < hist_cap) history[hl++] = nrm;
+        if (!isfinite(nrm)) {
+            status = ORC_EBREAKDOWN;
+            break;
+        }
+        /* line 5 */
+        if (!(nrm > tol * scale)) {
+            status = ORC_OK;
+            break;
+        }
+        if (k >= max_iter) {
+            status = ORC_ENOCONV;
+            break;
+        }
+        if (stall_window > 0) {
+            if (nrm <= 0.5 * best) {
+                best = nrm;
+                best_at = k;
+            } else if (k - best_at >= stall_window) {
+                status = ORC_ENOCONV;
+                break;
+            }
+        }
+        /* line 6: D = G^{-1} F P */
+        precond_apply(C, P, D);
+        matvecs++;
+        double dr = orc_dot(C, D, Rt);
+        if (dr == 0.0) { /* breakdown of the shadow product: restart with R */
+            memcpy(Rt, R, sizeof(double) * nt);
+            memcpy(P, R, sizeof(double) * nt);
+            rho = orc_dot(C, R, R);
+            restarts++;
+            precond_apply(C, P, D);
+            matvecs++;
+            dr = orc_dot(C, D, Rt);
+            if (dr == 0.0) {
+                status = ORC_EBREAKDOWN;
+                break;
+            }
+        }
+        /* line 7 */
+        double alpha = rho / dr;
+        /* line 8: S = R - alpha D */
+        for (size_t i = 0; i < nt; ++i) S[i] = R[i] - alpha * D[i];
+        if (half_step_check && !(orc_norm(C, S) > tol * scale)) {
+            for (size_t i = 0; i < nt; ++i) X[i] += alpha * P[i];
+            memcpy(R, S, sizeof(double) * nt);
+            k++;
+            continue; /* the head of the loop tests ||R|| = ||S|| and stops */
+        }
+        /* line 9: K = G^{-1} F S */
+        precond_apply(C, S, K);
+        matvecs++;
+        double ks = orc_dot(C, K, S);
+        double kk = orc_dot(C, K, K);
+        if (kk == 0.0) { /* S = 0: the half step solved the system */
+            for (size_t i = 0; i < nt; ++i) X[i] += alpha * P[i];
+            memcpy(R, S, sizeof(double) * nt);
+            k++;
+            continue;
+        }
+        /* line 10 */
+        double omega = ks / kk;
+        if (omega == 0.0) {
+            for (size_t i = 0; i < nt; ++i) X[i] += alpha * P[i];
+            memcpy(R, S, sizeof(double) * nt);
+            memcpy(Rt, R, sizeof(double) * nt);
+            memcpy(P, R, sizeof(double) * nt);
+            rho = orc_dot(C, R, R);
+            restarts++;
+            k++;
+            continue;
+        }
+        /* lines 11-12 */
+        for (size_t i = 0; i < nt; ++i) {
+            X[i] = X[i] + alpha * P[i] + omega * S[i];
+            R[i] = S[i] - omega * K[i];
+        }
+        /* line 13 */
+        double rho_new = orc_dot(C, R, Rt);
+        double beta = (alpha / omega) * (rho_new / rho);
+        /* line 14 */
+        for (size_t i = 0; i < nt; ++i) P[i] = R[i] + beta * (P[i] - omega * D[i]);
+        /* lines 15-17 */
+        if (fabs(rho_new) <= eps0) {
+            memcpy(Rt, R, sizeof(double) * nt);
+            memcpy(P, R, sizeof(double) * nt);
+            rho_new = orc_dot(C, R, R);
+            restarts++;
+        }
+        rho = rho_new;
+        /* line 18 */
+        k++;
+    }
+    if (info) {
+        info->status = status;
+        info->iters = k;
+        info->matvecs = matvecs;
+        info->restarts = restarts;
+        info->res_norm = nrm;
+    }
+    if (hist_len) *hist_len = hl;
+    free(B);
+    free(R);
+    free(Rt);
+    free(P);
+    free(D);
+    free(S);
+    free(K);
+    free(Tm);
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Parareal                                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Preconditioned Richardson X^{k+1} = X^k + G^{-1}(B - F X^k), `iters` steps
+ * from the X given on entry (Sec. 2, eq. (pararealAlgebraic)).
+ * history[k] = ||G^{-1}(B - F X^k)||_{N,inf}, k = 0..iters-1 (if non-NULL). */
+void orc_parareal_richardson(const orc_ctx *C, const double *u0, double *X, int iters,
+                             double *history)
+{
+    size_t np = (size_t)C->npts, nt = (size_t)C->N * np;
+    double *Tm = (double *)malloc(sizeof(double) * nt);
+    for (int k = 0; k < iters; ++k) {
+        orc_apply(C, X, Tm);
+        for (size_t i = 0; i < nt; ++i) Tm[i] = -Tm[i];
+        for (size_t j = 0; j < np; ++j) Tm[j] += u0[j];
+        orc_sweep(C, Tm, Tm);
+        if (history) history[k] = orc_norm(C, Tm);
+        for (size_t i = 0; i < nt; ++i) X[i] += Tm[i];
+    }
+    free(Tm);
+}
+
+/* Predictor-corrector recursion (Sec. 2, eq. (pararealscheme)), read as
+ *   lambda_0^{k+1} = u0,
+ *   lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) + F(lambda_n^k) - G(lambda_n^k).
+ * Lam holds lambda^k on entry (N slices) and lambda^{k+iters} on exit. */
+void orc_parareal_pc(const orc_ctx *C, const double *u0, double *Lam, int iters)
+{
+    size_t np = (size_t)C->npts, nt = (size_t)C->N * np;
+    double *old = (double *)malloc(sizeof(double) * nt);
+    double *f = (double *)malloc(sizeof(double) * nt);
+    double *g = (double *)malloc(sizeof(double) * np);
+    for (int k = 0; k < iters; ++k) {
+        memcpy(old, Lam, sizeof(double) * nt);
+        /* fine and old-coarse corrections of all slices (the parallel part) */
+        for (int n = 0; n + 1 < C->N; ++n) {
+            orc_F(C, old + (size_t)n * np, f + (size_t)n * np);
+            orc_G(C, old + (size_t)n * np, g);
+            for (size_t j = 0; j < np; ++j) f[(size_t)n * np + j] -= g[j];
+        }
+        /* sequential coarse prediction */
+        memcpy(Lam, u0, sizeof(double) * np);
+        for (int n = 0; n + 1 < C->N; ++n) {
+            orc_G(C, Lam + (size_t)n * np, g);
+            for (size_t j = 0; j < np; ++j)
+                Lam[(size_t)(n + 1) * np + j] = g[j] + f[(size_t)n * np + j];
+        }
+    }
+    free(old);
+    free(f);
+    free(g);
+}
