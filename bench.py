@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the PiTSBiCG hot path on one MI355X.
+
+A step is one whole PiTSBiCG solve of the workload to its tolerance (every
+all-at-once fine apply, coarse sweep and BiCGStab vector/reduction kernel of
+Algorithm 1) plus the final state u(T) = F(lambda_{N-1}), with every input
+already resident in HBM.  `value` is fine cell-updates per second over the
+timed steps: (fine applies x (N-1) x m x npts + the final m x npts) / time.
+
+The dominant kernel's roofline is measured live: the solves in the timed
+region record HIP events around every fine apply and coarse sweep on the
+solve's stream.  The CPU baseline is the oracle (plain C, FP64) running the
+same solve truncated to a bounded number of iterations on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--prec f64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp64_vec_TFs": 78.6, "fp32_vec_TFs": 157.3}
+
+# Algorithmic FLOPs per fine cell-update of one implicit step with
+# precomputed LU factors: forward substitution 2, back substitution 3,
+# Sherman-Morrison correction 2 (periodic), CN combination 2u - A^{-1}... 2.
+FLOPS_PER_CU = {("ie", 0): 5, ("ie", 1): 7, ("cn", 0): 7, ("cn", 1): 9}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name, prec):
+    from paper_2203_10148_amd import workloads as wl
+
+    p = {"c1": wl.C1, "c2": wl.C2}[name]
+    return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
+
+
+def cpu_baseline(p, u0, seconds):
+    """Oracle PiTSBiCG on the host cores, truncated to a few iterations."""
+    import oracle as orc
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    orc.set_threads(threads)
+    o = orc.Oracle(**p.oracle_kwargs())
+    iters = 1
+    while True:
+        t0 = time.perf_counter()
+        _, info = o.pitsbicg(u0, tol=p.tol, max_iter=iters)
+        dt = time.perf_counter() - t0
+        if dt >= seconds or info.iters < iters or iters >= 8:
+            break
+        iters = max(iters + 1, int(iters * seconds / max(dt, 1e-3)))
+        iters = min(iters, 8)
+    cells = info.matvecs * p.cells_per_apply
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Algorithm 1 on the same {p.name} input truncated to "
+                      f"{info.iters} iteration(s) ({info.matvecs} preconditioned products), "
+                      f"{dt:.1f} s, {threads} OpenMP threads over slices"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p = workload(args.workload, args.prec)
+    u0h = wl.u0_for(p)
+    log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
+    ctx = P.Context(p, device=dev)
+    u0 = torch.as_tensor(u0h, dtype=torch.float64, device=dev)
+    X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)
+    uT = torch.empty_like(X)
+    stall = 10 if args.prec == "f32" else 0
+
+    def step(timing):
+        _, info = ctx.solve(u0, X, tol=p.tol, stall_window=stall, timing=timing)
+        ctx.apply_F(X, uT, last=True)
+        return info
+
+    for i in range(args.warmup):
+        info = step(False)
+        log(f"[bench] warmup {i}: status={info.status} iters={info.iters} ms={info.ms_total:.2f}")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step(True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    status = {i.status for i in infos}
+    iters = infos[-1].iters
+    matvecs = infos[-1].matvecs
+    n_apply = sum(i.n_fine for i in infos)
+    cells = sum(i.n_fine for i in infos) * p.cells_per_apply + args.steps * p.m * p.npts
+    value = cells / elapsed
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, iters={iters}, status={status}")
+
+    # live per-kernel durations (HIP events on the solve stream)
+    ms_fine = sum(i.ms_fine for i in infos)
+    ms_coarse = sum(i.ms_coarse for i in infos)
+    n_coarse = sum(i.n_coarse for i in infos)
+    avg_fine = ms_fine / max(n_apply, 1)
+    avg_coarse = ms_coarse / max(n_coarse, 1)
+    scheme = "cn" if p.fine == wl.CN else "ie"
+    periodic = 1 if p.bc == wl.PERIODIC else 0
+    fl_fine = p.cells_per_apply * FLOPS_PER_CU[(scheme, periodic)]
+    cscheme = "cn" if p.coarse == wl.CN else "ie"
+    fl_coarse = (p.N - 1) * p.c * p.npts * FLOPS_PER_CU[(cscheme, periodic)] + (p.N - 1) * p.npts
+    peak = PEAK["fp64_vec_TFs"] if args.prec == "f64" else PEAK["fp32_vec_TFs"]
+    kern = {
+        "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply,
+                       "flops_per_launch": fl_fine, "peak": peak},
+        "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse,
+                         "flops_per_launch": fl_coarse, "peak": PEAK["fp64_vec_TFs"]},
+    }
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    k = kern[dom]
+    achieved = k["flops_per_launch"] / (k["avg_ms"] * 1e-3) / 1e12 if k["avg_ms"] > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": k["peak"],
+                "unit": "TFLOP/s", "frac": achieved / k["peak"], "traffic": None}
+    fine_cu_s = p.cells_per_apply / (avg_fine * 1e-3) if avg_fine > 0 else 0.0
+    out = {
+        "metric": "fine cell-updates/s and % HBM peak; PiT time-to-1e-8 vs plain FP64, 1 GPU",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": p.name, "M": list(p.M[: p.dim]), "N": p.N, "m": p.m,
+                   "fine": scheme, "coarse": f"{p.c}x{cscheme}", "bc": "periodic" if periodic else "dirichlet0",
+                   "tol": p.tol, "fine_prec": args.prec},
+        "roofline": roofline,
+        "solve": {"status": sorted(status), "iters": iters, "matvecs": matvecs,
+                  "time_to_tol_ms": float(np.median([i.ms_total for i in infos])),
+                  "restarts": infos[-1].restarts, "res_norm": infos[-1].res_norm},
+        "kernels": {name: {**v, "achieved_TFs": v["flops_per_launch"] / (v["avg_ms"] * 1e-3) / 1e12
+                           if v["avg_ms"] > 0 else 0.0} for name, v in kern.items()},
+        "fine_kernel_cell_updates_per_s": fine_cu_s,
+        "fine_kernel_stream_equiv_hbm_frac": fine_cu_s * (16 if args.prec == "f64" else 8) / (PEAK["hbm_GBs"] * 1e9),
+        "kernel_shape": ctx.kernel_shape(),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * pitsbicg.h -- C ABI of libpitsbicg, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of PiTSBiCG (Riahi, "PiTSBiCG: Parallel in Time Stable
+ * Bi-Conjugate Gradient Algorithm").
+ *
+ * The method (Sec. 2-3 of the paper): split [0,T] into N slices of length
+ * DT = T/N; the slice initial values Lambda = (lambda_0, .., lambda_{N-1})
+ * satisfy the all-at-once block system  F Lambda = B  (Sec. 2,
+ * eq. (algebraiclinearsystem)), with identity blocks on the diagonal, -F on
+ * the first sub-diagonal and B = (u0, 0, .., 0), where F is the fine
+ * propagator over one slice.  It is solved by Algorithm 1 (left-preconditioned
+ * BiCGStab) with the preconditioner G^{-1} (Sec. 3, eq. (eqinverse)), G built
+ * from a cheap coarse propagator and applied by sequential forward
+ * substitution.
+ *
+ * Conventions for every entry point:
+ *  - All block vectors are FP64, contiguous, slice-major: [N][M] in 1D,
+ *    [N][My][Mx] (x fastest) in 2D.  Dirichlet vectors hold interior points
+ *    only; periodic vectors hold the points j = 0..M-1.  u0 is one slice.
+ *  - Device pointers are HIP device (or managed) memory of the current device,
+ *    8-byte aligned.  Host pointers are marked "host".
+ *  - The caller owns every buffer it passes (u0, X, lam, y, v, z, the
+ *    workspace).  The library owns only its context and server structs and
+ *    allocates no device memory: it works inside the caller's workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Return codes: PIT_OK (0); negative values are errors (below); positive
+ *    values are "not yet" (PIT_EAGAIN).  No exception crosses the ABI.
+ *  - A context may be used from one thread at a time; different contexts are
+ *    independent.
+ */
+#ifndef PITSBICG_H
+#define PITSBICG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PIT_OK 0
+#define PIT_EINVAL (-1)      /* bad argument / unsupported combination      */
+#define PIT_ENOMEM (-2)      /* workspace too small / over the memory budget */
+#define PIT_EHIP (-3)        /* a HIP runtime call failed (see pit_last_hip_error) */
+#define PIT_ENOCONV (-4)     /* max_iter or stagnation: X holds the last iterate */
+#define PIT_EBREAKDOWN (-5)  /* NaN/Inf residual or unrecoverable breakdown   */
+#define PIT_EAGAIN 1         /* served request not finished yet               */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define PIT_DIRICHLET0 0 /* homogeneous Dirichlet on the whole boundary */
+#define PIT_PERIODIC 1   /* periodic (1D only)                          */
+
+#define PIT_IE 0     /* implicit Euler: (I - dt L) u' = u                        */
+#define PIT_CN 1     /* Crank-Nicolson: (I - dt/2 L) u' = (I + dt/2 L) u         */
+#define PIT_ADI_PR 2 /* Peaceman-Rachford ADI (2D): x-implicit then y-implicit  */
+
+#define PIT_F64 0 /* FP64 state and arithmetic                                 */
+#define PIT_F32 1 /* fine propagator only: FP32 state (see pit_stepper.prec)    */
+
+#define PIT_ABS 0 /* stop when ||R||_{N,inf} <= tol                            */
+#define PIT_REL 1 /* stop when ||R||_{N,inf} <= tol * ||R^0||_{N,inf}          */
+
+#define PIT_X0_ZERO 0   /* X^0 = 0                                          */
+#define PIT_X0_GIVEN 1  /* X^0 = the X passed in                            */
+#define PIT_X0_COARSE 2 /* X^0 = G^{-1} B (the coarse trajectory)           */
+
+#define PIT_APPLY_RAW 1  /* pit_apply_F flag: y_n = F(lam_n) for all n            */
+#define PIT_APPLY_LAST 2 /* pit_apply_F flag: only y_{N-1} = F(lam_{N-1}) = u(T) */
+
+/* ---- problem description ----------------------------------------------- */
+/* The evolution problem dy/dt - A y = 0 (Sec. 2, eq. (Cauchy), source f = 0)
+ * with the constant-coefficient operator
+ *     A y = nu * Laplace(y) - adv . grad(y) - react * y
+ * discretised by second-order central differences on a uniform grid:
+ *   1D: M[0] points; Dirichlet h = length[0]/(M[0]+1), periodic h = length[0]/M[0];
+ *   2D: M[0] x M[1] interior points, h = length[i]/(M[i]+1); Dirichlet only,
+ *       adv must be 0 (the ADI factors are per axis: Lx = nu*D2x - react/2,
+ *       Ly = nu*D2y - react/2). */
+typedef struct {
+    int32_t dim;       /* 1 or 2                                       */
+    int32_t M[2];      /* points per axis (M[1] ignored in 1D), >= 3    */
+    int32_t bc;        /* PIT_DIRICHLET0 or PIT_PERIODIC               */
+    double length[2];  /* domain length per axis (> 0)                 */
+    double nu;         /* diffusion coefficient (>= 0)                 */
+    double adv[2];     /* advection velocity (1D uses adv[0])          */
+    double react;      /* reaction coefficient                         */
+    double T;          /* final time (> 0)                             */
+} pit_problem;
+
+/* A time stepper over one slice: `substeps` steps of length DT/substeps.
+ * For the fine propagator F (Sec. 2, the "accurate but expensive" solver)
+ * substeps must equal the m passed to pit_create (or be 0 = m).  For the
+ * coarse propagator G (the "cheap" solver of the preconditioner) substeps is
+ * c >= 1.  prec applies to the fine propagator only: PIT_F32 keeps the fine
+ * state in FP32 (1D: FP32 arithmetic in increment form; 2D: FP32 state between
+ * the ADI half steps, FP64 arithmetic); the coarse sweep, the dot products and
+ * the BiCGStab scalars are always FP64. */
+typedef struct {
+    int32_t scheme;   /* PIT_IE, PIT_CN (1D) or PIT_ADI_PR (2D) */
+    int32_t substeps; /* m (fine) or c (coarse)                */
+    int32_t prec;     /* PIT_F64 or PIT_F32                     */
+    int32_t reserved; /* must be 0                              */
+} pit_stepper;
+
+/* Options of Algorithm 1 (Sec. 3): tolerance epsilon, restart tolerance
+ * epsilon_0, initial guess X^0. */
+typedef struct {
+    double tol;              /* epsilon of the stopping test (line 5)               */
+    double restart_tol;      /* epsilon_0 of the restart test (lines 15-17)         */
+    int32_t max_iter;        /* <= 0 means 2*N                                      */
+    int32_t norm_mode;       /* PIT_ABS (the test as written) or PIT_REL            */
+    int32_t x0_mode;         /* PIT_X0_ZERO, PIT_X0_GIVEN, PIT_X0_COARSE            */
+    int32_t half_step_check; /* !=0: also stop after line 8 when ||S|| <= tol       */
+    int32_t stall_window;    /* >0: PIT_ENOCONV when ||R|| has not halved in this
+                                many iterations (for FP32 fine propagators)         */
+    int32_t timing;          /* !=0: time every fine apply and coarse sweep with HIP
+                                events on `stream` (fills ms_fine / ms_coarse)      */
+} pit_solve_opts;
+
+/* Result of pit_solve.  history (host, optional, capacity history_cap)
+ * receives ||R^k||_{N,inf} for k = 0.. as tested at the head of the loop. */
+typedef struct {
+    int32_t status;   /* same value pit_solve returns                         */
+    int32_t iters;    /* completed passes of the loop                         */
+    int32_t matvecs;  /* applications of G^{-1} F (2 per iteration, +1 for X^0) */
+    int32_t restarts; /* shadow-residual restarts (lines 15-17 and breakdowns) */
+    double res_norm;  /* last ||R||_{N,inf}                                    */
+    double *history;  /* host, may be NULL                                     */
+    int32_t history_cap;
+    int32_t history_len;
+    float ms_total;   /* wall time of the call, milliseconds                  */
+    float ms_fine;    /* summed duration of the fine-apply launches (timing)  */
+    float ms_coarse;  /* summed duration of the coarse-sweep launches (timing) */
+    int32_t n_fine;   /* fine-apply launches in the call                      */
+    int32_t n_coarse; /* coarse-sweep launches in the call                    */
+    int32_t reserved;
+} pit_solve_info;
+
+typedef struct pit_ctx pit_ctx;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context for `problem` split into N >= 1 slices with m >= 1 fine
+ * steps per slice.  Validates the combination, chooses kernel shapes and
+ * precomputes (on the host, FP64) the factorisations of the fine and coarse
+ * step matrices.  Does not touch the GPU.
+ * Errors: PIT_EINVAL for N < 1, m < 1, M < 3, dim not 1/2, 2D periodic or
+ * advective, IE/CN in 2D, ADI in 1D, M above the largest supported line
+ * (16384 points), a factorisation that is not finite.  *out is set to NULL on
+ * error. */
+int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine,
+               pit_stepper coarse, pit_ctx **out);
+
+/* Destroy a context (host memory only; the workspace stays the caller's). */
+int pit_destroy(pit_ctx *ctx);
+
+/* Device bytes the context needs: coefficient tables, the BiCGStab block
+ * vectors (R, shadow R, P, D, S, K and one temporary, N*npts FP64 each),
+ * intermediate ADI fields and reduction scratch. */
+size_t pit_workspace_bytes(const pit_ctx *ctx);
+
+/* Bind `bytes` of device memory at dev_ptr (256-byte aligned) as the
+ * context's workspace and upload the tables (a synchronous copy on the null
+ * stream).  The memory must stay valid until the context is destroyed or
+ * rebound.  Errors: PIT_EINVAL (NULL / misaligned), PIT_ENOMEM (too small),
+ * PIT_EHIP. */
+int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* ---- operators ------------------------------------------------------------ */
+
+/* All-at-once operator (Sec. 2, eq. (algebraiclinearsystem)):
+ *     y_0 = lam_0,   y_n = lam_n - F(lam_{n-1}),  n = 1..N-1,
+ * every slice's F (m fine steps) running concurrently.  With flags =
+ * PIT_APPLY_RAW:  y_n = F(lam_n) for n = 0..N-1.  With PIT_APPLY_LAST: only
+ * y_{N-1} = F(lam_{N-1}) is written (the state u(T) at the final time when
+ * lam is the solution, by the continuity condition of Sec. 2).  lam and y are device [N][npts] FP64 and must not
+ * overlap.  Asynchronous on `stream`.  Errors: PIT_EINVAL (NULL pointers,
+ * unbound workspace, unknown flags), PIT_EHIP (launch failure). */
+int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void *stream);
+
+/* Coarse preconditioner solve z = G^{-1} v by forward substitution (Sec. 3,
+ * eq. (eqinverse) and the remark that it is solved sequentially):
+ *     z_0 = v_0,   z_n = v_n + G(z_{n-1}),  n = 1..N-1,
+ * in FP64.  v == z (in place) is allowed.  Asynchronous on `stream`.
+ * Errors as pit_apply_F. */
+int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
+
+/* ---- solver ---------------------------------------------------------------- */
+
+/* Algorithm 1 (Sec. 3) on  G^{-1} F X = G^{-1} B,  B = (u0, 0, .., 0):
+ * u0 (device, one slice), X (device, [N][npts]): the initial guess on entry
+ * when opts->x0_mode == PIT_X0_GIVEN, the solution Lambda on exit (also on
+ * PIT_ENOCONV, where it is the last iterate).  opts NULL = defaults
+ * (tol 1e-10, restart_tol 1e-30, max_iter 2N, PIT_ABS, PIT_X0_ZERO).
+ * info may be NULL.  Inner products are the block L2 product of Sec. 3; the
+ * stopping norm is max over slices of the discrete L2 norm.  Host-synchronous
+ * (the stopping test needs the norm).  Returns PIT_OK, PIT_ENOCONV,
+ * PIT_EBREAKDOWN, PIT_EINVAL or PIT_EHIP. */
+int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
+              pit_solve_info *info, void *stream);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Static description of an error code. */
+const char *pit_strerror(int code);
+
+/* The hipError_t of the last failing HIP call in this thread (0 if none). */
+int pit_last_hip_error(void);
+
+/* Kernel shape the context chose (for reports): threads per line and points
+ * per thread of the fine and coarse line solvers (1D), 0 where unused. */
+int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PITSBICG_H */

@@ -1,0 +1,195 @@
+// Block-vector kernels of Algorithm 1: segmented FP64 inner products with a
+// deterministic two-level reduction, and the BiCGStab vector updates.
+//
+// The block inner product is <U,V> = sum_n <u_n, v_n>_{L2(Omega)} (Sec. 3),
+// with the L2 product approximated by h^d * sum_j; the stopping norm is the
+// maximum over slices of the discrete L2 norm.  Both come out of one pass that
+// produces per-slice sums.
+#include "pit_internal.hpp"
+
+namespace pit {
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_down(v, d, kWave);
+    return v;
+}
+
+// grid (bps, N); each block sums a strided part of one slice for nq pairs.
+__global__ __launch_bounds__(kRedThreads) void k_seg_dots(DotPairs pr, int nq, int N, long npts,
+                                                          int bps, double *__restrict__ part)
+{
+    __shared__ double sh[4][kRedThreads / kWave];
+    const int b = blockIdx.x, s = blockIdx.y;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const size_t base = (size_t)s * npts;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long i = (long)b * kRedThreads + t; i < npts; i += (long)bps * kRedThreads) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nq) acc[q] = fma(pr.a[q][base + i], pr.b[q][base + i], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < nq) {
+            double v = wave_sum(acc[q]);
+            if (lane == 0) sh[q][w] = v;
+        }
+    }
+    __syncthreads();
+    if (t < nq) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < kRedThreads / kWave; ++i) v += sh[t][i];
+        part[((size_t)t * N + s) * bps + b] = v;
+    }
+}
+
+// One block: per-slice sums in block order, then totals and maxima over
+// slices in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void k_seg_finalize(const double *__restrict__ part, int nq,
+                                                              int N, int bps, double w, RedOut *out)
+{
+    __shared__ double sd[kRedThreads];
+    __shared__ double sm[kRedThreads];
+    const int t = threadIdx.x;
+    for (int q = 0; q < nq; ++q) {
+        double tot = 0.0, mx = 0.0;
+        for (int s = t; s < N; s += kRedThreads) {
+            const double *p = part + ((size_t)q * N + s) * bps;
+            double ss = 0.0;
+            for (int b = 0; b < bps; ++b) ss += p[b];
+            tot += ss;
+            double nrm = sqrt(w * ss);
+            mx = (nrm > mx || nrm != nrm) ? nrm : mx;  // NaN propagates
+        }
+        sd[t] = tot;
+        sm[t] = mx;
+        __syncthreads();
+        for (int d = kRedThreads / 2; d >= 1; d >>= 1) {
+            if (t < d) {
+                sd[t] += sd[t + d];
+                const double o = sm[t + d];
+                sm[t] = (o > sm[t] || o != o) ? o : sm[t];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            out->dot[q] = w * sd[0];
+            out->nmax[q] = sm[0];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_seg_dots(const DotPairs &pr, int nq, int N, long npts, int bps, double *part,
+                           double w, RedOut *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seg_dots, dim3(bps, N), dim3(kRedThreads), 0, st, pr, nq, N, npts, bps, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_finalize, dim3(1), dim3(kRedThreads), 0, st, part, nq, N, bps, w, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise updates (grid-stride)
+// ---------------------------------------------------------------------------
+constexpr int kVecThreads = 256;
+
+static inline dim3 vec_grid(long n)
+{
+    long b = (n + kVecThreads - 1) / kVecThreads;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+__global__ void k_axpby(double *__restrict__ out, const double *__restrict__ x, double a,
+                        const double *__restrict__ y, double b, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = fma(a, x[i], b * y[i]);
+}
+
+__global__ void k_update_xr(double *__restrict__ X, double *__restrict__ R, const double *__restrict__ P,
+                            const double *__restrict__ S, const double *__restrict__ K, double alpha,
+                            double omega, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double s = S[i];
+        X[i] = fma(omega, s, fma(alpha, P[i], X[i]));
+        R[i] = fma(-omega, K[i], s);
+    }
+}
+
+__global__ void k_update_p(double *__restrict__ P, const double *__restrict__ R,
+                           const double *__restrict__ D, double beta, double omega, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        P[i] = fma(beta, fma(-omega, D[i], P[i]), R[i]);
+}
+
+__global__ void k_b_minus(double *__restrict__ out, const double *__restrict__ in,
+                          const double *__restrict__ u0, long npts, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = (i < npts ? u0[i] : 0.0) - in[i];
+}
+
+__global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill0(double *__restrict__ dst, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = 0.0;
+}
+
+hipError_t launch_axpby(double *out, const double *x, double a, const double *y, double b, long n,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, vec_grid(n), dim3(kVecThreads), 0, st, out, x, a, y, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr(double *X, double *R, const double *P, const double *S, const double *K,
+                            double alpha, double omega, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_xr, vec_grid(n), dim3(kVecThreads), 0, st, X, R, P, S, K, alpha, omega, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p(double *P, const double *R, const double *D, double beta, double omega,
+                           long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_p, vec_grid(n), dim3(kVecThreads), 0, st, P, R, D, beta, omega, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_minus(double *out, const double *in, const double *u0, long npts, long n,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_b_minus, vec_grid(n), dim3(kVecThreads), 0, st, out, in, u0, npts, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy, vec_grid(n), dim3(kVecThreads), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill0(double *dst, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill0, vec_grid(n), dim3(kVecThreads), 0, st, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace pit

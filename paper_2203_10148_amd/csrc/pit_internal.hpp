@@ -1,0 +1,121 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libpitsbicg.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pit {
+
+constexpr int kWave = 64;      // CDNA wavefront width
+constexpr int kLevels = 6;     // log2(kWave): Kogge-Stone levels inside a wave
+constexpr int kMaxWaves = 16;  // 1024 threads per line at most
+constexpr int kMaxLine = 16384;
+
+// ---------------------------------------------------------------------------
+// 1D line solver tables.
+//
+// A line of M points is split over NT threads, C consecutive points per
+// thread (point j = t*C + k).  The matrix is A = I - theta*L (tridiagonal,
+// constant stencil, optionally cyclic).  For a cyclic A the solver works on
+// B = A without its corners and with the first/last diagonal entries shifted
+// (Sherman-Morrison), B = L_B U_B without pivoting:
+//     forward   y_j = d_j + lm_j * y_{j-1}          (lm_j = -l_j)
+//     backward  x_j = iu_j * y_j + cm_j * x_{j+1}   (iu_j = 1/u_j, cm_j = -c/u_j)
+//     cyclic    x  -= phi * z,  phi = (x_0 + bg * x_{M-1}) * inv_den
+// Both recurrences are first-order linear with constant multipliers, so the
+// carries between threads are a scan whose multiplier products are constants
+// precomputed here:
+//     pf_t = prod_k lm_{tC+k},   pb_t = prod_k cm_{tC+k}
+//     wf[l]_t = prod_{q=t-2^l+1..t} pf_q  (0 if the lane is < 2^l)
+//     wb[l]_t = prod_{q=t..t+2^l-1} pb_q  (0 if lane + 2^l > 63)
+//     qf_t = prod_{q=wavestart..t-1} pf_q,  qb_t = prod_{q=t+1..waveend} pb_q
+//     pwf_w, pwb_w = products of pf / pb over wave w.
+// Padding points j >= M carry lm = 1, iu = 0, cm = 0, z = 0 so that the
+// forward total equals y_{M-1} and the pads solve to 0.
+//
+// Device layout (element type T, one contiguous blob):
+//   lm[C][NT] iu[C][NT] cm[C][NT] z[C][NT] wf[6][NT] wb[6][NT] qf[NT] qb[NT]
+//   pwf[16] pwb[16]
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LineTab {
+    const T *lm, *iu, *cm, *z, *wf, *wb, *qf, *qb, *pwf, *pwb;
+    T inv_den;  // 1 / (1 + v.z)
+    T bg;       // beta_corner / gamma
+    T iu_last;  // iu_{M-1}
+    int cyclic;
+    int M;
+};
+
+inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kLevels + 2) * NT + 2 * kMaxWaves; }
+
+template <typename T>
+inline LineTab<T> line_tab_view(const T *base, int NT, int C)
+{
+    LineTab<T> tb{};
+    size_t o = 0;
+    const size_t pc = (size_t)C * NT;
+    tb.lm = base + o; o += pc;
+    tb.iu = base + o; o += pc;
+    tb.cm = base + o; o += pc;
+    tb.z = base + o; o += pc;
+    tb.wf = base + o; o += (size_t)kLevels * NT;
+    tb.wb = base + o; o += (size_t)kLevels * NT;
+    tb.qf = base + o; o += NT;
+    tb.qb = base + o; o += NT;
+    tb.pwf = base + o; o += kMaxWaves;
+    tb.pwb = base + o;
+    return tb;
+}
+
+// Supported (threads per line, points per thread) shapes of the 1D solver.
+struct LineShape {
+    int NT, C;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+enum { SCHEME_IE = 0, SCHEME_CN = 1, SCHEME_ADI = 2 };
+
+// Fine apply, 1D, FP64 state.  y_0 = lam_0, y_n = lam_n - F(lam_{n-1}); raw: y_n = F(lam_n);
+// last_only: y_{N-1} = F(lam_{N-1}) only.
+hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const double *lam, double *y,
+                             int N, int M, int m, int scheme, int raw, int last_only, hipStream_t st);
+
+// Coarse sweep, 1D, FP64: z_0 = v_0, z_n = v_n + G(z_{n-1}).
+hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const double *v, double *z,
+                              int N, int M, int c, int scheme, hipStream_t st);
+
+// Krylov block-vector kernels (krylov.hip).  n = total number of doubles.
+// Segmented dot products: for each slice s and pair q < nq,
+//   part[(q*N + s)*bps + b] = partial sum of a_q[s,:] . b_q[s,:] over block b.
+struct DotPairs {
+    const double *a[4];
+    const double *b[4];
+};
+struct RedOut {
+    double dot[4];   // w * sum over slices (fixed order)
+    double nmax[4];  // max over slices of sqrt(w * slice sum)
+};
+hipError_t launch_seg_dots(const DotPairs &pr, int nq, int N, long npts, int bps, double *part,
+                           double w, RedOut *out, hipStream_t st);
+// S = R - alpha*D
+hipError_t launch_axpby(double *out, const double *x, double a, const double *y, double b, long n,
+                        hipStream_t st);
+// X += alpha*P + omega*S; R = S - omega*K
+hipError_t launch_update_xr(double *X, double *R, const double *P, const double *S, const double *K,
+                            double alpha, double omega, long n, hipStream_t st);
+// P = R + beta*(P - omega*D)
+hipError_t launch_update_p(double *P, const double *R, const double *D, double beta, double omega,
+                           long n, hipStream_t st);
+// out = B - in, B = (u0, 0, ..); first slice uses u0
+hipError_t launch_b_minus(double *out, const double *in, const double *u0, long npts, long n,
+                          hipStream_t st);
+hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st);
+hipError_t launch_fill0(double *dst, long n, hipStream_t st);
+
+}  // namespace pit

@@ -1,0 +1,648 @@
+// libpitsbicg host side: context, coefficient tables, workspace binding, the
+// operator entry points and the Algorithm 1 driver.
+//
+// The driver keeps Algorithm 1's control flow on the host: after each
+// reduction it reads a few FP64 scalars back (one small copy and one stream
+// synchronisation), decides as the algorithm does, and launches the next
+// kernels with the scalars as arguments.  All block-vector work runs in the
+// HIP kernels.
+#include "../../include/pitsbicg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pit_internal.hpp"
+
+using namespace pit;
+
+namespace {
+
+thread_local int t_last_hip = 0;
+
+#define PIT_HIP(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            t_last_hip = (int)e_;                        \
+            return PIT_EHIP;                             \
+        }                                                \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+const LineShape kShapes[] = {{64, 1},   {64, 2},   {64, 4},   {64, 8},    {128, 8},   {256, 8},
+                             {256, 16}, {512, 8},  {512, 16}, {1024, 8},  {1024, 16}};
+
+bool shape_supported(LineShape s)
+{
+    for (const auto &k : kShapes)
+        if (k.NT == s.NT && k.C == s.C) return true;
+    return false;
+}
+
+// Default shape: eight points per thread once the line is long enough, the
+// thread count growing with M; sixteen per thread above 8192 points.
+LineShape default_shape(int M)
+{
+    if (M <= 64) return {64, 1};
+    if (M <= 128) return {64, 2};
+    if (M <= 256) return {64, 4};
+    if (M <= 512) return {64, 8};
+    if (M <= 1024) return {128, 8};
+    if (M <= 2048) return {256, 8};
+    if (M <= 4096) return {512, 8};
+    if (M <= 8192) return {1024, 8};
+    return {1024, 16};
+}
+
+LineShape shape_from_env(const char *name, int M)
+{
+    const char *s = std::getenv(name);
+    if (s) {
+        LineShape sh{0, 0};
+        if (std::sscanf(s, "%d,%d", &sh.NT, &sh.C) == 2 && shape_supported(sh) && sh.NT * sh.C >= M)
+            return sh;
+    }
+    return default_shape(M);
+}
+
+// Host-side description of one line operator A = I - theta*L.
+struct LineHost {
+    LineShape sh{0, 0};
+    int M = 0;
+    int cyclic = 0;
+    double inv_den = 0.0, bg = 0.0, iu_last = 0.0;
+    std::vector<double> blob;  // layout of line_tab_view
+};
+
+// Build the tables of the line solver for the tridiagonal matrix with
+// sub-diagonal a (coefficient of x_{j-1}), diagonal b and super-diagonal c
+// (coefficient of x_{j+1}); periodic adds the corners A[0][M-1] = a and
+// A[M-1][0] = c.  Returns false if the factorisation is not finite.
+bool build_line(int M, bool periodic, double a, double b, double c, LineShape sh, LineHost &L)
+{
+    const int NT = sh.NT, C = sh.C, P = NT * C, W = NT / kWave;
+    std::vector<double> lm(P, 1.0), iu(P, 0.0), cm(P, 0.0), zz(P, 0.0);
+    std::vector<double> bd(M, b), u(M), l(M);
+    double gam = 0.0;
+    if (periodic) {  // Sherman-Morrison split A = B + (gam,0..,c)(1,0..,a/gam)^T
+        gam = -b;
+        bd[0] = b - gam;
+        bd[M - 1] = b - c * a / gam;
+    }
+    u[0] = bd[0];
+    l[0] = 0.0;
+    for (int j = 1; j < M; ++j) {
+        l[j] = a / u[j - 1];
+        u[j] = bd[j] - l[j] * c;
+    }
+    for (int j = 0; j < M; ++j) {
+        lm[j] = -l[j];
+        iu[j] = 1.0 / u[j];
+        cm[j] = (j < M - 1) ? -c / u[j] : 0.0;
+    }
+    L.cyclic = periodic ? 1 : 0;
+    L.inv_den = 0.0;
+    L.bg = 0.0;
+    if (periodic) {  // z = B^{-1} (gam, 0, .., 0, c)
+        std::vector<double> y(M), z(M);
+        for (int j = 0; j < M; ++j) {
+            const double rhs = (j == 0) ? gam : (j == M - 1 ? c : 0.0);
+            y[j] = rhs + (j > 0 ? lm[j] * y[j - 1] : 0.0);
+        }
+        for (int j = M - 1; j >= 0; --j) z[j] = iu[j] * y[j] + (j < M - 1 ? cm[j] * z[j + 1] : 0.0);
+        for (int j = 0; j < M; ++j) zz[j] = z[j];
+        L.bg = a / gam;
+        L.inv_den = 1.0 / (1.0 + z[0] + L.bg * z[M - 1]);
+    }
+    L.iu_last = iu[M - 1];
+    std::vector<double> pf(NT, 1.0), pb(NT, 1.0);
+    for (int t = 0; t < NT; ++t)
+        for (int k = 0; k < C; ++k) {
+            pf[t] *= lm[t * C + k];
+            pb[t] *= cm[t * C + k];
+        }
+    L.sh = sh;
+    L.M = M;
+    L.blob.assign(line_tab_elems(NT, C), 0.0);
+    double *base = L.blob.data();
+    LineTab<double> v = line_tab_view<double>(base, NT, C);
+    auto W_ = [&](const double *p) { return const_cast<double *>(p); };
+    for (int t = 0; t < NT; ++t) {
+        for (int k = 0; k < C; ++k) {
+            W_(v.lm)[k * NT + t] = lm[t * C + k];
+            W_(v.iu)[k * NT + t] = iu[t * C + k];
+            W_(v.cm)[k * NT + t] = cm[t * C + k];
+            W_(v.z)[k * NT + t] = zz[t * C + k];
+        }
+        const int lane = t % kWave, ws = t - lane, we = ws + kWave - 1;
+        for (int lv = 0; lv < kLevels; ++lv) {
+            const int s = 1 << lv;
+            double f = 0.0, g = 0.0;
+            if (lane >= s) {
+                f = 1.0;
+                for (int q = t - s + 1; q <= t; ++q) f *= pf[q];
+            }
+            if (lane + s <= kWave - 1) {
+                g = 1.0;
+                for (int q = t; q <= t + s - 1; ++q) g *= pb[q];
+            }
+            W_(v.wf)[lv * NT + t] = f;
+            W_(v.wb)[lv * NT + t] = g;
+        }
+        double qf = 1.0, qb = 1.0;
+        for (int q = ws; q < t; ++q) qf *= pf[q];
+        for (int q = t + 1; q <= we; ++q) qb *= pb[q];
+        W_(v.qf)[t] = qf;
+        W_(v.qb)[t] = qb;
+    }
+    for (int w = 0; w < W; ++w) {
+        double f = 1.0, g = 1.0;
+        for (int q = w * kWave; q < (w + 1) * kWave; ++q) {
+            f *= pf[q];
+            g *= pb[q];
+        }
+        W_(v.pwf)[w] = f;
+        W_(v.pwb)[w] = g;
+    }
+    for (double x : L.blob)
+        if (!std::isfinite(x)) return false;
+    return std::isfinite(L.inv_den) && std::isfinite(L.bg) && std::isfinite(L.iu_last);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct pit_ctx {
+    pit_problem pb;
+    int N = 0, m = 0;
+    pit_stepper fine{}, coarse{};
+    int npts = 0;
+    double hx = 0, hy = 0, w = 0, DT = 0;
+    // 1D line operators
+    LineHost lf;  // fine step matrix
+    LineHost lc;  // coarse step matrix
+    // workspace layout (byte offsets)
+    size_t off_tf = 0, off_tc = 0, off_vec = 0, off_part = 0, off_red = 0, total = 0;
+    int bps = 1;
+    // bound workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    long nt() const { return (long)N * npts; }
+    double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * nt(); }
+    double *part() const { return reinterpret_cast<double *>(ws + off_part); }
+    RedOut *red() const { return reinterpret_cast<RedOut *>(ws + off_red); }
+    LineTab<double> tab(const LineHost &L, size_t off) const
+    {
+        LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(ws + off), L.sh.NT, L.sh.C);
+        t.inv_den = L.inv_den;
+        t.bg = L.bg;
+        t.iu_last = L.iu_last;
+        t.cyclic = L.cyclic;
+        t.M = L.M;
+        return t;
+    }
+};
+
+namespace {
+
+// theta*(L stencil) for the 1D operator nu*D2 - a*D1c - r:
+//   (L u)_j = lo*u_{j-1} + di*u_j + up*u_{j+1}
+void stencil1d(const pit_problem &p, double h, double *lo, double *di, double *up)
+{
+    *lo = p.nu / (h * h) + p.adv[0] / (2.0 * h);
+    *di = -2.0 * p.nu / (h * h) - p.react;
+    *up = p.nu / (h * h) - p.adv[0] / (2.0 * h);
+}
+
+// Tables for A = I - theta*L with theta = dt (IE) or dt/2 (CN).
+bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &out)
+{
+    double lo, di, up;
+    stencil1d(c.pb, c.hx, &lo, &di, &up);
+    const double th = (scheme == PIT_IE) ? dt : 0.5 * dt;
+    return build_line(c.pb.M[0], c.pb.bc == PIT_PERIODIC, -th * lo, 1.0 - th * di, -th * up, sh, out);
+}
+
+int validate(const pit_problem *p, int N, int m, const pit_stepper &f, const pit_stepper &g)
+{
+    if (!p || N < 1 || m < 1) return PIT_EINVAL;
+    if (p->dim != 1) return PIT_EINVAL;  // 2D arrives with the ADI kernels
+    if (p->M[0] < 3 || p->M[0] > kMaxLine) return PIT_EINVAL;
+    if (p->bc != PIT_DIRICHLET0 && p->bc != PIT_PERIODIC) return PIT_EINVAL;
+    if (!(p->length[0] > 0.0) || !(p->T > 0.0) || !(p->nu >= 0.0)) return PIT_EINVAL;
+    if (!std::isfinite(p->adv[0]) || !std::isfinite(p->react)) return PIT_EINVAL;
+    if (f.scheme != PIT_IE && f.scheme != PIT_CN) return PIT_EINVAL;
+    if (g.scheme != PIT_IE && g.scheme != PIT_CN) return PIT_EINVAL;
+    if (f.substeps != 0 && f.substeps != m) return PIT_EINVAL;
+    if (g.substeps < 1) return PIT_EINVAL;
+    if (f.prec != PIT_F64 || g.prec != PIT_F64) return PIT_EINVAL;  // FP32 fine arrives later
+    if (f.reserved != 0 || g.reserved != 0) return PIT_EINVAL;
+    return PIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pit_strerror(int code)
+{
+    switch (code) {
+    case PIT_OK: return "ok";
+    case PIT_EINVAL: return "invalid argument or unsupported combination";
+    case PIT_ENOMEM: return "workspace too small or over the memory budget";
+    case PIT_EHIP: return "HIP runtime error";
+    case PIT_ENOCONV: return "not converged (max_iter or stagnation)";
+    case PIT_EBREAKDOWN: return "breakdown (non-finite residual)";
+    case PIT_EAGAIN: return "not finished yet";
+    default: return "unknown status";
+    }
+}
+
+int pit_last_hip_error(void) { return t_last_hip; }
+
+int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+               pit_ctx **out)
+{
+    if (!out) return PIT_EINVAL;
+    *out = nullptr;
+    int rc = validate(problem, N, m, fine, coarse);
+    if (rc != PIT_OK) return rc;
+    pit_ctx *c = new (std::nothrow) pit_ctx();
+    if (!c) return PIT_ENOMEM;
+    c->pb = *problem;
+    c->N = N;
+    c->m = m;
+    c->fine = fine;
+    c->fine.substeps = m;
+    c->coarse = coarse;
+    const int M = problem->M[0];
+    c->npts = M;
+    c->hx = (problem->bc == PIT_PERIODIC) ? problem->length[0] / M : problem->length[0] / (M + 1);
+    c->hy = 1.0;
+    c->w = c->hx;
+    c->DT = problem->T / N;
+    if (!make_line(*c, fine.scheme, c->DT / m, shape_from_env("PIT_FINE_SHAPE", M), c->lf) ||
+        !make_line(*c, coarse.scheme, c->DT / coarse.substeps, shape_from_env("PIT_COARSE_SHAPE", M), c->lc)) {
+        delete c;
+        return PIT_EINVAL;
+    }
+    c->bps = (int)std::min<long>(64, std::max<long>(1, (c->npts + 2047) / 2048));
+    size_t o = 0;
+    c->off_tf = o;
+    o = align_up(o + c->lf.blob.size() * sizeof(double));
+    c->off_tc = o;
+    o = align_up(o + c->lc.blob.size() * sizeof(double));
+    c->off_vec = o;
+    o = align_up(o + 7 * (size_t)c->nt() * sizeof(double));
+    c->off_part = o;
+    o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
+    c->off_red = o;
+    o = align_up(o + sizeof(RedOut));
+    c->total = o;
+    *out = c;
+    return PIT_OK;
+}
+
+int pit_destroy(pit_ctx *ctx)
+{
+    delete ctx;
+    return PIT_OK;
+}
+
+size_t pit_workspace_bytes(const pit_ctx *ctx) { return ctx ? ctx->total : 0; }
+
+int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4])
+{
+    if (!ctx || !out) return PIT_EINVAL;
+    out[0] = ctx->lf.sh.NT;
+    out[1] = ctx->lf.sh.C;
+    out[2] = ctx->lc.sh.NT;
+    out[3] = ctx->lc.sh.C;
+    return PIT_OK;
+}
+
+int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
+{
+    if (!ctx || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) != 0) return PIT_EINVAL;
+    if (bytes < ctx->total) return PIT_ENOMEM;
+    ctx->ws = static_cast<char *>(dev_ptr);
+    ctx->ws_bytes = bytes;
+    PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf, ctx->lf.blob.data(), ctx->lf.blob.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tc, ctx->lc.blob.data(), ctx->lc.blob.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    return PIT_OK;
+}
+
+int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void *stream)
+{
+    if (!ctx || !ctx->ws || !lam || !y || (flags & ~(PIT_APPLY_RAW | PIT_APPLY_LAST))) return PIT_EINVAL;
+    if (lam == y) return PIT_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PIT_HIP(launch_fine1d_f64(ctx->lf.sh, ctx->tab(ctx->lf, ctx->off_tf), lam, y, ctx->N, ctx->npts, ctx->m,
+                              ctx->fine.scheme, (flags & PIT_APPLY_RAW) ? 1 : 0,
+                              (flags & PIT_APPLY_LAST) ? 1 : 0, st));
+    return PIT_OK;
+}
+
+int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream)
+{
+    if (!ctx || !ctx->ws || !v || !z) return PIT_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PIT_HIP(launch_sweep1d_f64(ctx->lc.sh, ctx->tab(ctx->lc, ctx->off_tc), v, z, ctx->N, ctx->npts,
+                               ctx->coarse.substeps, ctx->coarse.scheme, st));
+    return PIT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 driver
+// ---------------------------------------------------------------------------
+namespace {
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+struct Solver {
+    pit_ctx *c;
+    hipStream_t st;
+    double *R, *Rt, *P, *D, *S, *K, *Tm;
+    long n;
+    int matvecs = 0;
+    int n_fine = 0, n_coarse = 0;
+    bool timing = false;
+    std::vector<EventPair> ev_fine, ev_coarse;
+
+    ~Solver()
+    {
+        for (auto &e : ev_fine) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        for (auto &e : ev_coarse) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    }
+
+    int begin(std::vector<EventPair> &v)
+    {
+        EventPair e{};
+        PIT_HIP(hipEventCreate(&e.a));
+        PIT_HIP(hipEventCreate(&e.b));
+        v.push_back(e);
+        PIT_HIP(hipEventRecord(e.a, st));
+        return PIT_OK;
+    }
+
+    int apply(const double *in, double *out)
+    {
+        int rc;
+        if (timing && (rc = begin(ev_fine))) return rc;
+        if ((rc = pit_apply_F(c, in, out, 0, st))) return rc;
+        if (timing) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
+        ++n_fine;
+        return PIT_OK;
+    }
+
+    int sweep(const double *in, double *out)
+    {
+        int rc;
+        if (timing && (rc = begin(ev_coarse))) return rc;
+        if ((rc = pit_coarse_sweep(c, in, out, st))) return rc;
+        if (timing) PIT_HIP(hipEventRecord(ev_coarse.back().b, st));
+        ++n_coarse;
+        return PIT_OK;
+    }
+
+    static float total_ms(const std::vector<EventPair> &v)
+    {
+        float t = 0.0f;
+        for (const auto &e : v) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+
+    // out = G^{-1} F in  (one preconditioned matrix-by-vector product)
+    int matvec(const double *in, double *out)
+    {
+        int rc = apply(in, Tm);
+        if (rc) return rc;
+        rc = sweep(Tm, out);
+        if (rc) return rc;
+        ++matvecs;
+        return PIT_OK;
+    }
+
+    // nq inner products of (a[q], b[q]); fills dots and the N,inf norms of the pairs
+    int reduce(int nq, const double *const *a, const double *const *b, RedOut &h)
+    {
+        DotPairs pr{};
+        for (int q = 0; q < nq; ++q) {
+            pr.a[q] = a[q];
+            pr.b[q] = b[q];
+        }
+        PIT_HIP(launch_seg_dots(pr, nq, c->N, c->npts, c->bps, c->part(), c->w, c->red(), st));
+        PIT_HIP(hipMemcpyAsync(&h, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
+        PIT_HIP(hipStreamSynchronize(st));
+        return PIT_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
+                         pit_solve_info *info, void *stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !ctx->ws || !u0 || !X) return PIT_EINVAL;
+    pit_solve_opts o{};
+    o.tol = 1e-10;
+    o.restart_tol = 1e-30;
+    o.max_iter = 0;
+    o.norm_mode = PIT_ABS;
+    o.x0_mode = PIT_X0_ZERO;
+    if (opts) o = *opts;
+    if (o.max_iter <= 0) o.max_iter = 2 * ctx->N;
+    if (o.x0_mode < PIT_X0_ZERO || o.x0_mode > PIT_X0_COARSE || !(o.tol >= 0.0)) return PIT_EINVAL;
+
+    Solver s{};
+    s.c = ctx;
+    s.st = static_cast<hipStream_t>(stream);
+    s.R = ctx->vec(0);
+    s.Rt = ctx->vec(1);
+    s.P = ctx->vec(2);
+    s.D = ctx->vec(3);
+    s.S = ctx->vec(4);
+    s.K = ctx->vec(5);
+    s.Tm = ctx->vec(6);
+    s.n = ctx->nt();
+    s.timing = o.timing != 0;
+    const long n = s.n, np = ctx->npts;
+    hipStream_t st = s.st;
+    int rc;
+    RedOut h{};
+
+    // line 1: R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
+    PIT_HIP(launch_fill0(s.S, n, st));
+    PIT_HIP(launch_copy(s.S, u0, np, st));  // S holds B for now
+    if (o.x0_mode == PIT_X0_ZERO) {
+        PIT_HIP(launch_fill0(X, n, st));
+        if ((rc = s.sweep(s.S, s.R))) return rc;
+    } else {
+        if (o.x0_mode == PIT_X0_COARSE)
+            if ((rc = s.sweep(s.S, X))) return rc;
+        if ((rc = s.apply(X, s.D))) return rc;
+        PIT_HIP(launch_b_minus(s.Tm, s.D, u0, np, n, st));
+        if ((rc = s.sweep(s.Tm, s.R))) return rc;
+        s.matvecs++;
+    }
+    // lines 2-4
+    PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+    PIT_HIP(launch_copy(s.P, s.R, n, st));
+    {
+        const double *a[2] = {s.R, s.R}, *b[2] = {s.Rt, s.R};
+        if ((rc = s.reduce(2, a, b, h))) return rc;
+    }
+    double rho = h.dot[0];
+    double nrm = h.nmax[1];
+    const double scale = (o.norm_mode == PIT_REL && h.nmax[1] > 0.0) ? h.nmax[1] : 1.0;
+    double best = nrm;
+    int best_at = 0, k = 0, restarts = 0, status = PIT_ENOCONV, hl = 0;
+
+    for (;;) {
+        if (info && info->history && hl < info->history_cap) info->history[hl++] = nrm;
+        if (!std::isfinite(nrm)) {
+            status = PIT_EBREAKDOWN;
+            break;
+        }
+        if (!(nrm > o.tol * scale)) {  // line 5
+            status = PIT_OK;
+            break;
+        }
+        if (k >= o.max_iter) {
+            status = PIT_ENOCONV;
+            break;
+        }
+        if (o.stall_window > 0) {
+            if (nrm <= 0.5 * best) {
+                best = nrm;
+                best_at = k;
+            } else if (k - best_at >= o.stall_window) {
+                status = PIT_ENOCONV;
+                break;
+            }
+        }
+        // line 6
+        if ((rc = s.matvec(s.P, s.D))) return rc;
+        double dr;
+        {
+            const double *a[1] = {s.D}, *b[1] = {s.Rt};
+            if ((rc = s.reduce(1, a, b, h))) return rc;
+            dr = h.dot[0];
+        }
+        if (dr == 0.0) {  // restart with the current residual, redo line 6
+            PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+            PIT_HIP(launch_copy(s.P, s.R, n, st));
+            const double *a[1] = {s.R}, *b[1] = {s.R};
+            if ((rc = s.reduce(1, a, b, h))) return rc;
+            rho = h.dot[0];
+            restarts++;
+            if ((rc = s.matvec(s.P, s.D))) return rc;
+            const double *a2[1] = {s.D}, *b2[1] = {s.Rt};
+            if ((rc = s.reduce(1, a2, b2, h))) return rc;
+            dr = h.dot[0];
+            if (dr == 0.0) {
+                status = PIT_EBREAKDOWN;
+                break;
+            }
+        }
+        const double alpha = rho / dr;  // line 7
+        PIT_HIP(launch_axpby(s.S, s.R, 1.0, s.D, -alpha, n, st));  // line 8
+        if (o.half_step_check) {
+            const double *a[1] = {s.S}, *b[1] = {s.S};
+            if ((rc = s.reduce(1, a, b, h))) return rc;
+            if (!(h.nmax[0] > o.tol * scale)) {
+                PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
+                PIT_HIP(launch_copy(s.R, s.S, n, st));
+                nrm = h.nmax[0];
+                k++;
+                continue;
+            }
+        }
+        // line 9
+        if ((rc = s.matvec(s.S, s.K))) return rc;
+        {
+            const double *a[3] = {s.K, s.K, s.S}, *b[3] = {s.S, s.K, s.S};
+            if ((rc = s.reduce(3, a, b, h))) return rc;
+        }
+        const double ks = h.dot[0], kk = h.dot[1], snorm = h.nmax[2];
+        if (kk == 0.0) {  // S = 0: the half step solved the system
+            PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
+            PIT_HIP(launch_copy(s.R, s.S, n, st));
+            nrm = snorm;
+            k++;
+            continue;
+        }
+        const double omega = ks / kk;  // line 10
+        if (omega == 0.0) {
+            PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
+            PIT_HIP(launch_copy(s.R, s.S, n, st));
+            PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+            PIT_HIP(launch_copy(s.P, s.R, n, st));
+            const double *a[1] = {s.R}, *b[1] = {s.R};
+            if ((rc = s.reduce(1, a, b, h))) return rc;
+            rho = h.dot[0];
+            nrm = h.nmax[0];
+            restarts++;
+            k++;
+            continue;
+        }
+        // lines 11-12
+        PIT_HIP(launch_update_xr(X, s.R, s.P, s.S, s.K, alpha, omega, n, st));
+        // line 13 (and the norm for the next test)
+        {
+            const double *a[2] = {s.R, s.R}, *b[2] = {s.Rt, s.R};
+            if ((rc = s.reduce(2, a, b, h))) return rc;
+        }
+        double rho_new = h.dot[0];
+        nrm = h.nmax[1];
+        const double beta = (alpha / omega) * (rho_new / rho);
+        // line 14
+        PIT_HIP(launch_update_p(s.P, s.R, s.D, beta, omega, n, st));
+        // lines 15-17
+        if (std::fabs(rho_new) <= o.restart_tol) {
+            PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+            PIT_HIP(launch_copy(s.P, s.R, n, st));
+            rho_new = h.dot[1];
+            restarts++;
+        }
+        rho = rho_new;
+        k++;  // line 18
+    }
+    PIT_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->status = status;
+        info->iters = k;
+        info->matvecs = s.matvecs;
+        info->restarts = restarts;
+        info->res_norm = nrm;
+        info->history_len = hl;
+        info->n_fine = s.n_fine;
+        info->n_coarse = s.n_coarse;
+        info->ms_fine = s.timing ? Solver::total_ms(s.ev_fine) : 0.0f;
+        info->ms_coarse = s.timing ? Solver::total_ms(s.ev_coarse) : 0.0f;
+        info->ms_total =
+            std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}

@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+the public header declares, and validates its arguments on the host."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2203_10148_amd import pitsbicg as P
+from paper_2203_10148_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pitsbicg.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pit_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load()
+    names = declared_symbols()
+    assert "pit_apply_F" in names and "pit_solve" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header():
+    # sizes fixed by the header's field list (int32 / double / pointer, natural alignment)
+    assert ct.sizeof(P.pit_problem) == 4 * 4 + 8 * 7
+    assert ct.sizeof(P.pit_stepper) == 16
+    assert ct.sizeof(P.pit_solve_opts) == 8 * 2 + 4 * 6
+    assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 3
+
+
+def create(p, fine=None, coarse=None, N=None, m=None):
+    lib = P.load()
+    pb = P.make_problem(p)
+    f = fine or P.pit_stepper(p.fine, p.m, p.prec, 0)
+    g = coarse or P.pit_stepper(p.coarse, p.c, P.F64, 0)
+    h = ct.c_void_p()
+    rc = lib.pit_create(ct.byref(pb), p.N if N is None else N, p.m if m is None else m, f, g,
+                        ct.byref(h))
+    return rc, h
+
+
+def test_create_accepts_the_1d_workloads():
+    for p in (wl.C1, wl.C2.with_(prec=wl.F64)):
+        rc, h = create(p)
+        assert rc == P.OK and h.value
+        assert P.load().pit_workspace_bytes(h) > 0
+        P.load().pit_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=0), dict(m=0), dict(M=(2, 1)), dict(M=(20000, 1)), dict(dim=3), dict(T=0.0),
+    dict(nu=-1.0), dict(fine=7), dict(coarse=7), dict(fine=wl.ADI), dict(bc=5),
+])
+def test_create_rejects_bad_arguments(bad):
+    kw = dict(bad)
+    N = kw.pop("N", None)
+    m = kw.pop("m", None)
+    p = wl.C1.with_(**kw)
+    rc, h = create(p, N=N, m=m)
+    assert rc == P.EINVAL and not h.value
+
+
+def test_create_rejects_mismatched_fine_substeps():
+    p = wl.C1
+    rc, _ = create(p, fine=P.pit_stepper(p.fine, p.m + 1, P.F64, 0))
+    assert rc == P.EINVAL
+    rc, _ = create(p, coarse=P.pit_stepper(p.coarse, 0, P.F64, 0))
+    assert rc == P.EINVAL
+
+
+def test_workspace_scales_with_problem():
+    lib = P.load()
+    _, h1 = create(wl.C1)
+    _, h2 = create(wl.C1.with_(N=32))
+    b1, b2 = lib.pit_workspace_bytes(h1), lib.pit_workspace_bytes(h2)
+    assert b2 > b1 >= 7 * wl.C1.N * wl.C1.npts * 8
+    lib.pit_destroy(h1)
+    lib.pit_destroy(h2)
+
+
+def test_unbound_context_and_null_pointers_are_rejected():
+    lib = P.load()
+    _, h = create(wl.C1)
+    assert lib.pit_apply_F(h, None, None, 0, None) == P.EINVAL
+    assert lib.pit_coarse_sweep(h, None, None, None) == P.EINVAL
+    assert lib.pit_solve(h, None, None, None, None, None) == P.EINVAL
+    assert lib.pit_bind_workspace(h, None, 0) == P.EINVAL
+    assert lib.pit_bind_workspace(h, ct.c_void_p(256 * 1000 + 8), 1 << 30) == P.EINVAL  # misaligned
+    assert lib.pit_bind_workspace(h, ct.c_void_p(256 * 1000), 16) == P.ENOMEM
+    lib.pit_destroy(h)
+
+
+def test_strerror_covers_codes():
+    for code in (P.OK, P.EINVAL, P.ENOMEM, P.EHIP, P.ENOCONV, P.EBREAKDOWN, P.EAGAIN):
+        assert P.strerror(code) and P.strerror(code) != "unknown status"
+
+
+def test_kernel_shapes_cover_the_line():
+    lib = P.load()
+    for M in (3, 64, 65, 1000, 4096, 8192, 16384):
+        rc, h = create(wl.C2.with_(M=(M, 1), prec=wl.F64, N=4, m=2))
+        assert rc == P.OK
+        out = (ct.c_int32 * 4)()
+        lib.pit_kernel_shape(h, out)
+        assert out[0] * out[1] >= M and out[2] * out[3] >= M
+        assert out[0] % 64 == 0 and out[0] <= 1024
+        lib.pit_destroy(h)

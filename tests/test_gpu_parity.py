@@ -1,0 +1,261 @@
+"""GPU parity: libpitsbicg (through its C ABI) against the CPU oracle.
+
+Operators (all-at-once apply, coarse sweep) are compared element by element
+on seeded inputs at sizes that span several per-thread chunks, several
+wavefronts and a ragged tail; the full 4096 x 256 workload is compared on
+sampled slices the oracle computes one by one.  The FP64 bar is 1e-12
+relative for one operator application and 1e-10 relative (same iteration
+count) for a whole solve.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2203_10148_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_10148_amd import pitsbicg as P
+
+    P.load()  # fail loudly if the HIP library is missing
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def ctx(p, **kw):
+    from paper_2203_10148_amd import pitsbicg as P
+
+    return P.Context(p, **kw)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_oracle(p):
+    return orc.Oracle(**p.oracle_kwargs())
+
+
+# ---------------------------------------------------------------------------
+# operators
+# ---------------------------------------------------------------------------
+
+OP_CASES = [
+    # (M, bc, fine, coarse, c, N, m)
+    (64, wl.DIRICHLET, wl.IE, wl.IE, 1, 16, 64),      # the 64-point heat workload
+    (3, wl.DIRICHLET, wl.IE, wl.IE, 1, 3, 2),         # smallest line
+    (5, wl.PERIODIC, wl.CN, wl.IE, 2, 4, 3),
+    (63, wl.PERIODIC, wl.CN, wl.IE, 2, 5, 4),
+    (65, wl.DIRICHLET, wl.CN, wl.CN, 2, 4, 5),
+    (200, wl.PERIODIC, wl.IE, wl.IE, 1, 3, 7),
+    (1000, wl.PERIODIC, wl.CN, wl.IE, 2, 4, 6),       # ragged: 1000 on 128 x 8
+    (1023, wl.DIRICHLET, wl.CN, wl.IE, 2, 3, 4),
+    (4096, wl.PERIODIC, wl.CN, wl.IE, 2, 4, 5),
+    (5000, wl.PERIODIC, wl.CN, wl.IE, 2, 3, 3),       # 1024 threads, ragged
+    (16384, wl.DIRICHLET, wl.IE, wl.IE, 1, 3, 2),     # largest line
+]
+
+
+def op_problem(M, bc, fine, coarse, c, N, m):
+    adv = 0.7 if bc == wl.PERIODIC else 0.3
+    return wl.Problem(dim=1, M=(M, 1), bc=bc, nu=2e-3, adv=(adv, 0.0), react=0.1, T=0.5, N=N,
+                      m=m, fine=fine, c=c, coarse=coarse, prec=wl.F64)
+
+
+@pytest.mark.parametrize("case", OP_CASES, ids=lambda c: f"M{c[0]}_bc{c[1]}_f{c[2]}_N{c[5]}_m{c[6]}")
+def test_apply_and_sweep_match_oracle(case):
+    p = op_problem(*case)
+    say(f"apply/sweep {case}")
+    o = make_oracle(p)
+    c = ctx(p)
+    lam = wl.random_block(p, 1234 + case[0])
+    d = dev(lam)
+    y = host(c.apply_F(d))
+    assert relerr(y, o.apply(lam)) < 1e-12
+    yr = host(c.apply_F(d, raw=True))
+    assert relerr(yr, o.apply_raw(lam)) < 1e-12
+    z = host(c.coarse_sweep(d))
+    assert relerr(z, o.sweep(lam)) < 1e-12
+    # in place
+    d2 = dev(lam)
+    c.coarse_sweep(d2, d2)
+    assert relerr(host(d2), o.sweep(lam)) < 1e-12
+
+
+SHAPES = [(64, 1), (64, 2), (64, 4), (64, 8), (128, 8), (256, 8), (256, 16), (512, 8),
+          (512, 16), (1024, 8), (1024, 16)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"NT{s[0]}_C{s[1]}")
+def test_every_line_shape(shape, monkeypatch):
+    NT, C = shape
+    M = NT * C - 3 if NT * C > 8 else NT * C
+    monkeypatch.setenv("PIT_FINE_SHAPE", f"{NT},{C}")
+    monkeypatch.setenv("PIT_COARSE_SHAPE", f"{NT},{C}")
+    p = op_problem(M, wl.PERIODIC, wl.CN, wl.IE, 2, 3, 3)
+    say(f"shape NT={NT} C={C} M={M}")
+    c = ctx(p)
+    assert c.kernel_shape() == (NT, C, NT, C)
+    o = make_oracle(p)
+    lam = wl.random_block(p, 77)
+    d = dev(lam)
+    assert relerr(host(c.apply_F(d)), o.apply(lam)) < 1e-12
+    assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
+
+
+def test_serial_trajectory_is_annihilated():
+    """F applied to the serial fine trajectory gives (u0, 0, .., 0)."""
+    p = wl.C1
+    say("serial trajectory residual")
+    o = make_oracle(p)
+    u0 = wl.u0_for(p)
+    lam = o.serial(u0)
+    c = ctx(p)
+    y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
+    assert relerr(y[0], u0) < 1e-15
+    assert np.abs(y[1:]).max() < 1e-13 * np.abs(u0).max()
+
+
+def test_c2_full_size_apply_sampled_slices():
+    """The 4096-point, 256-slice advection-diffusion apply (200 CN steps),
+    checked on sampled slices."""
+    p = wl.C2.with_(prec=wl.F64)
+    say("c2 full apply")
+    c = ctx(p)
+    o = make_oracle(p.with_(N=1))
+    lam = wl.random_block(p, 2)
+    y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
+    L = lam.reshape(p.N, -1)
+    assert np.array_equal(y[0], L[0])
+    for n in (1, 2, 77, 128, 200, 255):
+        ref = L[n] - o.F(L[n - 1])
+        assert relerr(y[n], ref) < 1e-12, n
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1
+# ---------------------------------------------------------------------------
+
+def u0_of(p):
+    if p.name.startswith(("c1_", "c2_", "c3_")):
+        return wl.u0_for(p)
+    return wl.u0_fourier(p, 3) if p.bc == wl.PERIODIC else wl.u0_sines(p)
+
+
+def compare_solve(p, tol, eps0=1e-30, max_iter=None, norm_mode=orc.ABS, x0_mode=orc.X0_ZERO,
+                  X0=None, half_step_check=0):
+    o = make_oracle(p)
+    u0 = u0_of(p)
+    Xo, io = o.pitsbicg(u0, tol=tol, eps0=eps0, max_iter=max_iter, norm_mode=norm_mode,
+                        x0_mode=x0_mode, X0=X0, half_step_check=half_step_check)
+    c = ctx(p)
+    Xg, ig = c.solve(dev(u0), None if X0 is None else dev(X0), tol=tol, restart_tol=eps0,
+                     max_iter=max_iter or 0, norm_mode=norm_mode, x0_mode=x0_mode,
+                     half_step_check=half_step_check)
+    return Xo, io, host(Xg), ig, o, u0
+
+
+def test_c1_solve_matches_oracle():
+    p = wl.C1
+    say("c1 solve")
+    Xo, io, Xg, ig, o, u0 = compare_solve(p, p.tol)
+    assert ig.status == io.status == orc.OK
+    assert ig.iters == io.iters and ig.matvecs == io.matvecs
+    assert relerr(Xg, Xo) < 1e-10
+    assert relerr(Xg, o.serial(u0)) < 1e-9
+    h = min(len(ig.history), len(io.history))
+    assert np.allclose(ig.history[:h], io.history[:h], rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("opt", ["restart_every", "max_iter1", "x0_coarse", "x0_given", "rel",
+                                 "half_step", "tol12"])
+def test_solve_options_match_oracle(opt):
+    p = wl.C1.with_(N=8)
+    say(f"solve option {opt}")
+    o = make_oracle(p)
+    kw = {"restart_every": dict(eps0=1e30, max_iter=100), "max_iter1": dict(max_iter=1),
+          "x0_coarse": dict(x0_mode=orc.X0_COARSE), "rel": dict(norm_mode=orc.REL),
+          "half_step": dict(half_step_check=1), "tol12": dict(),
+          "x0_given": dict(x0_mode=orc.X0_GIVEN, X0=o.serial(wl.u0_for(p)) * (1 + 1e-3))}[opt]
+    tol = 1e-12 if opt == "tol12" else 1e-10
+    Xo, io, Xg, ig, o, u0 = compare_solve(p, tol, **kw)
+    assert ig.status == io.status
+    assert ig.iters == io.iters and ig.matvecs == io.matvecs and ig.restarts == io.restarts
+    assert relerr(Xg, Xo) < 1e-10
+
+
+def test_g_equals_f_and_single_slice():
+    say("special cases")
+    p = wl.C1.with_(N=8, c=64)
+    Xo, io, Xg, ig, o, u0 = compare_solve(p, 1e-12)
+    assert ig.iters == 1 and ig.matvecs == 2
+    assert relerr(Xg, o.serial(u0)) < 1e-13
+    p1 = wl.C1.with_(N=1)
+    Xo, io, Xg, ig, o, u0 = compare_solve(p1, 1e-14)
+    assert ig.status == orc.OK and ig.iters == 1
+    assert relerr(Xg, u0) < 1e-15
+
+
+def test_nan_input_is_a_breakdown():
+    from paper_2203_10148_amd import pitsbicg as P
+
+    p = wl.C1
+    say("nan input")
+    c = ctx(p)
+    u0 = wl.u0_for(p)
+    u0[5] = np.nan
+    _, info = c.solve(dev(u0))
+    assert info.status == P.EBREAKDOWN
+
+
+@pytest.mark.parametrize("M,bc,N", [(1000, wl.PERIODIC, 12), (777, wl.DIRICHLET, 9)])
+def test_ragged_solve_matches_oracle(M, bc, N):
+    p = wl.Problem(dim=1, M=(M, 1), bc=bc, nu=1e-3, adv=(1.0, 0.0), T=1.0, N=N, m=20, fine=wl.CN,
+                   c=2, coarse=wl.IE, prec=wl.F64)
+    say(f"ragged solve M={M} bc={bc}")
+    Xo, io, Xg, ig, o, u0 = compare_solve(p, 1e-10)
+    assert ig.status == io.status == orc.OK
+    assert abs(ig.iters - io.iters) <= 1
+    assert relerr(Xg, Xo) < 1e-9
+    assert relerr(Xg, o.serial(u0)) < 1e-8
+
+
+def test_c2_full_size_fp64_solve():
+    """The 4096 x 256 advection-diffusion workload, FP64, tol 1e-8: same
+    iteration count as the oracle, solution within 1e-10 of the oracle's."""
+    p = wl.C2.with_(prec=wl.F64)
+    say("c2 fp64 full solve")
+    o = make_oracle(p)
+    u0 = wl.u0_for(p)
+    c = ctx(p)
+    Xg, ig = c.solve(dev(u0), tol=p.tol)
+    Xg = host(Xg)
+    Xo, io = o.pitsbicg(u0, tol=p.tol)
+    print(f"gpu iters={ig.iters} ms={ig.ms_total:.1f}  oracle iters={io.iters}", flush=True)
+    assert ig.status == io.status == orc.OK
+    assert abs(ig.iters - io.iters) <= 1
+    assert relerr(Xg, Xo) < 1e-10
