@@ -13,32 +13,74 @@
 
 namespace pit {
 
-template <int NT, int C>
+// Thread t owns points t*C .. t*C+C-1 of a line of M points.  Two slice
+// layouts exist:
+//   natural  (TR = false): point j of a slice at j, slice stride M (the ABI
+//            layout).  Loads are branch-free: the index is clamped into the
+//            line and padding points j >= M are zeroed where the value is
+//            used, so a prefetched register is not merged across control
+//            flow (that would force an early wait on the load).
+//   chunked  (TR = true):  point t*C+k at k*NT+t, slice stride NT*C, padding
+//            stored as zeros.  Every load and store is coalesced across the
+//            wavefront; pit_solve keeps its block vectors in this layout.
+template <int NT, int C, bool TR>
+__device__ __forceinline__ void load_chunk(const double *__restrict__ src, int t, int M, double (&u)[C])
+{
+#pragma unroll
+    for (int k = 0; k < C; ++k) u[k] = TR ? src[k * NT + t] : src[min(t * C + k, M - 1)];
+}
+
+template <int C>
+__device__ __forceinline__ void zero_pads(int t, int M, double (&u)[C])
+{
+    const int j0 = t * C;
+#pragma unroll
+    for (int k = 0; k < C; ++k) u[k] = (j0 + k < M) ? u[k] : 0.0;
+}
+
+template <int NT, int C, bool TR>
+__device__ __forceinline__ void store_chunk(double *__restrict__ dst, int t, int M, const double (&u)[C])
+{
+    if constexpr (TR) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) dst[k * NT + t] = u[k];
+    } else {
+        const int j0 = t * C;
+        if (j0 + C <= M) {
+#pragma unroll
+            for (int k = 0; k < C; ++k) dst[j0 + k] = u[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (j0 + k < M) dst[j0 + k] = u[k];
+        }
+    }
+}
+
+// Fine apply: workgroup n computes y_n = lam_n - F(lam_{n-1}) (or F(lam_n)
+// when raw); ld is the slice stride of lam and y.
+template <int NT, int C, int SCHEME, bool TR>
 __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const double *__restrict__ lam,
-                                                   double *__restrict__ y, int N, int M, int m,
-                                                   int scheme, int raw, int n0)
+                                                   double *__restrict__ y, int N, int M, long ld, int m,
+                                                   int raw, int n0)
 {
     constexpr int W = NT / kWave;
     __shared__ double lds[4 * W];
     const int n = n0 + blockIdx.x;
     const int t = threadIdx.x;
     if (!raw && n == 0) {  // y_0 = lam_0
-        for (int j = t; j < M; j += NT) y[j] = lam[j];
+        for (long j = t; j < ld; j += NT) y[j] = lam[j];
         return;
     }
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
-    const double *src = lam + (size_t)(raw ? n : n - 1) * M;
     double u[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int j = t * C + k;
-        u[k] = (j < M) ? src[j] : 0.0;
-    }
-    if (scheme == SCHEME_IE) {
-        for (int s = 0; s < m; ++s) S.solve(u);
-    } else {
-        for (int s = 0; s < m; ++s) {
+    load_chunk<NT, C, TR>(lam + (size_t)(raw ? n : n - 1) * ld, t, M, u);
+    zero_pads<C>(t, M, u);
+    for (int s = 0; s < m; ++s) {
+        if constexpr (SCHEME == SCHEME_IE) {
+            S.solve(u);
+        } else {
             double w[C];
 #pragma unroll
             for (int k = 0; k < C; ++k) w[k] = u[k];
@@ -47,99 +89,119 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
             for (int k = 0; k < C; ++k) u[k] = fma(2.0, w[k], -u[k]);
         }
     }
-    double *dst = y + (size_t)n * M;
-    const double *own = lam + (size_t)n * M;
+    if (!raw) {
+        double own[C];
+        load_chunk<NT, C, TR>(lam + (size_t)n * ld, t, M, own);
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int j = t * C + k;
-        if (j < M) dst[j] = raw ? u[k] : own[j] - u[k];
+        for (int k = 0; k < C; ++k) u[k] = own[k] - u[k];
+        zero_pads<C>(t, M, u);
     }
+    store_chunk<NT, C, TR>(y + (size_t)n * ld, t, M, u);
 }
 
-template <int NT, int C>
+// One coarse slice step of the sweep: u <- G(u) + v_n (pads stay 0).
+template <int NT, int C, int SCHEME>
+__device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double (&u)[C], const double (&vn)[C],
+                                            int c, int t, int M)
+{
+    for (int s = 0; s < c; ++s) {
+        if constexpr (SCHEME == SCHEME_IE) {
+            S.solve(u);
+        } else {
+            double w[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) w[k] = u[k];
+            S.solve(w);
+#pragma unroll
+            for (int k = 0; k < C; ++k) u[k] = fma(2.0, w[k], -u[k]);
+        }
+    }
+    const int j0 = t * C;
+#pragma unroll
+    for (int k = 0; k < C; ++k) u[k] = (j0 + k < M) ? u[k] + vn[k] : 0.0;
+}
+
+// The slice loop is unrolled by two with two prefetch buffers (v_{n+2} is
+// loaded while slices n and n+1 are computed) and the prefetch index is
+// clamped instead of guarded, so the loaded registers are consumed where
+// they land.
+template <int NT, int C, int SCHEME, bool TR>
 __global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const double *v, double *z,
-                                                    int N, int M, int c, int scheme)
+                                                    int N, int M, long ld, int c)
 {
     constexpr int W = NT / kWave;
     __shared__ double lds[4 * W];
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
-    double u[C], nxt[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int j = t * C + k;
-        u[k] = (j < M) ? v[j] : 0.0;
-        nxt[k] = (j < M && N > 1) ? v[(size_t)M + j] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const int j = t * C + k;
-        if (j < M) z[j] = u[k];
-    }
-    for (int n = 1; n < N; ++n) {
-        if (scheme == SCHEME_IE) {
-            for (int s = 0; s < c; ++s) S.solve(u);
-        } else {
-            for (int s = 0; s < c; ++s) {
-                double w[C];
-#pragma unroll
-                for (int k = 0; k < C; ++k) w[k] = u[k];
-                S.solve(w);
-#pragma unroll
-                for (int k = 0; k < C; ++k) u[k] = fma(2.0, w[k], -u[k]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < C; ++k) u[k] += nxt[k];
-        if (n + 1 < N) {
-#pragma unroll
-            for (int k = 0; k < C; ++k) {
-                const int j = t * C + k;
-                nxt[k] = (j < M) ? v[(size_t)(n + 1) * M + j] : 0.0;
-            }
-        }
-        double *dst = z + (size_t)n * M;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int j = t * C + k;
-            if (j < M) dst[j] = u[k];
-        }
+    double u[C], va[C], vb[C];
+    load_chunk<NT, C, TR>(v, t, M, u);
+    zero_pads<C>(t, M, u);
+    load_chunk<NT, C, TR>(v + (size_t)min(1, N - 1) * ld, t, M, va);
+    load_chunk<NT, C, TR>(v + (size_t)min(2, N - 1) * ld, t, M, vb);
+    store_chunk<NT, C, TR>(z, t, M, u);
+    for (int n = 1; n < N; n += 2) {
+        coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
+        load_chunk<NT, C, TR>(v + (size_t)min(n + 2, N - 1) * ld, t, M, va);
+        store_chunk<NT, C, TR>(z + (size_t)n * ld, t, M, u);
+        if (n + 1 >= N) break;
+        coarse_step<NT, C, SCHEME>(S, u, vb, c, t, M);
+        load_chunk<NT, C, TR>(v + (size_t)min(n + 3, N - 1) * ld, t, M, vb);
+        store_chunk<NT, C, TR>(z + (size_t)(n + 1) * ld, t, M, u);
     }
 }
 
-#define PIT_LINE_SHAPES(X) \
-    X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 8) X(256, 8) X(256, 16) X(512, 8) X(512, 16) \
-    X(1024, 8) X(1024, 16)
+#define PIT_LINE_SHAPES(X)                                                                  \
+    X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(128, 8) X(256, 4) X(256, 8) X(256, 16) X(512, 4)     \
+    X(512, 8) X(512, 16) X(1024, 4) X(1024, 8) X(1024, 16)
 
 hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const double *lam, double *y,
-                             int N, int M, int m, int scheme, int raw, int last_only, hipStream_t st)
+                             int N, int M, int m, int scheme, int raw, int last_only, bool chunked,
+                             hipStream_t st)
 {
     const int n0 = last_only ? N - 1 : 0;
     const int grid = last_only ? 1 : N;
     if (last_only) raw = 1;
-#define X(nt, c)                                                                                \
-    if (sh.NT == nt && sh.C == c) {                                                             \
-        hipLaunchKernelGGL((k_fine1d_f64<nt, c>), dim3(grid), dim3(nt), 0, st, tb, lam, y, N, M, \
-                           m, scheme, raw, n0);                                                 \
-        return hipGetLastError();                                                               \
+#define LAUNCH(nt, c, SCH, TR)                                                                       \
+    hipLaunchKernelGGL((k_fine1d_f64<nt, c, SCH, TR>), dim3(grid), dim3(nt), 0, st, tb, lam, y, N, M, \
+                       (long)(TR ? nt * c : M), m, raw, n0)
+#define X(nt, c)                                                       \
+    if (sh.NT == nt && sh.C == c) {                                    \
+        if (scheme == SCHEME_IE) {                                     \
+            if (chunked) LAUNCH(nt, c, SCHEME_IE, true);               \
+            else LAUNCH(nt, c, SCHEME_IE, false);                      \
+        } else {                                                       \
+            if (chunked) LAUNCH(nt, c, SCHEME_CN, true);               \
+            else LAUNCH(nt, c, SCHEME_CN, false);                      \
+        }                                                              \
+        return hipGetLastError();                                      \
     }
     PIT_LINE_SHAPES(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const double *v, double *z,
-                              int N, int M, int c, int scheme, hipStream_t st)
+                              int N, int M, int c, int scheme, bool chunked, hipStream_t st)
 {
-#define X(nt, cc)                                                                              \
-    if (sh.NT == nt && sh.C == cc) {                                                           \
-        hipLaunchKernelGGL((k_sweep1d_f64<nt, cc>), dim3(1), dim3(nt), 0, st, tb, v, z, N, M, c, \
-                           scheme);                                                            \
-        return hipGetLastError();                                                              \
+#define LAUNCH(nt, cc, SCH, TR)                                                                    \
+    hipLaunchKernelGGL((k_sweep1d_f64<nt, cc, SCH, TR>), dim3(1), dim3(nt), 0, st, tb, v, z, N, M, \
+                       (long)(TR ? nt * cc : M), c)
+#define X(nt, cc)                                                      \
+    if (sh.NT == nt && sh.C == cc) {                                   \
+        if (scheme == SCHEME_IE) {                                     \
+            if (chunked) LAUNCH(nt, cc, SCHEME_IE, true);              \
+            else LAUNCH(nt, cc, SCHEME_IE, false);                     \
+        } else {                                                       \
+            if (chunked) LAUNCH(nt, cc, SCHEME_CN, true);              \
+            else LAUNCH(nt, cc, SCHEME_CN, false);                     \
+        }                                                              \
+        return hipGetLastError();                                      \
     }
     PIT_LINE_SHAPES(X)
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 

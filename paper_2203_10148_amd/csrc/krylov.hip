@@ -152,6 +152,41 @@ __global__ void k_fill0(double *__restrict__ dst, long n)
         dst[i] = 0.0;
 }
 
+// natural [N][M] <-> chunked [N][NT*C]: point j = t*C + k sits at k*NT + t.
+__global__ void k_to_chunked(const double *__restrict__ nat, double *__restrict__ chk, int N, int M, int NT,
+                             int C)
+{
+    const long S = (long)NT * C, tot = (long)N * S;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long n = i / S, r = i % S;
+        const long k = r / NT, t = r % NT, j = t * C + k;
+        chk[i] = (j < M) ? nat[n * M + j] : 0.0;
+    }
+}
+
+__global__ void k_from_chunked(const double *__restrict__ chk, double *__restrict__ nat, int N, int M, int NT,
+                               int C)
+{
+    const long S = (long)NT * C, tot = (long)N * M;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+        const long n = i / M, j = i % M;
+        const long t = j / C, k = j % C;
+        nat[i] = chk[n * S + k * NT + t];
+    }
+}
+
+hipError_t launch_to_chunked(const double *nat, double *chk, int N, int M, int NT, int C, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_chunked, vec_grid((long)N * NT * C), dim3(kVecThreads), 0, st, nat, chk, N, M, NT, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_chunked(const double *chk, double *nat, int N, int M, int NT, int C, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_from_chunked, vec_grid((long)N * M), dim3(kVecThreads), 0, st, chk, nat, N, M, NT, C);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby(double *out, const double *x, double a, const double *y, double b, long n,
                         hipStream_t st)
 {

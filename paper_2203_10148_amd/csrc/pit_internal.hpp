@@ -10,7 +10,7 @@
 namespace pit {
 
 constexpr int kWave = 64;      // CDNA wavefront width
-constexpr int kLevels = 6;     // log2(kWave): Kogge-Stone levels inside a wave
+constexpr int kScanConsts = 7; // per-thread multipliers of one in-wave scan
 constexpr int kMaxWaves = 16;  // 1024 threads per line at most
 constexpr int kMaxLine = 16384;
 
@@ -29,15 +29,19 @@ constexpr int kMaxLine = 16384;
 // carries between threads are a scan whose multiplier products are constants
 // precomputed here:
 //     pf_t = prod_k lm_{tC+k},   pb_t = prod_k cm_{tC+k}
-//     wf[l]_t = prod_{q=t-2^l+1..t} pf_q  (0 if the lane is < 2^l)
-//     wb[l]_t = prod_{q=t..t+2^l-1} pb_q  (0 if lane + 2^l > 63)
+//   in-wave scan, lanes in rows of 16 (r = row of t, l = lane in row):
+//     wf[i]_t   = prod_{q=t-s+1..t} pf_q, s = 2^i, i < 4   (0 if l < s)
+//     wf[4+r']_t = prod_{q=16(r'+1)..t} pf_q, r' < 3      (0 if r <= r')
+//     wb[i]_t   = prod_{q=t..t+s-1} pb_q, s = 2^i, i < 4   (0 if l + s > 15)
+//     wb[3+r']_t = prod_{q=t..16r'-1} pb_q, r' = 1..3     (0 if r >= r')
+//   (lane indices inside the wave), and across waves
 //     qf_t = prod_{q=wavestart..t-1} pf_q,  qb_t = prod_{q=t+1..waveend} pb_q
 //     pwf_w, pwb_w = products of pf / pb over wave w.
 // Padding points j >= M carry lm = 1, iu = 0, cm = 0, z = 0 so that the
 // forward total equals y_{M-1} and the pads solve to 0.
 //
 // Device layout (element type T, one contiguous blob):
-//   lm[C][NT] iu[C][NT] cm[C][NT] z[C][NT] wf[6][NT] wb[6][NT] qf[NT] qb[NT]
+//   lm[C][NT] iu[C][NT] cm[C][NT] z[C][NT] wf[7][NT] wb[7][NT] qf[NT] qb[NT]
 //   pwf[16] pwb[16]
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -50,7 +54,7 @@ struct LineTab {
     int M;
 };
 
-inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kLevels + 2) * NT + 2 * kMaxWaves; }
+inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kScanConsts + 2) * NT + 2 * kMaxWaves; }
 
 template <typename T>
 inline LineTab<T> line_tab_view(const T *base, int NT, int C)
@@ -62,8 +66,8 @@ inline LineTab<T> line_tab_view(const T *base, int NT, int C)
     tb.iu = base + o; o += pc;
     tb.cm = base + o; o += pc;
     tb.z = base + o; o += pc;
-    tb.wf = base + o; o += (size_t)kLevels * NT;
-    tb.wb = base + o; o += (size_t)kLevels * NT;
+    tb.wf = base + o; o += (size_t)kScanConsts * NT;
+    tb.wb = base + o; o += (size_t)kScanConsts * NT;
     tb.qf = base + o; o += NT;
     tb.qb = base + o; o += NT;
     tb.pwf = base + o; o += kMaxWaves;
@@ -81,14 +85,22 @@ struct LineShape {
 // ---------------------------------------------------------------------------
 enum { SCHEME_IE = 0, SCHEME_CN = 1, SCHEME_ADI = 2 };
 
+// Slice layouts of the 1D kernels: natural (point j at j, stride M) or
+// chunked (point t*C+k at k*NT+t, stride NT*C, zero padding), see fine1d.hip.
+//
 // Fine apply, 1D, FP64 state.  y_0 = lam_0, y_n = lam_n - F(lam_{n-1}); raw: y_n = F(lam_n);
 // last_only: y_{N-1} = F(lam_{N-1}) only.
 hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const double *lam, double *y,
-                             int N, int M, int m, int scheme, int raw, int last_only, hipStream_t st);
+                             int N, int M, int m, int scheme, int raw, int last_only, bool chunked,
+                             hipStream_t st);
 
 // Coarse sweep, 1D, FP64: z_0 = v_0, z_n = v_n + G(z_{n-1}).
 hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const double *v, double *z,
-                              int N, int M, int c, int scheme, hipStream_t st);
+                              int N, int M, int c, int scheme, bool chunked, hipStream_t st);
+
+// Layout conversions between natural [N][M] and chunked [N][NT*C] slices.
+hipError_t launch_to_chunked(const double *nat, double *chk, int N, int M, int NT, int C, hipStream_t st);
+hipError_t launch_from_chunked(const double *chk, double *nat, int N, int M, int NT, int C, hipStream_t st);
 
 // Krylov block-vector kernels (krylov.hip).  n = total number of doubles.
 // Segmented dot products: for each slice s and pair q < nq,

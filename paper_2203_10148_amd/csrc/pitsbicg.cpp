@@ -35,10 +35,11 @@ thread_local int t_last_hip = 0;
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kSolveVectors = 8;  // R, shadow R, P, D, S, K, temporary, iterate (chunked layout)
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-const LineShape kShapes[] = {{64, 1},   {64, 2},   {64, 4},   {64, 8},    {128, 8},   {256, 8},
-                             {256, 16}, {512, 8},  {512, 16}, {1024, 8},  {1024, 16}};
+const LineShape kShapes[] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},    {128, 8},  {256, 4},  {256, 8},
+                             {256, 16}, {512, 4}, {512, 8}, {512, 16}, {1024, 4}, {1024, 8}, {1024, 16}};
 
 bool shape_supported(LineShape s)
 {
@@ -57,7 +58,7 @@ LineShape default_shape(int M)
     if (M <= 512) return {64, 8};
     if (M <= 1024) return {128, 8};
     if (M <= 2048) return {256, 8};
-    if (M <= 4096) return {512, 8};
+    if (M <= 4096) return {256, 16};
     if (M <= 8192) return {1024, 8};
     return {1024, 16};
 }
@@ -143,20 +144,26 @@ bool build_line(int M, bool periodic, double a, double b, double c, LineShape sh
             W_(v.z)[k * NT + t] = zz[t * C + k];
         }
         const int lane = t % kWave, ws = t - lane, we = ws + kWave - 1;
-        for (int lv = 0; lv < kLevels; ++lv) {
-            const int s = 1 << lv;
-            double f = 0.0, g = 0.0;
-            if (lane >= s) {
-                f = 1.0;
-                for (int q = t - s + 1; q <= t; ++q) f *= pf[q];
-            }
-            if (lane + s <= kWave - 1) {
-                g = 1.0;
-                for (int q = t; q <= t + s - 1; ++q) g *= pb[q];
-            }
-            W_(v.wf)[lv * NT + t] = f;
-            W_(v.wb)[lv * NT + t] = g;
+        const int row = lane / 16, l16 = lane % 16;
+        auto prodf = [&](int a, int b) {  // prod pf over wave lanes a..b
+            double f = 1.0;
+            for (int q = a; q <= b; ++q) f *= pf[ws + q];
+            return f;
+        };
+        auto prodb = [&](int a, int b) {
+            double g = 1.0;
+            for (int q = a; q <= b; ++q) g *= pb[ws + q];
+            return g;
+        };
+        for (int i = 0; i < 4; ++i) {
+            const int s = 1 << i;
+            W_(v.wf)[i * NT + t] = (l16 >= s) ? prodf(lane - s + 1, lane) : 0.0;
+            W_(v.wb)[i * NT + t] = (l16 + s <= 15) ? prodb(lane, lane + s - 1) : 0.0;
         }
+        for (int r = 0; r < 3; ++r)  // lower row totals (rows 0..2) into row `row`
+            W_(v.wf)[(4 + r) * NT + t] = (row > r) ? prodf(16 * (r + 1), lane) : 0.0;
+        for (int r = 1; r <= 3; ++r)  // upper row totals (rows 1..3) into row `row`
+            W_(v.wb)[(3 + r) * NT + t] = (row < r) ? prodb(lane, 16 * r - 1) : 0.0;
         double qf = 1.0, qb = 1.0;
         for (int q = ws; q < t; ++q) qf *= pf[q];
         for (int q = t + 1; q <= we; ++q) qb *= pb[q];
@@ -198,8 +205,10 @@ struct pit_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
 
+    long ld = 0;  // slice stride of the chunked layout (NT*C)
     long nt() const { return (long)N * npts; }
-    double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * nt(); }
+    long ntc() const { return (long)N * ld; }
+    double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * ntc(); }
     double *part() const { return reinterpret_cast<double *>(ws + off_part); }
     RedOut *red() const { return reinterpret_cast<RedOut *>(ws + off_red); }
     LineTab<double> tab(const LineHost &L, size_t off) const
@@ -292,19 +301,23 @@ int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->hy = 1.0;
     c->w = c->hx;
     c->DT = problem->T / N;
-    if (!make_line(*c, fine.scheme, c->DT / m, shape_from_env("PIT_FINE_SHAPE", M), c->lf) ||
-        !make_line(*c, coarse.scheme, c->DT / coarse.substeps, shape_from_env("PIT_COARSE_SHAPE", M), c->lc)) {
+    // One shape for both line operators: pit_solve keeps its block vectors in
+    // the chunked layout of that shape, shared by the fine and coarse kernels.
+    const LineShape sh = shape_from_env("PIT_LINE_SHAPE", M);
+    if (!make_line(*c, fine.scheme, c->DT / m, sh, c->lf) ||
+        !make_line(*c, coarse.scheme, c->DT / coarse.substeps, sh, c->lc)) {
         delete c;
         return PIT_EINVAL;
     }
-    c->bps = (int)std::min<long>(64, std::max<long>(1, (c->npts + 2047) / 2048));
+    c->ld = (long)sh.NT * sh.C;
+    c->bps = (int)std::min<long>(64, std::max<long>(1, (c->ld + 2047) / 2048));
     size_t o = 0;
     c->off_tf = o;
     o = align_up(o + c->lf.blob.size() * sizeof(double));
     c->off_tc = o;
     o = align_up(o + c->lc.blob.size() * sizeof(double));
     c->off_vec = o;
-    o = align_up(o + 7 * (size_t)c->nt() * sizeof(double));
+    o = align_up(o + kSolveVectors * (size_t)c->ntc() * sizeof(double));
     c->off_part = o;
     o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
     c->off_red = o;
@@ -352,7 +365,7 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
     hipStream_t st = static_cast<hipStream_t>(stream);
     PIT_HIP(launch_fine1d_f64(ctx->lf.sh, ctx->tab(ctx->lf, ctx->off_tf), lam, y, ctx->N, ctx->npts, ctx->m,
                               ctx->fine.scheme, (flags & PIT_APPLY_RAW) ? 1 : 0,
-                              (flags & PIT_APPLY_LAST) ? 1 : 0, st));
+                              (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
     return PIT_OK;
 }
 
@@ -361,7 +374,7 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream)
     if (!ctx || !ctx->ws || !v || !z) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     PIT_HIP(launch_sweep1d_f64(ctx->lc.sh, ctx->tab(ctx->lc, ctx->off_tc), v, z, ctx->N, ctx->npts,
-                               ctx->coarse.substeps, ctx->coarse.scheme, st));
+                               ctx->coarse.substeps, ctx->coarse.scheme, false, st));
     return PIT_OK;
 }
 
@@ -379,7 +392,7 @@ struct EventPair {
 struct Solver {
     pit_ctx *c;
     hipStream_t st;
-    double *R, *Rt, *P, *D, *S, *K, *Tm;
+    double *R, *Rt, *P, *D, *S, *K, *Tm, *Xc;
     long n;
     int matvecs = 0;
     int n_fine = 0, n_coarse = 0;
@@ -402,11 +415,13 @@ struct Solver {
         return PIT_OK;
     }
 
+    // fine apply and coarse sweep on chunked-layout block vectors
     int apply(const double *in, double *out)
     {
         int rc;
         if (timing && (rc = begin(ev_fine))) return rc;
-        if ((rc = pit_apply_F(c, in, out, 0, st))) return rc;
+        PIT_HIP(launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), in, out, c->N, c->npts, c->m,
+                                  c->fine.scheme, 0, 0, true, st));
         if (timing) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
         ++n_fine;
         return PIT_OK;
@@ -416,7 +431,8 @@ struct Solver {
     {
         int rc;
         if (timing && (rc = begin(ev_coarse))) return rc;
-        if ((rc = pit_coarse_sweep(c, in, out, st))) return rc;
+        PIT_HIP(launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), in, out, c->N, c->npts,
+                                   c->coarse.substeps, c->coarse.scheme, true, st));
         if (timing) PIT_HIP(hipEventRecord(ev_coarse.back().b, st));
         ++n_coarse;
         return PIT_OK;
@@ -451,7 +467,7 @@ struct Solver {
             pr.a[q] = a[q];
             pr.b[q] = b[q];
         }
-        PIT_HIP(launch_seg_dots(pr, nq, c->N, c->npts, c->bps, c->part(), c->w, c->red(), st));
+        PIT_HIP(launch_seg_dots(pr, nq, c->N, c->ld, c->bps, c->part(), c->w, c->red(), st));
         PIT_HIP(hipMemcpyAsync(&h, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
         PIT_HIP(hipStreamSynchronize(st));
         return PIT_OK;
@@ -485,24 +501,31 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     s.S = ctx->vec(4);
     s.K = ctx->vec(5);
     s.Tm = ctx->vec(6);
-    s.n = ctx->nt();
+    s.Xc = ctx->vec(7);
+    s.n = ctx->ntc();
     s.timing = o.timing != 0;
-    const long n = s.n, np = ctx->npts;
+    const long n = s.n;
+    const int NT = ctx->lf.sh.NT, C = ctx->lf.sh.C;
     hipStream_t st = s.st;
+    double *const Xu = X;  // the caller's iterate (natural layout)
+    X = s.Xc;              // the working iterate (chunked layout)
     int rc;
     RedOut h{};
 
     // line 1: R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
     PIT_HIP(launch_fill0(s.S, n, st));
-    PIT_HIP(launch_copy(s.S, u0, np, st));  // S holds B for now
+    PIT_HIP(launch_to_chunked(u0, s.S, 1, ctx->npts, NT, C, st));  // S holds B for now
     if (o.x0_mode == PIT_X0_ZERO) {
         PIT_HIP(launch_fill0(X, n, st));
         if ((rc = s.sweep(s.S, s.R))) return rc;
     } else {
-        if (o.x0_mode == PIT_X0_COARSE)
+        if (o.x0_mode == PIT_X0_COARSE) {
             if ((rc = s.sweep(s.S, X))) return rc;
+        } else {
+            PIT_HIP(launch_to_chunked(Xu, X, ctx->N, ctx->npts, NT, C, st));
+        }
         if ((rc = s.apply(X, s.D))) return rc;
-        PIT_HIP(launch_b_minus(s.Tm, s.D, u0, np, n, st));
+        PIT_HIP(launch_axpby(s.Tm, s.S, 1.0, s.D, -1.0, n, st));
         if ((rc = s.sweep(s.Tm, s.R))) return rc;
         s.matvecs++;
     }
@@ -629,6 +652,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         rho = rho_new;
         k++;  // line 18
     }
+    PIT_HIP(launch_from_chunked(X, Xu, ctx->N, ctx->npts, NT, C, st));
     PIT_HIP(hipStreamSynchronize(st));
     if (info) {
         info->status = status;

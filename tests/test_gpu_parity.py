@@ -106,16 +106,15 @@ def test_apply_and_sweep_match_oracle(case):
     assert relerr(host(d2), o.sweep(lam)) < 1e-12
 
 
-SHAPES = [(64, 1), (64, 2), (64, 4), (64, 8), (128, 8), (256, 8), (256, 16), (512, 8),
-          (512, 16), (1024, 8), (1024, 16)]
+SHAPES = [(64, 1), (64, 2), (64, 4), (64, 8), (128, 8), (256, 4), (256, 8), (256, 16), (512, 4),
+          (512, 8), (512, 16), (1024, 4), (1024, 8), (1024, 16)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"NT{s[0]}_C{s[1]}")
 def test_every_line_shape(shape, monkeypatch):
     NT, C = shape
     M = NT * C - 3 if NT * C > 8 else NT * C
-    monkeypatch.setenv("PIT_FINE_SHAPE", f"{NT},{C}")
-    monkeypatch.setenv("PIT_COARSE_SHAPE", f"{NT},{C}")
+    monkeypatch.setenv("PIT_LINE_SHAPE", f"{NT},{C}")
     p = op_problem(M, wl.PERIODIC, wl.CN, wl.IE, 2, 3, 3)
     say(f"shape NT={NT} C={C} M={M}")
     c = ctx(p)
@@ -125,6 +124,30 @@ def test_every_line_shape(shape, monkeypatch):
     d = dev(lam)
     assert relerr(host(c.apply_F(d)), o.apply(lam)) < 1e-12
     assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(64, 2), (128, 8), (256, 4), (512, 8), (1024, 4)],
+                         ids=lambda s: f"NT{s[0]}_C{s[1]}")
+def test_solve_every_layout(shape, monkeypatch):
+    """pit_solve keeps its vectors in the chunked layout of the line shape
+    (padded to NT*C points); a ragged line exercises the padding."""
+    NT, C = shape
+    M = NT * C - 5
+    monkeypatch.setenv("PIT_LINE_SHAPE", f"{NT},{C}")
+    p = wl.Problem(dim=1, M=(M, 1), bc=wl.PERIODIC, nu=2e-3, adv=(0.8, 0.0), T=0.6, N=6, m=4,
+                   fine=wl.CN, c=2, coarse=wl.IE, prec=wl.F64)
+    say(f"solve layout NT={NT} C={C} M={M}")
+    o = make_oracle(p)
+    u0 = wl.u0_fourier(p, 5)
+    Xo, io = o.pitsbicg(u0, tol=1e-10)
+    c = ctx(p)
+    assert c.kernel_shape() == (NT, C, NT, C)
+    Xg, ig = c.solve(dev(u0), tol=1e-10)
+    Xg = host(Xg)
+    assert ig.status == io.status == orc.OK
+    assert abs(ig.iters - io.iters) <= 1
+    assert relerr(Xg, Xo) < 1e-9
+    assert relerr(Xg, o.serial(u0)) < 1e-9
 
 
 def test_serial_trajectory_is_annihilated():
@@ -146,7 +169,7 @@ def test_c2_full_size_apply_sampled_slices():
     p = wl.C2.with_(prec=wl.F64)
     say("c2 full apply")
     c = ctx(p)
-    o = make_oracle(p.with_(N=1))
+    o = make_oracle(p.with_(N=1, T=p.T / p.N))  # one slice of the same length DT
     lam = wl.random_block(p, 2)
     y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
     L = lam.reshape(p.N, -1)
@@ -245,17 +268,34 @@ def test_ragged_solve_matches_oracle(M, bc, N):
 
 
 def test_c2_full_size_fp64_solve():
-    """The 4096 x 256 advection-diffusion workload, FP64, tol 1e-8: same
-    iteration count as the oracle, solution within 1e-10 of the oracle's."""
+    """The 4096 x 256 advection-diffusion workload, FP64.
+
+    At the workload tolerance (1e-8, absolute) two correct runs of Algorithm 1
+    that round differently agree only to the level of their remaining error,
+    so there the check is the iteration count and the distance to the exact
+    (serial fine) solution.  Below about 1e-10 the residual of this
+    non-normal operator no longer decreases monotonically and iteration
+    counts are set by rounding, so at tol 1e-12 the check is the solution:
+    within 1e-10 of the serial fine trajectory.
+    """
     p = wl.C2.with_(prec=wl.F64)
     say("c2 fp64 full solve")
     o = make_oracle(p)
     u0 = wl.u0_for(p)
+    serial = o.serial(u0)
     c = ctx(p)
     Xg, ig = c.solve(dev(u0), tol=p.tol)
     Xg = host(Xg)
     Xo, io = o.pitsbicg(u0, tol=p.tol)
-    print(f"gpu iters={ig.iters} ms={ig.ms_total:.1f}  oracle iters={io.iters}", flush=True)
+    print(f"tol {p.tol}: gpu iters={ig.iters} ms={ig.ms_total:.1f}  oracle iters={io.iters} "
+          f"gpu-vs-oracle {relerr(Xg, Xo):.2e} gpu-vs-serial {relerr(Xg, serial):.2e} "
+          f"oracle-vs-serial {relerr(Xo, serial):.2e}", flush=True)
     assert ig.status == io.status == orc.OK
     assert abs(ig.iters - io.iters) <= 1
-    assert relerr(Xg, Xo) < 1e-10
+    assert ig.res_norm <= p.tol and io.res_norm <= p.tol
+    assert relerr(Xg, serial) < 1e-7 and relerr(Xg, Xo) < 1e-7
+    Xg, ig = c.solve(dev(u0), tol=1e-12)
+    Xg = host(Xg)
+    print(f"tol 1e-12: gpu iters={ig.iters} gpu-vs-serial {relerr(Xg, serial):.2e}", flush=True)
+    assert ig.status == orc.OK
+    assert relerr(Xg, serial) < 1e-10
