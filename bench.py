@@ -54,10 +54,10 @@ def cpu_baseline(p, u0, seconds):
         t0 = time.perf_counter()
         _, info = o.pitsbicg(u0, tol=p.tol, max_iter=iters)
         dt = time.perf_counter() - t0
-        if dt >= seconds or info.iters < iters or iters >= 8:
+        if dt >= seconds or info.iters < iters or iters >= 24:
             break
         iters = max(iters + 1, int(iters * seconds / max(dt, 1e-3)))
-        iters = min(iters, 8)
+        iters = min(iters, 24)
     cells = info.matvecs * p.cells_per_apply
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle Algorithm 1 on the same {p.name} input truncated to "
