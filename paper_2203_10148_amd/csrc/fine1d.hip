@@ -64,8 +64,7 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
                                                    double *__restrict__ y, int N, int M, long ld, int m,
                                                    int raw, int n0)
 {
-    constexpr int W = NT / kWave;
-    __shared__ double lds[4 * W];
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
     const int n = n0 + blockIdx.x;
     const int t = threadIdx.x;
     if (!raw && n == 0) {  // y_0 = lam_0
@@ -99,6 +98,43 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
     store_chunk<NT, C, TR>(y + (size_t)n * ld, t, M, u);
 }
 
+// Fine apply with an FP32 propagator: the slice state is FP32 and every step
+// is taken in increment form (LineSolver::step_delta), so rounding the step
+// matrix to FP32 perturbs only the increment, not the state; lam and y are FP64
+// and the subtraction y_n = lam_n - F(lam_{n-1}) is done in FP64.
+template <int NT, int C, bool TR>
+__global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const double *__restrict__ lam,
+                                                   double *__restrict__ y, int N, int M, long ld, int m,
+                                                   float pl, float pu, float pr, int periodic, int raw, int n0)
+{
+    __shared__ float lds[LineSolver<float, NT, C>::kLds];
+    const int n = n0 + blockIdx.x;
+    const int t = threadIdx.x;
+    if (!raw && n == 0) {  // y_0 = lam_0
+        for (long j = t; j < ld; j += NT) y[j] = lam[j];
+        return;
+    }
+    LineSolver<float, NT, C> S;
+    S.load(tb, lds);
+    double ud[C];
+    load_chunk<NT, C, TR>(lam + (size_t)(raw ? n : n - 1) * ld, t, M, ud);
+    zero_pads<C>(t, M, ud);
+    float u[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) u[k] = (float)ud[k];
+    for (int s = 0; s < m; ++s) S.step_delta(u, pl, pu, pr, M, periodic);
+#pragma unroll
+    for (int k = 0; k < C; ++k) ud[k] = (double)u[k];
+    if (!raw) {
+        double own[C];
+        load_chunk<NT, C, TR>(lam + (size_t)n * ld, t, M, own);
+#pragma unroll
+        for (int k = 0; k < C; ++k) ud[k] = own[k] - ud[k];
+        zero_pads<C>(t, M, ud);
+    }
+    store_chunk<NT, C, TR>(y + (size_t)n * ld, t, M, ud);
+}
+
 // One coarse slice step of the sweep: u <- G(u) + v_n (pads stay 0).
 template <int NT, int C, int SCHEME>
 __device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double (&u)[C], const double (&vn)[C],
@@ -129,8 +165,7 @@ template <int NT, int C, int SCHEME, bool TR>
 __global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const double *v, double *z,
                                                     int N, int M, long ld, int c)
 {
-    constexpr int W = NT / kWave;
-    __shared__ double lds[4 * W];
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
@@ -175,6 +210,28 @@ hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const doub
             else LAUNCH(nt, c, SCHEME_CN, false);                      \
         }                                                              \
         return hipGetLastError();                                      \
+    }
+    PIT_LINE_SHAPES(X)
+#undef X
+#undef LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const double *lam, double *y, int N,
+                             int M, int m, float pl, float pu, float pr, int periodic, int raw, int last_only,
+                             bool chunked, hipStream_t st)
+{
+    const int n0 = last_only ? N - 1 : 0;
+    const int grid = last_only ? 1 : N;
+    if (last_only) raw = 1;
+#define LAUNCH(nt, c, TR)                                                                         \
+    hipLaunchKernelGGL((k_fine1d_f32<nt, c, TR>), dim3(grid), dim3(nt), 0, st, tb, lam, y, N, M,   \
+                       (long)(TR ? nt * c : M), m, pl, pu, pr, periodic, raw, n0)
+#define X(nt, c)                                  \
+    if (sh.NT == nt && sh.C == c) {               \
+        if (chunked) LAUNCH(nt, c, true);         \
+        else LAUNCH(nt, c, false);                \
+        return hipGetLastError();                 \
     }
     PIT_LINE_SHAPES(X)
 #undef X

@@ -82,14 +82,16 @@ template <typename T, int NT, int C>
 struct LineSolver {
     static constexpr int W = NT / kWave;
     static_assert(NT % kWave == 0 && W <= kMaxWaves, "bad line shape");
+    // LDS slots (units of T)
+    static constexpr int kAggF = 0, kAggB = W, kPwf = 2 * W, kPwb = 3 * W, kRfw = 4 * W, kUFirst = 5 * W,
+                         kULast = 6 * W, kUWrap = 7 * W;
+    static constexpr int kLds = 7 * W + 2;
 
     T lm[C], iu[C], cm[C], z[C];
     T wf[kScanConsts], wb[kScanConsts];
-    T qf, qb;
+    T qf, qb, rf;
     T inv_den, bg, iu_last;
     int cyclic;
-    // LDS: [0,W) forward aggregates, [W,2W) backward aggregates,
-    //      [2W,3W) pwf, [3W,4W) pwb
     T *sh;
 
     __device__ __forceinline__ void load(const LineTab<T> &tb, T *lds)
@@ -109,66 +111,60 @@ struct LineSolver {
         }
         qf = tb.qf[t];
         qb = tb.qb[t];
+        rf = tb.rf[t];
         inv_den = tb.inv_den;
         bg = tb.bg;
         iu_last = tb.iu_last;
         cyclic = tb.cyclic;
         sh = lds;
         if (t < W) {
-            sh[2 * W + t] = tb.pwf[t];
-            sh[3 * W + t] = tb.pwb[t];
+            sh[kPwf + t] = tb.pwf[t];
+            sh[kPwb + t] = tb.pwb[t];
+            sh[kRfw + t] = tb.rfw[t];
         }
         __syncthreads();
     }
 
-    // Solve A x = d; d is overwritten by x.
-    __device__ __forceinline__ void solve(T (&d)[C])
+    // ---- forward elimination y_j = d_j + lm_j y_{j-1}: local pass + in-wave scan ----
+    __device__ __forceinline__ T fwd_scan(const T (&d)[C]) const
     {
-        const int t = threadIdx.x;
-        const int lane = t & (kWave - 1);
-        const int w = t / kWave;
-
-        // ---- forward elimination: y_j = d_j + lm_j y_{j-1} ----
         T e = T(0);
 #pragma unroll
         for (int k = 0; k < C; ++k) e = fma(lm[k], e, d[k]);
-        T v = scan_up(e, wf);
-        T cw = T(0), ytot;
-        if constexpr (W > 1) {
-            if (lane == kWave - 1) sh[w] = v;
-            __syncthreads();
-            T acc = T(0);
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                if (q == w) cw = acc;
-                acc = fma(sh[2 * W + q], acc, sh[q]);
-            }
-            ytot = acc;
-        } else {
-            ytot = readlane(v, kWave - 1);
-        }
-        const T prev = dpp<0x138>(v);  // wave_shr:1, lane 0 reads 0
-        T y = fma(qf, cw, prev);
+        return scan_up(e, wf);
+    }
+
+    // second local pass from the carry c = y_{tC-1}; d is overwritten by y
+    __device__ __forceinline__ void fwd_pass2(T (&d)[C], T c) const
+    {
+        T y = c;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             y = fma(lm[k], y, d[k]);
             d[k] = y;
         }
+    }
 
-        // ---- back substitution: x_j = iu_j y_j + cm_j x_{j+1} ----
+    // ---- back substitution x_j = iu_j y_j + cm_j x_{j+1}, then the periodic
+    // correction; ytot is the forward value at point M-1 ----
+    __device__ __forceinline__ void backward(T (&d)[C], T ytot)
+    {
+        const int t = threadIdx.x;
+        const int lane = t & (kWave - 1);
+        const int w = t / kWave;
         T b = T(0);
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) b = fma(cm[k], b, iu[k] * d[k]);
-        v = scan_down(b, wb);
+        T v = scan_down(b, wb);
         T cb = T(0), xtot;
         if constexpr (W > 1) {
-            if (lane == 0) sh[W + w] = v;
+            if (lane == 0) sh[kAggB + w] = v;
             __syncthreads();
             T acc = T(0);
 #pragma unroll
             for (int q = W - 1; q >= 0; --q) {
                 if (q == w) cb = acc;
-                acc = fma(sh[3 * W + q], acc, sh[W + q]);
+                acc = fma(sh[kPwb + q], acc, sh[kAggB + q]);
             }
             xtot = acc;
         } else {
@@ -181,14 +177,122 @@ struct LineSolver {
             x = fma(cm[k], x, iu[k] * d[k]);
             d[k] = x;
         }
-
-        // ---- Sherman-Morrison correction for the periodic case ----
-        if (cyclic) {
+        if (cyclic) {  // Sherman-Morrison correction
             const T xlast = iu_last * ytot;  // cm_{M-1} = 0
             const T phi = (xtot + bg * xlast) * inv_den;
 #pragma unroll
             for (int k = 0; k < C; ++k) d[k] = fma(-phi, z[k], d[k]);
         }
+    }
+
+    // Solve A x = d; d is overwritten by x.
+    __device__ __forceinline__ void solve(T (&d)[C])
+    {
+        const int t = threadIdx.x;
+        const int lane = t & (kWave - 1);
+        const int w = t / kWave;
+        const T v = fwd_scan(d);
+        T cw = T(0), ytot;
+        if constexpr (W > 1) {
+            if (lane == kWave - 1) sh[kAggF + w] = v;
+            __syncthreads();
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if (q == w) cw = acc;
+                acc = fma(sh[kPwf + q], acc, sh[kAggF + q]);
+            }
+            ytot = acc;
+        } else {
+            ytot = readlane(v, kWave - 1);
+        }
+        const T prev = dpp<0x138>(v);  // wave_shr:1, lane 0 reads 0
+        fwd_pass2(d, fma(qf, cw, prev));
+        backward(d, ytot);
+    }
+
+    // One step in increment form:  u <- u + A^{-1} r,  with
+    //   r_j = pl (u_{j-1} - u_j) + pu (u_{j+1} - u_j) - pr u_j    (= dt L u, written
+    // with differences so that a constant field gives exactly 0).  Neighbour
+    // values inside a wavefront come from DPP; the two neighbours across wave
+    // edges and the periodic wrap (point 0 <-> point M-1) are exchanged in the
+    // forward scan's LDS round and enter as late right-hand-side terms: their
+    // effect on the carries is linear (multipliers rf_t and rfw_w), so no extra
+    // barrier is needed and every copy of a neighbour value is exact.
+    __device__ __forceinline__ void step_delta(T (&u)[C], T pl, T pu, T pr, int M, int periodic)
+    {
+        const int t = threadIdx.x;
+        const int lane = t & (kWave - 1);
+        const int w = t / kWave;
+        const int j0 = t * C;
+        const T uprev = dpp<0x138>(u[C - 1]);  // lane-1's last point (lane 0 reads 0)
+        const T unext = dpp<0x130>(u[0]);      // lane+1's first point (lane 63 reads 0)
+        T d[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const T left = (k == 0) ? uprev : u[k - 1];
+            const T right = (k == C - 1) ? unext : u[k + 1];
+            const T r = fma(pl, left - u[k], fma(pu, right - u[k], -pr * u[k]));
+            d[k] = (j0 + k < M) ? r : T(0);
+        }
+        // value of point M-1 (owner only)
+        T uwrap = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            if (j0 + k == M - 1) uwrap = u[k];
+        const int owner_last = (M - 1) / C;   // thread holding point M-1
+        const int wstar = owner_last / kWave; // its wave
+        const T v = fwd_scan(d);
+        T cw = T(0), ytot, dL = T(0), dR = T(0), dM = T(0);
+        if constexpr (W > 1) {
+            if (lane == kWave - 1) {
+                sh[kAggF + w] = v;
+                sh[kULast + w] = u[C - 1];
+            }
+            if (lane == 0) sh[kUFirst + w] = u[0];
+            if (t == owner_last) sh[kUWrap] = uwrap;
+            __syncthreads();
+            const T u0 = sh[kUFirst];
+            const T uM = sh[kUWrap];
+            if (periodic) dM = pu * u0;
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
+                T l = T(0), r = T(0);
+                if (Pq < M) l = pl * ((q > 0) ? sh[kULast + q - 1] : (periodic ? uM : T(0)));
+                if (Qq < M - 1) r = pu * sh[kUFirst + q + 1];
+                if (q == w) {
+                    cw = acc;
+                    dL = l;
+                    dR = r;
+                }
+                T agg = sh[kAggF + q] + fma(sh[kRfw + q], l, r);
+                if (q == wstar) agg += dM;
+                acc = fma(sh[kPwf + q], acc, agg);
+            }
+            ytot = acc;
+        } else {
+            const T u0 = readlane(u[0], 0);
+            const T uM = readlane(uwrap, owner_last);
+            if (periodic) {
+                dM = pu * u0;
+                dL = pl * uM;
+            }
+            ytot = readlane(v, kWave - 1) + fma(sh[kRfw], dL, dM);
+        }
+        const T prev = dpp<0x138>(v);
+        const T c = (lane == 0) ? cw : fma(rf, dL, fma(qf, cw, prev));
+        // complete the right-hand side with the late terms
+        if (lane == 0 && j0 < M) d[0] += dL;
+        if (lane == kWave - 1 && j0 + C - 1 < M - 1) d[C - 1] += dR;
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            if (j0 + k == M - 1) d[k] += dM;
+        fwd_pass2(d, c);
+        backward(d, ytot);
+#pragma unroll
+        for (int k = 0; k < C; ++k) u[k] += d[k];
     }
 };
 

@@ -37,16 +37,19 @@ constexpr int kMaxLine = 16384;
 //   (lane indices inside the wave), and across waves
 //     qf_t = prod_{q=wavestart..t-1} pf_q,  qb_t = prod_{q=t+1..waveend} pb_q
 //     pwf_w, pwb_w = products of pf / pb over wave w.
+//   late right-hand-side terms at the first point P_w of wave w (increment form):
+//     rf_t  = prod_{i=P_w+1..tC-1} lm_i  (0 for lane 0),
+//     rfw_w = prod_{i=P_w+1..Q_w} lm_i   (Q_w = last point of wave w).
 // Padding points j >= M carry lm = 1, iu = 0, cm = 0, z = 0 so that the
 // forward total equals y_{M-1} and the pads solve to 0.
 //
 // Device layout (element type T, one contiguous blob):
 //   lm[C][NT] iu[C][NT] cm[C][NT] z[C][NT] wf[7][NT] wb[7][NT] qf[NT] qb[NT]
-//   pwf[16] pwb[16]
+//   pwf[16] pwb[16] rfw[16] rf[NT]
 // ---------------------------------------------------------------------------
 template <typename T>
 struct LineTab {
-    const T *lm, *iu, *cm, *z, *wf, *wb, *qf, *qb, *pwf, *pwb;
+    const T *lm, *iu, *cm, *z, *wf, *wb, *qf, *qb, *pwf, *pwb, *rfw, *rf;
     T inv_den;  // 1 / (1 + v.z)
     T bg;       // beta_corner / gamma
     T iu_last;  // iu_{M-1}
@@ -54,7 +57,7 @@ struct LineTab {
     int M;
 };
 
-inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kScanConsts + 2) * NT + 2 * kMaxWaves; }
+inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kScanConsts + 3) * NT + 3 * kMaxWaves; }
 
 template <typename T>
 inline LineTab<T> line_tab_view(const T *base, int NT, int C)
@@ -71,7 +74,9 @@ inline LineTab<T> line_tab_view(const T *base, int NT, int C)
     tb.qf = base + o; o += NT;
     tb.qb = base + o; o += NT;
     tb.pwf = base + o; o += kMaxWaves;
-    tb.pwb = base + o;
+    tb.pwb = base + o; o += kMaxWaves;
+    tb.rfw = base + o; o += kMaxWaves;
+    tb.rf = base + o;
     return tb;
 }
 
@@ -93,6 +98,12 @@ enum { SCHEME_IE = 0, SCHEME_CN = 1, SCHEME_ADI = 2 };
 hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const double *lam, double *y,
                              int N, int M, int m, int scheme, int raw, int last_only, bool chunked,
                              hipStream_t st);
+
+// Fine apply, 1D, FP32 state and arithmetic in increment form (see line1d.hpp);
+// lam and y stay FP64.  pl, pu, pr: dt L u = pl (u_{j-1}-u_j) + pu (u_{j+1}-u_j) - pr u_j.
+hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const double *lam, double *y, int N,
+                             int M, int m, float pl, float pu, float pr, int periodic, int raw, int last_only,
+                             bool chunked, hipStream_t st);
 
 // Coarse sweep, 1D, FP64: z_0 = v_0, z_n = v_n + G(z_{n-1}).
 hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const double *v, double *z,

@@ -81,6 +81,7 @@ struct LineHost {
     int cyclic = 0;
     double inv_den = 0.0, bg = 0.0, iu_last = 0.0;
     std::vector<double> blob;  // layout of line_tab_view
+    std::vector<float> blob32; // the same tables rounded to FP32
 };
 
 // Build the tables of the line solver for the tridiagonal matrix with
@@ -178,9 +179,24 @@ bool build_line(int M, bool periodic, double a, double b, double c, LineShape sh
         }
         W_(v.pwf)[w] = f;
         W_(v.pwb)[w] = g;
+        // late terms at the first point of the wave: products of lm after it
+        const int Pw = w * kWave * C, Qw = Pw + kWave * C - 1;
+        double r = 1.0;
+        for (int i = Pw + 1; i <= Qw; ++i) r *= lm[i];
+        W_(v.rfw)[w] = r;
+        for (int lane = 0; lane < kWave; ++lane) {
+            const int t = w * kWave + lane;
+            double rt = 0.0;
+            if (lane > 0) {
+                rt = 1.0;
+                for (int i = Pw + 1; i <= t * C - 1; ++i) rt *= lm[i];
+            }
+            W_(v.rf)[t] = rt;
+        }
     }
     for (double x : L.blob)
         if (!std::isfinite(x)) return false;
+    L.blob32.assign(L.blob.begin(), L.blob.end());
     return std::isfinite(L.inv_den) && std::isfinite(L.bg) && std::isfinite(L.iu_last);
 }
 
@@ -199,7 +215,9 @@ struct pit_ctx {
     LineHost lf;  // fine step matrix
     LineHost lc;  // coarse step matrix
     // workspace layout (byte offsets)
-    size_t off_tf = 0, off_tc = 0, off_vec = 0, off_part = 0, off_red = 0, total = 0;
+    size_t off_tf = 0, off_tf32 = 0, off_tc = 0, off_vec = 0, off_part = 0, off_red = 0, total = 0;
+    // increment-form stencil (FP32 fine propagator): dt L u = pl(u_{j-1}-u_j) + pu(u_{j+1}-u_j) - pr u_j
+    float pl = 0.f, pu = 0.f, pr = 0.f;
     int bps = 1;
     // bound workspace
     char *ws = nullptr;
@@ -211,6 +229,17 @@ struct pit_ctx {
     double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * ntc(); }
     double *part() const { return reinterpret_cast<double *>(ws + off_part); }
     RedOut *red() const { return reinterpret_cast<RedOut *>(ws + off_red); }
+    LineTab<float> tab32(const LineHost &L, size_t off) const
+    {
+        LineTab<float> t = line_tab_view<float>(reinterpret_cast<const float *>(ws + off), L.sh.NT, L.sh.C);
+        t.inv_den = (float)L.inv_den;
+        t.bg = (float)L.bg;
+        t.iu_last = (float)L.iu_last;
+        t.cyclic = L.cyclic;
+        t.M = L.M;
+        return t;
+    }
+    bool fine32() const { return fine.prec == PIT_F32; }
     LineTab<double> tab(const LineHost &L, size_t off) const
     {
         LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(ws + off), L.sh.NT, L.sh.C);
@@ -255,9 +284,24 @@ int validate(const pit_problem *p, int N, int m, const pit_stepper &f, const pit
     if (g.scheme != PIT_IE && g.scheme != PIT_CN) return PIT_EINVAL;
     if (f.substeps != 0 && f.substeps != m) return PIT_EINVAL;
     if (g.substeps < 1) return PIT_EINVAL;
-    if (f.prec != PIT_F64 || g.prec != PIT_F64) return PIT_EINVAL;  // FP32 fine arrives later
+    if ((f.prec != PIT_F64 && f.prec != PIT_F32) || g.prec != PIT_F64) return PIT_EINVAL;
     if (f.reserved != 0 || g.reserved != 0) return PIT_EINVAL;
     return PIT_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The fine apply in the precision the context was created with.
+hipError_t fine_launch(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool chunked,
+                       hipStream_t st)
+{
+    if (c->fine32())
+        return launch_fine1d_f32(c->lf.sh, c->tab32(c->lf, c->off_tf32), lam, y, c->N, c->npts, c->m, c->pl,
+                                 c->pu, c->pr, c->pb.bc == PIT_PERIODIC ? 1 : 0, raw, last, chunked, st);
+    return launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), lam, y, c->N, c->npts, c->m, c->fine.scheme,
+                             raw, last, chunked, st);
 }
 
 }  // namespace
@@ -309,11 +353,21 @@ int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         delete c;
         return PIT_EINVAL;
     }
+    {
+        double lo, di, up;
+        stencil1d(*problem, c->hx, &lo, &di, &up);
+        const double dt = c->DT / m;
+        c->pl = (float)(dt * lo);
+        c->pu = (float)(dt * up);
+        c->pr = (float)(dt * problem->react);
+    }
     c->ld = (long)sh.NT * sh.C;
     c->bps = (int)std::min<long>(64, std::max<long>(1, (c->ld + 2047) / 2048));
     size_t o = 0;
     c->off_tf = o;
     o = align_up(o + c->lf.blob.size() * sizeof(double));
+    c->off_tf32 = o;
+    o = align_up(o + (c->fine32() ? c->lf.blob32.size() * sizeof(float) : 0));
     c->off_tc = o;
     o = align_up(o + c->lc.blob.size() * sizeof(double));
     c->off_vec = o;
@@ -355,6 +409,9 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
                       hipMemcpyHostToDevice));
     PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tc, ctx->lc.blob.data(), ctx->lc.blob.size() * sizeof(double),
                       hipMemcpyHostToDevice));
+    if (ctx->fine32())
+        PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf32, ctx->lf.blob32.data(), ctx->lf.blob32.size() * sizeof(float),
+                          hipMemcpyHostToDevice));
     return PIT_OK;
 }
 
@@ -363,9 +420,7 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
     if (!ctx || !ctx->ws || !lam || !y || (flags & ~(PIT_APPLY_RAW | PIT_APPLY_LAST))) return PIT_EINVAL;
     if (lam == y) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PIT_HIP(launch_fine1d_f64(ctx->lf.sh, ctx->tab(ctx->lf, ctx->off_tf), lam, y, ctx->N, ctx->npts, ctx->m,
-                              ctx->fine.scheme, (flags & PIT_APPLY_RAW) ? 1 : 0,
-                              (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
+    PIT_HIP(fine_launch(ctx, lam, y, (flags & PIT_APPLY_RAW) ? 1 : 0, (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
     return PIT_OK;
 }
 
@@ -420,8 +475,7 @@ struct Solver {
     {
         int rc;
         if (timing && (rc = begin(ev_fine))) return rc;
-        PIT_HIP(launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), in, out, c->N, c->npts, c->m,
-                                  c->fine.scheme, 0, 0, true, st));
+        PIT_HIP(fine_launch(c, in, out, 0, 0, true, st));
         if (timing) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
         ++n_fine;
         return PIT_OK;

@@ -299,3 +299,78 @@ def test_c2_full_size_fp64_solve():
     print(f"tol 1e-12: gpu iters={ig.iters} gpu-vs-serial {relerr(Xg, serial):.2e}", flush=True)
     assert ig.status == orc.OK
     assert relerr(Xg, serial) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# FP32 fine propagator (increment form); coarse sweep and Krylov stay FP64
+# ---------------------------------------------------------------------------
+
+F32_CASES = [
+    # (M, bc, fine, shape)  -- shapes cover one wave, several waves and padding
+    (64, wl.DIRICHLET, wl.IE, (64, 1)),
+    (500, wl.PERIODIC, wl.CN, (64, 8)),
+    (1000, wl.PERIODIC, wl.CN, (128, 8)),
+    (4096, wl.PERIODIC, wl.CN, (256, 16)),
+    (4000, wl.DIRICHLET, wl.CN, (512, 8)),
+    (3000, wl.PERIODIC, wl.IE, (1024, 4)),
+    (16384, wl.PERIODIC, wl.CN, (1024, 16)),
+]
+
+
+@pytest.mark.parametrize("case", F32_CASES, ids=lambda c: f"M{c[0]}_bc{c[1]}_f{c[2]}_NT{c[3][0]}_C{c[3][1]}")
+def test_fp32_apply_matches_oracle(case, monkeypatch):
+    M, bc, fine, (NT, C) = case
+    monkeypatch.setenv("PIT_LINE_SHAPE", f"{NT},{C}")
+    p = wl.Problem(dim=1, M=(M, 1), bc=bc, nu=2e-3, adv=(0.7, 0.0), react=0.05, T=0.5, N=4, m=50,
+                   fine=fine, c=2, coarse=wl.IE, prec=wl.F32)
+    say(f"fp32 apply {case}")
+    o = make_oracle(p)
+    c = ctx(p)
+    assert c.kernel_shape()[:2] == (NT, C)
+    # A smooth block (the regime of the method) must meet 1e-5.  For a rough
+    # block the FP32 rounding of a right-hand side of size ~s*|u| (s = nu dt/h^2,
+    # the diffusion number) reaches the smooth modes, which A^{-1} does not
+    # damp, so the attainable accuracy scales with s: bound 1e-5 * max(1, s/64).
+    x = wl.grid_1d(p)
+    h = x[1] - x[0]
+    s_diff = p.nu * (p.T / p.N / p.m) / h ** 2
+    smooth = np.concatenate([np.sin(2 * np.pi * (n + 1) * x) + 0.3 * np.cos(6 * np.pi * x) for n in range(p.N)])
+    for lam, bound in ((smooth, 1e-5), (wl.random_block(p, 31), 1e-5 * max(1.0, s_diff / 64))):
+        y = host(c.apply_F(dev(lam)))
+        e1 = relerr(y, o.apply(lam))
+        yr = host(c.apply_F(dev(lam), raw=True))
+        e2 = relerr(yr, o.apply_raw(lam))
+        print(f"s={s_diff:.3g} bound={bound:.2e} apply {e1:.2e} raw {e2:.2e}", flush=True)
+        assert e1 < bound and e2 < bound
+
+
+def test_fp32_c2_full_size_solve():
+    """The 4096 x 256 advection-diffusion workload with an FP32 fine
+    propagator: within 1e-5 (relative, all slices) of the FP64 serial fine
+    trajectory, with FP64 dots, scalars and coarse sweep."""
+    p = wl.C2.with_(prec=wl.F32)
+    say("c2 fp32 full solve")
+    o = make_oracle(p)
+    u0 = wl.u0_for(p)
+    serial = o.serial(u0)
+    c = ctx(p)
+    Xg, ig = c.solve(dev(u0), tol=p.tol, stall_window=10)
+    Xg = host(Xg)
+    err = relerr(Xg, serial)
+    print(f"fp32: status={ig.status} iters={ig.iters} ms={ig.ms_total:.1f} rel.err vs fp64 serial={err:.2e}",
+          flush=True)
+    assert ig.status in (orc.OK, orc.ENOCONV)
+    assert err < 1e-5
+
+
+def test_fp32_small_solve_and_final_state():
+    p = wl.C1.with_(prec=wl.F32)
+    say("c1 fp32 solve")
+    o = make_oracle(p)
+    u0 = wl.u0_for(p)
+    serial, uT = o.serial(u0, want_uT=True)
+    c = ctx(p)
+    Xg, ig = c.solve(dev(u0), tol=1e-8, stall_window=10)
+    assert relerr(host(Xg), serial) < 1e-5
+    yl = host(c.apply_F(Xg, last=True)).reshape(p.N, -1)
+    assert relerr(yl[-1], uT) < 1e-5
