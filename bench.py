@@ -38,7 +38,9 @@ def log(msg):
 def workload(name, prec):
     from paper_2203_10148_amd import workloads as wl
 
-    p = {"c1": wl.C1, "c2": wl.C2}[name]
+    p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3}[name]
+    if prec is None:
+        return p
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
 
 
@@ -70,8 +72,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
-    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--prec", default=None, choices=["f64", "f32"],
+                    help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -89,6 +92,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     p = workload(args.workload, args.prec)
+    args.prec = "f32" if p.prec == wl.F32 else "f64"
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
     ctx = P.Context(p, device=dev)
@@ -127,23 +131,43 @@ def main():
     n_coarse = sum(i.n_coarse for i in infos)
     avg_fine = ms_fine / max(n_apply, 1)
     avg_coarse = ms_coarse / max(n_coarse, 1)
-    scheme = "cn" if p.fine == wl.CN else "ie"
     periodic = 1 if p.bc == wl.PERIODIC else 0
-    fl_fine = p.cells_per_apply * FLOPS_PER_CU[(scheme, periodic)]
-    cscheme = "cn" if p.coarse == wl.CN else "ie"
-    fl_coarse = (p.N - 1) * p.c * p.npts * FLOPS_PER_CU[(cscheme, periodic)] + (p.N - 1) * p.npts
-    peak = PEAK["fp64_vec_TFs"] if args.prec == "f64" else PEAK["fp32_vec_TFs"]
-    kern = {
-        "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply,
-                       "flops_per_launch": fl_fine, "peak": peak},
-        "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse,
-                         "flops_per_launch": fl_coarse, "peak": PEAK["fp64_vec_TFs"]},
-    }
+    if p.dim == 1:
+        scheme = "cn" if p.fine == wl.CN else "ie"
+        cscheme = "cn" if p.coarse == wl.CN else "ie"
+        fl_fine = p.cells_per_apply * FLOPS_PER_CU[(scheme, periodic)]
+        fl_coarse = (p.N - 1) * p.c * p.npts * FLOPS_PER_CU[(cscheme, periodic)] + (p.N - 1) * p.npts
+        peak = PEAK["fp64_vec_TFs"] if args.prec == "f64" else PEAK["fp32_vec_TFs"]
+        kern = {
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "alu",
+                           "work_per_launch": fl_fine, "unit": "TFLOP/s", "peak": peak},
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
+                             "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
+        }
+    else:
+        # 2D: the fine apply streams the field through HBM twice per PR-ADI step
+        # (x half step: read + write, y half step: read + write).
+        scheme, cscheme = "adi", "adi"
+        es = 4 if args.prec == "f32" else 8
+        by_fine = p.cells_per_apply * 4 * es
+        # coarse sweep per slice and step: x half (read 8 + write 8), y half (read 8 + base 8 + write 8)
+        by_coarse = (p.N - 1) * p.c * p.npts * 40
+        kern = {
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "hbm",
+                           "work_per_launch": by_fine, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "hbm",
+                             "work_per_launch": by_coarse, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
+        }
+    scale = {"TFLOP/s": 1e12, "GB/s": 1e9}
+
+    def rate(v):
+        return v["work_per_launch"] / (v["avg_ms"] * 1e-3) / scale[v["unit"]] if v["avg_ms"] > 0 else 0.0
+
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     k = kern[dom]
-    achieved = k["flops_per_launch"] / (k["avg_ms"] * 1e-3) / 1e12 if k["avg_ms"] > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": k["peak"],
-                "unit": "TFLOP/s", "frac": achieved / k["peak"], "traffic": None}
+    achieved = rate(k)
+    roofline = {"bound": k["bound"], "kernel": dom, "achieved": achieved, "peak": k["peak"], "unit": k["unit"],
+                "frac": achieved / k["peak"], "traffic": None}
     fine_cu_s = p.cells_per_apply / (avg_fine * 1e-3) if avg_fine > 0 else 0.0
     out = {
         "metric": "fine cell-updates/s and % HBM peak; PiT time-to-1e-8 vs plain FP64, 1 GPU",
@@ -157,8 +181,7 @@ def main():
         "solve": {"status": sorted(status), "iters": iters, "matvecs": matvecs,
                   "time_to_tol_ms": float(np.median([i.ms_total for i in infos])),
                   "restarts": infos[-1].restarts, "res_norm": infos[-1].res_norm},
-        "kernels": {name: {**v, "achieved_TFs": v["flops_per_launch"] / (v["avg_ms"] * 1e-3) / 1e12
-                           if v["avg_ms"] > 0 else 0.0} for name, v in kern.items()},
+        "kernels": {name: {**v, "achieved": rate(v)} for name, v in kern.items()},
         "fine_kernel_cell_updates_per_s": fine_cu_s,
         "fine_kernel_stream_equiv_hbm_frac": fine_cu_s * (16 if args.prec == "f64" else 8) / (PEAK["hbm_GBs"] * 1e9),
         "kernel_shape": ctx.kernel_shape(),

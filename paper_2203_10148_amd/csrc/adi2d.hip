@@ -1,0 +1,268 @@
+// 2D Peaceman-Rachford ADI half steps (Dirichlet-0, constant coefficients).
+//
+// One PR-ADI step with theta = dt/2 (Lx, Ly: nu*D2 - r/2 along each axis):
+//   x half step:  (I - theta Lx) u* = (I + theta Ly) u     solved along rows
+//   y half step:  (I - theta Ly) u' = (I + theta Lx) u*    solved along columns
+// Every slice of a block vector is independent, so each launch covers all the
+// slices it is given.  The fields between half steps are stored in S (float
+// for the FP32 fine propagator, double otherwise); the arithmetic is FP64.
+//
+// x half step: one wavefront per strip of R rows, lane l owns the x-points
+// l*C .. l*C+C-1 of the row, the row solve is the register-resident in-wave
+// line solver (no LDS, no barrier).  The y stencil uses a rolling window of
+// three rows held in rotating registers (no copies, so the row loaded ahead
+// stays in flight while the current row is solved).
+//
+// y half step: a workgroup owns 64 columns of one slice; wave w holds rows
+// w*CY .. w*CY+CY-1 of them, one column per lane.  Each lane's tridiagonal
+// recurrence along y runs locally with one LDS exchange of the per-lane
+// carries per direction (two barriers per half step); the row constants are
+// the same for every column and are read from LDS.
+#include "line1d.hpp"
+
+namespace pit {
+
+template <typename S>
+__device__ __forceinline__ double to_d(S v)
+{
+    return (double)v;
+}
+
+// ---------------------------------------------------------------------------
+// x half step
+// ---------------------------------------------------------------------------
+template <int C, typename SIN>
+__device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, int My, int Mx, int lane,
+                                         SIN (&r)[C])
+{
+    const SIN *row = slice + (size_t)min(max(j, 0), My - 1) * Mx;
+#pragma unroll
+    for (int k = 0; k < C; ++k) r[k] = row[min(lane * C + k, Mx - 1)];
+}
+
+template <int C, typename SIN, typename SOUT>
+__device__ __forceinline__ void x_row(LineSolver<double, kWave, C> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
+                                      const SIN (&nx)[C], int j, int My, int Mx, int lane, double ex, double ed,
+                                      SOUT *__restrict__ oslice)
+{
+    const double fp = (j > 0) ? 1.0 : 0.0, fn = (j + 1 < My) ? 1.0 : 0.0;
+    double d[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const double v = fma(ed, to_d(cu[k]), ex * fma(fp, to_d(pv[k]), fn * to_d(nx[k])));
+        d[k] = (lane * C + k < Mx) ? v : 0.0;
+    }
+    LS.solve(d);
+    SOUT *row = oslice + (size_t)j * Mx;
+    if (lane * C + C <= Mx) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) row[lane * C + k] = (SOUT)d[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            if (lane * C + k < Mx) row[lane * C + k] = (SOUT)d[k];
+    }
+}
+
+// grid: ceil(nslices * strips / 4) blocks of 4 waves; wave g handles strip
+// g % strips of slice g / strips.  in/out slice s sits at in + (s + in_off)*npts.
+template <int C, typename SIN, typename SOUT>
+__global__ __launch_bounds__(256) void k_adi_x(LineTab<double> tb, const SIN *__restrict__ in, long in_off,
+                                               SOUT *__restrict__ out, long out_off, int nslices, int Mx,
+                                               int My, int R, double ex, double ed)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int strips = (My + R - 1) / R;
+    const int g = blockIdx.x * 4 + threadIdx.x / kWave;
+    if (g >= nslices * strips) return;  // whole wavefront exits; no barriers below
+    const int s = g / strips, j0 = (g % strips) * R, j1 = min(j0 + R, My);
+    const long npts = (long)Mx * My;
+    const SIN *islice = in + (size_t)(s + in_off) * npts;
+    SOUT *oslice = out + (size_t)(s + out_off) * npts;
+    LineSolver<double, kWave, C> LS;
+    LS.load(tb, nullptr);
+    SIN a[C], b[C], c[C];
+    load_row<C>(islice, j0 - 1, My, Mx, lane, a);
+    load_row<C>(islice, j0, My, Mx, lane, b);
+    load_row<C>(islice, j0 + 1, My, Mx, lane, c);
+    for (int j = j0; j < j1; j += 3) {
+        x_row<C>(LS, a, b, c, j, My, Mx, lane, ex, ed, oslice);
+        load_row<C>(islice, j + 2, My, Mx, lane, a);
+        if (j + 1 >= j1) break;
+        x_row<C>(LS, b, c, a, j + 1, My, Mx, lane, ex, ed, oslice);
+        load_row<C>(islice, j + 3, My, Mx, lane, b);
+        if (j + 2 >= j1) break;
+        x_row<C>(LS, c, a, b, j + 2, My, Mx, lane, ex, ed, oslice);
+        load_row<C>(islice, j + 4, My, Mx, lane, c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y half step
+// ---------------------------------------------------------------------------
+// grid: nslices * ceil(Mx/64) blocks of WY waves.  Epilogue EPI: 0 stores u',
+// 1 stores base + sign*u' (FP64) -- the all-at-once apply's lam_n - F(...) and
+// the coarse sweep's v_n + G(...).
+template <int WY, int CY, typename SIN, typename SOUT, int EPI>
+__global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restrict__ in, long in_off,
+                                                   SOUT *__restrict__ out, long out_off,
+                                                   const double *__restrict__ base, long base_off, double sign,
+                                                   int nslices, int Mx, int My, double ex, double ed)
+{
+    constexpr int NR = WY * CY;
+    __shared__ double s_lm[NR], s_iu[NR], s_cm[NR];
+    __shared__ double s_pf[WY], s_pb[WY];
+    __shared__ double s_agg[2][WY][kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const int bx = (Mx + kWave - 1) / kWave;
+    const int s = blockIdx.x / bx, col0 = (blockIdx.x % bx) * kWave;
+    for (int i = t; i < NR; i += WY * kWave) {
+        s_lm[i] = tb.lm[i];
+        s_iu[i] = tb.iu[i];
+        s_cm[i] = tb.cm[i];
+    }
+    if (t < WY) {
+        s_pf[t] = tb.pwf[t];
+        s_pb[t] = tb.pwb[t];
+    }
+    __syncthreads();
+    if (s >= nslices) return;  // uniform per block
+    const long npts = (long)Mx * My;
+    const int col = col0 + lane;
+    const int cc = min(col, Mx - 1);
+    const bool live = col < Mx;
+    const SIN *islice = in + (size_t)(s + in_off) * npts;
+    const double fl = (col > 0) ? 1.0 : 0.0, fr = (col + 1 < Mx) ? 1.0 : 0.0;
+    const int cl = max(col - 1, 0), cr = min(col + 1, Mx - 1);
+    const int r0 = w * CY;
+
+    // right-hand side (I + theta Lx) u* for this lane's column segment
+    double d[CY];
+#pragma unroll
+    for (int r = 0; r < CY; ++r) {
+        const int j = min(r0 + r, My - 1);
+        const SIN *row = islice + (size_t)j * Mx;
+        const double v = to_d(row[cc]), vl = to_d(row[cl]), vr = to_d(row[cr]);
+        const double x = fma(ed, v, ex * fma(fl, vl, fr * vr));
+        d[r] = (live && r0 + r < My) ? x : 0.0;
+    }
+    // forward elimination along y
+    double e = 0.0;
+#pragma unroll
+    for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, d[r]);
+    s_agg[0][w][lane] = e;
+    __syncthreads();
+    double cw = 0.0;
+    for (int q = 0; q < w; ++q) cw = fma(s_pf[q], cw, s_agg[0][q][lane]);
+    double y = cw;
+#pragma unroll
+    for (int r = 0; r < CY; ++r) {
+        y = fma(s_lm[r0 + r], y, d[r]);
+        d[r] = y;
+    }
+    // back substitution along y
+    double bsum = 0.0;
+#pragma unroll
+    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * d[r]);
+    s_agg[1][w][lane] = bsum;
+    __syncthreads();
+    double cb = 0.0;
+    for (int q = WY - 1; q > w; --q) cb = fma(s_pb[q], cb, s_agg[1][q][lane]);
+    double x = cb;
+#pragma unroll
+    for (int r = CY - 1; r >= 0; --r) {
+        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * d[r]);
+        d[r] = x;
+    }
+    if (!live) return;
+    SOUT *oslice = out + (size_t)(s + out_off) * npts;
+    const double *bslice = EPI ? base + (size_t)(s + base_off) * npts : nullptr;
+#pragma unroll
+    for (int r = 0; r < CY; ++r) {
+        const int j = r0 + r;
+        if (j < My) {
+            const size_t o = (size_t)j * Mx + col;
+            if constexpr (EPI)
+                oslice[o] = (SOUT)fma(sign, d[r], bslice[o]);
+            else
+                oslice[o] = (SOUT)d[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define PIT_ADI_XC(X) X(1) X(2) X(4) X(8) X(16)
+#define PIT_ADI_YSHAPES(X) X(8, 16) X(8, 32) X(8, 64) X(16, 64)
+
+template <typename SIN, typename SOUT>
+static hipError_t adi_x_t(int C, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,
+                          int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
+{
+    const int strips = (My + R - 1) / R;
+    const int blocks = (nslices * strips + 3) / 4;
+#define X(c)                                                                                            \
+    if (C == c) {                                                                                       \
+        hipLaunchKernelGGL((k_adi_x<c, SIN, SOUT>), dim3(blocks), dim3(256), 0, st, tb, in, in_off, out, \
+                           out_off, nslices, Mx, My, R, ex, ed);                                        \
+        return hipGetLastError();                                                                       \
+    }
+    PIT_ADI_XC(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename SIN, typename SOUT, int EPI>
+static hipError_t adi_y_t(int WY, int CY, const ColTab &tb, const SIN *in, long in_off, SOUT *out, long out_off,
+                          const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
+                          double ed, hipStream_t st)
+{
+    const int blocks = nslices * ((Mx + kWave - 1) / kWave);
+#define X(wy, cy)                                                                                        \
+    if (WY == wy && CY == cy) {                                                                          \
+        hipLaunchKernelGGL((k_adi_y<wy, cy, SIN, SOUT, EPI>), dim3(blocks), dim3(wy * 64), 0, st, tb, in, \
+                           in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);          \
+        return hipGetLastError();                                                                        \
+    }
+    PIT_ADI_YSHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in, long in_off, AdiBuf out,
+                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
+{
+    if (in.f32 && out.f32)
+        return adi_x_t<float, float>(sh.cx, tb, in.f, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+    if (!in.f32 && out.f32)
+        return adi_x_t<double, float>(sh.cx, tb, in.d, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+    if (!in.f32 && !out.f32)
+        return adi_x_t<double, double>(sh.cx, tb, in.d, in_off, out.d, out_off, nslices, Mx, My, R, ex, ed, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
+                        const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
+                        double ed, hipStream_t st)
+{
+    const bool epi = base != nullptr;
+    if (in.f32 && out.f32 && !epi)
+        return adi_y_t<float, float, 0>(sh.wy, sh.cy, tb, in.f, in_off, out.f, out_off, nullptr, 0, 0.0, nslices,
+                                        Mx, My, ex, ed, st);
+    if (in.f32 && !out.f32 && epi)
+        return adi_y_t<float, double, 1>(sh.wy, sh.cy, tb, in.f, in_off, out.d, out_off, base, base_off, sign,
+                                         nslices, Mx, My, ex, ed, st);
+    if (in.f32 && !out.f32 && !epi)
+        return adi_y_t<float, double, 0>(sh.wy, sh.cy, tb, in.f, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
+                                         Mx, My, ex, ed, st);
+    if (!in.f32 && !out.f32 && epi)
+        return adi_y_t<double, double, 1>(sh.wy, sh.cy, tb, in.d, in_off, out.d, out_off, base, base_off, sign,
+                                          nslices, Mx, My, ex, ed, st);
+    if (!in.f32 && !out.f32 && !epi)
+        return adi_y_t<double, double, 0>(sh.wy, sh.cy, tb, in.d, in_off, out.d, out_off, nullptr, 0, 0.0,
+                                          nslices, Mx, My, ex, ed, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pit

@@ -89,14 +89,17 @@ struct LineSolver {
 
     T lm[C], iu[C], cm[C], z[C];
     T wf[kScanConsts], wb[kScanConsts];
-    T qf, qb, rf;
+    T qf, qb, rf, rfw0;
     T inv_den, bg, iu_last;
     int cyclic;
     T *sh;
 
+    // Loads the thread's constants.  With one wavefront per line (W == 1) the
+    // solver uses no LDS and no barrier, so several waves of a workgroup can
+    // each own an independent line (lds may then be null).
     __device__ __forceinline__ void load(const LineTab<T> &tb, T *lds)
     {
-        const int t = threadIdx.x;
+        const int t = threadIdx.x & (NT - 1);
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             lm[k] = tb.lm[k * NT + t];
@@ -112,17 +115,20 @@ struct LineSolver {
         qf = tb.qf[t];
         qb = tb.qb[t];
         rf = tb.rf[t];
+        rfw0 = tb.rfw[0];
         inv_den = tb.inv_den;
         bg = tb.bg;
         iu_last = tb.iu_last;
         cyclic = tb.cyclic;
         sh = lds;
-        if (t < W) {
-            sh[kPwf + t] = tb.pwf[t];
-            sh[kPwb + t] = tb.pwb[t];
-            sh[kRfw + t] = tb.rfw[t];
+        if constexpr (W > 1) {
+            if (t < W) {
+                sh[kPwf + t] = tb.pwf[t];
+                sh[kPwb + t] = tb.pwb[t];
+                sh[kRfw + t] = tb.rfw[t];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // ---- forward elimination y_j = d_j + lm_j y_{j-1}: local pass + in-wave scan ----
@@ -279,7 +285,7 @@ struct LineSolver {
                 dM = pu * u0;
                 dL = pl * uM;
             }
-            ytot = readlane(v, kWave - 1) + fma(sh[kRfw], dL, dM);
+            ytot = readlane(v, kWave - 1) + fma(rfw0, dL, dM);
         }
         const T prev = dpp<0x138>(v);
         const T c = (lane == 0) ? cw : fma(rf, dL, fma(qf, cw, prev));

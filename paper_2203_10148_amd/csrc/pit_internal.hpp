@@ -113,6 +113,36 @@ hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const dou
 hipError_t launch_to_chunked(const double *nat, double *chk, int N, int M, int NT, int C, hipStream_t st);
 hipError_t launch_from_chunked(const double *chk, double *nat, int N, int M, int NT, int C, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// 2D PR-ADI half steps (adi2d.hip)
+// ---------------------------------------------------------------------------
+// Row-constant tables of the y-direction solver for WY*CY rows (pads: lm = 1,
+// iu = 0, cm = 0) and the per-wave products of lm and cm.  Blob layout:
+// lm[NR] iu[NR] cm[NR] pwf[16] pwb[16].
+struct ColTab {
+    const double *lm, *iu, *cm, *pwf, *pwb;
+};
+inline size_t col_tab_elems(int nr) { return 3 * (size_t)nr + 2 * kMaxWaves; }
+inline ColTab col_tab_view(const double *base, int nr)
+{
+    return ColTab{base, base + nr, base + 2 * (size_t)nr, base + 3 * (size_t)nr, base + 3 * (size_t)nr + kMaxWaves};
+}
+// x: C points per lane (64 lanes per row); y: WY waves of CY rows per column.
+struct AdiShape {
+    int cx, wy, cy;
+};
+// A field buffer of either precision.
+struct AdiBuf {
+    float *f;
+    double *d;
+    bool f32;
+};
+hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in, long in_off, AdiBuf out,
+                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st);
+hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
+                        const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
+                        double ed, hipStream_t st);
+
 // Krylov block-vector kernels (krylov.hip).  n = total number of doubles.
 // Segmented dot products: for each slice s and pair q < nq,
 //   part[(q*N + s)*bps + b] = partial sum of a_q[s,:] . b_q[s,:] over block b.

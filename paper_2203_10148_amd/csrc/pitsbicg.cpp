@@ -35,7 +35,8 @@ thread_local int t_last_hip = 0;
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kSolveVectors = 8;  // R, shadow R, P, D, S, K, temporary, iterate (chunked layout)
+constexpr int kSolveVectors = 8;
+constexpr int kMaxAdi = 1024;  // points per axis of the 2D half-step kernels  // R, shadow R, P, D, S, K, temporary, iterate (chunked layout)
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 const LineShape kShapes[] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},    {128, 8},  {256, 4},  {256, 8},
@@ -223,7 +224,27 @@ struct pit_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
 
-    long ld = 0;  // slice stride of the chunked layout (NT*C)
+    // 2D PR-ADI: x tables (64 lanes x cx points per row) and y row tables,
+    // fine (theta = dt/2) and coarse (theta = DT/(2c)); explicit-part
+    // coefficients: the x half step applies (I + theta Ly), the y half step
+    // (I + theta Lx), each as ed*u + ex*(sum of the two neighbours).
+    AdiShape ash{0, 0, 0};
+    LineHost axf, axc;
+    std::vector<double> ayf, ayc;
+    double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
+    size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
+    int adi_R = 16;  // rows per wavefront in the fine x half step
+    bool dim2() const { return pb.dim == 2; }
+    AdiBuf fbuf(size_t off) const
+    {
+        AdiBuf b{nullptr, nullptr, fine32()};
+        if (b.f32) b.f = reinterpret_cast<float *>(ws + off);
+        else b.d = reinterpret_cast<double *>(ws + off);
+        return b;
+    }
+    double *ctmp(int i) const { return reinterpret_cast<double *>(ws + off_ctmp) + (size_t)i * npts; }
+
+    long ld = 0;  // slice stride of the block vectors inside pit_solve (1D: chunked NT*C, 2D: npts)
     long nt() const { return (long)N * npts; }
     long ntc() const { return (long)N * ld; }
     double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * ntc(); }
@@ -263,6 +284,45 @@ void stencil1d(const pit_problem &p, double h, double *lo, double *di, double *u
     *up = p.nu / (h * h) - p.adv[0] / (2.0 * h);
 }
 
+// Row tables of the y-direction solver: the LU factors of the My x My
+// tridiagonal (sub a, diagonal b, super c), padded to wy*cy rows, and the
+// products of lm and cm over each wave's rows.
+bool build_col(int My, double a, double b, double c, int wy, int cy, std::vector<double> &blob)
+{
+    const int nr = wy * cy;
+    std::vector<double> lm(nr, 1.0), iu(nr, 0.0), cm(nr, 0.0);
+    double u = b;
+    for (int j = 0; j < My; ++j) {
+        if (j > 0) {
+            const double l = a / u;
+            u = b - l * c;
+            lm[j] = -l;
+        } else {
+            lm[j] = 0.0;
+        }
+        iu[j] = 1.0 / u;
+        cm[j] = (j < My - 1) ? -c / u : 0.0;
+    }
+    blob.assign(col_tab_elems(nr), 0.0);
+    for (int j = 0; j < nr; ++j) {
+        blob[j] = lm[j];
+        blob[nr + j] = iu[j];
+        blob[2 * (size_t)nr + j] = cm[j];
+    }
+    for (int w = 0; w < wy; ++w) {
+        double f = 1.0, g = 1.0;
+        for (int j = w * cy; j < (w + 1) * cy; ++j) {
+            f *= lm[j];
+            g *= cm[j];
+        }
+        blob[3 * (size_t)nr + w] = f;
+        blob[3 * (size_t)nr + kMaxWaves + w] = g;
+    }
+    for (double x : blob)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
 // Tables for A = I - theta*L with theta = dt (IE) or dt/2 (CN).
 bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &out)
 {
@@ -272,16 +332,58 @@ bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &
     return build_line(c.pb.M[0], c.pb.bc == PIT_PERIODIC, -th * lo, 1.0 - th * di, -th * up, sh, out);
 }
 
+// 2D setup: shapes, x and y tables and explicit coefficients for the fine
+// (theta = dt/2) and coarse (theta = DT/(2c)) PR-ADI steps.
+bool setup_2d(pit_ctx &c)
+{
+    const int Mx = c.pb.M[0], My = c.pb.M[1];
+    int cx = 1;
+    while (64 * cx < Mx) cx *= 2;
+    const AdiShape menu[] = {{0, 8, 16}, {0, 8, 32}, {0, 8, 64}, {0, 16, 64}};
+    AdiShape sh{cx, 0, 0};
+    for (const auto &a : menu)
+        if (a.wy * a.cy >= My) {
+            sh.wy = a.wy;
+            sh.cy = a.cy;
+            break;
+        }
+    if (!sh.wy || cx > 16) return false;
+    c.ash = sh;
+    const double nu = c.pb.nu, r = c.pb.react;
+    const double kx = nu / (c.hx * c.hx), ky = nu / (c.hy * c.hy);
+    auto tables = [&](double th, LineHost &ax, std::vector<double> &ay, double &xex, double &xed, double &yex,
+                      double &yed) {
+        xex = th * ky;                      // x half step: (I + th Ly)
+        xed = 1.0 - 2.0 * th * ky - 0.5 * th * r;
+        yex = th * kx;                      // y half step: (I + th Lx)
+        yed = 1.0 - 2.0 * th * kx - 0.5 * th * r;
+        const bool okx = build_line(Mx, false, -th * kx, 1.0 + 2.0 * th * kx + 0.5 * th * r, -th * kx,
+                                    LineShape{64, cx}, ax);
+        const bool oky = build_col(My, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, sh.wy, sh.cy, ay);
+        return okx && oky;
+    };
+    const double thf = 0.5 * c.DT / c.m, thc = 0.5 * c.DT / c.coarse.substeps;
+    return tables(thf, c.axf, c.ayf, c.fx_ex, c.fx_ed, c.fy_ex, c.fy_ed) &&
+           tables(thc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed);
+}
+
 int validate(const pit_problem *p, int N, int m, const pit_stepper &f, const pit_stepper &g)
 {
     if (!p || N < 1 || m < 1) return PIT_EINVAL;
-    if (p->dim != 1) return PIT_EINVAL;  // 2D arrives with the ADI kernels
-    if (p->M[0] < 3 || p->M[0] > kMaxLine) return PIT_EINVAL;
-    if (p->bc != PIT_DIRICHLET0 && p->bc != PIT_PERIODIC) return PIT_EINVAL;
+    if (p->dim != 1 && p->dim != 2) return PIT_EINVAL;
     if (!(p->length[0] > 0.0) || !(p->T > 0.0) || !(p->nu >= 0.0)) return PIT_EINVAL;
     if (!std::isfinite(p->adv[0]) || !std::isfinite(p->react)) return PIT_EINVAL;
-    if (f.scheme != PIT_IE && f.scheme != PIT_CN) return PIT_EINVAL;
-    if (g.scheme != PIT_IE && g.scheme != PIT_CN) return PIT_EINVAL;
+    if (p->dim == 2) {
+        if (p->M[0] < 3 || p->M[1] < 3 || p->M[0] > kMaxAdi || p->M[1] > kMaxAdi) return PIT_EINVAL;
+        if (p->bc != PIT_DIRICHLET0 || p->adv[0] != 0.0 || p->adv[1] != 0.0) return PIT_EINVAL;
+        if (!(p->length[1] > 0.0)) return PIT_EINVAL;
+        if (f.scheme != PIT_ADI_PR || g.scheme != PIT_ADI_PR) return PIT_EINVAL;
+    } else {
+        if (p->M[0] < 3 || p->M[0] > kMaxLine) return PIT_EINVAL;
+        if (p->bc != PIT_DIRICHLET0 && p->bc != PIT_PERIODIC) return PIT_EINVAL;
+        if (f.scheme != PIT_IE && f.scheme != PIT_CN) return PIT_EINVAL;
+        if (g.scheme != PIT_IE && g.scheme != PIT_CN) return PIT_EINVAL;
+    }
     if (f.substeps != 0 && f.substeps != m) return PIT_EINVAL;
     if (g.substeps < 1) return PIT_EINVAL;
     if ((f.prec != PIT_F64 && f.prec != PIT_F32) || g.prec != PIT_F64) return PIT_EINVAL;
@@ -302,6 +404,87 @@ hipError_t fine_launch(const pit_ctx *c, const double *lam, double *y, int raw, 
                                  c->pu, c->pr, c->pb.bc == PIT_PERIODIC ? 1 : 0, raw, last, chunked, st);
     return launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), lam, y, c->N, c->npts, c->m, c->fine.scheme,
                              raw, last, chunked, st);
+}
+
+// 2D all-at-once apply: m PR-ADI steps on every slice, two launches per step.
+// Work slice s reads lam_{s+in_off} and writes y_{s+out_off}.
+hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int last, hipStream_t st)
+{
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    const long np = c->npts;
+    if (last) raw = 1;
+    const int ns = last ? 1 : (raw ? c->N : c->N - 1);
+    const long in_off = last ? c->N - 1 : 0;
+    const long out_off = last ? c->N - 1 : (raw ? 0 : 1);
+    hipError_t e;
+    if (!raw && (e = launch_copy(y, lam, np, st)) != hipSuccess) return e;  // y_0 = lam_0
+    if (ns == 0) return hipSuccess;
+    const LineTab<double> tx = [&] {
+        LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64, c->ash.cx);
+        t.cyclic = 0;
+        t.M = Mx;
+        return t;
+    }();
+    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy);
+    const AdiBuf lamb{nullptr, const_cast<double *>(lam), false}, yb{nullptr, y, false};
+    const AdiBuf ub = c->fbuf(c->off_ubuf), sb = c->fbuf(c->off_sbuf);
+    for (int step = 0; step < c->m; ++step) {
+        const bool first = step == 0, fin = step == c->m - 1;
+        if ((e = launch_adi_x(c->ash, tx, first ? lamb : ub, first ? in_off : 0, sb, 0, ns, Mx, My, c->adi_R,
+                              c->fx_ex, c->fx_ed, st)) != hipSuccess)
+            return e;
+        if (fin)
+            e = launch_adi_y(c->ash, ty, sb, 0, yb, out_off, raw ? nullptr : lam, out_off, -1.0, ns, Mx, My,
+                             c->fy_ex, c->fy_ed, st);
+        else
+            e = launch_adi_y(c->ash, ty, sb, 0, ub, 0, nullptr, 0, 0.0, ns, Mx, My, c->fy_ex, c->fy_ed, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// 2D coarse sweep: z_0 = v_0, z_n = v_n + G(z_{n-1}), G = c PR-ADI steps of
+// DT/c, FP64, one slice at a time (one row per wavefront for latency).
+hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st)
+{
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    const long np = c->npts;
+    hipError_t e;
+    if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
+    LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axc), 64, c->ash.cx);
+    tx.cyclic = 0;
+    tx.M = Mx;
+    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayc), c->ash.wy * c->ash.cy);
+    const AdiBuf zb{nullptr, z, false};
+    const AdiBuf ta{nullptr, c->ctmp(0), false}, tb{nullptr, c->ctmp(1), false};
+    const int cs = c->coarse.substeps;
+    for (int n = 1; n < c->N; ++n) {
+        for (int s = 0; s < cs; ++s) {
+            if ((e = launch_adi_x(c->ash, tx, s == 0 ? zb : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, c->cx_ex,
+                                  c->cx_ed, st)) != hipSuccess)
+                return e;
+            if (s == cs - 1)
+                e = launch_adi_y(c->ash, ty, ta, 0, zb, n, v, n, 1.0, 1, Mx, My, c->cy_ex, c->cy_ed, st);
+            else
+                e = launch_adi_y(c->ash, ty, ta, 0, tb, 0, nullptr, 0, 0.0, 1, Mx, My, c->cy_ex, c->cy_ed, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// The operators on block vectors of stride ld (chunked inside pit_solve in 1D).
+hipError_t op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal, hipStream_t st)
+{
+    if (c->dim2()) return apply_2d(c, lam, y, raw, last, st);
+    return fine_launch(c, lam, y, raw, last, internal, st);
+}
+
+hipError_t op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
+{
+    if (c->dim2()) return sweep_2d(c, v, z, st);
+    return launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), v, z, c->N, c->npts, c->coarse.substeps,
+                              c->coarse.scheme, internal, st);
 }
 
 }  // namespace
@@ -340,11 +523,49 @@ int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->fine.substeps = m;
     c->coarse = coarse;
     const int M = problem->M[0];
+    c->DT = problem->T / N;
+    if (problem->dim == 2) {
+        c->npts = problem->M[0] * problem->M[1];
+        c->hx = problem->length[0] / (problem->M[0] + 1);
+        c->hy = problem->length[1] / (problem->M[1] + 1);
+        c->w = c->hx * c->hy;
+        if (!setup_2d(*c)) {
+            delete c;
+            return PIT_EINVAL;
+        }
+        if (const char *e = std::getenv("PIT_ADI_ROWS")) c->adi_R = std::max(1, std::atoi(e));
+        c->ld = c->npts;
+        c->bps = (int)std::min<long>(64, std::max<long>(1, (c->ld + 4095) / 4096));
+        const size_t fs = c->fine32() ? sizeof(float) : sizeof(double);
+        size_t o = 0;
+        c->off_axf = o;
+        o = align_up(o + c->axf.blob.size() * sizeof(double));
+        c->off_axc = o;
+        o = align_up(o + c->axc.blob.size() * sizeof(double));
+        c->off_ayf = o;
+        o = align_up(o + c->ayf.size() * sizeof(double));
+        c->off_ayc = o;
+        o = align_up(o + c->ayc.size() * sizeof(double));
+        c->off_ubuf = o;
+        o = align_up(o + (size_t)N * c->npts * fs);
+        c->off_sbuf = o;
+        o = align_up(o + (size_t)N * c->npts * fs);
+        c->off_ctmp = o;
+        o = align_up(o + 2 * (size_t)c->npts * sizeof(double));
+        c->off_vec = o;
+        o = align_up(o + kSolveVectors * (size_t)c->ntc() * sizeof(double));
+        c->off_part = o;
+        o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
+        c->off_red = o;
+        o = align_up(o + sizeof(RedOut));
+        c->total = o;
+        *out = c;
+        return PIT_OK;
+    }
     c->npts = M;
     c->hx = (problem->bc == PIT_PERIODIC) ? problem->length[0] / M : problem->length[0] / (M + 1);
     c->hy = 1.0;
     c->w = c->hx;
-    c->DT = problem->T / N;
     // One shape for both line operators: pit_solve keeps its block vectors in
     // the chunked layout of that shape, shared by the fine and coarse kernels.
     const LineShape sh = shape_from_env("PIT_LINE_SHAPE", M);
@@ -392,6 +613,13 @@ size_t pit_workspace_bytes(const pit_ctx *ctx) { return ctx ? ctx->total : 0; }
 int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4])
 {
     if (!ctx || !out) return PIT_EINVAL;
+    if (ctx->dim2()) {  // 2D: 64 lanes x cx points per row; wy waves x cy rows per column
+        out[0] = 64;
+        out[1] = ctx->ash.cx;
+        out[2] = 64 * ctx->ash.wy;
+        out[3] = ctx->ash.cy;
+        return PIT_OK;
+    }
     out[0] = ctx->lf.sh.NT;
     out[1] = ctx->lf.sh.C;
     out[2] = ctx->lc.sh.NT;
@@ -405,6 +633,17 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
     if (bytes < ctx->total) return PIT_ENOMEM;
     ctx->ws = static_cast<char *>(dev_ptr);
     ctx->ws_bytes = bytes;
+    if (ctx->dim2()) {
+        PIT_HIP(hipMemcpy(ctx->ws + ctx->off_axf, ctx->axf.blob.data(), ctx->axf.blob.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        PIT_HIP(hipMemcpy(ctx->ws + ctx->off_axc, ctx->axc.blob.data(), ctx->axc.blob.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        PIT_HIP(hipMemcpy(ctx->ws + ctx->off_ayf, ctx->ayf.data(), ctx->ayf.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        PIT_HIP(hipMemcpy(ctx->ws + ctx->off_ayc, ctx->ayc.data(), ctx->ayc.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+        return PIT_OK;
+    }
     PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf, ctx->lf.blob.data(), ctx->lf.blob.size() * sizeof(double),
                       hipMemcpyHostToDevice));
     PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tc, ctx->lc.blob.data(), ctx->lc.blob.size() * sizeof(double),
@@ -420,7 +659,7 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
     if (!ctx || !ctx->ws || !lam || !y || (flags & ~(PIT_APPLY_RAW | PIT_APPLY_LAST))) return PIT_EINVAL;
     if (lam == y) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PIT_HIP(fine_launch(ctx, lam, y, (flags & PIT_APPLY_RAW) ? 1 : 0, (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
+    PIT_HIP(op_apply(ctx, lam, y, (flags & PIT_APPLY_RAW) ? 1 : 0, (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
     return PIT_OK;
 }
 
@@ -428,8 +667,7 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream)
 {
     if (!ctx || !ctx->ws || !v || !z) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PIT_HIP(launch_sweep1d_f64(ctx->lc.sh, ctx->tab(ctx->lc, ctx->off_tc), v, z, ctx->N, ctx->npts,
-                               ctx->coarse.substeps, ctx->coarse.scheme, false, st));
+    PIT_HIP(op_sweep(ctx, v, z, false, st));
     return PIT_OK;
 }
 
@@ -475,7 +713,7 @@ struct Solver {
     {
         int rc;
         if (timing && (rc = begin(ev_fine))) return rc;
-        PIT_HIP(fine_launch(c, in, out, 0, 0, true, st));
+        PIT_HIP(op_apply(c, in, out, 0, 0, true, st));
         if (timing) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
         ++n_fine;
         return PIT_OK;
@@ -485,8 +723,7 @@ struct Solver {
     {
         int rc;
         if (timing && (rc = begin(ev_coarse))) return rc;
-        PIT_HIP(launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), in, out, c->N, c->npts,
-                                   c->coarse.substeps, c->coarse.scheme, true, st));
+        PIT_HIP(op_sweep(c, in, out, true, st));
         if (timing) PIT_HIP(hipEventRecord(ev_coarse.back().b, st));
         ++n_coarse;
         return PIT_OK;
@@ -568,7 +805,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
 
     // line 1: R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
     PIT_HIP(launch_fill0(s.S, n, st));
-    PIT_HIP(launch_to_chunked(u0, s.S, 1, ctx->npts, NT, C, st));  // S holds B for now
+    if (ctx->dim2()) PIT_HIP(launch_copy(s.S, u0, ctx->npts, st));  // S holds B for now
+    else PIT_HIP(launch_to_chunked(u0, s.S, 1, ctx->npts, NT, C, st));
     if (o.x0_mode == PIT_X0_ZERO) {
         PIT_HIP(launch_fill0(X, n, st));
         if ((rc = s.sweep(s.S, s.R))) return rc;
@@ -576,7 +814,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         if (o.x0_mode == PIT_X0_COARSE) {
             if ((rc = s.sweep(s.S, X))) return rc;
         } else {
-            PIT_HIP(launch_to_chunked(Xu, X, ctx->N, ctx->npts, NT, C, st));
+            if (ctx->dim2()) PIT_HIP(launch_copy(X, Xu, n, st));
+            else PIT_HIP(launch_to_chunked(Xu, X, ctx->N, ctx->npts, NT, C, st));
         }
         if ((rc = s.apply(X, s.D))) return rc;
         PIT_HIP(launch_axpby(s.Tm, s.S, 1.0, s.D, -1.0, n, st));
@@ -706,7 +945,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         rho = rho_new;
         k++;  // line 18
     }
-    PIT_HIP(launch_from_chunked(X, Xu, ctx->N, ctx->npts, NT, C, st));
+    if (ctx->dim2()) PIT_HIP(launch_copy(Xu, X, n, st));
+    else PIT_HIP(launch_from_chunked(X, Xu, ctx->N, ctx->npts, NT, C, st));
     PIT_HIP(hipStreamSynchronize(st));
     if (info) {
         info->status = status;

@@ -374,3 +374,99 @@ def test_fp32_small_solve_and_final_state():
     assert relerr(host(Xg), serial) < 1e-5
     yl = host(c.apply_F(Xg, last=True)).reshape(p.N, -1)
     assert relerr(yl[-1], uT) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# 2D Peaceman-Rachford ADI
+# ---------------------------------------------------------------------------
+
+ADI_CASES = [
+    # (Mx, My, Lx, Ly, N, m, c, prec)
+    (24, 20, 1.0, 1.3, 4, 3, 1, wl.F64),
+    (100, 70, 1.0, 0.7, 3, 4, 2, wl.F64),
+    (64, 128, 1.0, 1.0, 3, 2, 1, wl.F64),
+    (130, 257, 1.0, 1.0, 2, 2, 1, wl.F64),
+    (512, 512, 1.0, 1.0, 3, 3, 1, wl.F64),
+    (100, 70, 1.0, 0.7, 3, 4, 2, wl.F32),
+    (512, 512, 1.0, 1.0, 3, 3, 1, wl.F32),
+]
+
+
+def adi_problem(Mx, My, Lx, Ly, N, m, c, prec):
+    return wl.Problem(dim=2, M=(Mx, My), length=(Lx, Ly), bc=wl.DIRICHLET, nu=0.05, react=0.2, T=0.05 * N,
+                      N=N, m=m, fine=wl.ADI, c=c, coarse=wl.ADI, prec=prec)
+
+
+@pytest.mark.parametrize("case", ADI_CASES, ids=lambda c: f"{c[0]}x{c[1]}_N{c[4]}_m{c[5]}_c{c[6]}_p{c[7]}")
+def test_adi_apply_and_sweep_match_oracle(case):
+    p = adi_problem(*case)
+    say(f"adi apply/sweep {case}")
+    o = make_oracle(p)
+    c = ctx(p)
+    # FP32 storage of the fields between half steps: a smooth block must meet
+    # 1e-5.  For a rough block the explicit half of a PR-ADI step amplifies
+    # modes rough along one axis by up to 1 + 4*rho (rho = theta nu / h^2) in the
+    # intermediate field, whose FP32 rounding then reaches the smooth modes:
+    # bound 1e-5 * max(1, rho/16).
+    hx, hy = p.length[0] / (p.M[0] + 1), p.length[1] / (p.M[1] + 1)
+    rho = 0.5 * (p.T / p.N / p.m) * p.nu / min(hx, hy) ** 2
+    rough_tol = 1e-12 if p.prec == wl.F64 else 1e-5 * max(1.0, rho / 16)
+    X, Y = wl.grid_2d(p)
+    smooth = np.concatenate([(np.sin(np.pi * X / p.length[0]) * np.sin((n + 1) * np.pi * Y / p.length[1])).reshape(-1)
+                             for n in range(p.N)])
+    for lam, tol in ((smooth, 1e-12 if p.prec == wl.F64 else 1e-5), (wl.random_block(p, 17), rough_tol)):
+        d = dev(lam)
+        e1 = relerr(host(c.apply_F(d)), o.apply(lam))
+        e2 = relerr(host(c.apply_F(d, raw=True)), o.apply_raw(lam))
+        yl = host(c.apply_F(d, last=True)).reshape(p.N, -1)
+        e3 = relerr(yl[-1], o.F(lam.reshape(p.N, -1)[-1]))
+        print(f"rho={rho:.3g} tol={tol:.2e} apply {e1:.2e} raw {e2:.2e} last {e3:.2e}", flush=True)
+        assert e1 < tol and e2 < tol and e3 < tol
+        assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
+        d2 = dev(lam)
+        c.coarse_sweep(d2, d2)
+        assert relerr(host(d2), o.sweep(lam)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [wl.F64, wl.F32])
+def test_adi_small_solve_matches_oracle(prec):
+    p = wl.Problem(dim=2, M=(40, 33), length=(1.0, 1.0), nu=0.05, T=0.5, N=8, m=8, fine=wl.ADI, c=1,
+                   coarse=wl.ADI, prec=prec)
+    say(f"adi small solve prec={prec}")
+    o = make_oracle(p)
+    u0 = wl.u0_bumps(p, 3)
+    Xo, io = o.pitsbicg(u0, tol=1e-10)
+    c = ctx(p)
+    Xg, ig = c.solve(dev(u0), tol=1e-10 if prec == wl.F64 else 1e-8, stall_window=0 if prec == wl.F64 else 10)
+    Xg = host(Xg)
+    serial = o.serial(u0)
+    if prec == wl.F64:
+        assert ig.status == io.status == orc.OK
+        assert abs(ig.iters - io.iters) <= 1
+        assert relerr(Xg, Xo) < 1e-9
+        assert relerr(Xg, serial) < 1e-9
+    else:
+        assert relerr(Xg, serial) < 1e-5
+
+
+def test_c3_full_size_fp32():
+    """The 512 x 512, 128-slice heat workload (64 PR-ADI steps, FP32 fine):
+    the apply on sampled slices, and the solve's first slices against the
+    FP64 serial fine trajectory."""
+    p = wl.C3
+    say("c3 full size")
+    c = ctx(p)
+    o1 = make_oracle(p.with_(N=1, T=p.T / p.N))  # one slice of length DT
+    lam = wl.random_block(p, 3)
+    y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
+    L = lam.reshape(p.N, -1)
+    for n in (1, 64, 127):
+        assert relerr(y[n], L[n] - o1.F(L[n - 1])) < 1e-5, n
+    u0 = wl.u0_for(p)
+    Xg, ig = c.solve(dev(u0), tol=p.tol, stall_window=10)
+    Xg = host(Xg).reshape(p.N, -1)
+    print(f"c3 fp32 solve: status={ig.status} iters={ig.iters} ms={ig.ms_total:.1f}", flush=True)
+    ref = u0.copy()
+    for n in range(6):
+        assert relerr(Xg[n], ref) < 1e-5, n
+        ref = o1.F(ref)
