@@ -28,22 +28,70 @@ __device__ __forceinline__ double to_d(S v)
     return (double)v;
 }
 
+// Buffer addressing: a scalar descriptor per slice, the row offset in a
+// scalar register and only the lane's column offset in a vector register.
+// Descriptor word 3 (0x00020000) selects raw 32-bit element access on CDNA.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(Rsrc r, int voff, int soff);
+template <>
+__device__ __forceinline__ float bload<float>(Rsrc r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(Rsrc r, int voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, int voff, int soff)
+{
+    using U2 = __attribute__((ext_vector_type(2))) unsigned;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, voff, soff, 0);
+}
+
 // ---------------------------------------------------------------------------
 // x half step
 // ---------------------------------------------------------------------------
+// Lane l's C consecutive values of row j (clamped into the slice).  When
+// every lane's chunk is inside the row and 16-byte aligned (vec), the chunk
+// is read with 16-byte loads: the address unit handles a 64-lane instruction
+// in a fixed number of cycles, so wide accesses move 4x the bytes per cycle.
 template <int C, typename SIN>
-__device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, int My, int Mx, int lane,
+__device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, int My, int Mx, int lane, bool vec,
                                          SIN (&r)[C])
 {
     const SIN *row = slice + (size_t)min(max(j, 0), My - 1) * Mx;
+    constexpr int V = 16 / sizeof(SIN);
+    if constexpr (C % V == 0) {
+        if (vec) {
+            using VT = __attribute__((ext_vector_type(V))) SIN;
+            const VT *p = reinterpret_cast<const VT *>(row + lane * C);
+#pragma unroll
+            for (int q = 0; q < C / V; ++q) {
+                const VT x = p[q];
+#pragma unroll
+                for (int i = 0; i < V; ++i) r[q * V + i] = x[i];
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < C; ++k) r[k] = row[min(lane * C + k, Mx - 1)];
 }
 
 template <int C, typename SIN, typename SOUT>
-__device__ __forceinline__ void x_row(LineSolver<double, kWave, C> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
-                                      const SIN (&nx)[C], int j, int My, int Mx, int lane, double ex, double ed,
-                                      SOUT *__restrict__ oslice)
+__device__ __forceinline__ void x_row(LineSolver<double, kWave, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
+                                      const SIN (&nx)[C], int j, int My, int Mx, int lane, bool vec, double ex,
+                                      double ed, SOUT *__restrict__ oslice)
 {
     const double fp = (j > 0) ? 1.0 : 0.0, fn = (j + 1 < My) ? 1.0 : 0.0;
     double d[C];
@@ -54,6 +102,21 @@ __device__ __forceinline__ void x_row(LineSolver<double, kWave, C> &LS, const SI
     }
     LS.solve(d);
     SOUT *row = oslice + (size_t)j * Mx;
+    constexpr int V = 16 / sizeof(SOUT);
+    if constexpr (C % V == 0) {
+        if (vec) {
+            using VT = __attribute__((ext_vector_type(V))) SOUT;
+            VT *p = reinterpret_cast<VT *>(row + lane * C);
+#pragma unroll
+            for (int q = 0; q < C / V; ++q) {
+                VT x;
+#pragma unroll
+                for (int i = 0; i < V; ++i) x[i] = (SOUT)d[q * V + i];
+                p[q] = x;
+            }
+            return;
+        }
+    }
     if (lane * C + C <= Mx) {
 #pragma unroll
         for (int k = 0; k < C; ++k) row[lane * C + k] = (SOUT)d[k];
@@ -73,27 +136,34 @@ __global__ __launch_bounds__(256) void k_adi_x(LineTab<double> tb, const SIN *__
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int strips = (My + R - 1) / R;
-    const int g = blockIdx.x * 4 + threadIdx.x / kWave;
+    // wave-uniform indices in scalar registers, so row addresses stay scalar
+    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / kWave);
     if (g >= nslices * strips) return;  // whole wavefront exits; no barriers below
     const int s = g / strips, j0 = (g % strips) * R, j1 = min(j0 + R, My);
     const long npts = (long)Mx * My;
     const SIN *islice = in + (size_t)(s + in_off) * npts;
     SOUT *oslice = out + (size_t)(s + out_off) * npts;
-    LineSolver<double, kWave, C> LS;
+    // 16-byte accesses when the row length keeps every lane chunk aligned
+    const bool vec = (Mx == kWave * C) && (Mx * sizeof(SIN)) % 16 == 0 && (Mx * sizeof(SOUT)) % 16 == 0;
+    LineSolver<double, kWave, C, false> LS;
     LS.load(tb, nullptr);
-    SIN a[C], b[C], c[C];
-    load_row<C>(islice, j0 - 1, My, Mx, lane, a);
-    load_row<C>(islice, j0, My, Mx, lane, b);
-    load_row<C>(islice, j0 + 1, My, Mx, lane, c);
-    for (int j = j0; j < j1; j += 3) {
-        x_row<C>(LS, a, b, c, j, My, Mx, lane, ex, ed, oslice);
-        load_row<C>(islice, j + 2, My, Mx, lane, a);
-        if (j + 1 >= j1) break;
-        x_row<C>(LS, b, c, a, j + 1, My, Mx, lane, ex, ed, oslice);
-        load_row<C>(islice, j + 3, My, Mx, lane, b);
-        if (j + 2 >= j1) break;
-        x_row<C>(LS, c, a, b, j + 2, My, Mx, lane, ex, ed, oslice);
-        load_row<C>(islice, j + 4, My, Mx, lane, c);
+    // Five rotating row buffers: row r uses the buffers of rows r-1, r, r+1
+    // while rows r+2 .. r+4 are in flight.  Reads past the strip are clamped
+    // to its last halo row (a cache hit), so no row is fetched from HBM twice.
+    SIN B[5][C];
+    const int jl = min(j1, My - 1);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) load_row<C>(islice, min(j0 - 1 + q, jl), My, Mx, lane, vec, B[q]);
+    for (int j = j0; j < j1; j += 5) {
+#define PIT_XSTEP(u)                                                                                       \
+    {                                                                                                      \
+        const int r = j + (u);                                                                             \
+        if (r >= j1) break;                                                                                \
+        x_row<C>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, ex, ed, oslice); \
+        load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                \
+    }
+        PIT_XSTEP(0) PIT_XSTEP(1) PIT_XSTEP(2) PIT_XSTEP(3) PIT_XSTEP(4)
+#undef PIT_XSTEP
     }
 }
 
@@ -113,7 +183,8 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     __shared__ double s_lm[NR], s_iu[NR], s_cm[NR];
     __shared__ double s_pf[WY], s_pb[WY];
     __shared__ double s_agg[2][WY][kWave];
-    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const int t = threadIdx.x, lane = t & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform (scalar) row segment
     const int bx = (Mx + kWave - 1) / kWave;
     const int s = blockIdx.x / bx, col0 = (blockIdx.x % bx) * kWave;
     for (int i = t; i < NR; i += WY * kWave) {
@@ -131,25 +202,47 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     const int col = col0 + lane;
     const int cc = min(col, Mx - 1);
     const bool live = col < Mx;
-    const SIN *islice = in + (size_t)(s + in_off) * npts;
+    const Rsrc rin = make_rsrc(in + (size_t)(s + in_off) * npts, (unsigned)(npts * sizeof(SIN)));
     const double fl = (col > 0) ? 1.0 : 0.0, fr = (col + 1 < Mx) ? 1.0 : 0.0;
-    const int cl = max(col - 1, 0), cr = min(col + 1, Mx - 1);
     const int r0 = w * CY;
+    constexpr int zi = sizeof(SIN), zo = sizeof(SOUT);
+    // The two halo columns of the strip for this wave's CY rows in one load:
+    // lane i < CY reads column col0-1 of row r0+i, lane CY+i column col0+64;
+    // row r's halo values are then taken with readlane.
+    static_assert(2 * CY <= kWave || CY == 64, "halo lanes");
+    SIN hv, hv2;
+    {
+        const int i = lane % CY;
+        const int hc = (lane < CY) ? max(col0 - 1, 0) : min(col0 + kWave, Mx - 1);
+        hv = bload<SIN>(rin, (min(r0 + i, My - 1) * Mx + hc) * zi, 0);
+        hv2 = hv;  // with CY == 64 the right halo needs a second load
+        if constexpr (CY == 64) hv2 = bload<SIN>(rin, (min(r0 + lane, My - 1) * Mx + min(col0 + kWave, Mx - 1)) * zi, 0);
+    }
 
-    // right-hand side (I + theta Lx) u* for this lane's column segment
-    double d[CY];
+    // Right-hand side (I + theta Lx) u* for this lane's column segment; the
+    // x-neighbours inside the wavefront come from DPP lane shifts.  The
+    // segment is kept in the field precision SIN between the passes; every
+    // recurrence runs in FP64 (only the stored intermediates are rounded).
+    SIN d[CY];
+#pragma unroll
+    for (int r = 0; r < CY; ++r) d[r] = bload<SIN>(rin, cc * zi, min(r0 + r, My - 1) * Mx * zi);
 #pragma unroll
     for (int r = 0; r < CY; ++r) {
-        const int j = min(r0 + r, My - 1);
-        const SIN *row = islice + (size_t)j * Mx;
-        const double v = to_d(row[cc]), vl = to_d(row[cl]), vr = to_d(row[cr]);
+        const double v = to_d(d[r]);
+        const double hl = to_d(readlane(hv, r));
+        const double hr = to_d(CY == 64 ? readlane(hv2, r) : readlane(hv, CY + (r % (kWave - CY + 1))));
+        // the lane shifts run in every lane (DPP is not speculatable inside a
+        // branch); the wave-edge lanes then take the halo values
+        const double sl = dpp<0x138>(v), sr = dpp<0x130>(v);
+        const double vl = (lane == 0) ? hl : sl;
+        const double vr = (lane == kWave - 1) ? hr : sr;
         const double x = fma(ed, v, ex * fma(fl, vl, fr * vr));
-        d[r] = (live && r0 + r < My) ? x : 0.0;
+        d[r] = (live && r0 + r < My) ? (SIN)x : (SIN)0;
     }
     // forward elimination along y
     double e = 0.0;
 #pragma unroll
-    for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, d[r]);
+    for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, to_d(d[r]));
     s_agg[0][w][lane] = e;
     __syncthreads();
     double cw = 0.0;
@@ -157,35 +250,30 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     double y = cw;
 #pragma unroll
     for (int r = 0; r < CY; ++r) {
-        y = fma(s_lm[r0 + r], y, d[r]);
-        d[r] = y;
+        y = fma(s_lm[r0 + r], y, to_d(d[r]));
+        d[r] = (SIN)y;
     }
     // back substitution along y
     double bsum = 0.0;
 #pragma unroll
-    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * d[r]);
+    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * to_d(d[r]));
     s_agg[1][w][lane] = bsum;
     __syncthreads();
     double cb = 0.0;
     for (int q = WY - 1; q > w; --q) cb = fma(s_pb[q], cb, s_agg[1][q][lane]);
+    // second backward pass: each solution value is stored as it is produced
+    const Rsrc rout = make_rsrc(out + (size_t)(s + out_off) * npts, (unsigned)(npts * zo));
+    const Rsrc rbase = make_rsrc(EPI ? base + (size_t)(s + base_off) * npts : base, EPI ? (unsigned)(npts * 8) : 0u);
     double x = cb;
 #pragma unroll
     for (int r = CY - 1; r >= 0; --r) {
-        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * d[r]);
-        d[r] = x;
-    }
-    if (!live) return;
-    SOUT *oslice = out + (size_t)(s + out_off) * npts;
-    const double *bslice = EPI ? base + (size_t)(s + base_off) * npts : nullptr;
-#pragma unroll
-    for (int r = 0; r < CY; ++r) {
+        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * to_d(d[r]));
         const int j = r0 + r;
-        if (j < My) {
-            const size_t o = (size_t)j * Mx + col;
+        if (live && j < My) {
             if constexpr (EPI)
-                oslice[o] = (SOUT)fma(sign, d[r], bslice[o]);
+                bstore((SOUT)fma(sign, x, bload<double>(rbase, col * 8, j * Mx * 8)), rout, col * zo, j * Mx * zo);
             else
-                oslice[o] = (SOUT)d[r];
+                bstore((SOUT)x, rout, col * zo, j * Mx * zo);
         }
     }
 }
@@ -194,7 +282,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 // launchers
 // ---------------------------------------------------------------------------
 #define PIT_ADI_XC(X) X(1) X(2) X(4) X(8) X(16)
-#define PIT_ADI_YSHAPES(X) X(8, 16) X(8, 32) X(8, 64) X(16, 64)
+#define PIT_ADI_YSHAPES(X) X(8, 16) X(8, 32) X(8, 64) X(16, 32) X(16, 64)
 
 template <typename SIN, typename SOUT>
 static hipError_t adi_x_t(int C, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,

@@ -78,7 +78,9 @@ __device__ __forceinline__ T scan_down(T v, const T (&m)[7])
     return fma(m[4], t1, fma(m[5], t2, fma(m[6], t3, v)));
 }
 
-template <typename T, int NT, int C>
+// CYC = false drops the periodic (Sherman-Morrison) part: no z vector in
+// registers and no correction.
+template <typename T, int NT, int C, bool CYC = true>
 struct LineSolver {
     static constexpr int W = NT / kWave;
     static_assert(NT % kWave == 0 && W <= kMaxWaves, "bad line shape");
@@ -105,7 +107,7 @@ struct LineSolver {
             lm[k] = tb.lm[k * NT + t];
             iu[k] = tb.iu[k * NT + t];
             cm[k] = tb.cm[k * NT + t];
-            z[k] = tb.z[k * NT + t];
+            if constexpr (CYC) z[k] = tb.z[k * NT + t];
         }
 #pragma unroll
         for (int l = 0; l < kScanConsts; ++l) {
@@ -183,7 +185,7 @@ struct LineSolver {
             x = fma(cm[k], x, iu[k] * d[k]);
             d[k] = x;
         }
-        if (cyclic) {  // Sherman-Morrison correction
+        if (CYC && cyclic) {  // Sherman-Morrison correction
             const T xlast = iu_last * ytot;  // cm_{M-1} = 0
             const T phi = (xtot + bg * xlast) * inv_den;
 #pragma unroll

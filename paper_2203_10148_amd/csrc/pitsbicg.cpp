@@ -233,7 +233,7 @@ struct pit_ctx {
     std::vector<double> ayf, ayc;
     double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
     size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
-    int adi_R = 16;  // rows per wavefront in the fine x half step
+    int adi_R = 32;  // rows per wavefront in the fine x half step
     bool dim2() const { return pb.dim == 2; }
     AdiBuf fbuf(size_t off) const
     {
@@ -339,7 +339,7 @@ bool setup_2d(pit_ctx &c)
     const int Mx = c.pb.M[0], My = c.pb.M[1];
     int cx = 1;
     while (64 * cx < Mx) cx *= 2;
-    const AdiShape menu[] = {{0, 8, 16}, {0, 8, 32}, {0, 8, 64}, {0, 16, 64}};
+    const AdiShape menu[] = {{0, 8, 16}, {0, 8, 32}, {0, 16, 32}, {0, 16, 64}};
     AdiShape sh{cx, 0, 0};
     for (const auto &a : menu)
         if (a.wy * a.cy >= My) {
@@ -348,6 +348,14 @@ bool setup_2d(pit_ctx &c)
             break;
         }
     if (!sh.wy || cx > 16) return false;
+    if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {  // tuning override "wy,cy"
+        int wy = 0, cy = 0;
+        if (std::sscanf(e, "%d,%d", &wy, &cy) == 2 && wy * cy >= My &&
+            ((wy == 8 && (cy == 16 || cy == 32 || cy == 64)) || (wy == 16 && (cy == 32 || cy == 64)))) {
+            sh.wy = wy;
+            sh.cy = cy;
+        }
+    }
     c.ash = sh;
     const double nu = c.pb.nu, r = c.pb.react;
     const double kx = nu / (c.hx * c.hx), ky = nu / (c.hy * c.hy);
