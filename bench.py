@@ -77,6 +77,9 @@ def main():
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", choices=["apply", "sweep"], default=None,
+                    help="counter-collection mode: run two fine applies (or coarse sweeps) of the "
+                         "workload and a 1 GiB device copy (the byte-count calibration), print nothing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -96,6 +99,20 @@ def main():
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
     ctx = P.Context(p, device=dev)
+    if args.probe:
+        lam = torch.as_tensor(wl.random_block(p, 1), dtype=torch.float64, device=dev)
+        out = torch.empty_like(lam)
+        for _ in range(2):
+            if args.probe == "apply":
+                ctx.apply_F(lam, out)
+            else:
+                ctx.coarse_sweep(lam, out)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] probe {args.probe} done")
+        return
     u0 = torch.as_tensor(u0h, dtype=torch.float64, device=dev)
     X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)
     uT = torch.empty_like(X)

@@ -31,6 +31,11 @@ __device__ __forceinline__ double to_d(S v)
 // Buffer addressing: a scalar descriptor per slice, the row offset in a
 // scalar register and only the lane's column offset in a vector register.
 // Descriptor word 3 (0x00020000) selects raw 32-bit element access on CDNA.
+// The range check covers the vector offset only (the scalar offset is added
+// unchecked): a lane whose vector offset is at or past the descriptor's byte
+// count reads 0 and its store is dropped, so callers keep the scalar offset
+// inside the buffer and mark a lane or row out of range through the vector
+// offset.
 using Rsrc = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ Rsrc make_rsrc(const void *p, unsigned bytes)
 {
@@ -127,6 +132,17 @@ __device__ __forceinline__ void x_row(LineSolver<double, kWave, C, false> &LS, c
     }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by block id, and each XCD
+// has its own L2.  Renumbering the blocks so that XCD x runs one contiguous
+// range of logical blocks keeps neighbouring strips (which share halo rows or
+// columns) on one L2, so a halo line is fetched from HBM once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + min(x, r) + k;
+}
+
 // grid: ceil(nslices * strips / 4) blocks of 4 waves; wave g handles strip
 // g % strips of slice g / strips.  in/out slice s sits at in + (s + in_off)*npts.
 template <int C, typename SIN, typename SOUT>
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(256) void k_adi_x(LineTab<double> tb, const SIN *__
     const int lane = threadIdx.x & (kWave - 1);
     const int strips = (My + R - 1) / R;
     // wave-uniform indices in scalar registers, so row addresses stay scalar
-    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / kWave);
+    const int g = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / kWave);
     if (g >= nslices * strips) return;  // whole wavefront exits; no barriers below
     const int s = g / strips, j0 = (g % strips) * R, j1 = min(j0 + R, My);
     const long npts = (long)Mx * My;
@@ -186,7 +202,8 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     const int t = threadIdx.x, lane = t & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform (scalar) row segment
     const int bx = (Mx + kWave - 1) / kWave;
-    const int s = blockIdx.x / bx, col0 = (blockIdx.x % bx) * kWave;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk / bx, col0 = (blk % bx) * kWave;
     for (int i = t; i < NR; i += WY * kWave) {
         s_lm[i] = tb.lm[i];
         s_iu[i] = tb.iu[i];
@@ -200,12 +217,18 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     if (s >= nslices) return;  // uniform per block
     const long npts = (long)Mx * My;
     const int col = col0 + lane;
-    const int cc = min(col, Mx - 1);
     const bool live = col < Mx;
     const Rsrc rin = make_rsrc(in + (size_t)(s + in_off) * npts, (unsigned)(npts * sizeof(SIN)));
-    const double fl = (col > 0) ? 1.0 : 0.0, fr = (col + 1 < Mx) ? 1.0 : 0.0;
     const int r0 = w * CY;
     constexpr int zi = sizeof(SIN), zo = sizeof(SOUT);
+    // Out-of-range buffer reads return 0, which supplies the zeros the
+    // stencil needs in lanes past the last column and for the Dirichlet
+    // boundary values left and right of the slice.  Rows past the last one
+    // re-read the last row: their table entries (lm 1, iu 0, cm 0) keep any
+    // finite value out of the real rows, and they are never stored.
+    constexpr int kOut = 0x40000000;
+    const int vcol = live ? col * zi : kOut;
+    auto in_row = [&](int r) { return bload<SIN>(rin, vcol, min(r0 + r, My - 1) * Mx * zi); };
     // The two halo columns of the strip for this wave's CY rows in one load:
     // lane i < CY reads column col0-1 of row r0+i, lane CY+i column col0+64;
     // row r's halo values are then taken with readlane.
@@ -213,36 +236,48 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     SIN hv, hv2;
     {
         const int i = lane % CY;
-        const int hc = (lane < CY) ? max(col0 - 1, 0) : min(col0 + kWave, Mx - 1);
-        hv = bload<SIN>(rin, (min(r0 + i, My - 1) * Mx + hc) * zi, 0);
+        const int hc = (lane < CY) ? col0 - 1 : col0 + kWave;
+        const bool in_range = hc >= 0 && hc < Mx && r0 + i < My;
+        hv = bload<SIN>(rin, in_range ? ((r0 + i) * Mx + hc) * zi : kOut, 0);
         hv2 = hv;  // with CY == 64 the right halo needs a second load
-        if constexpr (CY == 64) hv2 = bload<SIN>(rin, (min(r0 + lane, My - 1) * Mx + min(col0 + kWave, Mx - 1)) * zi, 0);
+        if constexpr (CY == 64) {
+            const int hc2 = col0 + kWave;
+            hv2 = bload<SIN>(rin, (hc2 < Mx && r0 + lane < My) ? ((r0 + lane) * Mx + hc2) * zi : kOut, 0);
+        }
     }
 
     // Right-hand side (I + theta Lx) u* for this lane's column segment; the
-    // x-neighbours inside the wavefront come from DPP lane shifts.  The
-    // segment is kept in the field precision SIN between the passes; every
-    // recurrence runs in FP64 (only the stored intermediates are rounded).
-    SIN d[CY];
+    // x-neighbours inside the wavefront come from DPP lane shifts of the
+    // stored values.  Every lane runs the cross-lane reads (DPP and readlane
+    // are not speculatable, so inside a conditional they would become a
+    // divergent branch); the wave-edge lanes then select the halo values.
+    auto rhs = [&](SIN v, int r) {
+        const SIN hl = readlane(hv, r);
+        const SIN hr = CY == 64 ? readlane(hv2, r) : readlane(hv, CY + (r % (kWave - CY + 1)));
+        const SIN sl = dpp<0x138>(v), sr = dpp<0x130>(v);
+        const SIN vl = (lane == 0) ? hl : sl;
+        const SIN vr = (lane == kWave - 1) ? hr : sr;
+        return fma(ed, to_d(v), ex * (to_d(vl) + to_d(vr)));
+    };
+    double d[CY];
+    if constexpr (sizeof(SIN) == sizeof(double)) {
+        // FP64 input: load straight into d and form the right-hand side in
+        // place (a separate copy of the rows would not fit in registers)
 #pragma unroll
-    for (int r = 0; r < CY; ++r) d[r] = bload<SIN>(rin, cc * zi, min(r0 + r, My - 1) * Mx * zi);
+        for (int r = 0; r < CY; ++r) d[r] = in_row(r);
 #pragma unroll
-    for (int r = 0; r < CY; ++r) {
-        const double v = to_d(d[r]);
-        const double hl = to_d(readlane(hv, r));
-        const double hr = to_d(CY == 64 ? readlane(hv2, r) : readlane(hv, CY + (r % (kWave - CY + 1))));
-        // the lane shifts run in every lane (DPP is not speculatable inside a
-        // branch); the wave-edge lanes then take the halo values
-        const double sl = dpp<0x138>(v), sr = dpp<0x130>(v);
-        const double vl = (lane == 0) ? hl : sl;
-        const double vr = (lane == kWave - 1) ? hr : sr;
-        const double x = fma(ed, v, ex * fma(fl, vl, fr * vr));
-        d[r] = (live && r0 + r < My) ? (SIN)x : (SIN)0;
+        for (int r = 0; r < CY; ++r) d[r] = rhs(d[r], r);
+    } else {
+        SIN raw[CY];
+#pragma unroll
+        for (int r = 0; r < CY; ++r) raw[r] = in_row(r);
+#pragma unroll
+        for (int r = 0; r < CY; ++r) d[r] = rhs(raw[r], r);
     }
     // forward elimination along y
     double e = 0.0;
 #pragma unroll
-    for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, to_d(d[r]));
+    for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, d[r]);
     s_agg[0][w][lane] = e;
     __syncthreads();
     double cw = 0.0;
@@ -250,31 +285,46 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     double y = cw;
 #pragma unroll
     for (int r = 0; r < CY; ++r) {
-        y = fma(s_lm[r0 + r], y, to_d(d[r]));
-        d[r] = (SIN)y;
+        y = fma(s_lm[r0 + r], y, d[r]);
+        d[r] = y;
     }
     // back substitution along y
+    const Rsrc rout = make_rsrc(out + (size_t)(s + out_off) * npts, (unsigned)(npts * zo));
+    const Rsrc rbase = make_rsrc(EPI ? base + (size_t)(s + base_off) * npts : base, EPI ? (unsigned)(npts * 8) : 0u);
+    const int vout = live ? col * zo : kOut, vbase = live ? col * 8 : kOut;
+    // The epilogue's base rows are read PB rows ahead of the second backward
+    // pass (the first PB before the backward exchange), so their latency is
+    // hidden behind the recurrence instead of stalling every row.
+    constexpr int PB = EPI ? (CY < 8 ? CY : 8) : 1;
+    auto base_row = [&](int r) {
+        const int j = r0 + r;  // rows past the last one: see in_row
+        return bload<double>(rbase, vbase, min(j, My - 1) * Mx * 8);
+    };
+    double bq[PB];
+    if constexpr (EPI) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) bq[q] = base_row(CY - 1 - q);
+    }
     double bsum = 0.0;
 #pragma unroll
-    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * to_d(d[r]));
+    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * d[r]);
     s_agg[1][w][lane] = bsum;
     __syncthreads();
     double cb = 0.0;
     for (int q = WY - 1; q > w; --q) cb = fma(s_pb[q], cb, s_agg[1][q][lane]);
     // second backward pass: each solution value is stored as it is produced
-    const Rsrc rout = make_rsrc(out + (size_t)(s + out_off) * npts, (unsigned)(npts * zo));
-    const Rsrc rbase = make_rsrc(EPI ? base + (size_t)(s + base_off) * npts : base, EPI ? (unsigned)(npts * 8) : 0u);
     double x = cb;
 #pragma unroll
     for (int r = CY - 1; r >= 0; --r) {
-        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * to_d(d[r]));
+        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * d[r]);
         const int j = r0 + r;
-        if (live && j < My) {
-            if constexpr (EPI)
-                bstore((SOUT)fma(sign, x, bload<double>(rbase, col * 8, j * Mx * 8)), rout, col * zo, j * Mx * zo);
-            else
-                bstore((SOUT)x, rout, col * zo, j * Mx * zo);
+        double o = x;
+        if constexpr (EPI) {
+            const int q = (CY - 1 - r) % PB;
+            o = fma(sign, x, bq[q]);
+            if (r - PB >= 0) bq[q] = base_row(r - PB);
         }
+        if (j < My) bstore((SOUT)o, rout, vout, j * Mx * zo);  // wave-uniform branch
     }
 }
 
