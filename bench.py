@@ -15,8 +15,12 @@ same solve truncated to a bounded number of iterations on the host cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--prec f64]
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,6 +37,123 @@ FLOPS_PER_CU = {("ie", 0): 5, ("ie", 1): 7, ("cn", 0): 7, ("cn", 1): 9}
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# Sources that the fine apply and coarse sweep kernels are compiled from; a
+# stored counter summary is only used while these files are unchanged.
+KERNEL_SOURCES = {1: ["fine1d.hip", "line1d.hpp", "pit_internal.hpp"],
+                  2: ["adi2d.hip", "line1d.hpp", "pit_internal.hpp"]}
+CSRC = os.path.join(ROOT, "paper_2203_10148_amd", "csrc")
+CAL_BYTES = 1 << 30  # the probe's device copy (read 1 GiB, write 1 GiB)
+
+
+def sources_sha(dim):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[dim]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name):
+    return re.sub(r"\(.*", "", name).replace("pit::", "")
+
+
+def summarize_stats(stats_csv, out, title, command):
+    """Markdown table of a rocprofv3 --stats kernel summary."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "", "```", command, "```", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def pmc_dispatches(path, counter):
+    """{dispatch id: (kernel name, KiB)} from a rocprofv3 --pmc counter_collection.csv."""
+    d = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = int(r["Dispatch_Id"])
+        name, v = d.get(k, (r["Kernel_Name"], 0.0))
+        d[k] = (name, v + float(r["Counter_Value"]))
+    return d
+
+
+def summarize_pmc(fetch_csv, write_csv, out, p, prec, unit, kernels, units, commands):
+    """HBM-side traffic per fine apply / coarse sweep from two counter runs of --probe.
+
+    FETCH_SIZE and WRITE_SIZE are each scaled by what they read for the
+    probe's 1 GiB device copy, then summed over the dispatches whose kernel
+    name matches `kernels` and divided by the number of probed units."""
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        d = pmc_dispatches(path, counter)
+        cal = max(v for n, v in d.values() if "copyBuffer" in n)
+        factor = CAL_BYTES / (cal * 1024.0)
+        per_kernel = {}
+        for n, v in d.values():
+            if "pit::" not in n or not re.search(kernels, n):
+                continue
+            c, t = per_kernel.get(short_name(n), (0, 0.0))
+            per_kernel[short_name(n)] = (c + 1, t + v * 1024.0 * factor)
+        n_units = sum(c for c, _ in per_kernel.values()) if units == 0 else units
+        res[key] = {"factor": factor, "cal_kib": cal, "kernels": per_kernel,
+                    "bytes": sum(t for _, t in per_kernel.values()) / n_units}
+    units = n_units
+    alg = algorithmic_bytes(p, prec, unit)
+    rec = {"workload": p.name, "prec": prec, "unit": unit, "fetch_bytes": res["fetch"]["bytes"],
+           "write_bytes": res["write"]["bytes"], "traffic_bytes": res["fetch"]["bytes"] + res["write"]["bytes"],
+           "algorithmic_bytes": alg, "fetch_factor": res["fetch"]["factor"], "write_factor": res["write"]["factor"],
+           "sources_sha256": sources_sha(p.dim)}
+    lines = [f"# HBM traffic: {unit} on {p.name} ({prec} fine)", "",
+             "Counter runs (from the repository root on one MI355X), one counter per run:", "", "```"]
+    lines += commands + ["```", "",
+                         f"Calibration: the probe's 1 GiB device copy reads FETCH_SIZE = {res['fetch']['cal_kib']:.0f} KiB "
+                         f"and WRITE_SIZE = {res['write']['cal_kib']:.0f} KiB, so the counters are scaled by "
+                         f"{res['fetch']['factor']:.4f} (fetch) and {res['write']['factor']:.4f} (write).", "",
+                         "| kernel | dispatches | fetch MiB/dispatch | write MiB/dispatch |", "|---|---:|---:|---:|"]
+    for n in res["fetch"]["kernels"]:
+        cf, tf = res["fetch"]["kernels"][n]
+        cw, tw = res["write"]["kernels"].get(n, (1, 0.0))
+        lines.append(f"| `{n}` | {cf} | {tf / cf / 2**20:.2f} | {tw / cw / 2**20:.2f} |")
+    lines += ["", f"Per {unit} ({units} probed): fetch {rec['fetch_bytes'] / 2**20:.1f} MiB, write "
+                  f"{rec['write_bytes'] / 2**20:.1f} MiB, total {rec['traffic_bytes'] / 2**20:.1f} MiB against "
+                  f"{alg / 2**20:.1f} MiB algorithmic ({rec['traffic_bytes'] / alg:.3f}x).", "",
+              f"<!-- traffic-json: {json.dumps(rec)} -->"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return rec
+
+
+def stored_traffic(p, prec, unit):
+    """Traffic per unit from a committed counter summary, if the kernel sources still match."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        m = re.search(r"<!-- traffic-json: (\{.*\}) -->", open(path).read())
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if (rec["workload"], rec["prec"], rec["unit"]) == (p.name, prec, unit):
+            if rec["sources_sha256"] == sources_sha(p.dim):
+                return rec, os.path.relpath(path, ROOT)
+            return None, os.path.relpath(path, ROOT) + " (stale: kernel sources changed since)"
+    return None, None
+
+
+def algorithmic_bytes(p, prec, unit):
+    """Algorithmic HBM bytes of one fine apply or coarse sweep (block vectors FP64)."""
+    from paper_2203_10148_amd import workloads as wl
+    if p.dim == 1:
+        return 2 * p.N * p.npts * 8  # slice in, slice out; the state stays on chip across steps
+    if unit == "fine_apply":
+        # each PR-ADI half step reads and writes the field once
+        return p.cells_per_apply * 4 * (4 if prec == "f32" else 8)
+    # coarse sweep per slice and step: x half (read 8 + write 8), y half (read 8 + base 8 + write 8)
+    return (p.N - 1) * p.c * p.npts * 40
 
 
 def workload(name, prec):
@@ -77,10 +198,27 @@ def main():
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--probe", choices=["apply", "sweep"], default=None,
-                    help="counter-collection mode: run two fine applies (or coarse sweeps) of the "
-                         "workload and a 1 GiB device copy (the byte-count calibration), print nothing")
+    ap.add_argument("--probe", choices=["apply", "sweep", "solve"], default=None,
+                    help="counter-collection mode: run two fine applies (or two coarse sweeps, or a one-iteration "
+                         "solve) of the workload and a 1 GiB device copy (the byte-count calibration)")
+    ap.add_argument("--stats-summary", nargs=4, metavar=("CSV", "OUT", "TITLE", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--pmc-summary", nargs=8,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "UNIT", "KERNEL_REGEX", "UNITS", "FETCH_CMD", "WRITE_CMD"),
+                    help="write the traffic summary of two --probe counter runs (FETCH_SIZE, WRITE_SIZE) and exit: "
+                         "UNIT is fine_apply or coarse_sweep, made of the dispatches matching KERNEL_REGEX, UNITS of "
+                         "them were probed (0: one unit per matching dispatch); --workload/--prec name the probed workload")
     args = ap.parse_args()
+    if args.stats_summary:
+        summarize_stats(*args.stats_summary)
+        return
+    if args.pmc_summary:
+        p = workload(args.workload, args.prec)
+        from paper_2203_10148_amd import workloads as wl
+        prec = "f32" if p.prec == wl.F32 else "f64"
+        fc, wc, out, unit, rx, units, cf, cw = args.pmc_summary
+        print(json.dumps(summarize_pmc(fc, wc, out, p, prec, unit, rx, int(units), [cf, cw])))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -102,7 +240,10 @@ def main():
     if args.probe:
         lam = torch.as_tensor(wl.random_block(p, 1), dtype=torch.float64, device=dev)
         out = torch.empty_like(lam)
-        for _ in range(2):
+        if args.probe == "solve":
+            ctx.solve(torch.as_tensor(u0h, dtype=torch.float64, device=dev), out, tol=p.tol, max_iter=1,
+                      raise_on_error=False)
+        for _ in range(2 if args.probe != "solve" else 0):
             if args.probe == "apply":
                 ctx.apply_F(lam, out)
             else:
@@ -165,10 +306,8 @@ def main():
         # 2D: the fine apply streams the field through HBM twice per PR-ADI step
         # (x half step: read + write, y half step: read + write).
         scheme, cscheme = "adi", "adi"
-        es = 4 if args.prec == "f32" else 8
-        by_fine = p.cells_per_apply * 4 * es
-        # coarse sweep per slice and step: x half (read 8 + write 8), y half (read 8 + base 8 + write 8)
-        by_coarse = (p.N - 1) * p.c * p.npts * 40
+        by_fine = algorithmic_bytes(p, args.prec, "fine_apply")
+        by_coarse = algorithmic_bytes(p, args.prec, "coarse_sweep")
         kern = {
             "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "hbm",
                            "work_per_launch": by_fine, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
@@ -185,6 +324,13 @@ def main():
     achieved = rate(k)
     roofline = {"bound": k["bound"], "kernel": dom, "achieved": achieved, "peak": k["peak"], "unit": k["unit"],
                 "frac": achieved / k["peak"], "traffic": None}
+    rec, src = stored_traffic(p, args.prec, dom)
+    if rec is not None:
+        roofline["traffic"] = rec["traffic_bytes"]
+        roofline["traffic_unit"] = f"bytes per {dom}"
+        roofline["traffic_vs_algorithmic"] = rec["traffic_bytes"] / algorithmic_bytes(p, args.prec, dom)
+    if src is not None:
+        roofline["traffic_source"] = src
     fine_cu_s = p.cells_per_apply / (avg_fine * 1e-3) if avg_fine > 0 else 0.0
     out = {
         "metric": "fine cell-updates/s and % HBM peak; PiT time-to-1e-8 vs plain FP64, 1 GPU",
