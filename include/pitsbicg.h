@@ -200,6 +200,103 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
 int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
               pit_solve_info *info, void *stream);
 
+/* ---- batched solves --------------------------------------------------------- */
+
+/* Many independent PiTSBiCG solves advanced together (any mix of 1D problems
+ * of different M, N, m and coefficients, and 2D problems).  Each instance
+ * follows exactly the control flow of pit_solve; its result does not depend
+ * on which other instances share the batch (the same kernels compute it with
+ * the same operation order), so a solve alone and the same solve inside any
+ * batch give identical bits.  1D instances of one line shape share each
+ * launch: one fine-apply launch covers all their slices, one coarse-sweep
+ * launch runs their sweeps concurrently (one workgroup each), and the
+ * inner products and vector updates of all listed instances take one launch
+ * each.  2D instances run their operators with their own launches.  Ready
+ * instances are advanced on up to four HIP streams. */
+typedef struct pit_batch pit_batch;
+
+/* Create a batch engine for up to max_count instances at once (no GPU work;
+ * creates its streams on the current device at bind). */
+int pit_batch_create(int32_t max_count, pit_batch **out);
+/* Device bytes the engine needs for its descriptors and argument buffers. */
+size_t pit_batch_workspace_bytes(const pit_batch *b);
+/* Bind device memory (256-byte aligned) as the engine's workspace; creates
+ * its HIP streams and events on the current device.  Errors: PIT_EINVAL,
+ * PIT_ENOMEM, PIT_EHIP. */
+int pit_batch_bind_workspace(pit_batch *b, void *dev_ptr, size_t bytes);
+int pit_batch_destroy(pit_batch *b);
+
+/* Solve count <= max_count problems: ctxs[i] (bound contexts, all distinct),
+ * u0[i] and X[i] as in pit_solve, opts NULL (defaults) or count entries,
+ * infos NULL or count entries.  Supported options: tol, restart_tol,
+ * max_iter, norm_mode, stall_window; x0_mode must be PIT_X0_ZERO and
+ * half_step_check 0 (else PIT_EINVAL before any work).  The engine first
+ * waits for `stream` and returns when every instance has finished
+ * (host-synchronous).  Returns PIT_OK when every instance returned PIT_OK,
+ * otherwise the first failing instance's status (each infos[i].status holds
+ * its own). */
+int pit_batch_solve(pit_batch *b, pit_ctx *const *ctxs, int32_t count, const double *const *u0,
+                    double *const *X, const pit_solve_opts *opts, pit_solve_info *infos, void *stream);
+
+/* ---- serving ------------------------------------------------------------------ */
+
+/* A request loop with continuous batching: submitted solves queue in arrival
+ * order and are admitted while a slot is free and their workspace fits in the
+ * device arena (the HBM budget); admitted solves advance in the batch engine
+ * above, so requests that arrive while others run join them on the GPU, and
+ * leave as they finish, freeing their slot and memory for the queue.  The
+ * caller provides the arena (device memory it owns); the server carves every
+ * request's workspace and its own buffers out of it and allocates no device
+ * memory.  A worker thread drives the GPU; pit_submit and pit_poll are
+ * thread-safe. */
+typedef struct pit_server pit_server;
+
+typedef struct {
+    void *arena;          /* device memory (256-byte aligned) = the HBM budget   */
+    uint64_t arena_bytes;
+    int32_t device;       /* HIP device of the arena                             */
+    int32_t max_slots;    /* solves on the GPU at once (>= 1)                    */
+    int32_t reserved[2];
+} pit_server_cfg;
+
+typedef struct {
+    pit_problem problem;
+    int32_t N, m;
+    pit_stepper fine, coarse;
+    const double *u0;     /* device, one slice; read after admission             */
+    double *X;            /* device [N][npts]; written before the request is done */
+    pit_solve_opts opts;  /* as pit_batch_solve                                  */
+} pit_request;
+
+typedef struct {
+    int32_t status;       /* the solve's status (as pit_solve), or PIT_ENOMEM when
+                             the request can never fit the arena                 */
+    int32_t iters, matvecs, restarts;
+    double res_norm;
+    double t_submit_ms;   /* times since server creation (steady clock)          */
+    double t_admit_ms;
+    double t_done_ms;
+    uint64_t workspace_bytes;
+    int32_t hip_error;    /* hipError_t of a failing HIP call (status PIT_EHIP)  */
+    int32_t reserved;
+} pit_result;
+
+/* Start a server (creates its worker thread).  Errors: PIT_EINVAL, PIT_ENOMEM
+ * (arena too small for the server's own buffers), PIT_EHIP. */
+int pit_server_create(const pit_server_cfg *cfg, pit_server **out);
+/* Queue a solve; *ticket identifies it.  The problem is validated here
+ * (PIT_EINVAL, nothing queued).  u0 and X must stay valid until pit_poll
+ * reports the request done. */
+int pit_submit(pit_server *s, const pit_request *req, uint64_t *ticket);
+/* PIT_EAGAIN while the request is queued or running; PIT_OK once it is done,
+ * with *res filled (then the ticket is retired); PIT_EINVAL for an unknown
+ * ticket. */
+int pit_poll(pit_server *s, uint64_t ticket, pit_result *res);
+/* Number of requests queued and running, and the arena bytes in use. */
+int pit_server_load(pit_server *s, int32_t *queued, int32_t *running, uint64_t *arena_used);
+/* Finish every queued and running request, stop the worker, free host state. */
+int pit_server_destroy(pit_server *s);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 
 /* Static description of an error code. */

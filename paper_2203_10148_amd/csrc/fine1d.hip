@@ -57,15 +57,15 @@ __device__ __forceinline__ void store_chunk(double *__restrict__ dst, int t, int
     }
 }
 
-// Fine apply: workgroup n computes y_n = lam_n - F(lam_{n-1}) (or F(lam_n)
-// when raw); ld is the slice stride of lam and y.
+// Fine apply of one slice: y_n = lam_n - F(lam_{n-1}) (or F(lam_n) when
+// raw); ld is the slice stride of lam and y.  Shared by the single-instance
+// kernel and the multi-instance one, so an instance computes the same bits in
+// either.
 template <int NT, int C, int SCHEME, bool TR>
-__global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const double *__restrict__ lam,
-                                                   double *__restrict__ y, int N, int M, long ld, int m,
-                                                   int raw, int n0)
+__device__ __forceinline__ void fine1d_f64_slice(const LineTab<double> &tb, const double *__restrict__ lam,
+                                                 double *__restrict__ y, int M, long ld, int m, int raw, int n,
+                                                 double *lds)
 {
-    __shared__ double lds[LineSolver<double, NT, C>::kLds];
-    const int n = n0 + blockIdx.x;
     const int t = threadIdx.x;
     if (!raw && n == 0) {  // y_0 = lam_0
         for (long j = t; j < ld; j += NT) y[j] = lam[j];
@@ -98,17 +98,26 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
     store_chunk<NT, C, TR>(y + (size_t)n * ld, t, M, u);
 }
 
-// Fine apply with an FP32 propagator: the slice state is FP32 and every step
-// is taken in increment form (LineSolver::step_delta), so rounding the step
-// matrix to FP32 perturbs only the increment, not the state; lam and y are FP64
-// and the subtraction y_n = lam_n - F(lam_{n-1}) is done in FP64.
-template <int NT, int C, bool TR>
-__global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const double *__restrict__ lam,
+template <int NT, int C, int SCHEME, bool TR>
+__global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const double *__restrict__ lam,
                                                    double *__restrict__ y, int N, int M, long ld, int m,
-                                                   float pl, float pu, float pr, int periodic, int raw, int n0)
+                                                   int raw, int n0)
 {
-    __shared__ float lds[LineSolver<float, NT, C>::kLds];
-    const int n = n0 + blockIdx.x;
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    fine1d_f64_slice<NT, C, SCHEME, TR>(tb, lam, y, M, ld, m, raw, n0 + blockIdx.x, lds);
+}
+
+// Fine apply with an FP32 propagator: the slice state is an FP32 pair
+// (value + compensation) and every step is taken in increment form
+// (LineSolver::step_delta), so rounding the step matrix to FP32 perturbs only
+// the increment, and the state's own rounding is carried in the compensation;
+// lam and y are FP64 and the subtraction y_n = lam_n - F(lam_{n-1}) is done in
+// FP64.
+template <int NT, int C, bool TR>
+__device__ __forceinline__ void fine1d_f32_slice(const LineTab<float> &tb, const double *__restrict__ lam,
+                                                 double *__restrict__ y, int M, long ld, int m, float pl,
+                                                 float pu, float pr, int periodic, int raw, int n, float *lds)
+{
     const int t = threadIdx.x;
     if (!raw && n == 0) {  // y_0 = lam_0
         for (long j = t; j < ld; j += NT) y[j] = lam[j];
@@ -119,12 +128,15 @@ __global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const doub
     double ud[C];
     load_chunk<NT, C, TR>(lam + (size_t)(raw ? n : n - 1) * ld, t, M, ud);
     zero_pads<C>(t, M, ud);
-    float u[C];
+    float u[C], lo[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) u[k] = (float)ud[k];
-    for (int s = 0; s < m; ++s) S.step_delta(u, pl, pu, pr, M, periodic);
+    for (int k = 0; k < C; ++k) {
+        u[k] = (float)ud[k];
+        lo[k] = (float)(ud[k] - (double)u[k]);
+    }
+    for (int s = 0; s < m; ++s) S.step_delta(u, lo, pl, pu, pr, M, periodic);
 #pragma unroll
-    for (int k = 0; k < C; ++k) ud[k] = (double)u[k];
+    for (int k = 0; k < C; ++k) ud[k] = (double)u[k] + (double)lo[k];
     if (!raw) {
         double own[C];
         load_chunk<NT, C, TR>(lam + (size_t)n * ld, t, M, own);
@@ -133,6 +145,15 @@ __global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const doub
         zero_pads<C>(t, M, ud);
     }
     store_chunk<NT, C, TR>(y + (size_t)n * ld, t, M, ud);
+}
+
+template <int NT, int C, bool TR>
+__global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const double *__restrict__ lam,
+                                                   double *__restrict__ y, int N, int M, long ld, int m,
+                                                   float pl, float pu, float pr, int periodic, int raw, int n0)
+{
+    __shared__ float lds[LineSolver<float, NT, C>::kLds];
+    fine1d_f32_slice<NT, C, TR>(tb, lam, y, M, ld, m, pl, pu, pr, periodic, raw, n0 + blockIdx.x, lds);
 }
 
 // One coarse slice step of the sweep: u <- G(u) + v_n (pads stay 0).
@@ -162,10 +183,9 @@ __device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double
 // clamped instead of guarded, so the loaded registers are consumed where
 // they land.
 template <int NT, int C, int SCHEME, bool TR>
-__global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const double *v, double *z,
-                                                    int N, int M, long ld, int c)
+__device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, const double *v, double *z, int N,
+                                                 int M, long ld, int c, double *lds)
 {
-    __shared__ double lds[LineSolver<double, NT, C>::kLds];
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
@@ -184,6 +204,54 @@ __global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const do
         load_chunk<NT, C, TR>(v + (size_t)min(n + 3, N - 1) * ld, t, M, vb);
         store_chunk<NT, C, TR>(z + (size_t)(n + 1) * ld, t, M, u);
     }
+}
+
+template <int NT, int C, int SCHEME, bool TR>
+__global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const double *v, double *z,
+                                                    int N, int M, long ld, int c)
+{
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    sweep1d_f64_line<NT, C, SCHEME, TR>(tb, v, z, N, M, ld, c, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-instance launches: one launch runs the fine apply (or the coarse
+// sweep) of every listed instance of one line shape; block b belongs to the
+// listed instance k with first[k] <= b < first[k+1].  Block vectors are in the
+// chunked layout.
+// ---------------------------------------------------------------------------
+template <int NT, int C, int SCHEME>
+__global__ __launch_bounds__(NT) void k_fine1d_f64_multi(Group g)
+{
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    const int k = group_find(g.first, g.count, blockIdx.x);
+    const int vin = g.aux[2 * k], vout = g.aux[2 * k + 1];
+    const Inst1d &d = g.inst[g.list[k]];
+    const long nv = (long)d.N * d.ld;
+    fine1d_f64_slice<NT, C, SCHEME, true>(d.tf, d.vec + vin * nv, d.vec + vout * nv, d.M, d.ld, d.m, 0,
+                                          blockIdx.x - g.first[k], lds);
+}
+
+template <int NT, int C>
+__global__ __launch_bounds__(NT) void k_fine1d_f32_multi(Group g)
+{
+    __shared__ float lds[LineSolver<float, NT, C>::kLds];
+    const int k = group_find(g.first, g.count, blockIdx.x);
+    const int vin = g.aux[2 * k], vout = g.aux[2 * k + 1];
+    const Inst1d &d = g.inst[g.list[k]];
+    const long nv = (long)d.N * d.ld;
+    fine1d_f32_slice<NT, C, true>(d.tf32, d.vec + vin * nv, d.vec + vout * nv, d.M, d.ld, d.m, d.pl, d.pu, d.pr,
+                                  d.periodic, 0, blockIdx.x - g.first[k], lds);
+}
+
+template <int NT, int C, int SCHEME>
+__global__ __launch_bounds__(NT) void k_sweep1d_f64_multi(Group g)
+{
+    __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    const Inst1d &d = g.inst[g.list[blockIdx.x]];
+    const int vin = g.aux[2 * blockIdx.x], vout = g.aux[2 * blockIdx.x + 1];
+    const long nv = (long)d.N * d.ld;
+    sweep1d_f64_line<NT, C, SCHEME, true>(d.tc, d.vec + vin * nv, d.vec + vout * nv, d.N, d.M, d.ld, d.c, lds);
 }
 
 #define PIT_LINE_SHAPES(X)                                                                  \
@@ -259,6 +327,40 @@ hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const dou
     PIT_LINE_SHAPES(X)
 #undef X
 #undef LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// grid: g.first[g.count] blocks (the listed instances' slice counts)
+hipError_t launch_fine1d_multi(LineShape sh, int fine32, int scheme, const Group &g, int nblocks, hipStream_t st)
+{
+#define X(nt, c)                                                                                             \
+    if (sh.NT == nt && sh.C == c) {                                                                          \
+        if (fine32)                                                                                          \
+            hipLaunchKernelGGL((k_fine1d_f32_multi<nt, c>), dim3(nblocks), dim3(nt), 0, st, g);              \
+        else if (scheme == SCHEME_IE)                                                                        \
+            hipLaunchKernelGGL((k_fine1d_f64_multi<nt, c, SCHEME_IE>), dim3(nblocks), dim3(nt), 0, st, g);   \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_fine1d_f64_multi<nt, c, SCHEME_CN>), dim3(nblocks), dim3(nt), 0, st, g);   \
+        return hipGetLastError();                                                                            \
+    }
+    PIT_LINE_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// grid: one block per listed instance
+hipError_t launch_sweep1d_multi(LineShape sh, int scheme, const Group &g, hipStream_t st)
+{
+#define X(nt, c)                                                                                             \
+    if (sh.NT == nt && sh.C == c) {                                                                          \
+        if (scheme == SCHEME_IE)                                                                             \
+            hipLaunchKernelGGL((k_sweep1d_f64_multi<nt, c, SCHEME_IE>), dim3(g.count), dim3(nt), 0, st, g);  \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_sweep1d_f64_multi<nt, c, SCHEME_CN>), dim3(g.count), dim3(nt), 0, st, g);  \
+        return hipGetLastError();                                                                            \
+    }
+    PIT_LINE_SHAPES(X)
+#undef X
     return hipErrorInvalidValue;
 }
 

@@ -18,12 +18,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// grid (bps, N); each block sums a strided part of one slice for nq pairs.
-__global__ __launch_bounds__(kRedThreads) void k_seg_dots(DotPairs pr, int nq, int N, long npts,
-                                                          int bps, double *__restrict__ part)
+// Block b of slice s sums a strided part of the slice for nq pairs (shared
+// by the single- and multi-instance kernels).
+__device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N, long npts, int bps,
+                                               double *__restrict__ part, int b, int s)
 {
     __shared__ double sh[4][kRedThreads / kWave];
-    const int b = blockIdx.x, s = blockIdx.y;
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     const size_t base = (size_t)s * npts;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -48,10 +48,17 @@ __global__ __launch_bounds__(kRedThreads) void k_seg_dots(DotPairs pr, int nq, i
     }
 }
 
+// grid (bps, N)
+__global__ __launch_bounds__(kRedThreads) void k_seg_dots(DotPairs pr, int nq, int N, long npts,
+                                                          int bps, double *__restrict__ part)
+{
+    seg_dots_block(pr, nq, N, npts, bps, part, blockIdx.x, blockIdx.y);
+}
+
 // One block: per-slice sums in block order, then totals and maxima over
 // slices in a fixed order.
-__global__ __launch_bounds__(kRedThreads) void k_seg_finalize(const double *__restrict__ part, int nq,
-                                                              int N, int bps, double w, RedOut *out)
+__device__ __forceinline__ void seg_finalize_block(const double *__restrict__ part, int nq, int N, int bps,
+                                                   double w, RedOut *out)
 {
     __shared__ double sd[kRedThreads];
     __shared__ double sm[kRedThreads];
@@ -85,6 +92,46 @@ __global__ __launch_bounds__(kRedThreads) void k_seg_finalize(const double *__re
     }
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_seg_finalize(const double *__restrict__ part, int nq,
+                                                              int N, int bps, double w, RedOut *out)
+{
+    seg_finalize_block(part, nq, N, bps, w, out);
+}
+
+// Multi-instance dots: the blocks of listed instance k are its (b, s) pairs
+// in the order b + bps*s.
+__global__ __launch_bounds__(kRedThreads) void k_seg_dots_multi(Group g)
+{
+    const int k = group_find(g.first, g.count, blockIdx.x);
+    const Inst1d &d = g.inst[g.list[k]];
+    const long nv = (long)d.N * d.ld;
+    const int *q9 = g.aux + kDotsAux * k;
+    const int nq = q9[0];
+    DotPairs pr{};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        pr.a[q] = d.vec + q9[1 + q] * nv;
+        pr.b[q] = d.vec + q9[5 + q] * nv;
+    }
+    const int local = blockIdx.x - g.first[k];
+    seg_dots_block(pr, nq, d.N, d.ld, d.bps, d.part, local % d.bps, local / d.bps);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_seg_finalize_multi(Group g)
+{
+    const Inst1d &d = g.inst[g.list[blockIdx.x]];
+    seg_finalize_block(d.part, g.aux[kDotsAux * blockIdx.x], d.N, d.bps, d.w, g.red + blockIdx.x);
+}
+
+hipError_t launch_dots_multi(const Group &g, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seg_dots_multi, dim3(nblocks), dim3(kRedThreads), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_finalize_multi, dim3(g.count), dim3(kRedThreads), 0, st, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_seg_dots(const DotPairs &pr, int nq, int N, long npts, int bps, double *part,
                            double w, RedOut *out, hipStream_t st)
 {
@@ -108,11 +155,24 @@ static inline dim3 vec_grid(long n)
     return dim3((unsigned)b);
 }
 
+// The update formulas, shared by the single- and multi-instance kernels.
+__device__ __forceinline__ double axpby_elem(double a, double x, double b, double y) { return fma(a, x, b * y); }
+__device__ __forceinline__ void update_xr_elem(double &X, double &R, double P, double S, double K, double alpha,
+                                               double omega)
+{
+    X = fma(omega, S, fma(alpha, P, X));
+    R = fma(-omega, K, S);
+}
+__device__ __forceinline__ double update_p_elem(double P, double R, double D, double beta, double omega)
+{
+    return fma(beta, fma(-omega, D, P), R);
+}
+
 __global__ void k_axpby(double *__restrict__ out, const double *__restrict__ x, double a,
                         const double *__restrict__ y, double b, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = fma(a, x[i], b * y[i]);
+        out[i] = axpby_elem(a, x[i], b, y[i]);
 }
 
 __global__ void k_update_xr(double *__restrict__ X, double *__restrict__ R, const double *__restrict__ P,
@@ -120,9 +180,10 @@ __global__ void k_update_xr(double *__restrict__ X, double *__restrict__ R, cons
                             double omega, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double s = S[i];
-        X[i] = fma(omega, s, fma(alpha, P[i], X[i]));
-        R[i] = fma(-omega, K[i], s);
+        double x = X[i], r;
+        update_xr_elem(x, r, P[i], S[i], K[i], alpha, omega);
+        X[i] = x;
+        R[i] = r;
     }
 }
 
@@ -130,7 +191,40 @@ __global__ void k_update_p(double *__restrict__ P, const double *__restrict__ R,
                            const double *__restrict__ D, double beta, double omega, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        P[i] = fma(beta, fma(-omega, D[i], P[i]), R[i]);
+        P[i] = update_p_elem(P[i], R[i], D[i], beta, omega);
+}
+
+// Multi-instance updates: listed instance k owns blocks first[k]..first[k+1)-1,
+// each covering kVecMultiSpan consecutive doubles of its block vectors.
+__global__ __launch_bounds__(kVecThreads) void k_vec_multi(Group g)
+{
+    const int k = group_find(g.first, g.count, blockIdx.x);
+    const int op = g.aux[k];
+    const Inst1d &d = g.inst[g.list[k]];
+    const long nv = (long)d.N * d.ld;
+    const double alpha = g.scal[4 * k], omega = g.scal[4 * k + 1], beta = g.scal[4 * k + 2];
+    double *R = d.vec + VEC_R * nv, *P = d.vec + VEC_P * nv, *D = d.vec + VEC_D * nv, *S = d.vec + VEC_S * nv;
+    double *K = d.vec + VEC_K * nv, *X = d.vec + VEC_X * nv;
+    const long i0 = (long)(blockIdx.x - g.first[k]) * kVecMultiSpan;
+    const long i1 = min(i0 + kVecMultiSpan, nv);
+    for (long i = i0 + threadIdx.x; i < i1; i += kVecThreads) {
+        if (op == VOP_S_AXPY) {
+            S[i] = axpby_elem(1.0, R[i], -alpha, D[i]);
+        } else if (op == VOP_UPDATE_XR) {
+            double x = X[i], r;
+            update_xr_elem(x, r, P[i], S[i], K[i], alpha, omega);
+            X[i] = x;
+            R[i] = r;
+        } else {
+            P[i] = update_p_elem(P[i], R[i], D[i], beta, omega);
+        }
+    }
+}
+
+hipError_t launch_vec_multi(const Group &g, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vec_multi, dim3(nblocks), dim3(kVecThreads), 0, st, g);
+    return hipGetLastError();
 }
 
 __global__ void k_b_minus(double *__restrict__ out, const double *__restrict__ in,

@@ -227,7 +227,7 @@ struct LineSolver {
     // forward scan's LDS round and enter as late right-hand-side terms: their
     // effect on the carries is linear (multipliers rf_t and rfw_w), so no extra
     // barrier is needed and every copy of a neighbour value is exact.
-    __device__ __forceinline__ void step_delta(T (&u)[C], T pl, T pu, T pr, int M, int periodic)
+    __device__ __forceinline__ void step_delta(T (&u)[C], T (&lo)[C], T pl, T pu, T pr, int M, int periodic)
     {
         const int t = threadIdx.x;
         const int lane = t & (kWave - 1);
@@ -299,8 +299,17 @@ struct LineSolver {
             if (j0 + k == M - 1) d[k] += dM;
         fwd_pass2(d, c);
         backward(d, ytot);
+        // u + lo += d, compensated: the state is the unevaluated sum u + lo
+        // and the rounding error of every update is carried in lo (TwoSum),
+        // so many small increments do not drift by the state's rounding.
 #pragma unroll
-        for (int k = 0; k < C; ++k) u[k] += d[k];
+        for (int k = 0; k < C; ++k) {
+            const T y = d[k] + lo[k];
+            const T s = u[k] + y;
+            const T bb = s - u[k];
+            lo[k] = (u[k] - (s - bb)) + (y - bb);
+            u[k] = s;
+        }
     }
 };
 

@@ -171,4 +171,70 @@ hipError_t launch_b_minus(double *out, const double *in, const double *u0, long 
 hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st);
 hipError_t launch_fill0(double *dst, long n, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Multi-instance launches (batched solves, batch.cpp).
+//
+// Every 1D instance of a batch keeps a device descriptor; a launch covers the
+// instances listed in a Group.  Block b of a launch belongs to the listed
+// instance k with first[k] <= b < first[k+1] (found by binary search over the
+// count+1 prefix), so instances of different sizes share one launch.  The
+// per-element and per-slice arithmetic is the single-instance kernels' own
+// (shared device functions), so an instance's result does not depend on the
+// other instances of the launch.
+// ---------------------------------------------------------------------------
+// Block vectors of a batched instance, in the chunked layout, vector q at
+// vec + q*N*ld.
+enum { VEC_R = 0, VEC_RT = 1, VEC_P = 2, VEC_D = 3, VEC_S = 4, VEC_K = 5, VEC_TM = 6, VEC_X = 7, VEC_COUNT = 8 };
+
+struct Inst1d {
+    LineTab<double> tf;   // fine step tables, FP64 form
+    LineTab<float> tf32;  // fine step tables, FP32 increment form
+    LineTab<double> tc;   // coarse step tables
+    double *vec;          // VEC_COUNT block vectors
+    double *part;         // partial sums of the segmented dots (4*N*bps)
+    long ld;              // slice stride (NT*C of the fine line shape)
+    int N, M, m, c, bps;
+    double w;             // h^d, the weight of the discrete L2 product
+    float pl, pu, pr;     // increment-form stencil of the FP32 fine step
+    int periodic;
+};
+
+struct Group {
+    const Inst1d *inst;   // descriptors of all instances (device)
+    const int *list;      // descriptor index of each listed instance
+    const int *first;     // block prefix, count+1 entries
+    const int *aux;       // per listed instance: fine/sweep {vin, vout}; dots {nq, a[4], b[4]}; vec {op}
+    const double *scal;   // 4 scalars per listed instance: alpha, omega, beta, spare
+    RedOut *red;          // reduction result per listed instance
+    int count;
+};
+constexpr int kDotsAux = 9;
+
+__device__ __forceinline__ int group_find(const int *first, int count, int b)
+{
+    int lo = 0, hi = count;  // first[lo] <= b < first[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Fine apply y = (lam_n - F(lam_{n-1}))_n of vector aux[2k] into vector
+// aux[2k+1] for the listed instances (all of line shape sh); nblocks = the sum
+// of their N.
+hipError_t launch_fine1d_multi(LineShape sh, int fine32, int scheme, const Group &g, int nblocks, hipStream_t st);
+// Coarse sweep of vector aux[2k] into aux[2k+1], one block per listed instance.
+hipError_t launch_sweep1d_multi(LineShape sh, int scheme, const Group &g, hipStream_t st);
+// Segmented dots of aux[9k] vector pairs (aux[9k+1+q], aux[9k+5+q]) per
+// listed instance; g.first is the prefix of bps*N; results into g.red[k].
+hipError_t launch_dots_multi(const Group &g, int nblocks, hipStream_t st);
+// Element-wise updates per listed instance; g.first is the prefix of the
+// blocks given to each instance (kVecMultiSpan doubles per block).
+constexpr int kVecMultiSpan = 256 * 8;
+enum { VOP_S_AXPY = 0, VOP_UPDATE_XR = 1, VOP_UPDATE_P = 2 };
+// (op = aux[k])
+hipError_t launch_vec_multi(const Group &g, int nblocks, hipStream_t st);
+
 }  // namespace pit

@@ -17,6 +17,7 @@
 #include <new>
 #include <vector>
 
+#include "ctx.hpp"
 #include "pit_internal.hpp"
 
 using namespace pit;
@@ -25,19 +26,13 @@ namespace {
 
 thread_local int t_last_hip = 0;
 
-#define PIT_HIP(expr)                                    \
-    do {                                                 \
-        hipError_t e_ = (expr);                          \
-        if (e_ != hipSuccess) {                          \
-            t_last_hip = (int)e_;                        \
-            return PIT_EHIP;                             \
-        }                                                \
-    } while (0)
+}  // namespace
 
-constexpr size_t kAlign = 256;
-constexpr int kSolveVectors = 8;
-constexpr int kMaxAdi = 1024;  // points per axis of the 2D half-step kernels  // R, shadow R, P, D, S, K, temporary, iterate (chunked layout)
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+void pit::set_last_hip(int code) { t_last_hip = code; }
+
+namespace {
+
+constexpr int kMaxAdi = 1024;  // points per axis of the 2D half-step kernels
 
 const LineShape kShapes[] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},    {128, 8},  {256, 4},  {256, 8},
                              {256, 16}, {512, 4}, {512, 8}, {512, 16}, {1024, 4}, {1024, 8}, {1024, 16}};
@@ -75,15 +70,6 @@ LineShape shape_from_env(const char *name, int M)
     return default_shape(M);
 }
 
-// Host-side description of one line operator A = I - theta*L.
-struct LineHost {
-    LineShape sh{0, 0};
-    int M = 0;
-    int cyclic = 0;
-    double inv_den = 0.0, bg = 0.0, iu_last = 0.0;
-    std::vector<double> blob;  // layout of line_tab_view
-    std::vector<float> blob32; // the same tables rounded to FP32
-};
 
 // Build the tables of the line solver for the tridiagonal matrix with
 // sub-diagonal a (coefficient of x_{j-1}), diagonal b and super-diagonal c
@@ -203,75 +189,6 @@ bool build_line(int M, bool periodic, double a, double b, double c, LineShape sh
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct pit_ctx {
-    pit_problem pb;
-    int N = 0, m = 0;
-    pit_stepper fine{}, coarse{};
-    int npts = 0;
-    double hx = 0, hy = 0, w = 0, DT = 0;
-    // 1D line operators
-    LineHost lf;  // fine step matrix
-    LineHost lc;  // coarse step matrix
-    // workspace layout (byte offsets)
-    size_t off_tf = 0, off_tf32 = 0, off_tc = 0, off_vec = 0, off_part = 0, off_red = 0, total = 0;
-    // increment-form stencil (FP32 fine propagator): dt L u = pl(u_{j-1}-u_j) + pu(u_{j+1}-u_j) - pr u_j
-    float pl = 0.f, pu = 0.f, pr = 0.f;
-    int bps = 1;
-    // bound workspace
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-
-    // 2D PR-ADI: x tables (64 lanes x cx points per row) and y row tables,
-    // fine (theta = dt/2) and coarse (theta = DT/(2c)); explicit-part
-    // coefficients: the x half step applies (I + theta Ly), the y half step
-    // (I + theta Lx), each as ed*u + ex*(sum of the two neighbours).
-    AdiShape ash{0, 0, 0};
-    LineHost axf, axc;
-    std::vector<double> ayf, ayc;
-    double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
-    size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
-    int adi_R = 32;  // rows per wavefront in the fine x half step
-    bool dim2() const { return pb.dim == 2; }
-    AdiBuf fbuf(size_t off) const
-    {
-        AdiBuf b{nullptr, nullptr, fine32()};
-        if (b.f32) b.f = reinterpret_cast<float *>(ws + off);
-        else b.d = reinterpret_cast<double *>(ws + off);
-        return b;
-    }
-    double *ctmp(int i) const { return reinterpret_cast<double *>(ws + off_ctmp) + (size_t)i * npts; }
-
-    long ld = 0;  // slice stride of the block vectors inside pit_solve (1D: chunked NT*C, 2D: npts)
-    long nt() const { return (long)N * npts; }
-    long ntc() const { return (long)N * ld; }
-    double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * ntc(); }
-    double *part() const { return reinterpret_cast<double *>(ws + off_part); }
-    RedOut *red() const { return reinterpret_cast<RedOut *>(ws + off_red); }
-    LineTab<float> tab32(const LineHost &L, size_t off) const
-    {
-        LineTab<float> t = line_tab_view<float>(reinterpret_cast<const float *>(ws + off), L.sh.NT, L.sh.C);
-        t.inv_den = (float)L.inv_den;
-        t.bg = (float)L.bg;
-        t.iu_last = (float)L.iu_last;
-        t.cyclic = L.cyclic;
-        t.M = L.M;
-        return t;
-    }
-    bool fine32() const { return fine.prec == PIT_F32; }
-    LineTab<double> tab(const LineHost &L, size_t off) const
-    {
-        LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(ws + off), L.sh.NT, L.sh.C);
-        t.inv_den = L.inv_den;
-        t.bg = L.bg;
-        t.iu_last = L.iu_last;
-        t.cyclic = L.cyclic;
-        t.M = L.M;
-        return t;
-    }
-};
 
 namespace {
 
@@ -481,21 +398,21 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
     return hipSuccess;
 }
 
-// The operators on block vectors of stride ld (chunked inside pit_solve in 1D).
-hipError_t op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal, hipStream_t st)
+}  // namespace
+
+hipError_t pit::op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal,
+                         hipStream_t st)
 {
     if (c->dim2()) return apply_2d(c, lam, y, raw, last, st);
     return fine_launch(c, lam, y, raw, last, internal, st);
 }
 
-hipError_t op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
+hipError_t pit::op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
 {
     if (c->dim2()) return sweep_2d(c, v, z, st);
     return launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), v, z, c->N, c->npts, c->coarse.substeps,
                               c->coarse.scheme, internal, st);
 }
-
-}  // namespace
 
 extern "C" {
 

@@ -60,9 +60,29 @@ class pit_solve_info(ct.Structure):
                 ("n_coarse", ct.c_int32), ("reserved", ct.c_int32)]
 
 
+class pit_server_cfg(ct.Structure):
+    _fields_ = [("arena", ct.c_void_p), ("arena_bytes", ct.c_uint64), ("device", ct.c_int32),
+                ("max_slots", ct.c_int32), ("reserved", ct.c_int32 * 2)]
+
+
+class pit_request(ct.Structure):
+    _fields_ = [("problem", pit_problem), ("N", ct.c_int32), ("m", ct.c_int32), ("fine", pit_stepper),
+                ("coarse", pit_stepper), ("u0", ct.c_void_p), ("X", ct.c_void_p), ("opts", pit_solve_opts)]
+
+
+class pit_result(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("iters", ct.c_int32), ("matvecs", ct.c_int32),
+                ("restarts", ct.c_int32), ("res_norm", ct.c_double), ("t_submit_ms", ct.c_double),
+                ("t_admit_ms", ct.c_double), ("t_done_ms", ct.c_double), ("workspace_bytes", ct.c_uint64),
+                ("hip_error", ct.c_int32), ("reserved", ct.c_int32)]
+
+
 EXPORTS = (
     "pit_create", "pit_destroy", "pit_workspace_bytes", "pit_bind_workspace", "pit_apply_F",
     "pit_coarse_sweep", "pit_solve", "pit_strerror", "pit_last_hip_error", "pit_kernel_shape",
+    "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
+    "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
+    "pit_server_destroy",
 )
 
 _lib = None
@@ -91,6 +111,18 @@ def load(path: str = LIB_PATH):
     lib.pit_strerror.restype = ct.c_char_p
     lib.pit_last_hip_error.restype = ct.c_int
     lib.pit_kernel_shape.argtypes = [vp, ct.POINTER(i32)]
+    lib.pit_batch_create.argtypes = [i32, ct.POINTER(vp)]
+    lib.pit_batch_workspace_bytes.argtypes = [vp]
+    lib.pit_batch_workspace_bytes.restype = sz
+    lib.pit_batch_bind_workspace.argtypes = [vp, vp, sz]
+    lib.pit_batch_destroy.argtypes = [vp]
+    lib.pit_batch_solve.argtypes = [vp, ct.POINTER(vp), i32, ct.POINTER(vp), ct.POINTER(vp),
+                                    ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
+    lib.pit_server_create.argtypes = [ct.POINTER(pit_server_cfg), ct.POINTER(vp)]
+    lib.pit_submit.argtypes = [vp, ct.POINTER(pit_request), ct.POINTER(ct.c_uint64)]
+    lib.pit_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(pit_result)]
+    lib.pit_server_load.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(ct.c_uint64)]
+    lib.pit_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -247,3 +279,141 @@ class Context:
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
                             info.ms_coarse, info.n_fine, info.n_coarse)
+
+
+def _opts(p, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS, stall_window=0):
+    return pit_solve_opts(p.tol if tol is None else tol, restart_tol, max_iter, norm_mode, X0_ZERO, 0,
+                          stall_window, 0)
+
+
+def _aligned(nbytes, device):
+    import torch
+
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    return buf, buf.data_ptr() + (-buf.data_ptr()) % 256
+
+
+class Batch:
+    """pit_batch: many independent solves advanced together (see pitsbicg.h)."""
+
+    def __init__(self, max_count, device=None):
+        lib = load()
+        h = ct.c_void_p()
+        _check(lib.pit_batch_create(int(max_count), ct.byref(h)), "pit_batch_create")
+        self._h = h
+        self.max_count = int(max_count)
+        n = int(lib.pit_batch_workspace_bytes(h))
+        self.ws, base = _aligned(n, device)
+        _check(lib.pit_batch_bind_workspace(h, base, n), "pit_batch_bind_workspace")
+
+    def solve(self, ctxs, u0s, Xs=None, *, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS,
+              stall_window=0, hist_cap=4096, stream=None):
+        """Solve every context's problem; returns (Xs, [SolveInfo])."""
+        import torch
+
+        n = len(ctxs)
+        if Xs is None:
+            Xs = [torch.empty(c.p.N * c.p.npts, dtype=torch.float64, device=u.device) for c, u in zip(ctxs, u0s)]
+        hs = (ct.c_void_p * n)(*[c._h.value for c in ctxs])
+        u = (ct.c_void_p * n)(*[_ptr(x, c.p.npts) for c, x in zip(ctxs, u0s)])
+        x = (ct.c_void_p * n)(*[_ptr(X, c.p.N * c.p.npts) for c, X in zip(ctxs, Xs)])
+        tols = tol if isinstance(tol, (list, tuple)) else [tol] * n
+        opts = (pit_solve_opts * n)(*[_opts(c.p, t, restart_tol, max_iter, norm_mode, stall_window)
+                                      for c, t in zip(ctxs, tols)])
+        hists = [np.zeros(hist_cap, dtype=np.float64) for _ in range(n)]
+        infos = (pit_solve_info * n)()
+        for i in range(n):
+            infos[i].history = hists[i].ctypes.data_as(ct.POINTER(ct.c_double))
+            infos[i].history_cap = hist_cap
+        rc = load().pit_batch_solve(self._h, hs, n, u, x, opts, infos, _stream(stream))
+        if rc in (EINVAL, EHIP, ENOMEM):
+            raise PitError(rc, "pit_batch_solve")
+        out = [SolveInfo(f.status, f.iters, f.matvecs, f.restarts, f.res_norm, hists[i][: f.history_len].copy(),
+                         f.ms_total, 0.0, 0.0, f.n_fine, f.n_coarse) for i, f in enumerate(infos)]
+        return Xs, out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pit_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    matvecs: int
+    restarts: int
+    res_norm: float
+    t_submit_ms: float
+    t_admit_ms: float
+    t_done_ms: float
+    workspace_bytes: int
+    hip_error: int
+
+    @property
+    def latency_ms(self):
+        return self.t_done_ms - self.t_submit_ms
+
+
+class Server:
+    """pit_server: request loop with HBM-budget admission and continuous batching.
+
+    The arena (the HBM budget) is a torch uint8 tensor owned here."""
+
+    def __init__(self, arena_bytes, max_slots=256, device=None):
+        import torch
+
+        dev = torch.device(device or "cuda")
+        self.arena, base = _aligned(int(arena_bytes), dev)
+        cfg = pit_server_cfg(base, int(arena_bytes), dev.index or 0, int(max_slots))
+        h = ct.c_void_p()
+        _check(load().pit_server_create(ct.byref(cfg), ct.byref(h)), "pit_server_create")
+        self._h = h
+
+    def submit(self, p, u0, X, *, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS, stall_window=0):
+        """Queue a solve of workloads.Problem p; u0 and X are device tensors the caller keeps alive
+        (their pending writes must be complete: synchronize first)."""
+        r = pit_request()
+        r.problem = make_problem(p)
+        r.N, r.m = p.N, p.m
+        r.fine = pit_stepper(p.fine, p.m, p.prec, 0)
+        r.coarse = pit_stepper(p.coarse, p.c, F64, 0)
+        r.u0 = _ptr(u0, p.npts)
+        r.X = _ptr(X, p.N * p.npts)
+        r.opts = _opts(p, tol, restart_tol, max_iter, norm_mode, stall_window)
+        t = ct.c_uint64()
+        _check(load().pit_submit(self._h, ct.byref(r), ct.byref(t)), "pit_submit")
+        return int(t.value)
+
+    def poll(self, ticket):
+        """None while pending, else the Result."""
+        r = pit_result()
+        rc = load().pit_poll(self._h, ct.c_uint64(ticket), ct.byref(r))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "pit_poll")
+        return Result(r.status, r.iters, r.matvecs, r.restarts, r.res_norm, r.t_submit_ms, r.t_admit_ms,
+                      r.t_done_ms, int(r.workspace_bytes), r.hip_error)
+
+    def load(self):
+        q, r, u = ct.c_int32(), ct.c_int32(), ct.c_uint64()
+        _check(load().pit_server_load(self._h, ct.byref(q), ct.byref(r), ct.byref(u)), "pit_server_load")
+        return int(q.value), int(r.value), int(u.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pit_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -33,6 +33,9 @@ def test_struct_layouts_match_header():
     assert ct.sizeof(P.pit_stepper) == 16
     assert ct.sizeof(P.pit_solve_opts) == 8 * 2 + 4 * 6
     assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 3
+    assert ct.sizeof(P.pit_server_cfg) == 8 + 8 + 4 * 4
+    assert ct.sizeof(P.pit_request) == ct.sizeof(P.pit_problem) + 4 * 2 + 16 * 2 + 8 * 2 + ct.sizeof(P.pit_solve_opts)
+    assert ct.sizeof(P.pit_result) == 4 * 4 + 8 * 4 + 8 + 4 * 2
 
 
 def create(p, fine=None, coarse=None, N=None, m=None):
@@ -112,3 +115,27 @@ def test_kernel_shapes_cover_the_line():
         assert out[0] * out[1] >= M and out[2] * out[3] >= M
         assert out[0] % 64 == 0 and out[0] <= 1024
         lib.pit_destroy(h)
+
+
+def test_batch_and_server_validate_on_the_host():
+    lib = P.load()
+    h = ct.c_void_p()
+    assert lib.pit_batch_create(0, ct.byref(h)) == P.EINVAL
+    assert lib.pit_batch_create(4, ct.byref(h)) == P.OK
+    need = lib.pit_batch_workspace_bytes(h)
+    assert need > 0
+    assert lib.pit_batch_bind_workspace(h, None, need) == P.EINVAL
+    assert lib.pit_batch_bind_workspace(h, ct.c_void_p(256 * 1000 + 8), need) == P.EINVAL  # misaligned
+    assert lib.pit_batch_bind_workspace(h, ct.c_void_p(256 * 1000), 16) == P.ENOMEM
+    # unbound engine: rejected before any device work
+    assert lib.pit_batch_solve(h, None, 0, None, None, None, None, None) == P.EINVAL
+    lib.pit_batch_destroy(h)
+    cfg = P.pit_server_cfg(None, 1 << 20, 0, 4)
+    s = ct.c_void_p()
+    assert lib.pit_server_create(ct.byref(cfg), ct.byref(s)) == P.EINVAL  # no arena
+    cfg = P.pit_server_cfg(256 * 1000, 1 << 20, 0, 0)
+    assert lib.pit_server_create(ct.byref(cfg), ct.byref(s)) == P.EINVAL  # no slots
+    cfg = P.pit_server_cfg(256 * 1000, 1024, 0, 4)
+    assert lib.pit_server_create(ct.byref(cfg), ct.byref(s)) == P.ENOMEM  # arena below its own buffers
+    assert lib.pit_submit(None, None, None) == P.EINVAL
+    assert lib.pit_poll(None, 1, None) == P.EINVAL

@@ -1,0 +1,350 @@
+"""GPU: batched solves (pit_batch_solve) and the request server (pit_submit /
+pit_poll), through the C ABI.
+
+Every instance of a batch follows pit_solve's control flow, so each is
+checked against the oracle's Algorithm 1 (FP64: same iteration count, 1e-10
+relative) or against the FP64 serial fine trajectory (FP32 fine propagator:
+1e-5 relative, stiffness-aware as in the single-instance tests), and against
+pit_solve on the same problem (the same iterations; the solutions to the
+FP64 parity bar, since the batched kernels may contract multiply-adds
+differently from the single-instance ones).  An instance solved alone,
+inside a batch and inside a served mix must give identical bits.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2203_10148_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_10148_amd import pitsbicg as P
+
+    P.load()  # fail loudly if the HIP library is missing
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def P_():
+    from paper_2203_10148_amd import pitsbicg as P
+
+    return P
+
+
+def u0_of(p, seed=3):
+    if p.name.startswith("c1_"):
+        return wl.u0_for(p)
+    if p.dim == 2:
+        return wl.u0_bumps(p, seed)
+    return wl.u0_fourier(p, seed) if p.bc == wl.PERIODIC else wl.u0_sines(p)
+
+
+def p1d(M, bc, N, m, fine=wl.CN, c=2, coarse=wl.IE, nu=1e-3, a=1.0, prec=wl.F64, T=1.0, name=""):
+    return wl.Problem(dim=1, M=(M, 1), bc=bc, nu=nu, adv=(a if bc == wl.PERIODIC else 0.0, 0.0), T=T, N=N, m=m,
+                      fine=fine, c=c, coarse=coarse, prec=prec, tol=1e-10, name=name)
+
+
+def p2d(Mx, My, N, m, prec, c=1):
+    return wl.Problem(dim=2, M=(Mx, My), bc=wl.DIRICHLET, nu=0.05, react=0.2, T=0.05 * N, N=N, m=m, fine=wl.ADI,
+                      c=c, coarse=wl.ADI, prec=prec, tol=1e-10, name=f"adi{Mx}x{My}")
+
+
+# instances of different line shapes, sizes, schemes and boundary conditions
+FP64_SET = [
+    wl.C1,
+    p1d(200, wl.PERIODIC, 6, 7, nu=1e-2, a=0.5, name="p200"),
+    p1d(1000, wl.PERIODIC, 12, 20, name="p1000"),
+    p1d(777, wl.DIRICHLET, 9, 20, name="d777"),
+    p1d(3000, wl.PERIODIC, 5, 10, nu=3e-4, a=1.5, name="p3000"),
+    p1d(5000, wl.PERIODIC, 4, 6, name="p5000"),
+]
+
+
+def batch_solve(problems, tol=None, **kw):
+    P = P_()
+    ctxs = [P.Context(p) for p in problems]
+    u0s = [dev(u0_of(p)) for p in problems]
+    b = P.Batch(len(problems))
+    Xs, infos = b.solve(ctxs, u0s, tol=tol, **kw)
+    return [host(X) for X in Xs], infos
+
+
+def test_batch_fp64_matches_oracle_and_pit_solve():
+    P = P_()
+    say("batch fp64 vs oracle")
+    Xs, infos = batch_solve(FP64_SET, tol=1e-10)
+    for p, X, inf in zip(FP64_SET, Xs, infos):
+        o = orc.Oracle(**p.oracle_kwargs())
+        u0 = u0_of(p)
+        Xo, io = o.pitsbicg(u0, tol=1e-10)
+        c = P.Context(p)
+        Xs1, i1 = c.solve(dev(u0), tol=1e-10)
+        Xs1 = host(Xs1)
+        print(f"{p.name or p.M}: batch iters={inf.iters} oracle={io.iters} pit_solve={i1.iters} "
+              f"vs oracle {relerr(X, Xo):.2e} vs pit_solve {relerr(X, Xs1):.2e}", flush=True)
+        assert inf.status == io.status == orc.OK
+        assert abs(inf.iters - io.iters) <= 1
+        assert inf.iters == i1.iters and inf.matvecs == i1.matvecs and inf.restarts == i1.restarts
+        assert relerr(X, Xo) < 1e-9
+        assert relerr(X, Xs1) < 1e-10
+        assert relerr(X, o.serial(u0)) < 1e-8
+
+
+def test_batch_restart_and_breakdown_paths():
+    """Restart every iteration (epsilon_0 huge), G = F (the half step solves
+    the system: <K,K> = 0) and a single slice, against pit_solve and the
+    oracle."""
+    P = P_()
+    say("batch special paths")
+    cases = [(wl.C1.with_(N=8, name="restart"), dict(restart_tol=1e30, max_iter=100)),
+             (wl.C1.with_(N=8, c=64, name="g_eq_f"), dict()),
+             (wl.C1.with_(N=1, name="one_slice"), dict())]
+    probs = [c for c, _ in cases]
+    for (p, kw) in cases:
+        Xs, infos = batch_solve([p], tol=1e-12, **kw)
+        X, inf = Xs[0], infos[0]
+        c = P.Context(p)
+        u0 = u0_of(p)
+        Xp, ip = c.solve(dev(u0), tol=1e-12, **kw)
+        o = orc.Oracle(**p.oracle_kwargs())
+        Xo, io = o.pitsbicg(u0, tol=1e-12, eps0=kw.get("restart_tol", 1e-30), max_iter=kw.get("max_iter"))
+        print(f"{p.name}: iters {inf.iters}/{ip.iters}/{io.iters} restarts {inf.restarts}/{ip.restarts}/"
+              f"{io.restarts} vs pit_solve {relerr(X, host(Xp)):.2e}", flush=True)
+        assert inf.status == ip.status == io.status
+        assert inf.iters == ip.iters == io.iters and inf.restarts == ip.restarts == io.restarts
+        assert inf.matvecs == ip.matvecs
+        assert relerr(X, host(Xp)) < 1e-10
+        assert relerr(X, Xo) < 1e-10
+    # all three together: the same bits as alone
+    Xs, infos = batch_solve(probs[1:], tol=1e-12)
+    for p, X in zip(probs[1:], Xs):
+        Xa, _ = batch_solve([p], tol=1e-12)
+        assert np.array_equal(X, Xa[0])
+
+
+MIX = [
+    wl.C1.with_(prec=wl.F32, name="c1_f32"),
+    p1d(1000, wl.PERIODIC, 12, 20, prec=wl.F32, name="p1000_f32"),
+    p1d(777, wl.DIRICHLET, 9, 20, name="d777"),
+    p2d(24, 20, 4, 3, wl.F64),
+    p2d(100, 70, 3, 4, wl.F32, c=2),
+]
+
+
+def fp32_bound(p):
+    # the single-instance FP32 bound: 1e-5, relaxed in proportion to the
+    # stiffness s = nu dt / h^2 beyond 64 (1D) and rho = theta nu / h^2 beyond 16 (2D)
+    if p.dim == 1:
+        h = (p.length[0] / p.M[0]) if p.bc == wl.PERIODIC else p.length[0] / (p.M[0] + 1)
+        s = p.nu * (p.T / p.N / p.m) / h ** 2
+        return 1e-5 * max(1.0, s / 64)
+    h = p.length[0] / (p.M[0] + 1)
+    rho = 0.5 * (p.T / p.N / p.m) * p.nu / h ** 2
+    return 1e-5 * max(1.0, rho / 16)
+
+
+def test_batch_mix_with_fp32_and_2d():
+    P = P_()
+    say("batch mix 1D/2D/fp32")
+    Xs, infos = batch_solve(MIX, tol=1e-9, stall_window=10)
+    for p, X, inf in zip(MIX, Xs, infos):
+        u0 = u0_of(p)
+        o = orc.Oracle(**p.oracle_kwargs())
+        serial = o.serial(u0)
+        c = P.Context(p)
+        Xp, ip = c.solve(dev(u0), tol=1e-9, stall_window=10)
+        Xp = host(Xp)
+        err = relerr(X, serial)
+        print(f"{p.name}: status {inf.status} iters {inf.iters}/{ip.iters} vs serial {err:.2e} "
+              f"vs pit_solve {relerr(X, Xp):.2e}", flush=True)
+        assert inf.iters == ip.iters and inf.status == ip.status
+        if p.prec == wl.F64:
+            assert inf.status == orc.OK and err < 1e-8
+        else:
+            assert inf.status in (orc.OK, orc.ENOCONV) and err < fp32_bound(p)
+        assert relerr(X, Xp) < (1e-10 if p.prec == wl.F64 else fp32_bound(p))
+
+
+def test_alone_equals_batched_bitwise():
+    say("alone vs batched bits")
+    probs = FP64_SET[:4] + MIX
+    Xs, infos = batch_solve(probs, tol=1e-9, stall_window=10)
+    for p, X, inf in zip(probs, Xs, infos):
+        Xa, ia = batch_solve([p], tol=1e-9, stall_window=10)
+        assert ia[0].iters == inf.iters and ia[0].status == inf.status
+        assert np.array_equal(Xa[0], X), p.name
+        assert np.array_equal(ia[0].history, inf.history)
+
+
+def test_c4_full_batch():
+    """The 64-instance batch at full size (FP32 fine, tol 1e-8).  Algorithm 1
+    converges for most instances; a few strongly advection-dominated ones
+    (cell Peclet up to 26) make no progress, as the FP64 oracle does on them
+    (see the next test), and must end with PIT_ENOCONV from the stagnation
+    rule.  Every converged instance is within its FP32 bound of the FP64
+    serial trajectory on its first 4 slices, the six cheapest on all slices,
+    and three instances alone give the batch's bits."""
+    P = P_()
+    say("c4 full batch")
+    insts = wl.c4_batch()
+    probs = [p for p, _ in insts]
+    ctxs = [P.Context(p) for p in probs]
+    u0h = [wl.u0_fourier(p, s) for p, s in insts]
+    u0s = [dev(u) for u in u0h]
+    b = P.Batch(len(probs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs, infos = b.solve(ctxs, u0s, tol=1e-8, stall_window=10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    conv = [i for i, inf in enumerate(infos) if inf.status == orc.OK]
+    # instances whose residual went below 1e-6 (converged, or stagnated at the
+    # FP32 rounding floor before reaching 1e-8)
+    low = [i for i, inf in enumerate(infos) if inf.history.min() <= 1e-6]
+    print(f"c4 batch: {dt * 1e3:.1f} ms, {len(conv)} of {len(probs)} reached tol, {len(low)} below 1e-6", flush=True)
+    for i, inf in enumerate(infos):
+        print(f"  inst {i}: M={probs[i].M[0]} N={probs[i].N} m={probs[i].m} nu={probs[i].nu:.1e} "
+              f"a={probs[i].adv[0]:.2f} status={inf.status} iters={inf.iters} min res={inf.history.min():.1e}",
+              flush=True)
+        assert inf.status in (orc.OK, orc.ENOCONV), (i, inf.status)
+    cost = [probs[i].N * probs[i].m * probs[i].M[0] for i in low]
+    cheap = {low[j] for j in np.argsort(cost)[:6]}
+    for i in low:
+        p, X = probs[i], host(Xs[i]).reshape(probs[i].N, -1)
+        K = 4
+        head = orc.Oracle(**p.with_(N=K, T=p.T * K / p.N).oracle_kwargs()).serial(u0h[i]).reshape(K, -1)
+        e = relerr(X[:K], head)
+        assert e < fp32_bound(p), (i, e)
+        if i in cheap:
+            full = orc.Oracle(**p.oracle_kwargs()).serial(u0h[i]).reshape(p.N, -1)
+            ef = relerr(X, full)
+            print(f"inst {i}: full trajectory err {ef:.2e}", flush=True)
+            assert ef < fp32_bound(p), (i, ef)
+    for i in (0, 17, 42):
+        Xa, ia = P.Batch(1).solve([ctxs[i]], [u0s[i]], tol=1e-8, stall_window=10)
+        assert ia[0].iters == infos[i].iters
+        assert torch.equal(Xa[0], Xs[i]), i
+
+
+def test_c4_nonconverging_instance_follows_the_oracle():
+    """Instance 14 of the batch (M 531, nu 1.3e-4, a 1.83: cell Peclet 26):
+    Algorithm 1 stagnates near 1e-2 and then grows, in the FP64 oracle and on
+    the GPU alike; both stop at max_iter with PIT_ENOCONV and their residual
+    histories agree over the first iterations."""
+    P = P_()
+    say("c4 non-converging instance")
+    p, seed = wl.c4_batch()[14]
+    p = p.with_(prec=wl.F64)
+    u0 = wl.u0_fourier(p, seed)
+    _, io = orc.Oracle(**p.oracle_kwargs()).pitsbicg(u0, tol=1e-8, max_iter=16)
+    _, ig = P.Context(p).solve(dev(u0), tol=1e-8, max_iter=16)
+    print(f"oracle {np.array2string(io.history[:8], precision=4)}\ngpu    "
+          f"{np.array2string(ig.history[:8], precision=4)}", flush=True)
+    assert io.status == ig.status == orc.ENOCONV
+    assert np.allclose(ig.history[:6], io.history[:6], rtol=1e-6)
+    assert ig.history[-1] > 1e-3 and io.history[-1] > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def serve(problems, arena_bytes=8 << 30, max_slots=64, sequential=False, tol=1e-9):
+    """Submit every problem (all at once, or one after the other) and wait."""
+    P = P_()
+    srv = P.Server(arena_bytes, max_slots=max_slots)
+    u0s = [dev(u0_of(p)) for p in problems]
+    Xs = [torch.full((p.N * p.npts,), float("nan"), dtype=torch.float64, device="cuda") for p in problems]
+    torch.cuda.synchronize()
+    results = [None] * len(problems)
+    peak = 0
+    t_end = time.time() + 90
+    if sequential:
+        for i, p in enumerate(problems):
+            t = srv.submit(p, u0s[i], Xs[i], tol=tol, stall_window=10)
+            while results[i] is None and time.time() < t_end:
+                results[i] = srv.poll(t)
+                time.sleep(0.001)
+    else:
+        tickets = [srv.submit(p, u0s[i], Xs[i], tol=tol, stall_window=10) for i, p in enumerate(problems)]
+        while any(r is None for r in results) and time.time() < t_end:
+            peak = max(peak, srv.load()[2])
+            for i, t in enumerate(tickets):
+                if results[i] is None:
+                    results[i] = srv.poll(t)
+            time.sleep(0.001)
+    srv.close()
+    assert all(r is not None for r in results), "server did not finish in time"
+    return [host(X) for X in Xs], results, peak
+
+
+def test_server_alone_equals_mix():
+    say("server alone vs mix")
+    probs = FP64_SET[:3] + MIX
+    Xm, rm, _ = serve(probs)
+    Xa, ra, _ = serve(probs, sequential=True)
+    for p, a, b, r1, r2 in zip(probs, Xa, Xm, ra, rm):
+        print(f"{p.name}: status {r1.status}/{r2.status} iters {r1.iters}/{r2.iters} "
+              f"latency {r1.latency_ms:.1f}/{r2.latency_ms:.1f} ms", flush=True)
+        assert r1.status == r2.status and r1.iters == r2.iters
+        assert r1.status in (orc.OK, orc.ENOCONV)
+        assert np.array_equal(a, b), p.name
+    # and the same bits as the batch engine called directly
+    Xb, ib = batch_solve(probs, tol=1e-9, stall_window=10)
+    for a, b in zip(Xb, Xm):
+        assert np.array_equal(a, b)
+
+
+def test_server_admission_by_budget():
+    """An arena that holds about two of the requests at a time: all finish,
+    later ones wait for memory, and the arena in use never exceeds it."""
+    P = P_()
+    say("server budget")
+    probs = [p1d(4096, wl.PERIODIC, 64, 16, prec=wl.F32, name=f"b{i}", nu=1e-3 * (i + 1)) for i in range(6)]
+    ws = P.Context(probs[0], bind=False).workspace_bytes
+    own = int(P.load().pit_batch_workspace_bytes(P.Batch(64)._h)) + 256  # the engine's buffers, 64 slots
+    arena = int(own + 2.5 * (ws + 256))
+    X, res, peak = serve(probs, arena_bytes=arena, max_slots=64)
+    for p, r in zip(probs, res):
+        assert r.status in (orc.OK, orc.ENOCONV)
+    assert peak <= arena
+    admits = sorted(r.t_admit_ms - r.t_submit_ms for r in res)
+    print(f"waits for admission (ms): {[round(a, 2) for a in admits]}", flush=True)
+    assert admits[-1] > admits[0]  # some requests waited for memory
+    # a request larger than the arena is refused with PIT_ENOMEM, not queued forever
+    srv = P.Server(own + (1 << 20), max_slots=64)
+    p = probs[0]
+    u0, Xo = dev(u0_of(p)), torch.empty(p.N * p.npts, dtype=torch.float64, device="cuda")
+    t = srv.submit(p, u0, Xo)
+    r = srv.poll(t)
+    srv.close()
+    assert r is not None and r.status == P.ENOMEM
