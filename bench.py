@@ -193,7 +193,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c1-c3: one solve per step; c4: the 64-instance batch per step; c5: a served "
+                         "Poisson stream (one pass of --requests requests)")
+    ap.add_argument("--requests", type=int, default=120, help="c5: how many requests of the stream to serve")
+    ap.add_argument("--rate", type=float, default=200.0, help="c5: arrival rate (requests/s)")
+    ap.add_argument("--arena-gib", type=float, default=160.0, help="c5: HBM budget of the server (GiB)")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -232,6 +237,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "c4":
+        return bench_batch(args, dev)
+    if args.workload == "c5":
+        return bench_serve(args, dev)
     p = workload(args.workload, args.prec)
     args.prec = "f32" if p.prec == wl.F32 else "f64"
     u0h = wl.u0_for(p)
@@ -352,6 +361,146 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, dev):
+    """The 64-instance batch (FP32 fine, tol 1e-8): a step is one batched solve
+    of all instances; also the single-instance solves, plain FP64 and FP32, one
+    after the other (the batch's baseline)."""
+    import numpy as np
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    insts = wl.c4_batch()
+    probs = [p for p, _ in insts]
+    u0h = [wl.u0_fourier(p, s) for p, s in insts]
+    log(f"[bench] c4: {len(probs)} instances, {sum(p.cells_per_apply for p in probs):.3e} cell-updates per apply round")
+    ctxs = [P.Context(p, device=dev) for p in probs]
+    u0s = [torch.as_tensor(u, dtype=torch.float64, device=dev) for u in u0h]
+    Xs = [torch.empty(p.N * p.npts, dtype=torch.float64, device=dev) for p in probs]
+    b = P.Batch(len(probs), device=dev)
+
+    def step():
+        return b.solve(ctxs, u0s, Xs, tol=1e-8, stall_window=10)[1]
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    cells = sum(i.n_fine * p.cells_per_apply for i, p in zip(infos, probs))
+    st = [i.status for i in infos]
+    log(f"[bench] batch: {ms:.1f} ms per batched solve, {st.count(0)} of {len(st)} reached tol")
+
+    def singles(prec):
+        tot, its = 0.0, 0
+        for p, u in zip(probs, u0s):
+            c = P.Context(p.with_(prec=prec), device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, inf = c.solve(u, tol=1e-8, stall_window=10)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t
+            its += inf.iters
+            c.close()
+        return tot, its
+
+    s64, it64 = singles(wl.F64)
+    log(f"[bench] single-instance plain FP64: {s64 * 1e3:.1f} ms summed")
+    s32, it32 = singles(wl.F32)
+    log(f"[bench] single-instance FP32: {s32 * 1e3:.1f} ms summed")
+    out = {
+        "metric": "fine cell-updates/s, 64-instance batched PiTSBiCG (FP32 fine, tol 1e-8), 1 GPU",
+        "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4_batch64", "instances": len(probs), "seed": 4, "tol": 1e-8, "fine_prec": "f32",
+                   "stall_window": 10},
+        "roofline": None,
+        "batch": {"makespan_ms": ms, "reached_tol": st.count(0), "stalled": st.count(-4),
+                  "iters": [i.iters for i in infos],
+                  "sum_single_fp64_ms": s64 * 1e3, "sum_single_fp64_iters": it64,
+                  "sum_single_fp32_ms": s32 * 1e3, "sum_single_fp32_iters": it32,
+                  "speedup_vs_single_fp64": s64 * 1e3 / ms, "speedup_vs_single_fp32": s32 * 1e3 / ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, dev):
+    """A served stream: the first --requests requests of the Poisson stream
+    (70% 1D advection-diffusion, 30% 2D heat, FP32 fine, tol 1e-8), submitted
+    at their arrival times; latency is arrival to completion."""
+    import numpy as np
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    reqs = wl.c5_requests(rate=args.rate)[: args.requests]
+    log(f"[bench] c5: {len(reqs)} requests at {args.rate}/s, arena {args.arena_gib} GiB")
+    u0s, Xs = [], []
+    for _, p, seed in reqs:
+        u = wl.u0_bumps(p, seed) if p.dim == 2 else wl.u0_fourier(p, seed)
+        u0s.append(torch.as_tensor(u, dtype=torch.float64, device=dev))
+        Xs.append(torch.empty(p.N * p.npts, dtype=torch.float64, device=dev))
+    srv = P.Server(int(args.arena_gib * 2**30), max_slots=256, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets, results = [], [None] * len(reqs)
+    nxt, last_log = 0, t0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt][0] <= now:
+            _, p, _ = reqs[nxt]
+            tickets.append(srv.submit(p, u0s[nxt], Xs[nxt], tol=1e-8, stall_window=10))
+            nxt += 1
+        for i, t in enumerate(tickets):
+            if results[i] is None:
+                results[i] = srv.poll(t)
+        done = sum(r is not None for r in results)
+        if time.perf_counter() - last_log > 5.0:
+            q, r, used = srv.load()
+            log(f"[bench] t={now:.1f}s submitted {nxt} done {done} queued {q} running {r} arena {used / 2**30:.1f} GiB")
+            last_log = time.perf_counter()
+        if done == len(reqs):
+            break
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.latency_ms for r in results])
+    wait = np.array([r.t_admit_ms - r.t_submit_ms for r in results])
+    dims = np.array([p.dim for _, p, _ in reqs])
+    st = [r.status for r in results]
+    cells = sum(r.matvecs * p.cells_per_apply for r, (_, p, _) in zip(results, reqs))
+    # the server clock starts at creation; first arrival to last completion
+    span = (max(r.t_done_ms for r in results) - min(r.t_submit_ms for r in results)) / 1e3
+
+    def pct(a, q):
+        return float(np.percentile(a, q)) if len(a) else None
+
+    out = {
+        "metric": "served PiTSBiCG solves/s with p50/p99 latency (FP32 fine, tol 1e-8), 1 GPU",
+        "value": len(reqs) / span, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5_serving", "requests": len(reqs), "rate_per_s": args.rate, "seed": 5,
+                   "arena_gib": args.arena_gib, "max_slots": 256, "tol": 1e-8},
+        "roofline": None,
+        "serving": {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": float(lat.max()),
+                    "p50_1d_ms": pct(lat[dims == 1], 50), "p99_1d_ms": pct(lat[dims == 1], 99),
+                    "p50_2d_ms": pct(lat[dims == 2], 50), "p99_2d_ms": pct(lat[dims == 2], 99),
+                    "p50_admission_wait_ms": pct(wait, 50), "p99_admission_wait_ms": pct(wait, 99),
+                    "span_s": span, "fine_cell_updates_per_s": cells / span,
+                    "reached_tol": st.count(0), "stalled": st.count(-4), "other_status": len(st) - st.count(0) - st.count(-4)},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -105,6 +105,7 @@ struct Lane {
     RedOut *h_red = nullptr;
     std::vector<Inst *> members;
     bool busy = false;
+    bool kind2d = false;
     uint64_t seq = 0;
 };
 
@@ -222,29 +223,54 @@ class Engine {
             complete(L, finished);
             progress = true;
         }
+        // Lanes: when both kinds are running, 1D rounds and 2D instances each
+        // keep half of the lanes, so neither starves the other; otherwise
+        // one kind may use all of them.
+        bool has1 = false, has2 = false;
+        for (const Inst *in : active_) (in->dim2() ? has2 : has1) = true;
+        int busy1 = 0, busy2 = 0;
+        for (const auto &L : lanes_)
+            if (L.busy) (L.kind2d ? busy2 : busy1)++;
+        const int cap1 = has2 ? kLanes / 2 : kLanes, cap2 = has1 ? kLanes / 2 : kLanes;
+        // 1D instances: the ready ones in groups of similar expected phase
+        // length (powers of two), so a short phase does not wait for the
+        // longest sweep of the round; groups are merged down to the free lanes.
+        std::map<int, std::vector<Inst *>, std::greater<int>> buckets;
+        for (Inst *in : active_)
+            if (!in->in_flight && !in->dim2()) buckets[(int)std::floor(std::log2(phase_us(in)))].push_back(in);
+        std::vector<std::vector<Inst *>> groups;
+        for (auto &kv : buckets) groups.push_back(std::move(kv.second));
+        int free1 = 0;
+        for (const auto &L : lanes_)
+            if (!L.busy) free1++;
+        free1 = std::min(free1, cap1 - busy1);
+        while ((int)groups.size() > std::max(free1, 1)) {
+            auto last = std::move(groups.back());
+            groups.pop_back();
+            groups.back().insert(groups.back().end(), last.begin(), last.end());
+        }
+        if (free1 > 0) {
+            for (auto &g : groups) {
+                Lane *L = free_lane();
+                if (!L) break;
+                int rc = issue_batch(*L, g);
+                if (rc) return rc;
+                start(*L, g, false);
+                progress = true;
+            }
+        }
         // 2D instances: one lane each
         for (Inst *in : active_) {
             if (in->in_flight || !in->dim2()) continue;
+            if (busy2 >= cap2) break;
             Lane *L = free_lane();
             if (!L) break;
             std::vector<Inst *> one{in};
             int rc = issue_single(*L, in);
             if (rc) return rc;
-            start(*L, one);
+            start(*L, one, true);
+            busy2++;
             progress = true;
-        }
-        // 1D instances: all ready ones together
-        std::vector<Inst *> ready;
-        for (Inst *in : active_)
-            if (!in->in_flight && !in->dim2()) ready.push_back(in);
-        if (!ready.empty()) {
-            Lane *L = free_lane();
-            if (L) {
-                int rc = issue_batch(*L, ready);
-                if (rc) return rc;
-                start(*L, ready);
-                progress = true;
-            }
         }
         return PIT_OK;
     }
@@ -254,16 +280,6 @@ class Engine {
         for (const auto &L : lanes_)
             if (L.busy) return true;
         return false;
-    }
-
-    // Wait until the oldest running phase ends (no busy lanes: returns at once).
-    int wait_oldest()
-    {
-        const Lane *o = nullptr;
-        for (const auto &L : lanes_)
-            if (L.busy && (!o || L.seq < o->seq)) o = &L;
-        if (o) PIT_HIP(hipEventSynchronize(o->ev));
-        return PIT_OK;
     }
 
     // After a HIP failure: finish every active instance with PIT_EHIP once the
@@ -310,6 +326,22 @@ class Engine {
         bound_ = false;
     }
 
+    // Expected length of a 1D instance's next phase (microseconds, rough):
+    // a fine apply is m chained line solves, a coarse sweep (N-1)c of them,
+    // a line solve about (0.5 + M/8192) us; the other phases are short.
+    static double phase_us(const Inst *in)
+    {
+        const pit_ctx *c = in->ctx;
+        const double solve = 0.5 + c->npts / 8192.0;
+        const double sweep = (double)(c->N - 1) * c->coarse.substeps * solve;
+        switch (in->ph) {
+        case PH_INIT: return 2.0 + sweep;
+        case PH_A:
+        case PH_B: return 2.0 + c->m * solve + sweep;
+        default: return 2.0;
+        }
+    }
+
     Lane *free_lane()
     {
         for (auto &L : lanes_)
@@ -317,10 +349,11 @@ class Engine {
         return nullptr;
     }
 
-    void start(Lane &L, const std::vector<Inst *> &members)
+    void start(Lane &L, const std::vector<Inst *> &members, bool kind2d)
     {
         L.members = members;
         L.busy = true;
+        L.kind2d = kind2d;
         L.seq = ++seq_;
         for (Inst *in : members) in->in_flight = true;
     }
@@ -870,10 +903,9 @@ int pit_batch_solve(pit_batch *b, pit_ctx *const *ctxs, int32_t count, const dou
         }
         for (Inst *in : finished) in->t_done = ms_since(t0);
         finished.clear();
-        if (!progress && (rc = b->eng.wait_oldest())) {
-            b->eng.fail_all(pit_last_hip_error(), finished);
-            break;
-        }
+        // nothing finished or started: look again shortly (every lane is
+        // polled, so a short phase on one lane is not held up by a long one)
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(10));
     }
     for (Inst *in : finished) in->t_done = ms_since(t0);
     int first_bad = PIT_OK;

@@ -189,12 +189,25 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
-    double u[C], va[C], vb[C];
+    // With 1024 threads (128 registers per lane) and 8 points per thread a
+    // second prefetch buffer does not fit; one is enough there, since v_n is
+    // only needed after the c solves of the step.
+    constexpr bool kTwoBuffers = NT * C <= 4096;
+    double u[C], va[C];
     load_chunk<NT, C, TR>(v, t, M, u);
     zero_pads<C>(t, M, u);
     load_chunk<NT, C, TR>(v + (size_t)min(1, N - 1) * ld, t, M, va);
-    load_chunk<NT, C, TR>(v + (size_t)min(2, N - 1) * ld, t, M, vb);
     store_chunk<NT, C, TR>(z, t, M, u);
+    if constexpr (!kTwoBuffers) {
+        for (int n = 1; n < N; ++n) {
+            coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
+            load_chunk<NT, C, TR>(v + (size_t)min(n + 1, N - 1) * ld, t, M, va);
+            store_chunk<NT, C, TR>(z + (size_t)n * ld, t, M, u);
+        }
+        return;
+    }
+    double vb[C];
+    load_chunk<NT, C, TR>(v + (size_t)min(2, N - 1) * ld, t, M, vb);
     for (int n = 1; n < N; n += 2) {
         coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
         load_chunk<NT, C, TR>(v + (size_t)min(n + 2, N - 1) * ld, t, M, va);

@@ -45,7 +45,9 @@ bool shape_supported(LineShape s)
 }
 
 // Default shape: eight points per thread once the line is long enough, the
-// thread count growing with M; sixteen per thread above 8192 points.
+// thread count growing with M; sixteen per thread above 4096 points (with
+// 1024 threads a lane has only 128 registers, too few for 8 FP64 points of
+// state, prefetch and tables).
 LineShape default_shape(int M)
 {
     if (M <= 64) return {64, 1};
@@ -55,7 +57,7 @@ LineShape default_shape(int M)
     if (M <= 1024) return {128, 8};
     if (M <= 2048) return {256, 8};
     if (M <= 4096) return {256, 16};
-    if (M <= 8192) return {1024, 8};
+    if (M <= 8192) return {512, 16};
     return {1024, 16};
 }
 
