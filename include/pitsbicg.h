@@ -200,6 +200,28 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
 int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
               pit_solve_info *info, void *stream);
 
+/* ---- line-shape autotuning (1D) --------------------------------------------- */
+
+/* A 1D line of M points is solved by NT threads holding C points each
+ * (NT*C >= M); the best (NT, C) depends on M, on the steppers and on the GPU.
+ * pit_autotune times one preconditioned product (the fine apply and the coarse
+ * sweep, as pit_solve runs them) of this problem for every supported shape
+ * with M <= NT*C <= 4M, using `scratch` (device, 256-byte aligned, at least
+ * pit_autotune_scratch_bytes) as the workspace, and records the fastest in a
+ * process-wide table keyed by the line-length class (M rounded up to a power
+ * of two), the boundary condition, both steppers' schemes, the fine precision
+ * and the coarse substeps.  Later pit_create calls for matching problems use
+ * the recorded shape (unless the PIT_LINE_SHAPE environment variable forces
+ * one).  Host-synchronous on `stream`.  out = {NT, C}; *out_ms (may be NULL)
+ * = the winner's time.  Errors: PIT_EINVAL (2D, bad arguments), PIT_ENOMEM
+ * (no shape fits the scratch), PIT_EHIP. */
+size_t pit_autotune_scratch_bytes(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine,
+                                  pit_stepper coarse);
+int pit_autotune(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+                 void *scratch, size_t bytes, int32_t out[2], float *out_ms, void *stream);
+/* Forget every recorded shape (pit_create falls back to its defaults). */
+int pit_autotune_reset(void);
+
 /* ---- batched solves --------------------------------------------------------- */
 
 /* Many independent PiTSBiCG solves advanced together (any mix of 1D problems

@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -59,6 +62,39 @@ LineShape default_shape(int M)
     if (M <= 4096) return {256, 16};
     if (M <= 8192) return {512, 16};
     return {1024, 16};
+}
+
+// Shapes chosen by pit_autotune, per line-length class and stepper kinds.
+struct TuneKey {
+    int mclass, bc, fine_scheme, fine_prec, coarse_scheme, c;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(mclass, bc, fine_scheme, fine_prec, coarse_scheme, c) <
+               std::tie(o.mclass, o.bc, o.fine_scheme, o.fine_prec, o.coarse_scheme, o.c);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, LineShape> g_tuned;
+
+int length_class(int M)
+{
+    int k = 64;
+    while (k < M) k *= 2;
+    return k;
+}
+
+TuneKey tune_key(const pit_problem &p, const pit_stepper &f, const pit_stepper &g)
+{
+    return TuneKey{length_class(p.M[0]), p.bc, f.scheme, f.prec, g.scheme, g.substeps};
+}
+
+bool tuned_shape(const TuneKey &k, int M, LineShape &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(k);
+    if (it == g_tuned.end() || it->second.NT * it->second.C < M) return false;
+    out = it->second;
+    return true;
 }
 
 LineShape shape_from_env(const char *name, int M)
@@ -434,8 +470,14 @@ const char *pit_strerror(int code)
 
 int pit_last_hip_error(void) { return t_last_hip; }
 
-int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
-               pit_ctx **out)
+}  // extern "C"
+
+namespace {
+
+// pit_create with the 1D line shape forced (autotuning) or chosen: an
+// environment override, else the tuned table, else the default.
+int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+               const LineShape *force, pit_ctx **out)
 {
     if (!out) return PIT_EINVAL;
     *out = nullptr;
@@ -495,7 +537,13 @@ int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->w = c->hx;
     // One shape for both line operators: pit_solve keeps its block vectors in
     // the chunked layout of that shape, shared by the fine and coarse kernels.
-    const LineShape sh = shape_from_env("PIT_LINE_SHAPE", M);
+    LineShape sh = shape_from_env("PIT_LINE_SHAPE", M);
+    if (force) {
+        sh = *force;
+    } else if (!std::getenv("PIT_LINE_SHAPE")) {
+        LineShape t{0, 0};
+        if (tuned_shape(tune_key(*problem, fine, coarse), M, t)) sh = t;
+    }
     if (!make_line(*c, fine.scheme, c->DT / m, sh, c->lf) ||
         !make_line(*c, coarse.scheme, c->DT / coarse.substeps, sh, c->lc)) {
         delete c;
@@ -527,6 +575,16 @@ int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->total = o;
     *out = c;
     return PIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pit_create(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+               pit_ctx **out)
+{
+    return create_ctx(problem, N, m, fine, coarse, nullptr, out);
 }
 
 int pit_destroy(pit_ctx *ctx)
@@ -891,3 +949,104 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     }
     return status;
 }
+
+// ---------------------------------------------------------------------------
+// Line-shape autotuner: times one preconditioned product (fine apply plus
+// coarse sweep, in the layout pit_solve uses) for every supported shape that
+// covers the line, and records the fastest for pit_create.
+// ---------------------------------------------------------------------------
+namespace {
+
+std::vector<LineShape> tune_candidates(int M)
+{
+    std::vector<LineShape> v;
+    for (const auto &k : kShapes)
+        if (k.NT * k.C >= M && k.NT * k.C <= std::max(4 * M, 64)) v.push_back(k);
+    if (v.empty()) v.push_back(default_shape(M));
+    return v;
+}
+
+struct EventGuard {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventGuard()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+struct CtxGuard {
+    pit_ctx *c = nullptr;
+    ~CtxGuard() { delete c; }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t pit_autotune_scratch_bytes(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine,
+                                  pit_stepper coarse)
+{
+    if (validate(problem, N, m, fine, coarse) != PIT_OK || problem->dim != 1) return 0;
+    size_t mx = 0;
+    for (LineShape sh : tune_candidates(problem->M[0])) {
+        CtxGuard g;
+        if (create_ctx(problem, N, m, fine, coarse, &sh, &g.c) == PIT_OK) mx = std::max(mx, g.c->total);
+    }
+    return mx;
+}
+
+int pit_autotune(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+                 void *scratch, size_t bytes, int32_t out[2], float *out_ms, void *stream)
+{
+    if (!problem || !out || !scratch || (reinterpret_cast<uintptr_t>(scratch) % kAlign) != 0) return PIT_EINVAL;
+    int rc = validate(problem, N, m, fine, coarse);
+    if (rc != PIT_OK) return rc;
+    if (problem->dim != 1) return PIT_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EventGuard ev;
+    PIT_HIP(hipEventCreate(&ev.a));
+    PIT_HIP(hipEventCreate(&ev.b));
+    float best = 0.0f;
+    LineShape bs{0, 0};
+    for (LineShape sh : tune_candidates(problem->M[0])) {
+        CtxGuard g;
+        if (create_ctx(problem, N, m, fine, coarse, &sh, &g.c) != PIT_OK || g.c->total > bytes) continue;
+        if ((rc = pit_bind_workspace(g.c, scratch, bytes)) != PIT_OK) return rc;
+        pit_ctx *c = g.c;
+        PIT_HIP(launch_fill0(c->vec(0), kSolveVectors * c->ntc(), st));
+        float t = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {  // the first is a warm-up
+            PIT_HIP(hipEventRecord(ev.a, st));
+            PIT_HIP(op_apply(c, c->vec(2), c->vec(6), 0, 0, true, st));
+            PIT_HIP(op_sweep(c, c->vec(6), c->vec(3), true, st));
+            PIT_HIP(hipEventRecord(ev.b, st));
+            PIT_HIP(hipEventSynchronize(ev.b));
+            float ms = 0.0f;
+            PIT_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (rep == 1 || (rep > 1 && ms < t)) t = ms;
+        }
+        if (bs.NT == 0 || t < best) {
+            best = t;
+            bs = sh;
+        }
+    }
+    if (bs.NT == 0) return PIT_ENOMEM;  // no candidate fitted the scratch memory
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(*problem, fine, coarse)] = bs;
+    }
+    out[0] = bs.NT;
+    out[1] = bs.C;
+    if (out_ms) *out_ms = best;
+    return PIT_OK;
+}
+
+int pit_autotune_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    return PIT_OK;
+}
+
+}  // extern "C"

@@ -82,7 +82,7 @@ EXPORTS = (
     "pit_coarse_sweep", "pit_solve", "pit_strerror", "pit_last_hip_error", "pit_kernel_shape",
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
-    "pit_server_destroy",
+    "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
 )
 
 _lib = None
@@ -123,6 +123,10 @@ def load(path: str = LIB_PATH):
     lib.pit_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(pit_result)]
     lib.pit_server_load.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(ct.c_uint64)]
     lib.pit_server_destroy.argtypes = [vp]
+    lib.pit_autotune_scratch_bytes.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper]
+    lib.pit_autotune_scratch_bytes.restype = sz
+    lib.pit_autotune.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper, vp, sz,
+                                 ct.POINTER(i32), ct.POINTER(ct.c_float), vp]
     _lib = lib
     return lib
 
@@ -279,6 +283,29 @@ class Context:
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
                             info.ms_coarse, info.n_fine, info.n_coarse)
+
+
+def autotune(p, device=None, stream=None):
+    """Time every line shape for workloads.Problem p (1D) and record the fastest for
+    later contexts of the same class; returns ((NT, C), ms)."""
+    lib = load()
+    pb = make_problem(p)
+    fine = pit_stepper(p.fine, p.m, p.prec, 0)
+    coarse = pit_stepper(p.coarse, p.c, F64, 0)
+    n = int(lib.pit_autotune_scratch_bytes(ct.byref(pb), p.N, p.m, fine, coarse))
+    if n == 0:
+        raise PitError(EINVAL, "pit_autotune_scratch_bytes")
+    buf, base = _aligned(n, device)
+    out = (ct.c_int32 * 2)()
+    ms = ct.c_float()
+    _check(lib.pit_autotune(ct.byref(pb), p.N, p.m, fine, coarse, base, n, out, ct.byref(ms), _stream(stream)),
+           "pit_autotune")
+    del buf
+    return (int(out[0]), int(out[1])), float(ms.value)
+
+
+def autotune_reset():
+    load().pit_autotune_reset()
 
 
 def _opts(p, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS, stall_window=0):

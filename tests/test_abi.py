@@ -139,3 +139,20 @@ def test_batch_and_server_validate_on_the_host():
     assert lib.pit_server_create(ct.byref(cfg), ct.byref(s)) == P.ENOMEM  # arena below its own buffers
     assert lib.pit_submit(None, None, None) == P.EINVAL
     assert lib.pit_poll(None, 1, None) == P.EINVAL
+
+
+def test_autotune_scratch_covers_every_candidate_shape():
+    lib = P.load()
+    p = wl.C2.with_(N=4, m=2)
+    pb = P.make_problem(p)
+    f, g = P.pit_stepper(p.fine, p.m, p.prec, 0), P.pit_stepper(p.coarse, p.c, P.F64, 0)
+    n = lib.pit_autotune_scratch_bytes(ct.byref(pb), p.N, p.m, f, g)
+    _, h = create(p)
+    assert n >= lib.pit_workspace_bytes(h) > 0
+    lib.pit_destroy(h)
+    out = (ct.c_int32 * 2)()
+    assert lib.pit_autotune(ct.byref(pb), p.N, p.m, f, g, None, n, out, None, None) == P.EINVAL
+    p2 = wl.C3.with_(N=2, m=2)
+    pb2 = P.make_problem(p2)
+    f2, g2 = P.pit_stepper(p2.fine, p2.m, p2.prec, 0), P.pit_stepper(p2.coarse, p2.c, P.F64, 0)
+    assert lib.pit_autotune_scratch_bytes(ct.byref(pb2), p2.N, p2.m, f2, g2) == 0  # 1D only

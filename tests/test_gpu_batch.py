@@ -348,3 +348,24 @@ def test_server_admission_by_budget():
     r = srv.poll(t)
     srv.close()
     assert r is not None and r.status == P.ENOMEM
+
+
+def test_autotuned_shape_is_used_and_correct():
+    """The autotuner records a shape; the next context of that class uses it
+    and still matches the oracle; after a reset the default returns."""
+    P = P_()
+    say("autotune")
+    p = p1d(1500, wl.PERIODIC, 8, 12, name="tune1500")
+    default = P.Context(p).kernel_shape()[:2]
+    (nt, c), ms = P.autotune(p)
+    print(f"default {default} tuned {(nt, c)} {ms:.3f} ms per product", flush=True)
+    assert nt * c >= 1500 and ms > 0
+    ctx = P.Context(p)
+    assert ctx.kernel_shape()[:2] == (nt, c)
+    u0 = u0_of(p)
+    X, inf = ctx.solve(dev(u0), tol=1e-10)
+    Xo, io = orc.Oracle(**p.oracle_kwargs()).pitsbicg(u0, tol=1e-10)
+    assert inf.status == io.status == orc.OK and abs(inf.iters - io.iters) <= 1
+    assert relerr(host(X), Xo) < 1e-9
+    P.autotune_reset()
+    assert P.Context(p).kernel_shape()[:2] == default
