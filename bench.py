@@ -156,10 +156,13 @@ def algorithmic_bytes(p, prec, unit):
     return (p.N - 1) * p.c * p.npts * 40
 
 
-def workload(name, prec):
+def workload(name, prec, side=None):
     from paper_2203_10148_amd import workloads as wl
 
     p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3}[name]
+    if side and p.dim == 2 and side != p.M[0]:
+        # the same 2D recipe on a larger square (its working set beyond the 256 MiB MALL)
+        p = p.with_(M=(side, side), name=f"{p.name}_{side}")
     if prec is None:
         return p
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
@@ -200,6 +203,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="c5: arrival rate (requests/s)")
     ap.add_argument("--arena-gib", type=float, default=160.0, help="c5: HBM budget of the server (GiB)")
     ap.add_argument("--no-autotune", action="store_true", help="c4: keep the default line shapes")
+    ap.add_argument("--no-compare", action="store_true", help="c1/c2: skip the solve in the other fine precision")
+    ap.add_argument("--side", type=int, default=None, help="c3: grid side (default 512)")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -219,7 +224,7 @@ def main():
         summarize_stats(*args.stats_summary)
         return
     if args.pmc_summary:
-        p = workload(args.workload, args.prec)
+        p = workload(args.workload, args.prec, args.side)
         from paper_2203_10148_amd import workloads as wl
         prec = "f32" if p.prec == wl.F32 else "f64"
         fc, wc, out, unit, rx, units, cf, cw = args.pmc_summary
@@ -242,7 +247,7 @@ def main():
         return bench_batch(args, dev)
     if args.workload == "c5":
         return bench_serve(args, dev)
-    p = workload(args.workload, args.prec)
+    p = workload(args.workload, args.prec, args.side)
     args.prec = "f32" if p.prec == wl.F32 else "f64"
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
@@ -359,6 +364,28 @@ def main():
         "fine_kernel_stream_equiv_hbm_frac": fine_cu_s * (16 if args.prec == "f64" else 8) / (PEAK["hbm_GBs"] * 1e9),
         "kernel_shape": ctx.kernel_shape(),
     }
+    # the other fine-propagator form on the same input (FP32 fine with FP64
+    # reductions vs plain FP64), outside the timed region
+    if p.dim == 1 and not args.no_compare:
+        other = wl.F64 if p.prec == wl.F32 else wl.F32
+        po = p.with_(prec=other)
+        co = P.Context(po, device=dev)
+        Xo = torch.empty_like(X)
+        so = 10 if other == wl.F32 else 0
+        co.solve(u0, Xo, tol=p.tol, stall_window=so)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            _, io = co.solve(u0, Xo, tol=p.tol, stall_window=so)
+            times.append(io.ms_total)
+        diff = float(torch.linalg.vector_norm(Xo - X) / torch.linalg.vector_norm(X))
+        out["compare"] = {"form": "f32" if other == wl.F32 else "f64", "time_to_tol_ms": float(np.median(times)),
+                          "status": io.status, "iters": io.iters, "res_norm": io.res_norm,
+                          "rel_diff_from_timed_form": diff,
+                          "note": "an FP32 fine propagator stops at its residual floor (stall rule, status -4) "
+                                  "when tol is below it"}
+        log(f"[bench] compare {out['compare']['form']}: {out['compare']['time_to_tol_ms']:.2f} ms, "
+            f"status {io.status}, iters {io.iters}, rel. diff {diff:.2e}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds)

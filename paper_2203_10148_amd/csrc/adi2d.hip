@@ -186,77 +186,105 @@ __global__ __launch_bounds__(256) void k_adi_x(LineTab<double> tb, const SIN *__
 // ---------------------------------------------------------------------------
 // y half step
 // ---------------------------------------------------------------------------
-// grid: nslices * ceil(Mx/64) blocks of WY waves.  Epilogue EPI: 0 stores u',
-// 1 stores base + sign*u' (FP64) -- the all-at-once apply's lam_n - F(...) and
-// the coarse sweep's v_n + G(...).
-template <int WY, int CY, typename SIN, typename SOUT, int EPI>
+// grid: nslices * ceil(Mx/CW) blocks of WY waves, CW = 64/SEG columns per
+// block.  A wave holds SEG row segments of CY rows: lane l works on column
+// col0 + l % CW, segment g = SEG*w + l / CW (rows g*CY .. g*CY+CY-1), so
+// WY*SEG*CY rows in all.  Epilogue EPI: 0 stores u', 1 stores base +
+// sign*u' (FP64) -- the all-at-once apply's lam_n - F(...) and the coarse
+// sweep's v_n + G(...).
+template <int WY, int CY, int SEG, typename SIN, typename SOUT, int EPI>
 __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restrict__ in, long in_off,
                                                    SOUT *__restrict__ out, long out_off,
                                                    const double *__restrict__ base, long base_off, double sign,
                                                    int nslices, int Mx, int My, double ex, double ed)
 {
-    constexpr int NR = WY * CY;
+    constexpr int CW = kWave / SEG, NS = WY * SEG, NR = NS * CY;
+    static_assert(SEG == 1 || SEG == 2, "one or two segments per wave");
+    static_assert(SEG == 1 ? (2 * CY <= kWave) : (CY == 32), "halo lanes");
     __shared__ double s_lm[NR], s_iu[NR], s_cm[NR];
-    __shared__ double s_pf[WY], s_pb[WY];
-    __shared__ double s_agg[2][WY][kWave];
+    __shared__ double s_pf[NS], s_pb[NS];
+    __shared__ double s_agg[2][NS][CW];
     const int t = threadIdx.x, lane = t & (kWave - 1);
-    const int w = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform (scalar) row segment
-    const int bx = (Mx + kWave - 1) / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform (scalar)
+    const int cl = lane % CW, sg = lane / CW;
+    const int g = w * SEG + sg;  // this lane's row segment
+    const int bx = (Mx + CW - 1) / CW;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s = blk / bx, col0 = (blk % bx) * kWave;
+    const int s = blk / bx, col0 = (blk % bx) * CW;
     for (int i = t; i < NR; i += WY * kWave) {
         s_lm[i] = tb.lm[i];
         s_iu[i] = tb.iu[i];
         s_cm[i] = tb.cm[i];
     }
-    if (t < WY) {
+    if (t < NS) {
         s_pf[t] = tb.pwf[t];
         s_pb[t] = tb.pwb[t];
     }
     __syncthreads();
     if (s >= nslices) return;  // uniform per block
     const long npts = (long)Mx * My;
-    const int col = col0 + lane;
+    const int col = col0 + cl;
     const bool live = col < Mx;
     const Rsrc rin = make_rsrc(in + (size_t)(s + in_off) * npts, (unsigned)(npts * sizeof(SIN)));
-    const int r0 = w * CY;
+    const int r0 = g * CY;
     constexpr int zi = sizeof(SIN), zo = sizeof(SOUT);
     // Out-of-range buffer reads return 0, which supplies the zeros the
     // stencil needs in lanes past the last column and for the Dirichlet
-    // boundary values left and right of the slice.  Rows past the last one
-    // re-read the last row: their table entries (lm 1, iu 0, cm 0) keep any
-    // finite value out of the real rows, and they are never stored.
+    // boundary values left and right of the slice.
     constexpr int kOut = 0x40000000;
-    const int vcol = live ? col * zi : kOut;
-    auto in_row = [&](int r) { return bload<SIN>(rin, vcol, min(r0 + r, My - 1) * Mx * zi); };
-    // The two halo columns of the strip for this wave's CY rows in one load:
-    // lane i < CY reads column col0-1 of row r0+i, lane CY+i column col0+64;
-    // row r's halo values are then taken with readlane.
-    static_assert(2 * CY <= kWave || CY == 64, "halo lanes");
+    // With one segment per wave the row offset is wave-uniform (scalar) and
+    // rows past the last one re-read the last row; with two the segment's
+    // first row goes into the lane's offset and rows past the last one are
+    // marked out of range there (read as 0, stores dropped).  Either way the
+    // pad rows' table entries (lm 1, iu 0, cm 0) keep them out of the real
+    // rows.
+    const int vlane = live ? (col + (SEG == 1 ? 0 : r0 * Mx)) * zi : kOut;
+    auto row_off = [&](int r, int v, int z) {  // (vector, scalar) offsets of row r0 + r
+        if constexpr (SEG == 1) return int2{v, min(r0 + r, My - 1) * Mx * z};
+        else return int2{(r0 + r < My) ? v : kOut, r * Mx * z};
+    };
+    auto in_row = [&](int r) {
+        const int2 o = row_off(r, vlane, zi);
+        return bload<SIN>(rin, o.x, o.y);
+    };
+    // The halo columns of the strip for this wave's SEG*CY rows: lane i <
+    // SEG*CY of hv reads column col0-1 of the wave's i-th row, hv2 (or the
+    // upper lanes of hv when SEG*CY <= 32) column col0+CW; row r's halo
+    // values are then taken with readlane.
+    constexpr int HR = SEG * CY;  // halo rows per wave
     SIN hv, hv2;
     {
-        const int i = lane % CY;
-        const int hc = (lane < CY) ? col0 - 1 : col0 + kWave;
-        const bool in_range = hc >= 0 && hc < Mx && r0 + i < My;
-        hv = bload<SIN>(rin, in_range ? ((r0 + i) * Mx + hc) * zi : kOut, 0);
-        hv2 = hv;  // with CY == 64 the right halo needs a second load
-        if constexpr (CY == 64) {
-            const int hc2 = col0 + kWave;
-            hv2 = bload<SIN>(rin, (hc2 < Mx && r0 + lane < My) ? ((r0 + lane) * Mx + hc2) * zi : kOut, 0);
+        const int wr0 = w * HR;
+        const int i = lane % HR;
+        const bool split = 2 * HR <= kWave;
+        const int hc = (split && lane >= HR) ? col0 + CW : col0 - 1;
+        hv = bload<SIN>(rin, (hc >= 0 && hc < Mx && wr0 + i < My) ? ((wr0 + i) * Mx + hc) * zi : kOut, 0);
+        hv2 = hv;
+        if constexpr (2 * HR > kWave) {
+            const int hc2 = col0 + CW;
+            hv2 = bload<SIN>(rin, (hc2 < Mx && wr0 + lane < My) ? ((wr0 + lane) * Mx + hc2) * zi : kOut, 0);
         }
     }
 
     // Right-hand side (I + theta Lx) u* for this lane's column segment; the
-    // x-neighbours inside the wavefront come from DPP lane shifts of the
-    // stored values.  Every lane runs the cross-lane reads (DPP and readlane
-    // are not speculatable, so inside a conditional they would become a
-    // divergent branch); the wave-edge lanes then select the halo values.
+    // x-neighbours inside the strip come from DPP lane shifts of the stored
+    // values.  Every lane runs the cross-lane reads (DPP and readlane are not
+    // speculatable, so inside a conditional they would become a divergent
+    // branch); the strip-edge lanes then select the halo values.
     auto rhs = [&](SIN v, int r) {
-        const SIN hl = readlane(hv, r);
-        const SIN hr = CY == 64 ? readlane(hv2, r) : readlane(hv, CY + (r % (kWave - CY + 1)));
+        SIN hl, hr;
+        if constexpr (SEG == 1) {
+            hl = readlane(hv, r);
+            hr = (2 * HR > kWave) ? readlane(hv2, r) : readlane(hv, HR + (r % (kWave - HR + 1)));
+        } else {
+            const SIN l0 = readlane(hv, r), l1 = readlane(hv, CY + r);
+            const SIN r0v = readlane(hv2, r), r1v = readlane(hv2, CY + r);
+            hl = sg ? l1 : l0;
+            hr = sg ? r1v : r0v;
+        }
         const SIN sl = dpp<0x138>(v), sr = dpp<0x130>(v);
-        const SIN vl = (lane == 0) ? hl : sl;
-        const SIN vr = (lane == kWave - 1) ? hr : sr;
+        const SIN vl = (cl == 0) ? hl : sl;
+        const SIN vr = (cl == CW - 1) ? hr : sr;
         return fma(ed, to_d(v), ex * (to_d(vl) + to_d(vr)));
     };
     double d[CY];
@@ -278,10 +306,13 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     double e = 0.0;
 #pragma unroll
     for (int r = 0; r < CY; ++r) e = fma(s_lm[r0 + r], e, d[r]);
-    s_agg[0][w][lane] = e;
+    s_agg[0][g][cl] = e;
     __syncthreads();
     double cw = 0.0;
-    for (int q = 0; q < w; ++q) cw = fma(s_pf[q], cw, s_agg[0][q][lane]);
+    for (int q = 0; q < w * SEG + SEG - 1; ++q) {  // segments before g (predicated: g differs by half-wave)
+        const double n = fma(s_pf[q], cw, s_agg[0][q][cl]);
+        cw = (q < g) ? n : cw;
+    }
     double y = cw;
 #pragma unroll
     for (int r = 0; r < CY; ++r) {
@@ -291,14 +322,15 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     // back substitution along y
     const Rsrc rout = make_rsrc(out + (size_t)(s + out_off) * npts, (unsigned)(npts * zo));
     const Rsrc rbase = make_rsrc(EPI ? base + (size_t)(s + base_off) * npts : base, EPI ? (unsigned)(npts * 8) : 0u);
-    const int vout = live ? col * zo : kOut, vbase = live ? col * 8 : kOut;
+    const int vout = live ? (col + (SEG == 1 ? 0 : r0 * Mx)) * zo : kOut;
+    const int vbase = live ? (col + (SEG == 1 ? 0 : r0 * Mx)) * 8 : kOut;
     // The epilogue's base rows are read PB rows ahead of the second backward
     // pass (the first PB before the backward exchange), so their latency is
     // hidden behind the recurrence instead of stalling every row.
-    constexpr int PB = EPI ? (CY < 8 ? CY : 8) : 1;
+    constexpr int PB = EPI ? (CY < 8 ? CY : ((SEG == 2 && WY == 16 && sizeof(SIN) == 8) ? 4 : 8)) : 1;
     auto base_row = [&](int r) {
-        const int j = r0 + r;  // rows past the last one: see in_row
-        return bload<double>(rbase, vbase, min(j, My - 1) * Mx * 8);
+        const int2 o = row_off(r, vbase, 8);
+        return bload<double>(rbase, o.x, o.y);
     };
     double bq[PB];
     if constexpr (EPI) {
@@ -308,23 +340,30 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     double bsum = 0.0;
 #pragma unroll
     for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * d[r]);
-    s_agg[1][w][lane] = bsum;
+    s_agg[1][g][cl] = bsum;
     __syncthreads();
     double cb = 0.0;
-    for (int q = WY - 1; q > w; --q) cb = fma(s_pb[q], cb, s_agg[1][q][lane]);
+    for (int q = NS - 1; q > w * SEG; --q) {  // segments after g
+        const double n = fma(s_pb[q], cb, s_agg[1][q][cl]);
+        cb = (q > g) ? n : cb;
+    }
     // second backward pass: each solution value is stored as it is produced
     double x = cb;
 #pragma unroll
     for (int r = CY - 1; r >= 0; --r) {
         x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * d[r]);
-        const int j = r0 + r;
         double o = x;
         if constexpr (EPI) {
             const int q = (CY - 1 - r) % PB;
             o = fma(sign, x, bq[q]);
             if (r - PB >= 0) bq[q] = base_row(r - PB);
         }
-        if (j < My) bstore((SOUT)o, rout, vout, j * Mx * zo);  // wave-uniform branch
+        if constexpr (SEG == 1) {
+            if (r0 + r < My) bstore((SOUT)o, rout, vout, (r0 + r) * Mx * zo);  // wave-uniform branch
+        } else {
+            const int2 of = row_off(r, vout, zo);
+            bstore((SOUT)o, rout, of.x, of.y);
+        }
     }
 }
 
@@ -332,7 +371,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 // launchers
 // ---------------------------------------------------------------------------
 #define PIT_ADI_XC(X) X(1) X(2) X(4) X(8) X(16)
-#define PIT_ADI_YSHAPES(X) X(8, 16) X(8, 32) X(8, 64) X(16, 32) X(16, 64)
+#define PIT_ADI_YSHAPES(X) X(8, 16, 1) X(8, 32, 1) X(16, 32, 1) X(8, 32, 2) X(16, 32, 2)
 
 template <typename SIN, typename SOUT>
 static hipError_t adi_x_t(int C, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,
@@ -352,16 +391,17 @@ static hipError_t adi_x_t(int C, const LineTab<double> &tb, const SIN *in, long 
 }
 
 template <typename SIN, typename SOUT, int EPI>
-static hipError_t adi_y_t(int WY, int CY, const ColTab &tb, const SIN *in, long in_off, SOUT *out, long out_off,
-                          const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
-                          double ed, hipStream_t st)
+static hipError_t adi_y_t(const AdiShape &sh, const ColTab &tb, const SIN *in, long in_off, SOUT *out,
+                          long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
+                          double ex, double ed, hipStream_t st)
 {
-    const int blocks = nslices * ((Mx + kWave - 1) / kWave);
-#define X(wy, cy)                                                                                        \
-    if (WY == wy && CY == cy) {                                                                          \
-        hipLaunchKernelGGL((k_adi_y<wy, cy, SIN, SOUT, EPI>), dim3(blocks), dim3(wy * 64), 0, st, tb, in, \
-                           in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);          \
-        return hipGetLastError();                                                                        \
+    const int cw = kWave / sh.seg;
+    const int blocks = nslices * ((Mx + cw - 1) / cw);
+#define X(WY_, CY_, SG_)                                                                                         \
+    if (sh.wy == WY_ && sh.cy == CY_ && sh.seg == SG_) {                                                        \
+        hipLaunchKernelGGL((k_adi_y<WY_, CY_, SG_, SIN, SOUT, EPI>), dim3(blocks), dim3(WY_ * 64), 0, st, tb,   \
+                           in, in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);              \
+        return hipGetLastError();                                                                                \
     }
     PIT_ADI_YSHAPES(X)
 #undef X
@@ -386,19 +426,19 @@ hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in
 {
     const bool epi = base != nullptr;
     if (in.f32 && out.f32 && !epi)
-        return adi_y_t<float, float, 0>(sh.wy, sh.cy, tb, in.f, in_off, out.f, out_off, nullptr, 0, 0.0, nslices,
+        return adi_y_t<float, float, 0>(sh, tb, in.f, in_off, out.f, out_off, nullptr, 0, 0.0, nslices,
                                         Mx, My, ex, ed, st);
     if (in.f32 && !out.f32 && epi)
-        return adi_y_t<float, double, 1>(sh.wy, sh.cy, tb, in.f, in_off, out.d, out_off, base, base_off, sign,
+        return adi_y_t<float, double, 1>(sh, tb, in.f, in_off, out.d, out_off, base, base_off, sign,
                                          nslices, Mx, My, ex, ed, st);
     if (in.f32 && !out.f32 && !epi)
-        return adi_y_t<float, double, 0>(sh.wy, sh.cy, tb, in.f, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
+        return adi_y_t<float, double, 0>(sh, tb, in.f, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
                                          Mx, My, ex, ed, st);
     if (!in.f32 && !out.f32 && epi)
-        return adi_y_t<double, double, 1>(sh.wy, sh.cy, tb, in.d, in_off, out.d, out_off, base, base_off, sign,
+        return adi_y_t<double, double, 1>(sh, tb, in.d, in_off, out.d, out_off, base, base_off, sign,
                                           nslices, Mx, My, ex, ed, st);
     if (!in.f32 && !out.f32 && !epi)
-        return adi_y_t<double, double, 0>(sh.wy, sh.cy, tb, in.d, in_off, out.d, out_off, nullptr, 0, 0.0,
+        return adi_y_t<double, double, 0>(sh, tb, in.d, in_off, out.d, out_off, nullptr, 0, 0.0,
                                           nslices, Mx, My, ex, ed, st);
     return hipErrorInvalidValue;
 }

@@ -116,20 +116,22 @@ hipError_t launch_from_chunked(const double *chk, double *nat, int N, int M, int
 // ---------------------------------------------------------------------------
 // 2D PR-ADI half steps (adi2d.hip)
 // ---------------------------------------------------------------------------
-// Row-constant tables of the y-direction solver for WY*CY rows (pads: lm = 1,
-// iu = 0, cm = 0) and the per-wave products of lm and cm.  Blob layout:
-// lm[NR] iu[NR] cm[NR] pwf[16] pwb[16].
+// Row-constant tables of the y-direction solver for NS segments of CY rows
+// (pads: lm = 1, iu = 0, cm = 0) and the per-segment products of lm and cm.
+// Blob layout: lm[NR] iu[NR] cm[NR] pwf[32] pwb[32].
+constexpr int kMaxSegs = 32;
 struct ColTab {
     const double *lm, *iu, *cm, *pwf, *pwb;
 };
-inline size_t col_tab_elems(int nr) { return 3 * (size_t)nr + 2 * kMaxWaves; }
+inline size_t col_tab_elems(int nr) { return 3 * (size_t)nr + 2 * kMaxSegs; }
 inline ColTab col_tab_view(const double *base, int nr)
 {
-    return ColTab{base, base + nr, base + 2 * (size_t)nr, base + 3 * (size_t)nr, base + 3 * (size_t)nr + kMaxWaves};
+    return ColTab{base, base + nr, base + 2 * (size_t)nr, base + 3 * (size_t)nr, base + 3 * (size_t)nr + kMaxSegs};
 }
-// x: C points per lane (64 lanes per row); y: WY waves of CY rows per column.
+// x: C points per lane (64 lanes per row); y: WY waves, each with SEG row
+// segments of CY rows (64/SEG columns per workgroup).
 struct AdiShape {
-    int cx, wy, cy;
+    int cx, wy, cy, seg;
 };
 // A field buffer of either precision.
 struct AdiBuf {

@@ -240,11 +240,11 @@ void stencil1d(const pit_problem &p, double h, double *lo, double *di, double *u
 }
 
 // Row tables of the y-direction solver: the LU factors of the My x My
-// tridiagonal (sub a, diagonal b, super c), padded to wy*cy rows, and the
-// products of lm and cm over each wave's rows.
-bool build_col(int My, double a, double b, double c, int wy, int cy, std::vector<double> &blob)
+// tridiagonal (sub a, diagonal b, super c), padded to ns*cy rows, and the
+// products of lm and cm over each segment's rows.
+bool build_col(int My, double a, double b, double c, int ns, int cy, std::vector<double> &blob)
 {
-    const int nr = wy * cy;
+    const int nr = ns * cy;
     std::vector<double> lm(nr, 1.0), iu(nr, 0.0), cm(nr, 0.0);
     double u = b;
     for (int j = 0; j < My; ++j) {
@@ -264,14 +264,14 @@ bool build_col(int My, double a, double b, double c, int wy, int cy, std::vector
         blob[nr + j] = iu[j];
         blob[2 * (size_t)nr + j] = cm[j];
     }
-    for (int w = 0; w < wy; ++w) {
+    for (int w = 0; w < ns; ++w) {
         double f = 1.0, g = 1.0;
         for (int j = w * cy; j < (w + 1) * cy; ++j) {
             f *= lm[j];
             g *= cm[j];
         }
         blob[3 * (size_t)nr + w] = f;
-        blob[3 * (size_t)nr + kMaxWaves + w] = g;
+        blob[3 * (size_t)nr + kMaxSegs + w] = g;
     }
     for (double x : blob)
         if (!std::isfinite(x)) return false;
@@ -294,22 +294,25 @@ bool setup_2d(pit_ctx &c)
     const int Mx = c.pb.M[0], My = c.pb.M[1];
     int cx = 1;
     while (64 * cx < Mx) cx *= 2;
-    const AdiShape menu[] = {{0, 8, 16}, {0, 8, 32}, {0, 16, 32}, {0, 16, 64}};
-    AdiShape sh{cx, 0, 0};
+    // y shapes (waves, rows per segment, segments per wave), smallest first;
+    // the kernels in adi2d.hip are instantiated for exactly these
+    // (two segments of 32 rows beat one segment up to 512 rows: 32-column
+    // blocks, twice as many workgroups and two resident per CU)
+    const AdiShape menu[] = {{0, 8, 16, 1}, {0, 8, 32, 1}, {0, 8, 32, 2}, {0, 16, 32, 2}, {0, 16, 32, 1}};
+    auto rows = [](const AdiShape &a) { return a.wy * a.cy * a.seg; };
+    AdiShape sh{cx, 0, 0, 0};
     for (const auto &a : menu)
-        if (a.wy * a.cy >= My) {
-            sh.wy = a.wy;
-            sh.cy = a.cy;
+        if (rows(a) >= My) {
+            sh = a;
+            sh.cx = cx;
             break;
         }
     if (!sh.wy || cx > 16) return false;
-    if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {  // tuning override "wy,cy"
-        int wy = 0, cy = 0;
-        if (std::sscanf(e, "%d,%d", &wy, &cy) == 2 && wy * cy >= My &&
-            ((wy == 8 && (cy == 16 || cy == 32 || cy == 64)) || (wy == 16 && (cy == 32 || cy == 64)))) {
-            sh.wy = wy;
-            sh.cy = cy;
-        }
+    if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {  // tuning override "wy,cy,seg"
+        AdiShape o{cx, 0, 0, 0};
+        if (std::sscanf(e, "%d,%d,%d", &o.wy, &o.cy, &o.seg) == 3 && rows(o) >= My)
+            for (const auto &a : menu)
+                if (a.wy == o.wy && a.cy == o.cy && a.seg == o.seg) sh = o;
     }
     c.ash = sh;
     const double nu = c.pb.nu, r = c.pb.react;
@@ -322,7 +325,7 @@ bool setup_2d(pit_ctx &c)
         yed = 1.0 - 2.0 * th * kx - 0.5 * th * r;
         const bool okx = build_line(Mx, false, -th * kx, 1.0 + 2.0 * th * kx + 0.5 * th * r, -th * kx,
                                     LineShape{64, cx}, ax);
-        const bool oky = build_col(My, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, sh.wy, sh.cy, ay);
+        const bool oky = build_col(My, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, sh.wy * sh.seg, sh.cy, ay);
         return okx && oky;
     };
     const double thf = 0.5 * c.DT / c.m, thc = 0.5 * c.DT / c.coarse.substeps;
@@ -388,7 +391,7 @@ hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int
         t.M = Mx;
         return t;
     }();
-    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy);
+    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy * c->ash.seg);
     const AdiBuf lamb{nullptr, const_cast<double *>(lam), false}, yb{nullptr, y, false};
     const AdiBuf ub = c->fbuf(c->off_ubuf), sb = c->fbuf(c->off_sbuf);
     for (int step = 0; step < c->m; ++step) {
@@ -417,7 +420,7 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
     LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axc), 64, c->ash.cx);
     tx.cyclic = 0;
     tx.M = Mx;
-    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayc), c->ash.wy * c->ash.cy);
+    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayc), c->ash.wy * c->ash.cy * c->ash.seg);
     const AdiBuf zb{nullptr, z, false};
     const AdiBuf ta{nullptr, c->ctmp(0), false}, tb{nullptr, c->ctmp(1), false};
     const int cs = c->coarse.substeps;
@@ -602,7 +605,7 @@ int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4])
         out[0] = 64;
         out[1] = ctx->ash.cx;
         out[2] = 64 * ctx->ash.wy;
-        out[3] = ctx->ash.cy;
+        out[3] = ctx->ash.cy * ctx->ash.seg;
         return PIT_OK;
     }
     out[0] = ctx->lf.sh.NT;

@@ -389,15 +389,18 @@ ADI_CASES = [
     (512, 512, 1.0, 1.0, 3, 3, 1, wl.F64),
     (100, 70, 1.0, 0.7, 3, 4, 2, wl.F32),
     (512, 512, 1.0, 1.0, 3, 3, 1, wl.F32),
+    (300, 600, 1.0, 1.2, 2, 2, 1, wl.F64),     # 600 rows: two row segments per wavefront
+    (1024, 1024, 1.0, 1.0, 2, 4, 1, wl.F32, 1.8e-3),   # largest side; time step of the served 2D requests
 ]
 
 
-def adi_problem(Mx, My, Lx, Ly, N, m, c, prec):
-    return wl.Problem(dim=2, M=(Mx, My), length=(Lx, Ly), bc=wl.DIRICHLET, nu=0.05, react=0.2, T=0.05 * N,
-                      N=N, m=m, fine=wl.ADI, c=c, coarse=wl.ADI, prec=prec)
+def adi_problem(Mx, My, Lx, Ly, N, m, c, prec, T=None):
+    return wl.Problem(dim=2, M=(Mx, My), length=(Lx, Ly), bc=wl.DIRICHLET, nu=0.05, react=0.2,
+                      T=0.05 * N if T is None else T, N=N, m=m, fine=wl.ADI, c=c, coarse=wl.ADI, prec=prec)
 
 
-@pytest.mark.parametrize("case", ADI_CASES, ids=lambda c: f"{c[0]}x{c[1]}_N{c[4]}_m{c[5]}_c{c[6]}_p{c[7]}")
+@pytest.mark.parametrize("case", ADI_CASES, ids=lambda c: f"{c[0]}x{c[1]}_N{c[4]}_m{c[5]}_c{c[6]}_p{c[7]}"
+                         + (f"_T{c[8]}" if len(c) > 8 else ""))
 def test_adi_apply_and_sweep_match_oracle(case):
     p = adi_problem(*case)
     say(f"adi apply/sweep {case}")
@@ -426,6 +429,20 @@ def test_adi_apply_and_sweep_match_oracle(case):
         d2 = dev(lam)
         c.coarse_sweep(d2, d2)
         assert relerr(host(d2), o.sweep(lam)) < 1e-12
+
+
+def test_adi_one_segment_shape_on_a_short_column(monkeypatch):
+    """The 16-wave, 1-segment y shape forced on 500 rows (pad rows past the
+    last one, re-read from the last row), against the oracle."""
+    monkeypatch.setenv("PIT_ADI_YSHAPE", "16,32,1")
+    p = adi_problem(200, 500, 1.0, 1.0, 3, 2, 1, wl.F64)
+    say("adi y shape 16,32,1 on 200x500")
+    c = ctx(p)
+    assert c.kernel_shape()[2:] == (1024, 32)
+    o = make_oracle(p)
+    lam = wl.random_block(p, 5)
+    assert relerr(host(c.apply_F(dev(lam))), o.apply(lam)) < 1e-12
+    assert relerr(host(c.coarse_sweep(dev(lam))), o.sweep(lam)) < 1e-12
 
 
 @pytest.mark.parametrize("prec", [wl.F64, wl.F32])
