@@ -93,8 +93,8 @@ __device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, i
     for (int k = 0; k < C; ++k) r[k] = row[min(lane * C + k, Mx - 1)];
 }
 
-template <int C, typename SIN, typename SOUT>
-__device__ __forceinline__ void x_row(LineSolver<double, kWave, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
+template <int NT, int C, typename SIN, typename SOUT>
+__device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
                                       const SIN (&nx)[C], int j, int My, int Mx, int lane, bool vec, double ex,
                                       double ed, SOUT *__restrict__ oslice)
 {
@@ -143,40 +143,50 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return x * q + min(x, r) + k;
 }
 
-// grid: ceil(nslices * strips / 4) blocks of 4 waves; wave g handles strip
-// g % strips of slice g / strips.  in/out slice s sits at in + (s + in_off)*npts.
-template <int C, typename SIN, typename SOUT>
-__global__ __launch_bounds__(256) void k_adi_x(LineTab<double> tb, const SIN *__restrict__ in, long in_off,
-                                               SOUT *__restrict__ out, long out_off, int nslices, int Mx,
-                                               int My, int R, double ex, double ed)
+// A row of Mx points is solved by XW wavefronts (NT = 64*XW threads, C points
+// each).  XW = 1: blocks of 4 independent waves, wave g handles strip g of
+// all nslices*strips strips (strip: R consecutive rows of one slice).  XW = 2
+// (rows wider than 512 points): blocks of one wave pair, block g handles strip
+// g, and the pair's line solves exchange their carries through LDS.  in/out
+// slice s sits at in + (s + in_off)*npts.
+template <int XW, int C, typename SIN, typename SOUT>
+__global__ __launch_bounds__(XW == 1 ? 256 : 128) void k_adi_x(LineTab<double> tb, const SIN *__restrict__ in,
+                                                               long in_off, SOUT *__restrict__ out, long out_off,
+                                                               int nslices, int Mx, int My, int R, double ex,
+                                                               double ed)
 {
-    const int lane = threadIdx.x & (kWave - 1);
+    constexpr int NT = kWave * XW;
+    const int lane = threadIdx.x & (NT - 1);  // thread of the row group
     const int strips = (My + R - 1) / R;
-    // wave-uniform indices in scalar registers, so row addresses stay scalar
-    const int g = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / kWave);
-    if (g >= nslices * strips) return;  // whole wavefront exits; no barriers below
+    // group-uniform indices in scalar registers, so row addresses stay scalar
+    const int g = XW == 1 ? __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / kWave)
+                          : xcd_block(blockIdx.x, gridDim.x);
+    if (g >= nslices * strips) return;  // the whole group exits (a block for XW = 2); no barriers skipped
     const int s = g / strips, j0 = (g % strips) * R, j1 = min(j0 + R, My);
     const long npts = (long)Mx * My;
     const SIN *islice = in + (size_t)(s + in_off) * npts;
     SOUT *oslice = out + (size_t)(s + out_off) * npts;
-    // 16-byte accesses when the row length keeps every lane chunk aligned
-    const bool vec = (Mx == kWave * C) && (Mx * sizeof(SIN)) % 16 == 0 && (Mx * sizeof(SOUT)) % 16 == 0;
-    LineSolver<double, kWave, C, false> LS;
-    LS.load(tb, nullptr);
+    // 16-byte accesses when the row length keeps every thread's chunk aligned
+    const bool vec = (Mx == NT * C) && (Mx * sizeof(SIN)) % 16 == 0 && (Mx * sizeof(SOUT)) % 16 == 0;
+    __shared__ double lds[XW == 1 ? 1 : LineSolver<double, NT, C, false>::kLds];
+    LineSolver<double, NT, C, false> LS;
+    LS.load(tb, XW == 1 ? nullptr : lds);
     // Five rotating row buffers: row r uses the buffers of rows r-1, r, r+1
     // while rows r+2 .. r+4 are in flight.  Reads past the strip are clamped
     // to its last halo row (a cache hit), so no row is fetched from HBM twice.
+    // Every thread of a group runs the same rows, so the solver's barriers
+    // (XW = 2) match.
     SIN B[5][C];
     const int jl = min(j1, My - 1);
 #pragma unroll
     for (int q = 0; q < 5; ++q) load_row<C>(islice, min(j0 - 1 + q, jl), My, Mx, lane, vec, B[q]);
     for (int j = j0; j < j1; j += 5) {
-#define PIT_XSTEP(u)                                                                                       \
-    {                                                                                                      \
-        const int r = j + (u);                                                                             \
-        if (r >= j1) break;                                                                                \
-        x_row<C>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, ex, ed, oslice); \
-        load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                \
+#define PIT_XSTEP(u)                                                                                           \
+    {                                                                                                          \
+        const int r = j + (u);                                                                                 \
+        if (r >= j1) break;                                                                                    \
+        x_row<NT, C>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, ex, ed, oslice); \
+        load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                    \
     }
         PIT_XSTEP(0) PIT_XSTEP(1) PIT_XSTEP(2) PIT_XSTEP(3) PIT_XSTEP(4)
 #undef PIT_XSTEP
@@ -370,20 +380,20 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define PIT_ADI_XC(X) X(1) X(2) X(4) X(8) X(16)
+#define PIT_ADI_XC(X) X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 8)
 #define PIT_ADI_YSHAPES(X) X(8, 16, 1) X(8, 32, 1) X(16, 32, 1) X(8, 32, 2) X(16, 32, 2)
 
 template <typename SIN, typename SOUT>
-static hipError_t adi_x_t(int C, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,
-                          int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
+static hipError_t adi_x_t(const AdiShape &sh, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out,
+                          long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
 {
     const int strips = (My + R - 1) / R;
-    const int blocks = (nslices * strips + 3) / 4;
-#define X(c)                                                                                            \
-    if (C == c) {                                                                                       \
-        hipLaunchKernelGGL((k_adi_x<c, SIN, SOUT>), dim3(blocks), dim3(256), 0, st, tb, in, in_off, out, \
-                           out_off, nslices, Mx, My, R, ex, ed);                                        \
-        return hipGetLastError();                                                                       \
+    const int blocks = sh.xw == 1 ? (nslices * strips + 3) / 4 : nslices * strips;
+#define X(XW_, C_)                                                                                              \
+    if (sh.xw == XW_ && sh.cx == C_) {                                                                          \
+        hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT>), dim3(blocks), dim3(XW_ == 1 ? 256 : 128), 0, st, tb,   \
+                           in, in_off, out, out_off, nslices, Mx, My, R, ex, ed);                               \
+        return hipGetLastError();                                                                               \
     }
     PIT_ADI_XC(X)
 #undef X
@@ -412,11 +422,11 @@ hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in
                         long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
 {
     if (in.f32 && out.f32)
-        return adi_x_t<float, float>(sh.cx, tb, in.f, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<float, float>(sh, tb, in.f, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
     if (!in.f32 && out.f32)
-        return adi_x_t<double, float>(sh.cx, tb, in.d, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<double, float>(sh, tb, in.d, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
     if (!in.f32 && !out.f32)
-        return adi_x_t<double, double>(sh.cx, tb, in.d, in_off, out.d, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<double, double>(sh, tb, in.d, in_off, out.d, out_off, nslices, Mx, My, R, ex, ed, st);
     return hipErrorInvalidValue;
 }
 

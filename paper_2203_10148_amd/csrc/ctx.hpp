@@ -68,7 +68,7 @@ struct pit_ctx {
     // fine (theta = dt/2) and coarse (theta = DT/(2c)); explicit-part
     // coefficients: the x half step applies (I + theta Ly), the y half step
     // (I + theta Lx), each as ed*u + ex*(sum of the two neighbours).
-    AdiShape ash{0, 0, 0, 0};
+    AdiShape ash{0, 0, 0, 0, 1};
     LineHost axf, axc;
     std::vector<double> ayf, ayc;
     double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;

@@ -128,10 +128,11 @@ inline ColTab col_tab_view(const double *base, int nr)
 {
     return ColTab{base, base + nr, base + 2 * (size_t)nr, base + 3 * (size_t)nr, base + 3 * (size_t)nr + kMaxSegs};
 }
-// x: C points per lane (64 lanes per row); y: WY waves, each with SEG row
-// segments of CY rows (64/SEG columns per workgroup).
+// x: a row on XW wavefronts, cx points per thread (64*XW*cx >= Mx); y: WY
+// waves, each with SEG row segments of CY rows (64/SEG columns per
+// workgroup).
 struct AdiShape {
-    int cx, wy, cy, seg;
+    int cx, wy, cy, seg, xw;
 };
 // A field buffer of either precision.
 struct AdiBuf {

@@ -292,24 +292,28 @@ bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &
 bool setup_2d(pit_ctx &c)
 {
     const int Mx = c.pb.M[0], My = c.pb.M[1];
+    // rows up to 512 points on one wavefront (up to 8 points per lane), wider
+    // rows on two (128 threads x 8 points)
+    const int xw = Mx > 512 ? 2 : 1;
     int cx = 1;
-    while (64 * cx < Mx) cx *= 2;
+    while (64 * xw * cx < Mx) cx *= 2;
     // y shapes (waves, rows per segment, segments per wave), smallest first;
     // the kernels in adi2d.hip are instantiated for exactly these
     // (two segments of 32 rows beat one segment up to 512 rows: 32-column
     // blocks, twice as many workgroups and two resident per CU)
-    const AdiShape menu[] = {{0, 8, 16, 1}, {0, 8, 32, 1}, {0, 8, 32, 2}, {0, 16, 32, 2}, {0, 16, 32, 1}};
+    const AdiShape menu[] = {{0, 8, 16, 1, 0}, {0, 8, 32, 1, 0}, {0, 8, 32, 2, 0}, {0, 16, 32, 2, 0}, {0, 16, 32, 1, 0}};
     auto rows = [](const AdiShape &a) { return a.wy * a.cy * a.seg; };
-    AdiShape sh{cx, 0, 0, 0};
+    AdiShape sh{cx, 0, 0, 0, xw};
     for (const auto &a : menu)
         if (rows(a) >= My) {
             sh = a;
             sh.cx = cx;
+            sh.xw = xw;
             break;
         }
-    if (!sh.wy || cx > 16) return false;
+    if (!sh.wy || cx > 8) return false;
     if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {  // tuning override "wy,cy,seg"
-        AdiShape o{cx, 0, 0, 0};
+        AdiShape o{cx, 0, 0, 0, xw};
         if (std::sscanf(e, "%d,%d,%d", &o.wy, &o.cy, &o.seg) == 3 && rows(o) >= My)
             for (const auto &a : menu)
                 if (a.wy == o.wy && a.cy == o.cy && a.seg == o.seg) sh = o;
@@ -324,7 +328,7 @@ bool setup_2d(pit_ctx &c)
         yex = th * kx;                      // y half step: (I + th Lx)
         yed = 1.0 - 2.0 * th * kx - 0.5 * th * r;
         const bool okx = build_line(Mx, false, -th * kx, 1.0 + 2.0 * th * kx + 0.5 * th * r, -th * kx,
-                                    LineShape{64, cx}, ax);
+                                    LineShape{64 * xw, cx}, ax);
         const bool oky = build_col(My, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, sh.wy * sh.seg, sh.cy, ay);
         return okx && oky;
     };
@@ -386,7 +390,7 @@ hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int
     if (!raw && (e = launch_copy(y, lam, np, st)) != hipSuccess) return e;  // y_0 = lam_0
     if (ns == 0) return hipSuccess;
     const LineTab<double> tx = [&] {
-        LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64, c->ash.cx);
+        LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64 * c->ash.xw, c->ash.cx);
         t.cyclic = 0;
         t.M = Mx;
         return t;
@@ -417,7 +421,7 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
     const long np = c->npts;
     hipError_t e;
     if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
-    LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axc), 64, c->ash.cx);
+    LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axc), 64 * c->ash.xw, c->ash.cx);
     tx.cyclic = 0;
     tx.M = Mx;
     const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayc), c->ash.wy * c->ash.cy * c->ash.seg);
@@ -602,7 +606,7 @@ int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4])
 {
     if (!ctx || !out) return PIT_EINVAL;
     if (ctx->dim2()) {  // 2D: 64 lanes x cx points per row; wy waves x cy rows per column
-        out[0] = 64;
+        out[0] = 64 * ctx->ash.xw;
         out[1] = ctx->ash.cx;
         out[2] = 64 * ctx->ash.wy;
         out[3] = ctx->ash.cy * ctx->ash.seg;

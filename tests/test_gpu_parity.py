@@ -390,6 +390,7 @@ ADI_CASES = [
     (100, 70, 1.0, 0.7, 3, 4, 2, wl.F32),
     (512, 512, 1.0, 1.0, 3, 3, 1, wl.F32),
     (300, 600, 1.0, 1.2, 2, 2, 1, wl.F64),     # 600 rows: two row segments per wavefront
+    (700, 130, 1.0, 0.8, 2, 3, 2, wl.F64),     # 700-point rows on two wavefronts, ragged
     (1024, 1024, 1.0, 1.0, 2, 4, 1, wl.F32, 1.8e-3),   # largest side; time step of the served 2D requests
 ]
 
