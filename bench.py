@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="c4: keep the default line shapes")
     ap.add_argument("--no-compare", action="store_true", help="c1/c2: skip the solve in the other fine precision")
     ap.add_argument("--side", type=int, default=None, help="c3: grid side (default 512)")
+    ap.add_argument("--no-singles", action="store_true", help="c4: skip the single-instance baseline solves")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -386,6 +387,21 @@ def main():
                                   "when tol is below it"}
         log(f"[bench] compare {out['compare']['form']}: {out['compare']['time_to_tol_ms']:.2f} ms, "
             f"status {io.status}, iters {io.iters}, rel. diff {diff:.2e}")
+    # parareal (Sec. 2, eq. (pararealAlgebraic)) on the same input and kernels,
+    # to the same tolerance on its update norm: the paper's comparison
+    if not args.no_compare:
+        Xp = torch.empty_like(X)
+        ctx.parareal(u0, Xp, tol=p.tol)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(2):
+            _, ip = ctx.parareal(u0, Xp, tol=p.tol)
+            times.append(ip.ms_total)
+        out["compare_parareal"] = {"time_to_tol_ms": float(np.median(times)), "status": ip.status,
+                                   "iters": ip.iters, "matvecs": ip.matvecs, "final_update_norm": ip.res_norm,
+                                   "pitsbicg_matvecs": matvecs}
+        log(f"[bench] parareal: {float(np.median(times)):.2f} ms, {ip.iters} iterations ({ip.matvecs} products) "
+            f"vs PiTSBiCG {matvecs} products")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds)
@@ -442,22 +458,29 @@ def bench_batch(args, dev):
     log(f"[bench] batch: {ms:.1f} ms per batched solve, {st.count(0)} of {len(st)} reached tol")
 
     def singles(prec):
-        tot, its = 0.0, 0
+        tot, its, mx = 0.0, 0, 0.0
         for p, u in zip(probs, u0s):
             c = P.Context(p.with_(prec=prec), device=dev)
             torch.cuda.synchronize()
             t = time.perf_counter()
             _, inf = c.solve(u, tol=1e-8, stall_window=10)
             torch.cuda.synchronize()
-            tot += time.perf_counter() - t
+            dt = time.perf_counter() - t
+            tot += dt
+            mx = max(mx, dt)
             its += inf.iters
             c.close()
-        return tot, its
+        return tot, its, mx
 
-    s64, it64 = singles(wl.F64)
-    log(f"[bench] single-instance plain FP64: {s64 * 1e3:.1f} ms summed")
-    s32, it32 = singles(wl.F32)
-    log(f"[bench] single-instance FP32: {s32 * 1e3:.1f} ms summed")
+    if args.no_singles:
+        out = {"metric": "c4 batch only", "makespan_ms": ms, "value": cells * args.steps / elapsed,
+               "reached_tol": st.count(0)}
+        print(json.dumps(out), flush=True)
+        return
+    s64, it64, m64 = singles(wl.F64)
+    log(f"[bench] single-instance plain FP64: {s64 * 1e3:.1f} ms summed, slowest {m64 * 1e3:.1f} ms")
+    s32, it32, m32 = singles(wl.F32)
+    log(f"[bench] single-instance FP32: {s32 * 1e3:.1f} ms summed, slowest {m32 * 1e3:.1f} ms")
     out = {
         "metric": "fine cell-updates/s, 64-instance batched PiTSBiCG (FP32 fine, tol 1e-8), 1 GPU",
         "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -470,6 +493,7 @@ def bench_batch(args, dev):
                   "iters": [i.iters for i in infos],
                   "sum_single_fp64_ms": s64 * 1e3, "sum_single_fp64_iters": it64,
                   "sum_single_fp32_ms": s32 * 1e3, "sum_single_fp32_iters": it32,
+                  "slowest_single_fp64_ms": m64 * 1e3, "slowest_single_fp32_ms": m32 * 1e3,
                   "speedup_vs_single_fp64": s64 * 1e3 / ms, "speedup_vs_single_fp32": s32 * 1e3 / ms},
     }
     print(json.dumps(out), flush=True)

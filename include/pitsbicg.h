@@ -319,6 +319,24 @@ int pit_server_load(pit_server *s, int32_t *queued, int32_t *running, uint64_t *
 /* Finish every queued and running request, stop the worker, free host state. */
 int pit_server_destroy(pit_server *s);
 
+/* ---- parareal ------------------------------------------------------------- */
+
+/* Parareal in its algebraic form (Sec. 2, eq. (pararealAlgebraic)): the
+ * Richardson iteration on the preconditioned system,
+ *     X^{k+1} = X^k + G^{-1}(B - F X^k),
+ * one preconditioned product per iteration (Algorithm 1 uses two), on the
+ * same fine apply and coarse sweep.  It is exact after N iterations.
+ * history[k] receives ||G^{-1}(B - F X^k)||_{N,inf} (the norm of the update).
+ * Stops after the update whose norm passes the test of opts->tol (absolute,
+ * or relative to the first with PIT_REL), or after max_iter iterations
+ * (default N + 1: X^N is exact and the next update, zero up to rounding,
+ * shows it); tol 0 runs exactly max_iter iterations and returns PIT_OK.
+ * opts->x0_mode as pit_solve; restart_tol, half_step_check and stall_window
+ * are ignored.  Host-synchronous.  Returns PIT_OK, PIT_ENOCONV (max_iter
+ * reached above tol), PIT_EBREAKDOWN, PIT_EINVAL or PIT_EHIP. */
+int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
+                 pit_solve_info *info, void *stream);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 
 /* Static description of an error code. */

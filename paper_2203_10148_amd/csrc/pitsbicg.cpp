@@ -1057,3 +1057,95 @@ int pit_autotune_reset(void)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Parareal as preconditioned Richardson (Sec. 2, eq. (pararealAlgebraic)):
+//   X^{k+1} = X^k + G^{-1}(B - F X^k),
+// one preconditioned product per iteration on the same apply and sweep as
+// Algorithm 1; exact after N iterations (the iteration matrix I - G^{-1}F is
+// nilpotent).
+// ---------------------------------------------------------------------------
+extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
+                            pit_solve_info *info, void *stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !ctx->ws || !u0 || !X) return PIT_EINVAL;
+    pit_solve_opts o{};
+    o.tol = 0.0;
+    o.max_iter = 0;
+    o.norm_mode = PIT_ABS;
+    o.x0_mode = PIT_X0_ZERO;
+    if (opts) o = *opts;
+    // X^N is exact; the (N+1)-th update (zero up to rounding) is what shows it
+    if (o.max_iter <= 0) o.max_iter = ctx->N + 1;
+    if (o.x0_mode < PIT_X0_ZERO || o.x0_mode > PIT_X0_COARSE || !(o.tol >= 0.0)) return PIT_EINVAL;
+    Solver s{};
+    s.c = ctx;
+    s.st = static_cast<hipStream_t>(stream);
+    s.timing = o.timing != 0;
+    const long n = ctx->ntc();
+    const int NT = ctx->lf.sh.NT, C = ctx->lf.sh.C;
+    hipStream_t st = s.st;
+    double *const Xu = X;
+    double *const Xc = ctx->vec(7), *const R = ctx->vec(0), *const U0 = ctx->vec(1);
+    // u0 in the working layout (slice 0 of B)
+    PIT_HIP(launch_fill0(U0, n, st));
+    if (ctx->dim2()) PIT_HIP(launch_copy(U0, u0, ctx->npts, st));
+    else PIT_HIP(launch_to_chunked(u0, U0, 1, ctx->npts, NT, C, st));
+    int rc;
+    if (o.x0_mode == PIT_X0_ZERO) {
+        PIT_HIP(launch_fill0(Xc, n, st));
+    } else if (o.x0_mode == PIT_X0_COARSE) {
+        if ((rc = s.sweep(U0, Xc))) return rc;
+    } else if (ctx->dim2()) {
+        PIT_HIP(launch_copy(Xc, Xu, n, st));
+    } else {
+        PIT_HIP(launch_to_chunked(Xu, Xc, ctx->N, ctx->npts, NT, C, st));
+    }
+    RedOut h{};
+    double nrm = 0.0, scale = 1.0;
+    int k = 0, hl = 0, status = PIT_ENOCONV;
+    for (; k < o.max_iter; ++k) {
+        // R = G^{-1}(B - F X)
+        if ((rc = s.apply(Xc, R))) return rc;
+        PIT_HIP(launch_b_minus(R, R, U0, ctx->ld, n, st));
+        if ((rc = s.sweep(R, R))) return rc;
+        s.matvecs++;
+        {
+            const double *a[1] = {R}, *b[1] = {R};
+            if ((rc = s.reduce(1, a, b, h))) return rc;
+        }
+        nrm = h.nmax[0];
+        if (k == 0 && o.norm_mode == PIT_REL && nrm > 0.0) scale = nrm;
+        if (info && info->history && hl < info->history_cap) info->history[hl++] = nrm;
+        PIT_HIP(launch_axpby(Xc, Xc, 1.0, R, 1.0, n, st));  // X^{k+1} = X^k + R^k
+        if (!std::isfinite(nrm)) {
+            status = PIT_EBREAKDOWN;
+            ++k;
+            break;
+        }
+        if (!(nrm > o.tol * scale)) {
+            status = PIT_OK;
+            ++k;
+            break;
+        }
+    }
+    if (status == PIT_ENOCONV && o.tol == 0.0) status = PIT_OK;  // a fixed number of iterations asked for
+    if (ctx->dim2()) PIT_HIP(launch_copy(Xu, Xc, n, st));
+    else PIT_HIP(launch_from_chunked(Xc, Xu, ctx->N, ctx->npts, NT, C, st));
+    PIT_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->status = status;
+        info->iters = k;
+        info->matvecs = s.matvecs;
+        info->restarts = 0;
+        info->res_norm = nrm;
+        info->history_len = hl;
+        info->n_fine = s.n_fine;
+        info->n_coarse = s.n_coarse;
+        info->ms_fine = s.timing ? Solver::total_ms(s.ev_fine) : 0.0f;
+        info->ms_coarse = s.timing ? Solver::total_ms(s.ev_coarse) : 0.0f;
+        info->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}

@@ -83,6 +83,7 @@ EXPORTS = (
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
     "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
+    "pit_parareal",
 )
 
 _lib = None
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH):
     lib.pit_apply_F.argtypes = [vp, vp, vp, i32, vp]
     lib.pit_coarse_sweep.argtypes = [vp, vp, vp, vp]
     lib.pit_solve.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
+    lib.pit_parareal.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
     lib.pit_strerror.argtypes = [ct.c_int]
     lib.pit_strerror.restype = ct.c_char_p
     lib.pit_last_hip_error.restype = ct.c_int
@@ -280,6 +282,26 @@ class Context:
                               _stream(stream))
         if rc in (EINVAL, EHIP) or (raise_on_error and rc < 0):
             raise PitError(rc, "pit_solve")
+        return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
+                            hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
+                            info.ms_coarse, info.n_fine, info.n_coarse)
+
+    def parareal(self, u0, X=None, *, tol=0.0, max_iter=0, norm_mode=ABS, x0_mode=X0_ZERO, hist_cap=4096,
+                 stream=None, timing=False):
+        """Parareal (Richardson form) with the library's apply and sweep; returns (X, SolveInfo)."""
+        import torch
+
+        if X is None:
+            X = torch.empty(self.p.N * self.p.npts, dtype=torch.float64, device=u0.device)
+        o = pit_solve_opts(tol, 0.0, max_iter, norm_mode, x0_mode, 0, 0, 1 if timing else 0)
+        hist = np.zeros(hist_cap, dtype=np.float64)
+        info = pit_solve_info()
+        info.history = hist.ctypes.data_as(ct.POINTER(ct.c_double))
+        info.history_cap = hist_cap
+        rc = load().pit_parareal(self._h, _ptr(u0, self.p.npts), _ptr(X, self.p.N * self.p.npts), ct.byref(o),
+                                 ct.byref(info), _stream(stream))
+        if rc in (EINVAL, EHIP):
+            raise PitError(rc, "pit_parareal")
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
                             info.ms_coarse, info.n_fine, info.n_coarse)

@@ -243,6 +243,41 @@ def test_g_equals_f_and_single_slice():
     assert relerr(Xg, u0) < 1e-15
 
 
+PARAREAL_CASES = {
+    "heat64": wl.C1,
+    "periodic1000": wl.Problem(dim=1, M=(1000, 1), bc=wl.PERIODIC, nu=1e-3, adv=(1.0, 0.0), T=1.0, N=12, m=20,
+                               fine=wl.CN, c=2, coarse=wl.IE, prec=wl.F64),
+    "adi40x33": wl.Problem(dim=2, M=(40, 33), length=(1.0, 1.0), nu=0.05, T=0.5, N=8, m=8, fine=wl.ADI, c=1,
+                           coarse=wl.ADI, prec=wl.F64),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PARAREAL_CASES))
+def test_parareal_matches_oracle_and_is_exact_at_n(name):
+    """Parareal as preconditioned Richardson (Sec. 2, eq. (pararealAlgebraic)):
+    k iterations against the oracle's (iterate and update norms), and N
+    iterations against the serial fine trajectory (nilpotency)."""
+    p = PARAREAL_CASES[name]
+    say(f"parareal {name}")
+    o = make_oracle(p)
+    u0 = wl.u0_bumps(p, 3) if p.dim == 2 else u0_of(p)
+    c = ctx(p)
+    k = 3
+    Xo, ho = o.parareal_richardson(u0, k)
+    Xg, ig = c.parareal(dev(u0), max_iter=k)
+    assert ig.status == orc.OK and ig.iters == k and ig.matvecs == k
+    assert relerr(host(Xg), Xo) < 1e-12
+    assert np.allclose(ig.history, ho, rtol=1e-10, atol=1e-300)
+    Xn, inn = c.parareal(dev(u0), max_iter=p.N)
+    e = relerr(host(Xn), o.serial(u0))
+    print(f"{name}: {k} iterations vs oracle {relerr(host(Xg), Xo):.2e}; N={p.N} iterations vs serial {e:.2e}",
+          flush=True)
+    assert e < 1e-12
+    # with a tolerance: stops after the first update below it
+    Xt, it = c.parareal(dev(u0), tol=1e-6)
+    assert it.status == orc.OK and it.history[-1] <= 1e-6 and (len(it.history) == 1 or it.history[-2] > 1e-6)
+
+
 def test_nan_input_is_a_breakdown():
     from paper_2203_10148_amd import pitsbicg as P
 
