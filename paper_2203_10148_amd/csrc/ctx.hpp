@@ -74,6 +74,20 @@ struct pit_ctx {
     double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
     size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
     int adi_R = 32;  // rows per wavefront in the fine x half step
+    // 2D: the launch sequences of the fine apply (2m launches) and of the
+    // coarse sweep (2(N-1)c launches) captured as HIP graphs, one per
+    // (operation, input, output), replayed on the caller's stream
+    struct Graph {
+        int op;
+        const void *in;
+        void *out;
+        int raw, last;
+        hipGraphExec_t exec;
+    };
+    mutable std::vector<Graph> graphs;
+    mutable hipStream_t capture = nullptr;
+    void drop_graphs() const;
+    ~pit_ctx();
     bool dim2() const { return pb.dim == 2; }
     AdiBuf fbuf(size_t off) const
     {

@@ -445,16 +445,71 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
 
 }  // namespace
 
+void pit_ctx::drop_graphs() const
+{
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
+
+pit_ctx::~pit_ctx()
+{
+    drop_graphs();
+    if (capture) (void)hipStreamDestroy(capture);
+}
+
+namespace {
+
+// Graph replay is on unless PIT_GRAPHS=0 (eager launches, for comparison).
+bool graphs_enabled()
+{
+    const char *e = std::getenv("PIT_GRAPHS");
+    return !(e && e[0] == '0');
+}
+
+// Run the launch sequence `launches` as a HIP graph: captured once per
+// (op, in, out, flags) on the context's own capture stream (a capture cannot
+// run on the legacy null stream), then replayed on `st`.  The sequences hold
+// kernels only.
+template <class F>
+hipError_t replay(const pit_ctx *c, int op, const void *in, void *out, int raw, int last, hipStream_t st,
+                  F &&launches)
+{
+    if (!graphs_enabled()) return launches(st);
+    for (const auto &g : c->graphs)
+        if (g.op == op && g.in == in && g.out == out && g.raw == raw && g.last == last)
+            return hipGraphLaunch(g.exec, st);
+    if (c->graphs.size() >= 8) c->drop_graphs();  // bounded: callers cycle through few buffers
+    hipError_t e;
+    if (!c->capture && (e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t el = launches(c->capture);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(c->capture, &gr);
+    if (el != hipSuccess || e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return el != hipSuccess ? el : e;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return e;
+    c->graphs.push_back(pit_ctx::Graph{op, in, out, raw, last, ex});
+    return hipGraphLaunch(ex, st);
+}
+
+}  // namespace
+
 hipError_t pit::op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal,
                          hipStream_t st)
 {
-    if (c->dim2()) return apply_2d(c, lam, y, raw, last, st);
+    if (c->dim2())
+        return replay(c, 0, lam, y, raw, last, st, [&](hipStream_t s) { return apply_2d(c, lam, y, raw, last, s); });
     return fine_launch(c, lam, y, raw, last, internal, st);
 }
 
 hipError_t pit::op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
 {
-    if (c->dim2()) return sweep_2d(c, v, z, st);
+    if (c->dim2()) return replay(c, 1, v, z, 0, 0, st, [&](hipStream_t s) { return sweep_2d(c, v, z, s); });
     return launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), v, z, c->N, c->npts, c->coarse.substeps,
                               c->coarse.scheme, internal, st);
 }
@@ -625,6 +680,7 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
     if (bytes < ctx->total) return PIT_ENOMEM;
     ctx->ws = static_cast<char *>(dev_ptr);
     ctx->ws_bytes = bytes;
+    ctx->drop_graphs();  // captured launches point into the old workspace
     if (ctx->dim2()) {
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_axf, ctx->axf.blob.data(), ctx->axf.blob.size() * sizeof(double),
                           hipMemcpyHostToDevice));

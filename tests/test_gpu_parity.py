@@ -481,6 +481,33 @@ def test_adi_one_segment_shape_on_a_short_column(monkeypatch):
     assert relerr(host(c.coarse_sweep(dev(lam))), o.sweep(lam)) < 1e-12
 
 
+def test_adi_graph_replays_equal_eager_launches(monkeypatch):
+    """The 2D apply and sweep run as captured HIP graphs; every replay, with
+    other work and synchronisations in between, gives the bits of the eager
+    launch sequence (PIT_GRAPHS=0)."""
+    p = adi_problem(100, 70, 1.0, 0.7, 4, 3, 2, wl.F32)
+    say("adi graph replays")
+    lam1, lam2 = dev(wl.random_block(p, 21)), dev(wl.random_block(p, 22))
+    monkeypatch.setenv("PIT_GRAPHS", "0")
+    ce = ctx(p)
+    ref = [host(ce.apply_F(lam1)), host(ce.coarse_sweep(lam1)), host(ce.apply_F(lam2)), host(ce.coarse_sweep(lam2))]
+    monkeypatch.delenv("PIT_GRAPHS")
+    cg = ctx(p)
+    y1, z1 = torch.empty_like(lam1), torch.empty_like(lam1)
+    y2, z2 = torch.empty_like(lam2), torch.empty_like(lam2)
+    for rep in range(3):
+        cg.apply_F(lam1, y1)
+        scratch = lam2 * 2.0 + 1.0  # other work on the stream between replays
+        cg.coarse_sweep(lam1, z1)
+        torch.cuda.synchronize()
+        cg.apply_F(lam2, y2)
+        cg.coarse_sweep(lam2, z2)
+        got = [host(y1), host(z1), host(y2), host(z2)]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+        del scratch
+
+
 @pytest.mark.parametrize("prec", [wl.F64, wl.F32])
 def test_adi_small_solve_matches_oracle(prec):
     p = wl.Problem(dim=2, M=(40, 33), length=(1.0, 1.0), nu=0.05, T=0.5, N=8, m=8, fine=wl.ADI, c=1,
