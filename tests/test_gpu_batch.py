@@ -369,3 +369,56 @@ def test_autotuned_shape_is_used_and_correct():
     assert relerr(host(X), Xo) < 1e-9
     P.autotune_reset()
     assert P.Context(p).kernel_shape()[:2] == default
+
+
+def test_batch_rejects_bad_requests_before_any_work():
+    P = P_()
+    say("batch argument checks")
+    p = wl.C1
+    c1, c2 = P.Context(p), P.Context(p)
+    u0 = dev(u0_of(p))
+    b = P.Batch(4)
+    Xs, infos = b.solve([], [])  # an empty batch is a no-op
+    assert Xs == [] and infos == []
+    with pytest.raises(P.PitError):  # the same context twice
+        b.solve([c1, c1], [u0, u0])
+    lib = P.load()
+    import ctypes as ct
+    hs = (ct.c_void_p * 1)(c2._h.value)
+    u = (ct.c_void_p * 1)(u0.data_ptr())
+    X = torch.empty(p.N * p.npts, dtype=torch.float64, device="cuda")
+    x = (ct.c_void_p * 1)(X.data_ptr())
+    o = (P.pit_solve_opts * 1)(P.pit_solve_opts(1e-10, 1e-30, 0, P.ABS, P.X0_GIVEN, 0, 0, 0))
+    assert lib.pit_batch_solve(b._h, hs, 1, u, x, o, None, None) == P.EINVAL  # x0 given: not batched
+    o[0].x0_mode, o[0].half_step_check = P.X0_ZERO, 1
+    assert lib.pit_batch_solve(b._h, hs, 1, u, x, o, None, None) == P.EINVAL
+    assert lib.pit_batch_solve(b._h, hs, 5, u, x, None, None, None) == P.EINVAL  # above max_count
+
+
+def test_server_retires_tickets_and_drains_on_destroy():
+    """A polled result retires its ticket (a second poll is EINVAL);
+    destroying the server finishes queued and running requests first."""
+    P = P_()
+    say("server tickets and drain")
+    probs = FP64_SET[:3]
+    srv = P.Server(4 << 30, max_slots=2)
+    u0s = [dev(u0_of(p)) for p in probs]
+    Xs = [torch.full((p.N * p.npts,), float("nan"), dtype=torch.float64, device="cuda") for p in probs]
+    torch.cuda.synchronize()
+    t0 = srv.submit(probs[0], u0s[0], Xs[0], tol=1e-10)
+    r = None
+    deadline = time.time() + 60
+    while r is None and time.time() < deadline:
+        r = srv.poll(t0)
+        time.sleep(0.001)
+    assert r is not None and r.status == orc.OK
+    with pytest.raises(P.PitError):
+        srv.poll(t0)
+    with pytest.raises(P.PitError):
+        srv.poll(987654321)
+    for i in (1, 2):
+        srv.submit(probs[i], u0s[i], Xs[i], tol=1e-10)
+    srv.close()  # waits for both
+    Xb, ib = batch_solve(probs[1:], tol=1e-10)
+    for a, b in zip(Xs[1:], Xb):
+        assert np.array_equal(host(a), b)

@@ -276,6 +276,13 @@ def test_parareal_matches_oracle_and_is_exact_at_n(name):
     # with a tolerance: stops after the first update below it
     Xt, it = c.parareal(dev(u0), tol=1e-6)
     assert it.status == orc.OK and it.history[-1] <= 1e-6 and (len(it.history) == 1 or it.history[-2] > 1e-6)
+    # from a given iterate (the oracle's X^1) and from the coarse trajectory (= X^1 from zero)
+    X1, _ = o.parareal_richardson(u0, 1)
+    Xo2, _ = o.parareal_richardson(u0, 2, X0=X1)
+    Xg2, _ = c.parareal(dev(u0), dev(X1.copy()), max_iter=2, x0_mode=orc.X0_GIVEN)
+    assert relerr(host(Xg2), Xo2) < 1e-12
+    Xc2, _ = c.parareal(dev(u0), max_iter=2, x0_mode=orc.X0_COARSE)
+    assert relerr(host(Xc2), Xo2) < 1e-12
 
 
 def test_nan_input_is_a_breakdown():
