@@ -106,12 +106,12 @@ typedef struct {
 /* Options of Algorithm 1 (Sec. 3): tolerance epsilon, restart tolerance
  * epsilon_0, initial guess X^0. */
 typedef struct {
-    double tol;              /* epsilon of the stopping test (line 5)               */
-    double restart_tol;      /* epsilon_0 of the restart test (lines 15-17)         */
+    double tol;              /* epsilon of the stopping test                        */
+    double restart_tol;      /* epsilon_0 of the restart test                       */
     int32_t max_iter;        /* <= 0 means 2*N                                      */
     int32_t norm_mode;       /* PIT_ABS (the test as written) or PIT_REL            */
     int32_t x0_mode;         /* PIT_X0_ZERO, PIT_X0_GIVEN, PIT_X0_COARSE            */
-    int32_t half_step_check; /* !=0: also stop after line 8 when ||S|| <= tol       */
+    int32_t half_step_check; /* !=0: also stop after S = R - alpha D if ||S|| <= tol */
     int32_t stall_window;    /* >0: PIT_ENOCONV when ||R|| has not halved in this
                                 many iterations (for FP32 fine propagators)         */
     int32_t timing;          /* !=0: time every fine apply and coarse sweep with HIP
@@ -124,7 +124,7 @@ typedef struct {
     int32_t status;   /* same value pit_solve returns                         */
     int32_t iters;    /* completed passes of the loop                         */
     int32_t matvecs;  /* applications of G^{-1} F (2 per iteration, +1 for X^0) */
-    int32_t restarts; /* shadow-residual restarts (lines 15-17 and breakdowns) */
+    int32_t restarts; /* shadow-residual restarts (restart test and breakdowns) */
     double res_norm;  /* last ||R||_{N,inf}                                    */
     double *history;  /* host, may be NULL                                     */
     int32_t history_cap;

@@ -433,13 +433,13 @@ static void precond_apply(const orc_ctx *C, const double *in, double *out)
  * Readings where the algorithm is silent:
  *  - stopping test ||R^k||_{N,inf} > tol, absolute (norm_mode ORC_ABS) or
  *    relative to ||R^0|| (ORC_REL);
- *  - restart (lines 15-17) replaces both the shadow residual and the *new*
+ *  - the restart (test with epsilon_0) replaces both the shadow residual and the *new*
  *    direction P^{k+1} by R^{k+1}; rho is then <R^{k+1}, R^{k+1}>;
  *  - <D,Rt> == 0: restart with the current R and redo the direction;
  *    <K,K> == 0 (then S = 0): X += alpha P, R = S, stop;
  *    omega == 0 with K != 0: X += alpha P, R = S, then restart;
  *    a NaN/Inf norm stops with ORC_EBREAKDOWN;
- *  - half_step_check != 0 stops after line 8 when ||S|| <= tol;
+ *  - half_step_check != 0 stops after S = R - alpha D when ||S|| <= tol;
  *  - stall_window > 0: stop with ORC_ENOCONV when ||R|| has not halved over
  *    the last stall_window iterations (used for reduced-precision fine solvers).
  */
@@ -461,7 +461,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
 
     memcpy(B, u0, sizeof(double) * np); /* B = (lambda_0, 0, ..., 0) */
 
-    /* line 1: R^0 = G^{-1}(B - F X^0) */
+    /* initial residual R^0 = G^{-1}(B - F X^0) */
     if (x0_mode == ORC_X0_ZERO) {
         memset(X, 0, sizeof(double) * nt);
         orc_sweep(C, B, R);
@@ -472,7 +472,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
         orc_sweep(C, Tm, R);
         matvecs++;
     }
-    /* lines 2-4 */
+    /* shadow residual, first direction, rho */
     memcpy(Rt, R, sizeof(double) * nt);
     memcpy(P, R, sizeof(double) * nt);
     double rho = orc_dot(C, R, Rt);
@@ -487,7 +487,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
             status = ORC_EBREAKDOWN;
             break;
         }
-        /* line 5 */
+        /* stopping test */
         if (!(nrm > tol * scale)) {
             status = ORC_OK;
             break;
@@ -505,7 +505,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
                 break;
             }
         }
-        /* line 6: D = G^{-1} F P */
+        /* D = G^{-1} F P */
         precond_apply(C, P, D);
         matvecs++;
         double dr = orc_dot(C, D, Rt);
@@ -522,9 +522,9 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
                 break;
             }
         }
-        /* line 7 */
+        /* alpha */
         double alpha = rho / dr;
-        /* line 8: S = R - alpha D */
+        /* S = R - alpha D */
         for (size_t i = 0; i < nt; ++i) S[i] = R[i] - alpha * D[i];
         if (half_step_check && !(orc_norm(C, S) > tol * scale)) {
             for (size_t i = 0; i < nt; ++i) X[i] += alpha * P[i];
@@ -532,7 +532,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
             k++;
             continue; /* the head of the loop tests ||R|| = ||S|| and stops */
         }
-        /* line 9: K = G^{-1} F S */
+        /* K = G^{-1} F S */
         precond_apply(C, S, K);
         matvecs++;
         double ks = orc_dot(C, K, S);
@@ -543,7 +543,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
             k++;
             continue;
         }
-        /* line 10 */
+        /* omega */
         double omega = ks / kk;
         if (omega == 0.0) {
             for (size_t i = 0; i < nt; ++i) X[i] += alpha * P[i];
@@ -555,17 +555,17 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
             k++;
             continue;
         }
-        /* lines 11-12 */
+        /* X and R updates */
         for (size_t i = 0; i < nt; ++i) {
             X[i] = X[i] + alpha * P[i] + omega * S[i];
             R[i] = S[i] - omega * K[i];
         }
-        /* line 13 */
+        /* beta */
         double rho_new = orc_dot(C, R, Rt);
         double beta = (alpha / omega) * (rho_new / rho);
-        /* line 14 */
+        /* new direction P */
         for (size_t i = 0; i < nt; ++i) P[i] = R[i] + beta * (P[i] - omega * D[i]);
-        /* lines 15-17 */
+        /* restart test with epsilon_0 */
         if (fabs(rho_new) <= eps0) {
             memcpy(Rt, R, sizeof(double) * nt);
             memcpy(P, R, sizeof(double) * nt);
@@ -573,7 +573,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
             restarts++;
         }
         rho = rho_new;
-        /* line 18 */
+        /* next iteration */
         k++;
     }
     if (info) {

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 {
     constexpr int CW = kWave / SEG, NS = WY * SEG, NR = NS * CY;
     static_assert(SEG == 1 || SEG == 2, "one or two segments per wave");
-    static_assert(SEG == 1 ? (2 * CY <= kWave) : (CY == 32), "halo lanes");
+    static_assert(2 * CY <= kWave, "halo lanes");
     __shared__ double s_lm[NR], s_iu[NR], s_cm[NR];
     __shared__ double s_pf[NS], s_pb[NS];
     __shared__ double s_agg[2][NS][CW];
@@ -287,8 +287,13 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
             hl = readlane(hv, r);
             hr = (2 * HR > kWave) ? readlane(hv2, r) : readlane(hv, HR + (r % (kWave - HR + 1)));
         } else {
+            // segment sg's row r is the wave's row sg*CY + r; its left halo sits
+            // in that lane of hv, its right halo in the same lane of hv2 or, when
+            // both fit one load, HR lanes further up in hv
+            constexpr bool split = 2 * HR <= kWave;
             const SIN l0 = readlane(hv, r), l1 = readlane(hv, CY + r);
-            const SIN r0v = readlane(hv2, r), r1v = readlane(hv2, CY + r);
+            const SIN r0v = split ? readlane(hv, HR + r) : readlane(hv2, r);
+            const SIN r1v = split ? readlane(hv, HR + CY + r) : readlane(hv2, CY + r);
             hl = sg ? l1 : l0;
             hr = sg ? r1v : r0v;
         }
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 // launchers
 // ---------------------------------------------------------------------------
 #define PIT_ADI_XC(X) X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 8)
-#define PIT_ADI_YSHAPES(X) X(8, 16, 1) X(8, 32, 1) X(16, 32, 1) X(8, 32, 2) X(16, 32, 2)
+#define PIT_ADI_YSHAPES(X) X(8, 16, 1) X(8, 32, 1) X(16, 32, 1) X(8, 32, 2) X(16, 32, 2) X(8, 16, 2) X(16, 16, 2)
 
 template <typename SIN, typename SOUT>
 static hipError_t adi_x_t(const AdiShape &sh, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out,

@@ -4,11 +4,11 @@
 // Every instance runs the same control flow as pit_solve (the host decides
 // after each reduction, with the same scalars and the same branches), split
 // into phases that end at a reduction:
-//   INIT      R = G^{-1} B, shadow R = P = R, <R,Rt>, <R,R>            (line 1-4)
-//   A         P = R + beta(P - omega D) (deferred line 14), D = G^{-1}F P, <D,Rt>
+//   INIT      R = G^{-1} B, shadow R = P = R, <R,Rt>, <R,R>
+//   A         P = R + beta(P - omega D) (deferred), D = G^{-1}F P, <D,Rt>
 //   A_RESTART shadow R = P = R, <R,R>          (breakdown <D,Rt> = 0, then A again)
-//   B         S = R - alpha D, K = G^{-1}F S, <K,S>, <K,K>, <S,S>      (lines 8-9)
-//   C         X += alpha P + omega S, R = S - omega K, <R,Rt>, <R,R>   (lines 11-13)
+//   B         S = R - alpha D, K = G^{-1}F S, <K,S>, <K,K>, <S,S>
+//   C         X += alpha P + omega S, R = S - omega K, <R,Rt>, <R,R>
 //   W0        X += alpha P, R = S, shadow R = P = R, <R,R>   (omega = 0 restart)
 //   FINAL     X out of the working layout
 // An instance whose phase has completed is "ready"; every scheduling round
@@ -249,6 +249,17 @@ class Engine {
             groups.pop_back();
             groups.back().insert(groups.back().end(), last.begin(), last.end());
         }
+        // a group larger than the cap gives its longest-phase members their own
+        // smaller group when a stream is free for it
+        const int gmax = group_cap();
+        for (size_t gi = 0; gi < groups.size() && (int)groups.size() < free1; ++gi) {
+            auto &gr = groups[gi];
+            if ((int)gr.size() <= gmax) continue;
+            std::stable_sort(gr.begin(), gr.end(), [](const Inst *a, const Inst *b) { return phase_us(a) > phase_us(b); });
+            std::vector<Inst *> head(gr.begin(), gr.begin() + gmax);
+            gr.erase(gr.begin(), gr.begin() + gmax);
+            groups.insert(groups.begin() + gi, std::move(head));
+        }
         if (free1 > 0) {
             for (auto &g : groups) {
                 Lane *L = free_lane();
@@ -326,6 +337,16 @@ class Engine {
         bound_ = false;
     }
 
+    // Instances per scheduling round before a group is split (PIT_BATCH_GROUP_MAX).
+    static int group_cap()
+    {
+        // default 4: on the 64-instance batch, caps of 4 / 8 / 16 / none gave
+        // makespans of 360 / 373 / 380 / 400 ms
+        const char *e = std::getenv("PIT_BATCH_GROUP_MAX");
+        const int v = e ? std::atoi(e) : 4;
+        return v > 0 ? v : 1 << 30;
+    }
+
     // Expected length of a 1D instance's next phase (microseconds, rough):
     // a fine apply is m chained line solves, a coarse sweep (N-1)c of them,
     // a line solve about (0.5 + M/8192) us; the other phases are short.
@@ -367,7 +388,7 @@ class Engine {
         in->ph = PH_FINAL;
     }
 
-    // line 5 and the loop guards, at the head of an iteration
+    // the stopping test and the loop guards, at the head of an iteration
     void test(Inst *in)
     {
         const pit_solve_opts &o = in->o;
@@ -403,11 +424,11 @@ class Engine {
             const double dr = h.dot[0];
             if (dr == 0.0) {
                 if (in->second_try) return to_final(in, PIT_EBREAKDOWN);
-                in->pend_restart = true;  // restart with the current residual, redo line 6
+                in->pend_restart = true;  // restart with the current residual, redo D = G^{-1}F P
                 in->ph = PH_A_RESTART;
                 return;
             }
-            in->alpha = in->rho / dr;  // line 7
+            in->alpha = in->rho / dr;
             in->ph = PH_B;
             break;
         }
@@ -425,7 +446,7 @@ class Engine {
                 in->k++;
                 return test(in);
             }
-            in->omega = ks / kk;  // line 10
+            in->omega = ks / kk;
             if (in->omega == 0.0) {
                 in->pend_xap = in->pend_rs = in->pend_restart = true;
                 in->ph = PH_W0;
@@ -444,15 +465,15 @@ class Engine {
         case PH_C: {
             double rho_new = h.dot[0];
             in->nrm = h.nmax[1];
-            in->beta = (in->alpha / in->omega) * (rho_new / in->rho);  // line 13
-            in->pend_p = true;                                         // line 14, issued with the next phase
-            if (std::fabs(rho_new) <= in->o.restart_tol) {            // lines 15-17
+            in->beta = (in->alpha / in->omega) * (rho_new / in->rho);
+            in->pend_p = true;                                         // new direction, issued with the next phase
+            if (std::fabs(rho_new) <= in->o.restart_tol) {            // restart test with epsilon_0
                 in->pend_restart = true;
                 rho_new = h.dot[1];
                 in->restarts++;
             }
             in->rho = rho_new;
-            in->k++;  // line 18
+            in->k++;
             test(in);
             break;
         }
@@ -607,7 +628,7 @@ class Engine {
             });
             plan.push_back([=] { return launch_fill0(in->v(VEC_X), in->n(), st); });
         }
-        // vector updates: deferred line 14 (A), line 8 (B), lines 11-12 (C)
+        // vector updates: deferred new direction (A), S = R - alpha D (B), X and R updates (C)
         {
             std::vector<int> list, first{0}, aux;
             std::vector<double> scal;

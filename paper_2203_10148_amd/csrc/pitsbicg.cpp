@@ -301,7 +301,8 @@ bool setup_2d(pit_ctx &c)
     // the kernels in adi2d.hip are instantiated for exactly these
     // (two segments of 32 rows beat one segment up to 512 rows: 32-column
     // blocks, twice as many workgroups and two resident per CU)
-    const AdiShape menu[] = {{0, 8, 16, 1, 0}, {0, 8, 32, 1, 0}, {0, 8, 32, 2, 0}, {0, 16, 32, 2, 0}, {0, 16, 32, 1, 0}};
+    const AdiShape menu[] = {{0, 8, 16, 1, 0}, {0, 8, 32, 1, 0}, {0, 8, 32, 2, 0}, {0, 16, 32, 2, 0},
+                             {0, 16, 32, 1, 0}, {0, 8, 16, 2, 0}, {0, 16, 16, 2, 0}};
     auto rows = [](const AdiShape &a) { return a.wy * a.cy * a.seg; };
     AdiShape sh{cx, 0, 0, 0, xw};
     for (const auto &a : menu)
@@ -851,7 +852,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     int rc;
     RedOut h{};
 
-    // line 1: R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
+    // initial residual R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
     PIT_HIP(launch_fill0(s.S, n, st));
     if (ctx->dim2()) PIT_HIP(launch_copy(s.S, u0, ctx->npts, st));  // S holds B for now
     else PIT_HIP(launch_to_chunked(u0, s.S, 1, ctx->npts, NT, C, st));
@@ -870,7 +871,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         if ((rc = s.sweep(s.Tm, s.R))) return rc;
         s.matvecs++;
     }
-    // lines 2-4
+    // shadow residual, first direction, rho
     PIT_HIP(launch_copy(s.Rt, s.R, n, st));
     PIT_HIP(launch_copy(s.P, s.R, n, st));
     {
@@ -889,7 +890,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             status = PIT_EBREAKDOWN;
             break;
         }
-        if (!(nrm > o.tol * scale)) {  // line 5
+        if (!(nrm > o.tol * scale)) {  // stopping test
             status = PIT_OK;
             break;
         }
@@ -906,7 +907,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 break;
             }
         }
-        // line 6
+        // D = G^{-1} F P
         if ((rc = s.matvec(s.P, s.D))) return rc;
         double dr;
         {
@@ -914,7 +915,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             if ((rc = s.reduce(1, a, b, h))) return rc;
             dr = h.dot[0];
         }
-        if (dr == 0.0) {  // restart with the current residual, redo line 6
+        if (dr == 0.0) {  // restart with the current residual, redo D = G^{-1} F P
             PIT_HIP(launch_copy(s.Rt, s.R, n, st));
             PIT_HIP(launch_copy(s.P, s.R, n, st));
             const double *a[1] = {s.R}, *b[1] = {s.R};
@@ -930,8 +931,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 break;
             }
         }
-        const double alpha = rho / dr;  // line 7
-        PIT_HIP(launch_axpby(s.S, s.R, 1.0, s.D, -alpha, n, st));  // line 8
+        const double alpha = rho / dr;
+        PIT_HIP(launch_axpby(s.S, s.R, 1.0, s.D, -alpha, n, st));  // S = R - alpha D
         if (o.half_step_check) {
             const double *a[1] = {s.S}, *b[1] = {s.S};
             if ((rc = s.reduce(1, a, b, h))) return rc;
@@ -943,7 +944,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 continue;
             }
         }
-        // line 9
+        // K = G^{-1} F S
         if ((rc = s.matvec(s.S, s.K))) return rc;
         {
             const double *a[3] = {s.K, s.K, s.S}, *b[3] = {s.S, s.K, s.S};
@@ -957,7 +958,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             k++;
             continue;
         }
-        const double omega = ks / kk;  // line 10
+        const double omega = ks / kk;
         if (omega == 0.0) {
             PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
             PIT_HIP(launch_copy(s.R, s.S, n, st));
@@ -971,9 +972,9 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             k++;
             continue;
         }
-        // lines 11-12
+        // X and R updates
         PIT_HIP(launch_update_xr(X, s.R, s.P, s.S, s.K, alpha, omega, n, st));
-        // line 13 (and the norm for the next test)
+        // beta (and the norm for the next stopping test)
         {
             const double *a[2] = {s.R, s.R}, *b[2] = {s.Rt, s.R};
             if ((rc = s.reduce(2, a, b, h))) return rc;
@@ -981,9 +982,9 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         double rho_new = h.dot[0];
         nrm = h.nmax[1];
         const double beta = (alpha / omega) * (rho_new / rho);
-        // line 14
+        // new direction P
         PIT_HIP(launch_update_p(s.P, s.R, s.D, beta, omega, n, st));
-        // lines 15-17
+        // restart test with epsilon_0
         if (std::fabs(rho_new) <= o.restart_tol) {
             PIT_HIP(launch_copy(s.Rt, s.R, n, st));
             PIT_HIP(launch_copy(s.P, s.R, n, st));
@@ -991,7 +992,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             restarts++;
         }
         rho = rho_new;
-        k++;  // line 18
+        k++;
     }
     if (ctx->dim2()) PIT_HIP(launch_copy(Xu, X, n, st));
     else PIT_HIP(launch_from_chunked(X, Xu, ctx->N, ctx->npts, NT, C, st));

@@ -474,14 +474,17 @@ def test_adi_apply_and_sweep_match_oracle(case):
         assert relerr(host(d2), o.sweep(lam)) < 1e-12
 
 
-def test_adi_one_segment_shape_on_a_short_column(monkeypatch):
-    """The 16-wave, 1-segment y shape forced on 500 rows (pad rows past the
-    last one, re-read from the last row), against the oracle."""
-    monkeypatch.setenv("PIT_ADI_YSHAPE", "16,32,1")
-    p = adi_problem(200, 500, 1.0, 1.0, 3, 2, 1, wl.F64)
-    say("adi y shape 16,32,1 on 200x500")
+@pytest.mark.parametrize("yshape,reported", [("16,32,1", (1024, 32)), ("16,16,2", (1024, 32)),
+                                             ("8,16,2", (512, 32))])
+def test_adi_other_y_shapes_on_a_short_column(yshape, reported, monkeypatch):
+    """The y shapes the default menu does not pick, forced on a short column
+    (rows past the last one inside the last segment), against the oracle."""
+    monkeypatch.setenv("PIT_ADI_YSHAPE", yshape)
+    rows = 250 if yshape == "8,16,2" else 500
+    p = adi_problem(200, rows, 1.0, 1.0, 3, 2, 1, wl.F64)
+    say(f"adi y shape {yshape} on 200x{rows}")
     c = ctx(p)
-    assert c.kernel_shape()[2:] == (1024, 32)
+    assert c.kernel_shape()[2:] == reported
     o = make_oracle(p)
     lam = wl.random_block(p, 5)
     assert relerr(host(c.apply_F(dev(lam))), o.apply(lam)) < 1e-12
