@@ -35,6 +35,7 @@ struct LineHost {
     int M = 0;
     int cyclic = 0;
     double inv_den = 0.0, bg = 0.0, iu_last = 0.0;
+    double a = 0.0, c = 0.0;  // off-diagonals of the line matrix
     std::vector<double> blob;  // layout of line_tab_view
     std::vector<float> blob32; // the same tables rounded to FP32
 };
@@ -110,6 +111,8 @@ struct pit_ctx {
         t.inv_den = (float)L.inv_den;
         t.bg = (float)L.bg;
         t.iu_last = (float)L.iu_last;
+        t.na = (float)-L.a;
+        t.nc = (float)-L.c;
         t.cyclic = L.cyclic;
         t.M = L.M;
         return t;
@@ -121,6 +124,8 @@ struct pit_ctx {
         t.inv_den = L.inv_den;
         t.bg = L.bg;
         t.iu_last = L.iu_last;
+        t.na = -L.a;
+        t.nc = -L.c;
         t.cyclic = L.cyclic;
         t.M = L.M;
         return t;

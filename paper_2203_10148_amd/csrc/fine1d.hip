@@ -189,6 +189,41 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(tb, lds);
+    if constexpr (line_compact(NT, C)) {
+        // 16 FP64 points per lane at 1024 threads leave no registers for a
+        // prefetch buffer.  Instead, while step n-1 runs, every thread touches
+        // one element per 128-byte line of v_n (chunked: line k = t mod 16 of
+        // its 16-thread group; natural: its own first point), so the loads
+        // after the c solves of step n hit L2.
+        double u[C];
+        load_chunk<NT, C, TR>(v, t, M, u);
+        zero_pads<C>(t, M, u);
+        store_chunk<NT, C, TR>(z, t, M, u);
+        const long tofs = TR ? (long)(t & 15) * NT + t : (long)min(t * C, M - 1);
+        for (int n = 1; n < N; ++n) {
+            const double touch = v[(size_t)n * ld + tofs];
+            for (int s = 0; s < c; ++s) {
+                if constexpr (SCHEME == SCHEME_IE) {
+                    S.solve(u);
+                } else {
+                    double w[C];
+#pragma unroll
+                    for (int k = 0; k < C; ++k) w[k] = u[k];
+                    S.solve(w);
+#pragma unroll
+                    for (int k = 0; k < C; ++k) u[k] = fma(2.0, w[k], -u[k]);
+                }
+            }
+            asm volatile("" ::"v"(touch));  // the touched value is consumed here, long after it landed
+            double vn[C];
+            load_chunk<NT, C, TR>(v + (size_t)n * ld, t, M, vn);
+            const int j0 = t * C;
+#pragma unroll
+            for (int k = 0; k < C; ++k) u[k] = (j0 + k < M) ? u[k] + vn[k] : 0.0;
+            store_chunk<NT, C, TR>(z + (size_t)n * ld, t, M, u);
+        }
+        return;
+    }
     // With 1024 threads (128 registers per lane) and 8 points per thread a
     // second prefetch buffer does not fit; one is enough there, since v_n is
     // only needed after the c solves of the step.

@@ -79,21 +79,33 @@ __device__ __forceinline__ T scan_down(T v, const T (&m)[7])
 }
 
 // CYC = false drops the periodic (Sherman-Morrison) part: no z vector in
-// registers and no correction.
-template <typename T, int NT, int C, bool CYC = true>
+// registers and no correction.  CP selects the compact tables (only iu per
+// point; see pit_internal.hpp), which the longest FP64 lines need.  FP32
+// tables take half the registers and keep the register form.
+template <typename T, int NT, int C, bool CYC = true, bool CP = line_compact(NT, C) && sizeof(T) == 8>
 struct LineSolver {
     static constexpr int W = NT / kWave;
     static_assert(NT % kWave == 0 && W <= kMaxWaves, "bad line shape");
+    static_assert(!CP || W > 1, "the compact form hands y_{M-1} over in LDS");
+    // z in LDS instead of registers (lines longer than kCompactAbove points)
+    static constexpr bool kZLds = line_compact(NT, C) && CYC;
+    // More than 8 waves: the wave aggregates are combined by a DPP scan over
+    // lanes 0..W-1 (lane q holds wave q's aggregate) instead of a Horner loop
+    // over W LDS values in every thread, whose unrolled selects and loads
+    // would not fit the registers of a 1024-thread workgroup.
+    static constexpr bool kLaneComb = W > 8;
     // LDS slots (units of T)
     static constexpr int kAggF = 0, kAggB = W, kPwf = 2 * W, kPwb = 3 * W, kRfw = 4 * W, kUFirst = 5 * W,
-                         kULast = 6 * W, kUWrap = 7 * W;
-    static constexpr int kLds = 7 * W + 2;
+                         kULast = 6 * W, kUWrap = 7 * W, kYLast = 7 * W + 1, kMf = 7 * W + 2,
+                         kMb = kMf + (kLaneComb ? 4 * 16 : 0), kZ = kMb + (kLaneComb ? 4 * 16 : 0);
+    static constexpr int kLds = kZ + (kZLds ? NT * C : 0);
 
     T lm[C], iu[C], cm[C], z[C];
     T wf[kScanConsts], wb[kScanConsts];
     T qf, qb, rf, rfw0;
     T inv_den, bg, iu_last;
-    int cyclic;
+    T iup, na, nc;  // compact: iu of the point before the chunk, -a, -c
+    int cyclic, M;
     T *sh;
 
     // Loads the thread's constants.  With one wavefront per line (W == 1) the
@@ -102,12 +114,23 @@ struct LineSolver {
     __device__ __forceinline__ void load(const LineTab<T> &tb, T *lds)
     {
         const int t = threadIdx.x & (NT - 1);
+        cyclic = tb.cyclic;
+        sh = lds;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            lm[k] = tb.lm[k * NT + t];
             iu[k] = tb.iu[k * NT + t];
-            cm[k] = tb.cm[k * NT + t];
-            if constexpr (CYC) z[k] = tb.z[k * NT + t];
+            if constexpr (!CP) {
+                lm[k] = tb.lm[k * NT + t];
+                cm[k] = tb.cm[k * NT + t];
+            }
+            if constexpr (CYC && !kZLds) z[k] = tb.z[k * NT + t];
+            if constexpr (kZLds)
+                if (cyclic) sh[kZ + k * NT + t] = tb.z[k * NT + t];
+        }
+        if constexpr (CP) {
+            iup = (t > 0) ? tb.iu[(C - 1) * NT + t - 1] : T(0);
+            na = tb.na;
+            nc = tb.nc;
         }
 #pragma unroll
         for (int l = 0; l < kScanConsts; ++l) {
@@ -121,24 +144,67 @@ struct LineSolver {
         inv_den = tb.inv_den;
         bg = tb.bg;
         iu_last = tb.iu_last;
-        cyclic = tb.cyclic;
-        sh = lds;
+        M = tb.M;
         if constexpr (W > 1) {
             if (t < W) {
                 sh[kPwf + t] = tb.pwf[t];
                 sh[kPwb + t] = tb.pwb[t];
                 sh[kRfw + t] = tb.rfw[t];
             }
+            if constexpr (kLaneComb) {
+                // level multipliers of the lane scans over the waves:
+                //   up:   prod pwf over waves q-s+1..q   (0 if q < s)
+                //   down: prod pwb over waves q..q+s-1   (0 if q+s > W-1)
+                if (t < 16) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int s = 1 << i;
+                        T f = T(0), b = T(0);
+                        if (t < W && t >= s) {
+                            f = T(1);
+                            for (int q = t - s + 1; q <= t; ++q) f *= tb.pwf[q];
+                        }
+                        if (t + s <= W - 1) {
+                            b = T(1);
+                            for (int q = t; q < t + s; ++q) b *= tb.pwb[q];
+                        }
+                        sh[kMf + 16 * i + t] = f;
+                        sh[kMb + 16 * i + t] = b;
+                    }
+                }
+            }
             __syncthreads();
         }
+    }
+
+    // Inclusive scans over the wave aggregates held in lanes 0..W-1 (other
+    // lanes carry 0 and are ignored): up combines waves 0..q into lane q, down
+    // waves q..W-1.
+    __device__ __forceinline__ T lane_scan_up(T g, int lane) const
+    {
+        const int q = lane & 15;
+        T v = (lane < W) ? g : T(0);
+        v = fma(sh[kMf + q], dpp<0x111>(v), v);
+        v = fma(sh[kMf + 16 + q], dpp<0x112>(v), v);
+        v = fma(sh[kMf + 32 + q], dpp<0x114>(v), v);
+        return fma(sh[kMf + 48 + q], dpp<0x118>(v), v);
+    }
+    __device__ __forceinline__ T lane_scan_down(T g, int lane) const
+    {
+        const int q = lane & 15;
+        T v = (lane < W) ? g : T(0);
+        v = fma(sh[kMb + q], dpp<0x101>(v), v);
+        v = fma(sh[kMb + 16 + q], dpp<0x102>(v), v);
+        v = fma(sh[kMb + 32 + q], dpp<0x104>(v), v);
+        return fma(sh[kMb + 48 + q], dpp<0x108>(v), v);
     }
 
     // ---- forward elimination y_j = d_j + lm_j y_{j-1}: local pass + in-wave scan ----
     __device__ __forceinline__ T fwd_scan(const T (&d)[C]) const
     {
-        T e = T(0);
+        T e = d[0];
 #pragma unroll
-        for (int k = 0; k < C; ++k) e = fma(lm[k], e, d[k]);
+        for (int k = 1; k < C; ++k) e = CP ? fma(na, iu[k - 1] * e, d[k]) : fma(lm[k], e, d[k]);
         return scan_up(e, wf);
     }
 
@@ -148,9 +214,17 @@ struct LineSolver {
         T y = c;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            y = fma(lm[k], y, d[k]);
+            if constexpr (CP) y = fma(na, (k == 0 ? iup : iu[k - 1]) * y, d[k]);
+            else y = fma(lm[k], y, d[k]);
             d[k] = y;
         }
+    }
+
+    // one backward step x = iu_k y + cm_k x_next
+    __device__ __forceinline__ T bstep(int k, T x, T y) const
+    {
+        if constexpr (CP) return iu[k] * fma(nc, x, y);
+        else return fma(cm[k], x, iu[k] * y);
     }
 
     // ---- back substitution x_j = iu_j y_j + cm_j x_{j+1}, then the periodic
@@ -160,21 +234,38 @@ struct LineSolver {
         const int t = threadIdx.x;
         const int lane = t & (kWave - 1);
         const int w = t / kWave;
-        T b = T(0);
+        T b = iu[C - 1] * d[C - 1];
 #pragma unroll
-        for (int k = C - 1; k >= 0; --k) b = fma(cm[k], b, iu[k] * d[k]);
+        for (int k = C - 2; k >= 0; --k) b = bstep(k, b, d[k]);
         T v = scan_down(b, wb);
         T cb = T(0), xtot;
         if constexpr (W > 1) {
             if (lane == 0) sh[kAggB + w] = v;
-            __syncthreads();
-            T acc = T(0);
+            if constexpr (CP && CYC) {  // y_{M-1}: the forward total is not it here
+                if (cyclic) {
+                    const int j0 = t * C;
 #pragma unroll
-            for (int q = W - 1; q >= 0; --q) {
-                if (q == w) cb = acc;
-                acc = fma(sh[kPwb + q], acc, sh[kAggB + q]);
+                    for (int k = 0; k < C; ++k)
+                        if (j0 + k == M - 1) sh[kYLast] = d[k];
+                }
             }
-            xtot = acc;
+            __syncthreads();
+            if constexpr (CP && CYC) ytot = sh[kYLast];
+            if constexpr (kLaneComb) {
+                const T S = lane_scan_down(sh[kAggB + (lane & (W - 1))], lane);
+                const int wu = __builtin_amdgcn_readfirstlane(w);
+                const T nx = readlane(S, min(wu + 1, W - 1));
+                cb = (wu < W - 1) ? nx : T(0);
+                xtot = readlane(S, 0);
+            } else {
+                T acc = T(0);
+#pragma unroll
+                for (int q = W - 1; q >= 0; --q) {
+                    if (q == w) cb = acc;
+                    acc = fma(sh[kPwb + q], acc, sh[kAggB + q]);
+                }
+                xtot = acc;
+            }
         } else {
             xtot = readlane(v, 0);
         }
@@ -182,14 +273,14 @@ struct LineSolver {
         T x = fma(qb, cb, next);
 #pragma unroll
         for (int k = C - 1; k >= 0; --k) {
-            x = fma(cm[k], x, iu[k] * d[k]);
+            x = bstep(k, x, d[k]);
             d[k] = x;
         }
         if (CYC && cyclic) {  // Sherman-Morrison correction
-            const T xlast = iu_last * ytot;  // cm_{M-1} = 0
+            const T xlast = iu_last * ytot;  // x_{M-1} = iu_{M-1} y_{M-1}: nothing lies beyond it
             const T phi = (xtot + bg * xlast) * inv_den;
 #pragma unroll
-            for (int k = 0; k < C; ++k) d[k] = fma(-phi, z[k], d[k]);
+            for (int k = 0; k < C; ++k) d[k] = fma(-phi, kZLds ? sh[kZ + k * NT + t] : z[k], d[k]);
         }
     }
 
@@ -204,13 +295,21 @@ struct LineSolver {
         if constexpr (W > 1) {
             if (lane == kWave - 1) sh[kAggF + w] = v;
             __syncthreads();
-            T acc = T(0);
+            if constexpr (kLaneComb) {
+                const T S = lane_scan_up(sh[kAggF + (lane & (W - 1))], lane);
+                const int wu = __builtin_amdgcn_readfirstlane(w);
+                const T pv = readlane(S, max(wu - 1, 0));
+                cw = (wu > 0) ? pv : T(0);
+                ytot = readlane(S, W - 1);
+            } else {
+                T acc = T(0);
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                if (q == w) cw = acc;
-                acc = fma(sh[kPwf + q], acc, sh[kAggF + q]);
+                for (int q = 0; q < W; ++q) {
+                    if (q == w) cw = acc;
+                    acc = fma(sh[kPwf + q], acc, sh[kAggF + q]);
+                }
+                ytot = acc;
             }
-            ytot = acc;
         } else {
             ytot = readlane(v, kWave - 1);
         }
@@ -263,23 +362,40 @@ struct LineSolver {
             const T u0 = sh[kUFirst];
             const T uM = sh[kUWrap];
             if (periodic) dM = pu * u0;
-            T acc = T(0);
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
+            if constexpr (kLaneComb) {  // lane q assembles wave q's terms
+                const int q = lane & (W - 1);
                 const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
                 T l = T(0), r = T(0);
                 if (Pq < M) l = pl * ((q > 0) ? sh[kULast + q - 1] : (periodic ? uM : T(0)));
                 if (Qq < M - 1) r = pu * sh[kUFirst + q + 1];
-                if (q == w) {
-                    cw = acc;
-                    dL = l;
-                    dR = r;
-                }
                 T agg = sh[kAggF + q] + fma(sh[kRfw + q], l, r);
                 if (q == wstar) agg += dM;
-                acc = fma(sh[kPwf + q], acc, agg);
+                const T S = lane_scan_up(agg, lane);
+                const int wu = __builtin_amdgcn_readfirstlane(w);
+                const T pv = readlane(S, max(wu - 1, 0));
+                cw = (wu > 0) ? pv : T(0);
+                dL = readlane(l, wu);
+                dR = readlane(r, wu);
+                ytot = readlane(S, W - 1);
+            } else {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
+                    T l = T(0), r = T(0);
+                    if (Pq < M) l = pl * ((q > 0) ? sh[kULast + q - 1] : (periodic ? uM : T(0)));
+                    if (Qq < M - 1) r = pu * sh[kUFirst + q + 1];
+                    if (q == w) {
+                        cw = acc;
+                        dL = l;
+                        dR = r;
+                    }
+                    T agg = sh[kAggF + q] + fma(sh[kRfw + q], l, r);
+                    if (q == wstar) agg += dM;
+                    acc = fma(sh[kPwf + q], acc, agg);
+                }
+                ytot = acc;
             }
-            ytot = acc;
         } else {
             const T u0 = readlane(u[0], 0);
             const T uM = readlane(uwrap, owner_last);

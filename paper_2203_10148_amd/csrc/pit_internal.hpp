@@ -13,6 +13,9 @@ constexpr int kWave = 64;      // CDNA wavefront width
 constexpr int kScanConsts = 7; // per-thread multipliers of one in-wave scan
 constexpr int kMaxWaves = 16;  // 1024 threads per line at most
 constexpr int kMaxLine = 16384;
+constexpr int kCompactAbove = 8192;  // longer lines use the compact solver tables
+
+constexpr bool line_compact(int NT, int C) { return NT * C > kCompactAbove; }
 
 // ---------------------------------------------------------------------------
 // 1D line solver tables.
@@ -43,6 +46,18 @@ constexpr int kMaxLine = 16384;
 // Padding points j >= M carry lm = 1, iu = 0, cm = 0, z = 0 so that the
 // forward total equals y_{M-1} and the pads solve to 0.
 //
+// Compact form (FP64 lines longer than kCompactAbove points): the off-diagonals of
+// B are the constants a and c, so lm_j = -a iu_{j-1} and cm_j = -c iu_j, and
+// the solver keeps only iu per point and forms the multipliers as it goes:
+//     forward   y_j = d_j - a (iu_{j-1} y_{j-1})
+//     backward  x_j = iu_j (y_j - c x_{j+1})
+// which leaves room in the registers for 16 FP64 points per thread at 1024
+// threads.  The scan constants are then built from these effective
+// multipliers (lm_0 = 0, the first pad has lm = -a iu_{M-1}, later pads 0), so
+// the forward total is not y_{M-1}: the owner of point M-1 hands it over in
+// the backward LDS round instead, and the cyclic vector z lives in LDS.  The
+// FP32 tables of such a line keep the register form.
+//
 // Device layout (element type T, one contiguous blob):
 //   lm[C][NT] iu[C][NT] cm[C][NT] z[C][NT] wf[7][NT] wb[7][NT] qf[NT] qb[NT]
 //   pwf[16] pwb[16] rfw[16] rf[NT]
@@ -53,6 +68,7 @@ struct LineTab {
     T inv_den;  // 1 / (1 + v.z)
     T bg;       // beta_corner / gamma
     T iu_last;  // iu_{M-1}
+    T na, nc;   // -a, -c: the negated off-diagonals (used by the compact form)
     int cyclic;
     int M;
 };

@@ -150,78 +150,97 @@ bool build_line(int M, bool periodic, double a, double b, double c, LineShape sh
         L.inv_den = 1.0 / (1.0 + z[0] + L.bg * z[M - 1]);
     }
     L.iu_last = iu[M - 1];
-    std::vector<double> pf(NT, 1.0), pb(NT, 1.0);
-    for (int t = 0; t < NT; ++t)
-        for (int k = 0; k < C; ++k) {
-            pf[t] *= lm[t * C + k];
-            pb[t] *= cm[t * C + k];
+    L.a = a;
+    L.c = c;
+    // Scan constants and device layout for the multipliers lm, cm.
+    auto fill = [&](const std::vector<double> &lm, const std::vector<double> &cm, std::vector<double> &blob) {
+        std::vector<double> pf(NT, 1.0), pb(NT, 1.0);
+        for (int t = 0; t < NT; ++t)
+            for (int k = 0; k < C; ++k) {
+                pf[t] *= lm[t * C + k];
+                pb[t] *= cm[t * C + k];
+            }
+        blob.assign(line_tab_elems(NT, C), 0.0);
+        double *base = blob.data();
+        LineTab<double> v = line_tab_view<double>(base, NT, C);
+        auto W_ = [&](const double *p) { return const_cast<double *>(p); };
+        for (int t = 0; t < NT; ++t) {
+            for (int k = 0; k < C; ++k) {
+                W_(v.lm)[k * NT + t] = lm[t * C + k];
+                W_(v.iu)[k * NT + t] = iu[t * C + k];
+                W_(v.cm)[k * NT + t] = cm[t * C + k];
+                W_(v.z)[k * NT + t] = zz[t * C + k];
+            }
+            const int lane = t % kWave, ws = t - lane, we = ws + kWave - 1;
+            const int row = lane / 16, l16 = lane % 16;
+            auto prodf = [&](int a, int b) {  // prod pf over wave lanes a..b
+                double f = 1.0;
+                for (int q = a; q <= b; ++q) f *= pf[ws + q];
+                return f;
+            };
+            auto prodb = [&](int a, int b) {
+                double g = 1.0;
+                for (int q = a; q <= b; ++q) g *= pb[ws + q];
+                return g;
+            };
+            for (int i = 0; i < 4; ++i) {
+                const int s = 1 << i;
+                W_(v.wf)[i * NT + t] = (l16 >= s) ? prodf(lane - s + 1, lane) : 0.0;
+                W_(v.wb)[i * NT + t] = (l16 + s <= 15) ? prodb(lane, lane + s - 1) : 0.0;
+            }
+            for (int r = 0; r < 3; ++r)  // lower row totals (rows 0..2) into row `row`
+                W_(v.wf)[(4 + r) * NT + t] = (row > r) ? prodf(16 * (r + 1), lane) : 0.0;
+            for (int r = 1; r <= 3; ++r)  // upper row totals (rows 1..3) into row `row`
+                W_(v.wb)[(3 + r) * NT + t] = (row < r) ? prodb(lane, 16 * r - 1) : 0.0;
+            double qf = 1.0, qb = 1.0;
+            for (int q = ws; q < t; ++q) qf *= pf[q];
+            for (int q = t + 1; q <= we; ++q) qb *= pb[q];
+            W_(v.qf)[t] = qf;
+            W_(v.qb)[t] = qb;
         }
+        for (int w = 0; w < W; ++w) {
+            double f = 1.0, g = 1.0;
+            for (int q = w * kWave; q < (w + 1) * kWave; ++q) {
+                f *= pf[q];
+                g *= pb[q];
+            }
+            W_(v.pwf)[w] = f;
+            W_(v.pwb)[w] = g;
+            // late terms at the first point of the wave: products of lm after it
+            const int Pw = w * kWave * C, Qw = Pw + kWave * C - 1;
+            double r = 1.0;
+            for (int i = Pw + 1; i <= Qw; ++i) r *= lm[i];
+            W_(v.rfw)[w] = r;
+            for (int lane = 0; lane < kWave; ++lane) {
+                const int t = w * kWave + lane;
+                double rt = 0.0;
+                if (lane > 0) {
+                    rt = 1.0;
+                    for (int i = Pw + 1; i <= t * C - 1; ++i) rt *= lm[i];
+                }
+                W_(v.rf)[t] = rt;
+            }
+        }
+    };
     L.sh = sh;
     L.M = M;
-    L.blob.assign(line_tab_elems(NT, C), 0.0);
-    double *base = L.blob.data();
-    LineTab<double> v = line_tab_view<double>(base, NT, C);
-    auto W_ = [&](const double *p) { return const_cast<double *>(p); };
-    for (int t = 0; t < NT; ++t) {
-        for (int k = 0; k < C; ++k) {
-            W_(v.lm)[k * NT + t] = lm[t * C + k];
-            W_(v.iu)[k * NT + t] = iu[t * C + k];
-            W_(v.cm)[k * NT + t] = cm[t * C + k];
-            W_(v.z)[k * NT + t] = zz[t * C + k];
+    fill(lm, cm, L.blob);
+    // FP32 tables keep the register form: forming an FP32 multiplier from
+    // rounded a and iu would add two roundings to every step of the
+    // recurrences, which a stiff line amplifies.
+    L.blob32.assign(L.blob.begin(), L.blob.end());
+    if (line_compact(NT, C)) {  // FP64: the multipliers the compact solver forms from iu
+        std::vector<double> lme(P), cme(P);
+        for (int j = 0; j < P; ++j) {
+            lme[j] = (j == 0) ? 0.0 : -a * iu[j - 1];
+            cme[j] = -c * iu[j];
         }
-        const int lane = t % kWave, ws = t - lane, we = ws + kWave - 1;
-        const int row = lane / 16, l16 = lane % 16;
-        auto prodf = [&](int a, int b) {  // prod pf over wave lanes a..b
-            double f = 1.0;
-            for (int q = a; q <= b; ++q) f *= pf[ws + q];
-            return f;
-        };
-        auto prodb = [&](int a, int b) {
-            double g = 1.0;
-            for (int q = a; q <= b; ++q) g *= pb[ws + q];
-            return g;
-        };
-        for (int i = 0; i < 4; ++i) {
-            const int s = 1 << i;
-            W_(v.wf)[i * NT + t] = (l16 >= s) ? prodf(lane - s + 1, lane) : 0.0;
-            W_(v.wb)[i * NT + t] = (l16 + s <= 15) ? prodb(lane, lane + s - 1) : 0.0;
-        }
-        for (int r = 0; r < 3; ++r)  // lower row totals (rows 0..2) into row `row`
-            W_(v.wf)[(4 + r) * NT + t] = (row > r) ? prodf(16 * (r + 1), lane) : 0.0;
-        for (int r = 1; r <= 3; ++r)  // upper row totals (rows 1..3) into row `row`
-            W_(v.wb)[(3 + r) * NT + t] = (row < r) ? prodb(lane, 16 * r - 1) : 0.0;
-        double qf = 1.0, qb = 1.0;
-        for (int q = ws; q < t; ++q) qf *= pf[q];
-        for (int q = t + 1; q <= we; ++q) qb *= pb[q];
-        W_(v.qf)[t] = qf;
-        W_(v.qb)[t] = qb;
-    }
-    for (int w = 0; w < W; ++w) {
-        double f = 1.0, g = 1.0;
-        for (int q = w * kWave; q < (w + 1) * kWave; ++q) {
-            f *= pf[q];
-            g *= pb[q];
-        }
-        W_(v.pwf)[w] = f;
-        W_(v.pwb)[w] = g;
-        // late terms at the first point of the wave: products of lm after it
-        const int Pw = w * kWave * C, Qw = Pw + kWave * C - 1;
-        double r = 1.0;
-        for (int i = Pw + 1; i <= Qw; ++i) r *= lm[i];
-        W_(v.rfw)[w] = r;
-        for (int lane = 0; lane < kWave; ++lane) {
-            const int t = w * kWave + lane;
-            double rt = 0.0;
-            if (lane > 0) {
-                rt = 1.0;
-                for (int i = Pw + 1; i <= t * C - 1; ++i) rt *= lm[i];
-            }
-            W_(v.rf)[t] = rt;
-        }
+        fill(lme, cme, L.blob);
     }
     for (double x : L.blob)
         if (!std::isfinite(x)) return false;
-    L.blob32.assign(L.blob.begin(), L.blob.end());
+    for (float x : L.blob32)
+        if (!std::isfinite(x)) return false;
     return std::isfinite(L.inv_den) && std::isfinite(L.bg) && std::isfinite(L.iu_last);
 }
 

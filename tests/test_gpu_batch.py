@@ -86,6 +86,7 @@ FP64_SET = [
     p1d(777, wl.DIRICHLET, 9, 20, name="d777"),
     p1d(3000, wl.PERIODIC, 5, 10, nu=3e-4, a=1.5, name="p3000"),
     p1d(5000, wl.PERIODIC, 4, 6, name="p5000"),
+    p1d(12000, wl.PERIODIC, 4, 5, name="p12000"),   # compact line tables
 ]
 
 
@@ -157,6 +158,7 @@ MIX = [
     p1d(777, wl.DIRICHLET, 9, 20, name="d777"),
     p2d(24, 20, 4, 3, wl.F64),
     p2d(100, 70, 3, 4, wl.F32, c=2),
+    p1d(9500, wl.PERIODIC, 4, 8, prec=wl.F32, name="p9500_f32"),
 ]
 
 

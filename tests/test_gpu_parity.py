@@ -77,6 +77,11 @@ OP_CASES = [
     (4096, wl.PERIODIC, wl.CN, wl.IE, 2, 4, 5),
     (5000, wl.PERIODIC, wl.CN, wl.IE, 2, 3, 3),       # 1024 threads, ragged
     (16384, wl.DIRICHLET, wl.IE, wl.IE, 1, 3, 2),     # largest line
+    # lines above 8192 points: compact solver tables, 16 waves combined by a lane scan
+    (12345, wl.PERIODIC, wl.CN, wl.IE, 2, 3, 3),
+    (9001, wl.PERIODIC, wl.IE, wl.IE, 2, 3, 4),
+    (16384, wl.PERIODIC, wl.IE, wl.CN, 1, 3, 2),
+    (8193, wl.DIRICHLET, wl.CN, wl.IE, 2, 3, 3),      # one point past the register form
 ]
 
 
@@ -126,7 +131,7 @@ def test_every_line_shape(shape, monkeypatch):
     assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(64, 2), (128, 8), (256, 4), (512, 8), (1024, 4)],
+@pytest.mark.parametrize("shape", [(64, 2), (128, 8), (256, 4), (512, 8), (1024, 4), (1024, 16)],
                          ids=lambda s: f"NT{s[0]}_C{s[1]}")
 def test_solve_every_layout(shape, monkeypatch):
     """pit_solve keeps its vectors in the chunked layout of the line shape
@@ -356,6 +361,8 @@ F32_CASES = [
     (4000, wl.DIRICHLET, wl.CN, (512, 8)),
     (3000, wl.PERIODIC, wl.IE, (1024, 4)),
     (16384, wl.PERIODIC, wl.CN, (1024, 16)),
+    (10000, wl.PERIODIC, wl.IE, (1024, 16)),
+    (9000, wl.DIRICHLET, wl.CN, (1024, 16)),
 ]
 
 
