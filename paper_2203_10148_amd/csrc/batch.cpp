@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -72,6 +73,8 @@ struct Inst {
     size_t ws_off = 0, ws_bytes = 0;
     int hip_error = 0;
     int index = 0;
+    double t_ready = 0, t_issue = 0;  // current phase, engine clock (for the trace)
+    int lane = -1, group = 0;
 
     bool dim2() const { return ctx->dim2(); }
     long n() const { return ctx->ntc(); }
@@ -123,8 +126,20 @@ namespace pit {
 
 class Engine {
   public:
-    explicit Engine(int max_slots) : max_(max_slots) {}
-    ~Engine() { release(); }
+    explicit Engine(int max_slots) : max_(max_slots), t0_(std::chrono::steady_clock::now())
+    {
+        // PIT_BATCH_TRACE=<file>: one CSV line per completed phase (times in
+        // ms on the engine's clock: ready, issued, seen complete by the host)
+        if (const char *f = std::getenv("PIT_BATCH_TRACE")) {
+            trace_ = std::fopen(f, "w");
+            if (trace_) std::fprintf(trace_, "index,M,N,m,phase,lane,group,t_ready,t_issue,t_done\n");
+        }
+    }
+    ~Engine()
+    {
+        release();
+        if (trace_) std::fclose(trace_);
+    }
 
     static size_t args_cap(int max_slots) { return 65536 + (size_t)max_slots * 640; }
     static size_t bytes(int max_slots)
@@ -185,6 +200,7 @@ class Engine {
         free_.pop_back();
         in->ph = PH_INIT;
         in->in_flight = false;
+        in->t_ready = now();
         if (!in->dim2()) {
             const pit_ctx *c = in->ctx;
             Inst1d d{};
@@ -321,6 +337,13 @@ class Engine {
     std::vector<Inst *> active_;
     Lane lanes_[kLanes];
     uint64_t seq_ = 0;
+    std::chrono::steady_clock::time_point t0_;
+    FILE *trace_ = nullptr;
+
+    double now() const
+    {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+    }
 
     void release()
     {
@@ -376,7 +399,13 @@ class Engine {
         L.busy = true;
         L.kind2d = kind2d;
         L.seq = ++seq_;
-        for (Inst *in : members) in->in_flight = true;
+        const double t = trace_ ? now() : 0.0;
+        for (Inst *in : members) {
+            in->in_flight = true;
+            in->t_issue = t;
+            in->lane = (int)(&L - lanes_);
+            in->group = (int)members.size();
+        }
     }
 
     // -------------------------------------------------------------------
@@ -487,9 +516,14 @@ class Engine {
 
     void complete(Lane &L, std::vector<Inst *> &finished)
     {
+        const double t = trace_ ? now() : 0.0;
         for (Inst *in : L.members) {
             in->in_flight = false;
             const RedOut h = in->red_pos >= 0 ? L.h_red[in->red_pos] : RedOut{};
+            if (trace_)
+                std::fprintf(trace_, "%d,%d,%d,%d,%d,%d,%d,%.4f,%.4f,%.4f\n", in->index, in->ctx->npts, in->ctx->N,
+                             in->ctx->m, (int)in->ph, in->lane, in->group, in->t_ready, in->t_issue, t);
+            in->t_ready = t;
             advance(in, h);
             if (in->ph == PH_DONE) {
                 free_.push_back(in->slot);

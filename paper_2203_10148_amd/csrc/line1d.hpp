@@ -89,11 +89,15 @@ struct LineSolver {
     static_assert(!CP || W > 1, "the compact form hands y_{M-1} over in LDS");
     // z in LDS instead of registers (lines longer than kCompactAbove points)
     static constexpr bool kZLds = line_compact(NT, C) && CYC;
-    // More than 8 waves: the wave aggregates are combined by a DPP scan over
-    // lanes 0..W-1 (lane q holds wave q's aggregate) instead of a Horner loop
-    // over W LDS values in every thread, whose unrolled selects and loads
-    // would not fit the registers of a 1024-thread workgroup.
-    static constexpr bool kLaneComb = W > 8;
+    // The wave aggregates are combined by a DPP scan over lanes 0..W-1 (lane q
+    // holds wave q's aggregate) instead of a Horner loop over W LDS values in
+    // every thread, whose unrolled selects and per-wave masks cost registers
+    // (at 16 waves more than a 1024-thread workgroup has) and instructions.
+    // FP32 (the increment-form step, with its per-wave late terms) from 4
+    // waves on: 15% off the batched fine applies.  FP64 from 16 waves: at 4
+    // and 8 waves its Horner loop was as fast or slightly faster.
+    static constexpr bool kLaneComb = W > (sizeof(T) == 8 ? 8 : 2);
+    static constexpr int kCombLevels = W > 8 ? 4 : W > 4 ? 3 : W > 2 ? 2 : 1;
     // LDS slots (units of T)
     static constexpr int kAggF = 0, kAggB = W, kPwf = 2 * W, kPwb = 3 * W, kRfw = 4 * W, kUFirst = 5 * W,
                          kULast = 6 * W, kUWrap = 7 * W, kYLast = 7 * W + 1, kMf = 7 * W + 2,
@@ -185,18 +189,20 @@ struct LineSolver {
         const int q = lane & 15;
         T v = (lane < W) ? g : T(0);
         v = fma(sh[kMf + q], dpp<0x111>(v), v);
-        v = fma(sh[kMf + 16 + q], dpp<0x112>(v), v);
-        v = fma(sh[kMf + 32 + q], dpp<0x114>(v), v);
-        return fma(sh[kMf + 48 + q], dpp<0x118>(v), v);
+        if constexpr (kCombLevels > 1) v = fma(sh[kMf + 16 + q], dpp<0x112>(v), v);
+        if constexpr (kCombLevels > 2) v = fma(sh[kMf + 32 + q], dpp<0x114>(v), v);
+        if constexpr (kCombLevels > 3) v = fma(sh[kMf + 48 + q], dpp<0x118>(v), v);
+        return v;
     }
     __device__ __forceinline__ T lane_scan_down(T g, int lane) const
     {
         const int q = lane & 15;
         T v = (lane < W) ? g : T(0);
         v = fma(sh[kMb + q], dpp<0x101>(v), v);
-        v = fma(sh[kMb + 16 + q], dpp<0x102>(v), v);
-        v = fma(sh[kMb + 32 + q], dpp<0x104>(v), v);
-        return fma(sh[kMb + 48 + q], dpp<0x108>(v), v);
+        if constexpr (kCombLevels > 1) v = fma(sh[kMb + 16 + q], dpp<0x102>(v), v);
+        if constexpr (kCombLevels > 2) v = fma(sh[kMb + 32 + q], dpp<0x104>(v), v);
+        if constexpr (kCombLevels > 3) v = fma(sh[kMb + 48 + q], dpp<0x108>(v), v);
+        return v;
     }
 
     // ---- forward elimination y_j = d_j + lm_j y_{j-1}: local pass + in-wave scan ----
@@ -334,21 +340,25 @@ struct LineSolver {
         const int j0 = t * C;
         const T uprev = dpp<0x138>(u[C - 1]);  // lane-1's last point (lane 0 reads 0)
         const T unext = dpp<0x130>(u[0]);      // lane+1's first point (lane 63 reads 0)
+        // Padding points hold exactly 0, so the only one with a nonzero
+        // right-hand side is point M, pl*u_{M-1}, when its left neighbour is
+        // in the same wave: it reaches only the pads' forward values and the
+        // forward total, which is corrected below, and the pads still solve
+        // to 0.  So no point needs a mask here.
         T d[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const T left = (k == 0) ? uprev : u[k - 1];
             const T right = (k == C - 1) ? unext : u[k + 1];
-            const T r = fma(pl, left - u[k], fma(pu, right - u[k], -pr * u[k]));
-            d[k] = (j0 + k < M) ? r : T(0);
+            d[k] = fma(pl, left - u[k], fma(pu, right - u[k], -pr * u[k]));
         }
-        // value of point M-1 (owner only)
-        T uwrap = T(0);
-#pragma unroll
-        for (int k = 0; k < C; ++k)
-            if (j0 + k == M - 1) uwrap = u[k];
-        const int owner_last = (M - 1) / C;   // thread holding point M-1
-        const int wstar = owner_last / kWave; // its wave
+        // point M-1: its thread, its index in that thread's chunk, its wave
+        // (all uniform, so u_{M-1} is read with one readlane of one register)
+        const int owner_last = (M - 1) / C;
+        const int kk = (M - 1) - owner_last * C;
+        const int wstar = owner_last / kWave;
+        const int wu = __builtin_amdgcn_readfirstlane(w);
+        const bool padfix = M < NT * C && M % (kWave * C) != 0;
         const T v = fwd_scan(d);
         T cw = T(0), ytot, dL = T(0), dR = T(0), dM = T(0);
         if constexpr (W > 1) {
@@ -357,7 +367,13 @@ struct LineSolver {
                 sh[kULast + w] = u[C - 1];
             }
             if (lane == 0) sh[kUFirst + w] = u[0];
-            if (t == owner_last) sh[kUWrap] = uwrap;
+            if (wu == wstar) {
+                T val = T(0);
+#pragma unroll
+                for (int k = 0; k < C; ++k)
+                    if (k == kk) val = readlane(u[k], owner_last & (kWave - 1));
+                if (lane == 0) sh[kUWrap] = val;
+            }
             __syncthreads();
             const T u0 = sh[kUFirst];
             const T uM = sh[kUWrap];
@@ -371,7 +387,6 @@ struct LineSolver {
                 T agg = sh[kAggF + q] + fma(sh[kRfw + q], l, r);
                 if (q == wstar) agg += dM;
                 const T S = lane_scan_up(agg, lane);
-                const int wu = __builtin_amdgcn_readfirstlane(w);
                 const T pv = readlane(S, max(wu - 1, 0));
                 cw = (wu > 0) ? pv : T(0);
                 dL = readlane(l, wu);
@@ -396,34 +411,38 @@ struct LineSolver {
                 }
                 ytot = acc;
             }
+            if (padfix) ytot -= pl * uM;
         } else {
             const T u0 = readlane(u[0], 0);
-            const T uM = readlane(uwrap, owner_last);
+            T uM = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (k == kk) uM = readlane(u[k], owner_last);
             if (periodic) {
                 dM = pu * u0;
                 dL = pl * uM;
             }
             ytot = readlane(v, kWave - 1) + fma(rfw0, dL, dM);
+            if (padfix) ytot -= pl * uM;
         }
         const T prev = dpp<0x138>(v);
         const T c = (lane == 0) ? cw : fma(rf, dL, fma(qf, cw, prev));
         // complete the right-hand side with the late terms
         if (lane == 0 && j0 < M) d[0] += dL;
         if (lane == kWave - 1 && j0 + C - 1 < M - 1) d[C - 1] += dR;
-#pragma unroll
-        for (int k = 0; k < C; ++k)
-            if (j0 + k == M - 1) d[k] += dM;
+        if (t == owner_last) d[__builtin_amdgcn_readfirstlane(kk)] += dM;
         fwd_pass2(d, c);
         backward(d, ytot);
         // u + lo += d, compensated: the state is the unevaluated sum u + lo
-        // and the rounding error of every update is carried in lo (TwoSum),
-        // so many small increments do not drift by the state's rounding.
+        // and the rounding error of every update is carried in lo, so many
+        // small increments do not drift by the state's rounding.  The error
+        // term is Fast2Sum's, exact whenever |increment| <= |u| (the regime
+        // where drift builds up); otherwise it is an ordinary rounding.
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const T y = d[k] + lo[k];
             const T s = u[k] + y;
-            const T bb = s - u[k];
-            lo[k] = (u[k] - (s - bb)) + (y - bb);
+            lo[k] = y - (s - u[k]);
             u[k] = s;
         }
     }

@@ -363,6 +363,10 @@ F32_CASES = [
     (16384, wl.PERIODIC, wl.CN, (1024, 16)),
     (10000, wl.PERIODIC, wl.IE, (1024, 16)),
     (9000, wl.DIRICHLET, wl.CN, (1024, 16)),
+    # padding that starts at a wave's first lane (its first point gets no
+    # right-hand side from the left neighbour): 2 and 16 waves
+    (512, wl.PERIODIC, wl.CN, (128, 8)),
+    (8192, wl.PERIODIC, wl.IE, (1024, 16)),
 ]
 
 
