@@ -182,8 +182,9 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
 /* Coarse preconditioner solve z = G^{-1} v by forward substitution (Sec. 3,
  * eq. (eqinverse) and the remark that it is solved sequentially):
  *     z_0 = v_0,   z_n = v_n + G(z_{n-1}),  n = 1..N-1,
- * in FP64.  v == z (in place) is allowed.  Asynchronous on `stream`.
- * Errors as pit_apply_F. */
+ * in FP64.  v == z (in place) is allowed.  Asynchronous on `stream`.  In 1D
+ * two of the context's block vectors serve as scratch, so the call must not
+ * overlap another call on the same context.  Errors as pit_apply_F. */
 int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
 
 /* ---- solver ---------------------------------------------------------------- */

@@ -735,7 +735,18 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream)
 {
     if (!ctx || !ctx->ws || !v || !z) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PIT_HIP(op_sweep(ctx, v, z, false, st));
+    if (ctx->dim2()) {
+        PIT_HIP(op_sweep(ctx, v, z, false, st));
+        return PIT_OK;
+    }
+    // 1D: through the chunked layout (two of the context's block vectors),
+    // where every load and store of the sequential sweep is coalesced; the
+    // two layout passes cost far less than the strided accesses they replace.
+    const int NT = ctx->lc.sh.NT, C = ctx->lc.sh.C;
+    double *a = ctx->vec(0), *b = ctx->vec(1);
+    PIT_HIP(launch_to_chunked(v, a, ctx->N, ctx->npts, NT, C, st));
+    PIT_HIP(op_sweep(ctx, a, b, true, st));
+    PIT_HIP(launch_from_chunked(b, z, ctx->N, ctx->npts, NT, C, st));
     return PIT_OK;
 }
 
