@@ -175,7 +175,9 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes);
  * PIT_APPLY_RAW:  y_n = F(lam_n) for n = 0..N-1.  With PIT_APPLY_LAST: only
  * y_{N-1} = F(lam_{N-1}) is written (the state u(T) at the final time when
  * lam is the solution, by the continuity condition of Sec. 2).  lam and y are device [N][npts] FP64 and must not
- * overlap.  Asynchronous on `stream`.  Errors: PIT_EINVAL (NULL pointers,
+ * overlap.  Asynchronous on `stream`.  For 1D lines above 8192 points two of
+ * the context's block vectors serve as scratch, so the call must not overlap
+ * another call on the same context.  Errors: PIT_EINVAL (NULL pointers,
  * unbound workspace, unknown flags), PIT_EHIP (launch failure). */
 int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void *stream);
 

@@ -727,7 +727,21 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
     if (!ctx || !ctx->ws || !lam || !y || (flags & ~(PIT_APPLY_RAW | PIT_APPLY_LAST))) return PIT_EINVAL;
     if (lam == y) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PIT_HIP(op_apply(ctx, lam, y, (flags & PIT_APPLY_RAW) ? 1 : 0, (flags & PIT_APPLY_LAST) ? 1 : 0, false, st));
+    const int raw = (flags & PIT_APPLY_RAW) ? 1 : 0, last = (flags & PIT_APPLY_LAST) ? 1 : 0;
+    const int NT = ctx->lf.sh.NT, C = ctx->lf.sh.C;
+    if (!ctx->dim2() && line_compact(NT, C)) {
+        // Lines above 8192 points: the natural-layout kernels of that shape
+        // spill, so convert through two of the context's block vectors and
+        // run the chunked kernels (as pit_solve does).
+        double *a = ctx->vec(0), *b = ctx->vec(1);
+        const long n1 = (long)(ctx->N - 1);
+        PIT_HIP(launch_to_chunked(lam, a, ctx->N, ctx->npts, NT, C, st));
+        PIT_HIP(op_apply(ctx, a, b, raw, last, true, st));
+        if (last) PIT_HIP(launch_from_chunked(b + n1 * ctx->ld, y + n1 * ctx->npts, 1, ctx->npts, NT, C, st));
+        else PIT_HIP(launch_from_chunked(b, y, ctx->N, ctx->npts, NT, C, st));
+        return PIT_OK;
+    }
+    PIT_HIP(op_apply(ctx, lam, y, raw, last, false, st));
     return PIT_OK;
 }
 

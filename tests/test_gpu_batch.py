@@ -424,3 +424,32 @@ def test_server_retires_tickets_and_drains_on_destroy():
     Xb, ib = batch_solve(probs[1:], tol=1e-10)
     for a, b in zip(Xs[1:], Xb):
         assert np.array_equal(host(a), b)
+
+
+def test_batch_phase_trace(tmp_path, monkeypatch):
+    """PIT_BATCH_TRACE: one CSV line per completed phase, times ordered
+    ready <= issue <= done, one INIT and one FINAL phase per instance."""
+    P = P_()
+    say("batch phase trace")
+    path = tmp_path / "trace.csv"
+    monkeypatch.setenv("PIT_BATCH_TRACE", str(path))
+    probs = FP64_SET[:3]
+    ctxs = [P.Context(p) for p in probs]
+    u0s = [dev(u0_of(p)) for p in probs]
+    b = P.Batch(len(probs))
+    Xs, infos = b.solve(ctxs, u0s, tol=1e-10)
+    b.close()
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    assert rows and set(rows[0]) == {"index", "M", "N", "m", "phase", "lane", "group", "t_ready", "t_issue",
+                                     "t_done"}
+    for r in rows:
+        assert float(r["t_ready"]) <= float(r["t_issue"]) + 1e-6 <= float(r["t_done"]) + 2e-6
+        assert 0 <= int(r["lane"]) < 4 and int(r["group"]) >= 1
+    for i, (p, inf) in enumerate(zip(probs, infos)):
+        mine = [r for r in rows if int(r["index"]) == i]
+        phases = [int(r["phase"]) for r in mine]
+        assert phases[0] == 0 and phases[-1] == 6  # INIT first, FINAL last
+        assert int(mine[0]["M"]) == p.npts and int(mine[0]["N"]) == p.N
+        # two preconditioned products per iteration (phases A and B)
+        assert sum(1 for q in phases if q in (1, 3)) == inf.matvecs

@@ -103,6 +103,12 @@ def test_apply_and_sweep_match_oracle(case):
     assert relerr(y, o.apply(lam)) < 1e-12
     yr = host(c.apply_F(d, raw=True))
     assert relerr(yr, o.apply_raw(lam)) < 1e-12
+    # PIT_APPLY_LAST: only slice N-1 is written, F(lam_{N-1})
+    mark = dev(np.full(p.N * p.npts, 7.0))
+    yl = host(c.apply_F(d, mark, last=True)).reshape(p.N, -1)
+    yo = o.apply_raw(lam).reshape(p.N, -1)
+    assert relerr(yl[-1], yo[-1]) < 1e-12
+    assert np.all(yl[:-1] == 7.0)
     z = host(c.coarse_sweep(d))
     assert relerr(z, o.sweep(lam)) < 1e-12
     # in place
