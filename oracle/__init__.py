@@ -13,7 +13,10 @@ Bi-Conjugate Gradient Algorithm"):
   * ``dot`` / ``norm``  -- block inner product and the N,inf stopping norm (Sec. 3);
   * ``pitsbicg``        -- Algorithm 1 (Sec. 3);
   * ``parareal_*``      -- Sec. 2, eqs. (pararealAlgebraic) and (pararealscheme);
-  * ``serial``          -- the serial fine trajectory, the exact solution.
+  * ``serial``          -- the serial fine trajectory, the exact solution;
+  * ``source``/``forced`` -- an optional source constant in time (Sec. 2, eq.
+                           (Cauchy)): F becomes affine, B = (u0, b, .., b) with
+                           b = F(0) the forced response of one slice.
 """
 from __future__ import annotations
 
@@ -68,6 +71,8 @@ def _load():
                                ct.c_double, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
                                ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int]
     lib.orc_destroy.argtypes = [ct.c_void_p]
+    lib.orc_set_source.argtypes = [ct.c_void_p, _D]
+    lib.orc_forced.argtypes = [ct.c_void_p, _D]
     lib.orc_npts.argtypes = [ct.c_void_p]
     lib.orc_npts.restype = ct.c_int
     lib.orc_weight.argtypes = [ct.c_void_p]
@@ -137,7 +142,7 @@ class Oracle:
     """One PiT problem: a grid, an operator, N slices, fine and coarse steppers."""
 
     def __init__(self, *, dim=1, M=(64, 1), bc=DIRICHLET, length=(1.0, 1.0), nu=1.0,
-                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE):
+                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None):
         lib = _load()
         Mx, My = (M, 1) if isinstance(M, int) else (int(M[0]), int(M[1]))
         self.dim, self.Mx, self.My, self.N = dim, Mx, (My if dim == 2 else 1), N
@@ -149,6 +154,24 @@ class Oracle:
         self._h = h
         self.npts = lib.orc_npts(h)
         self.weight = lib.orc_weight(h)
+        if source is not None:
+            self.set_source(source)
+
+    def set_source(self, f):
+        """Set the source f (one slice of values), or remove it with None."""
+        if f is None:
+            _lib.orc_set_source(self._h, None)
+            return
+        f = self._c(f)
+        if f.size != self.npts:
+            raise ValueError("oracle: source size")
+        _lib.orc_set_source(self._h, _p(f))
+
+    def forced(self):
+        """b = F(0): the forced response of one slice."""
+        b = self._slice()
+        _lib.orc_forced(self._h, _p(b))
+        return b
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

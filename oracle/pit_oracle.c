@@ -30,11 +30,19 @@
  * experiments): 1D Dirichlet-0 or periodic, 2D Dirichlet-0 on a rectangle,
  * second-order central differences.
  *   L u = nu*D2 u - a*D1c u - r*u                       (1D)
- *   IE:  (I - dt L) u' = u
- *   CN:  (I - dt/2 L) u' = (I + dt/2 L) u
- *   PR-ADI (2D): (I - dt/2 Lx) u* = (I + dt/2 Ly) u,
- *                (I - dt/2 Ly) u' = (I + dt/2 Lx) u*,
+ *   IE:  (I - dt L) u' = u + dt f
+ *   CN:  (I - dt/2 L) u' = (I + dt/2 L) u + dt f
+ *   PR-ADI (2D): (I - dt/2 Lx) u* = (I + dt/2 Ly) u + dt/2 f,
+ *                (I - dt/2 Ly) u' = (I + dt/2 Lx) u* + dt/2 f,
  *       with Lx = nu*D2x - ax*D1x - r/2 and Ly = nu*D2y - ay*D1y - r/2.
+ * f is an optional source, constant in time (the source term of Sec. 2, eq.
+ * (Cauchy)); without it f = 0.  With a source the slice propagator is affine,
+ * F(u) = F0(u) + b with b = F(0), the forced response of one slice.  The
+ * all-at-once system keeps its linear operator (F0 below the diagonal) and
+ * gets B = (u0, b, .., b): its solution is again the serial trajectory
+ * lambda_{n+1} = F(lambda_n) (the middle entries of B in Sec. 2, eq.
+ * (algebraiclinearsystem)).  The preconditioner uses the linear coarse
+ * propagator G0.
  * Tridiagonal systems: Thomas algorithm without pivoting.  Periodic (cyclic)
  * systems: Sherman-Morrison rank-one correction.
  *
@@ -64,6 +72,7 @@ typedef struct {
     double hx, hy; /* grid spacing */
     double w;      /* L2 quadrature weight h^d */
     double DT;     /* slice length T/N */
+    double *src;   /* source f (npts values, owned) or NULL */
 } orc_ctx;
 
 static int g_threads = 1;
@@ -183,9 +192,10 @@ static size_t step_work(const orc_ctx *C)
     return (size_t)C->npts + 12 * (size_t)nmax;
 }
 
-/* out = one step of `scheme` with time step dt applied to u (no aliasing). */
+/* out = one step of `scheme` with time step dt applied to u (no aliasing);
+ * f is the source (NULL: none). */
 static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, double *out,
-                     double *work)
+                     double *work, const double *f)
 {
     if (C->dim == 1) {
         int n = C->Mx;
@@ -193,8 +203,13 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
         op1d(C->nu, C->ax, C->react, C->hx, &lo, &di, &up);
         double *rhs = work, *lw = work + n;
         if (scheme == ORC_IE) {
-            implicit_line(n, C->bc, dt, lo, di, up, u, out, lw);
-        } else { /* CN: rhs = (I + dt/2 L) u */
+            if (f) { /* rhs = u + dt f */
+                for (int j = 0; j < n; ++j) rhs[j] = u[j] + dt * f[j];
+                implicit_line(n, C->bc, dt, lo, di, up, rhs, out, lw);
+            } else {
+                implicit_line(n, C->bc, dt, lo, di, up, u, out, lw);
+            }
+        } else { /* CN: rhs = (I + dt/2 L) u + dt f */
             double th = 0.5 * dt;
             for (int j = 0; j < n; ++j) {
                 double um, uq;
@@ -206,6 +221,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
                     uq = (j < n - 1) ? u[j + 1] : 0.0;
                 }
                 rhs[j] = u[j] + th * (lo * um + di * u[j] + up * uq);
+                if (f) rhs[j] += dt * f[j];
             }
             implicit_line(n, C->bc, th, lo, di, up, rhs, out, lw);
         }
@@ -222,34 +238,36 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
     double *sol = line + nmax;     /* nmax */
     double *lw = sol + nmax;       /* 9*nmax */
     double th = 0.5 * dt;
-    /* half-step 1: rhs = (I + th*Ly) u, then (I - th*Lx) u* = rhs row by row */
+    /* half-step 1: rhs = (I + th*Ly) u + th*f, then (I - th*Lx) u* = rhs row by row */
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             double c0 = u[j * nx + i];
             double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
             double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
             line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
+            if (f) line[i] += th * f[j * nx + i];
         }
         implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
         for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
     }
-    /* half-step 2: rhs = (I + th*Lx) u*, then (I - th*Ly) u' = rhs column by column */
+    /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column */
     for (int i = 0; i < nx; ++i) {
         for (int j = 0; j < ny; ++j) {
             double c0 = star[j * nx + i];
             double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
             double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
             line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
+            if (f) line[j] += th * f[j * nx + i];
         }
         implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
         for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
     }
 }
 
-/* Apply `nsteps` steps of `scheme`, each of length span/nsteps:
- * out = step^nsteps(in).  in and out may alias. */
+/* Apply `nsteps` steps of `scheme`, each of length span/nsteps, with source f
+ * (NULL: none): out = step^nsteps(in).  in and out may alias. */
 static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
-                      double *out)
+                      double *out, const double *f)
 {
     size_t np = (size_t)C->npts;
     double dt = span / nsteps;
@@ -257,7 +275,7 @@ static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, con
     double *a = base, *b = base + np, *work = base + 2 * np;
     memcpy(a, in, sizeof(double) * np);
     for (int s = 0; s < nsteps; ++s) {
-        one_step(C, scheme, dt, a, b, work);
+        one_step(C, scheme, dt, a, b, work, f);
         double *t = a;
         a = b;
         b = t;
@@ -306,27 +324,69 @@ orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, doubl
     return C;
 }
 
-void orc_destroy(orc_ctx *C) { free(C); }
+void orc_destroy(orc_ctx *C)
+{
+    if (C) free(C->src);
+    free(C);
+}
+
+/* Set (a copy of) the source f, npts values in slice layout; NULL removes it. */
+void orc_set_source(orc_ctx *C, const double *f)
+{
+    free(C->src);
+    C->src = NULL;
+    if (f) {
+        C->src = (double *)malloc(sizeof(double) * (size_t)C->npts);
+        memcpy(C->src, f, sizeof(double) * (size_t)C->npts);
+    }
+}
+
+/* The linear part F0 of the fine propagator (no source). */
+static void F_lin(const orc_ctx *C, const double *in, double *out)
+{
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL);
+}
+
+/* b = F(0): the forced response of one slice (0 without a source). */
+void orc_forced(const orc_ctx *C, double *b)
+{
+    memset(b, 0, sizeof(double) * (size_t)C->npts);
+    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src);
+}
+
+/* B = (u0, b, .., b) (Sec. 2, eq. (algebraiclinearsystem)). */
+static void build_B(const orc_ctx *C, const double *u0, double *B)
+{
+    size_t np = (size_t)C->npts;
+    memcpy(B, u0, sizeof(double) * np);
+    if (C->N > 1) {
+        orc_forced(C, B + np);
+        for (int n = 2; n < C->N; ++n) memcpy(B + (size_t)n * np, B + np, sizeof(double) * np);
+    }
+}
 int orc_npts(const orc_ctx *C) { return C->npts; }
 double orc_weight(const orc_ctx *C) { return C->w; }
 
-/* Fine propagator over one slice: m steps of dt = DT/m (Sec. 2). */
+/* Fine propagator over one slice: m steps of dt = DT/m (Sec. 2), with the
+ * source if one is set (affine). */
 void orc_F(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out);
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src);
 }
 
-/* Coarse propagator over one slice: c steps of DT/c. */
+/* Coarse propagator over one slice: c steps of DT/c, linear (the
+ * preconditioner's G; a source cancels from the parareal corrections). */
 void orc_G(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->coarse_scheme, C->c, C->DT, in, out);
+    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL);
 }
 
-/* One step of `scheme` with step dt (exported for the closed-form pins). */
+/* One step of `scheme` with step dt and the source if set (exported for the
+ * closed-form pins). */
 void orc_step(const orc_ctx *C, int scheme, double dt, const double *in, double *out)
 {
     double *work = (double *)malloc(sizeof(double) * step_work(C));
-    one_step(C, scheme, dt, in, out, work);
+    one_step(C, scheme, dt, in, out, work, C->src);
     free(work);
 }
 
@@ -334,7 +394,8 @@ void orc_step(const orc_ctx *C, int scheme, double dt, const double *in, double 
 /* Block operators (Sec. 2 eq. (algebraiclinearsystem), Sec. 3 eq. (eqinverse)) */
 /* ------------------------------------------------------------------------- */
 
-/* y_0 = lam_0,  y_n = lam_n - F(lam_{n-1}),  n = 1..N-1.  y must not alias lam. */
+/* y_0 = lam_0,  y_n = lam_n - F0(lam_{n-1}),  n = 1..N-1 (the linear
+ * all-at-once operator).  y must not alias lam. */
 void orc_apply(const orc_ctx *C, const double *lam, double *y)
 {
     size_t np = (size_t)C->npts;
@@ -342,13 +403,14 @@ void orc_apply(const orc_ctx *C, const double *lam, double *y)
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int n = 1; n < C->N; ++n) {
         double *f = (double *)malloc(sizeof(double) * np);
-        orc_F(C, lam + (size_t)(n - 1) * np, f);
+        F_lin(C, lam + (size_t)(n - 1) * np, f);
         for (size_t j = 0; j < np; ++j) y[(size_t)n * np + j] = lam[(size_t)n * np + j] - f[j];
         free(f);
     }
 }
 
-/* y_n = F(lam_n) for n = 0..N-1 (the last row gives u(T) = F(lam_{N-1})). */
+/* y_n = F(lam_n) for n = 0..N-1, the source included (the last row gives
+ * u(T) = F(lam_{N-1})). */
 void orc_apply_raw(const orc_ctx *C, const double *lam, double *y)
 {
     size_t np = (size_t)C->npts;
@@ -425,7 +487,7 @@ static void precond_apply(const orc_ctx *C, const double *in, double *out)
 }
 
 /*
- * Solve G^{-1} F X = G^{-1} B with B = (u0, 0, .., 0) by Algorithm 1.
+ * Solve G^{-1} F X = G^{-1} B with B = (u0, b, .., b) by Algorithm 1.
  * X: initial guess on entry when x0_mode == ORC_X0_GIVEN, solution on exit.
  * history (optional, capacity hist_cap): ||R^k|| for k = 0.. (the value tested
  * at the head of the loop).  Returns the status; fills *info.
@@ -459,7 +521,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
     int status = ORC_ENOCONV, k = 0, matvecs = 0, restarts = 0, hl = 0;
     double nrm = 0.0;
 
-    memcpy(B, u0, sizeof(double) * np); /* B = (lambda_0, 0, ..., 0) */
+    build_B(C, u0, B); /* B = (lambda_0, b, ..., b), b = 0 without a source */
 
     /* initial residual R^0 = G^{-1}(B - F X^0) */
     if (x0_mode == ORC_X0_ZERO) {
@@ -607,15 +669,17 @@ void orc_parareal_richardson(const orc_ctx *C, const double *u0, double *X, int 
 {
     size_t np = (size_t)C->npts, nt = (size_t)C->N * np;
     double *Tm = (double *)malloc(sizeof(double) * nt);
+    double *B = (double *)malloc(sizeof(double) * nt);
+    build_B(C, u0, B);
     for (int k = 0; k < iters; ++k) {
         orc_apply(C, X, Tm);
-        for (size_t i = 0; i < nt; ++i) Tm[i] = -Tm[i];
-        for (size_t j = 0; j < np; ++j) Tm[j] += u0[j];
+        for (size_t i = 0; i < nt; ++i) Tm[i] = B[i] - Tm[i];
         orc_sweep(C, Tm, Tm);
         if (history) history[k] = orc_norm(C, Tm);
         for (size_t i = 0; i < nt; ++i) X[i] += Tm[i];
     }
     free(Tm);
+    free(B);
 }
 
 /* Predictor-corrector recursion (Sec. 2, eq. (pararealscheme)), read as

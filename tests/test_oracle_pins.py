@@ -496,3 +496,125 @@ def test_paper_settings_golden():
     assert info.matvecs == g["matvecs_per_iteration"]["pitsbicg"] * info.iters
     _, hist = o.parareal_richardson(wl.u0_for(p), 3)
     assert len(hist) == 3 * g["matvecs_per_iteration"]["parareal"]
+
+
+# ---------------------------------------------------------------------------
+# Source term constant in time (Sec. 2, eq. (Cauchy) with f(x)): the slice
+# propagator becomes affine, F(u) = F0(u) + b, b = F(0).  Pinned by modal
+# recurrences on exact grid eigenvectors, written here from the scheme
+# definitions: per step a mode coefficient c with source coefficient phi goes
+#   IE:  c' = (c + dt phi) / (1 - dt mu)
+#   CN:  c' = ((1 + dt mu/2) c + dt phi) / (1 - dt mu/2)
+#   PR-ADI: c* = ((1 + th my) c + th phi) / (1 - th mx),
+#           c' = ((1 + th mx) c* + th phi) / (1 - th my),   th = dt/2
+# ---------------------------------------------------------------------------
+
+def modal_step(scheme, dt, mu, c, phi):
+    if scheme == wl.IE:
+        return (c + dt * phi) / (1 - dt * mu)
+    return ((1 + 0.5 * dt * mu) * c + dt * phi) / (1 - 0.5 * dt * mu)
+
+
+def modal_serial(scheme, dt, m, N, mu, c0, phi):
+    """Mode coefficient of lambda_0..lambda_{N-1} and of u(T)."""
+    out, c = [], c0
+    for _ in range(N + 1):
+        out.append(c)
+        for _ in range(m):
+            c = modal_step(scheme, dt, mu, c, phi)
+    return out
+
+
+@pytest.mark.parametrize("scheme", [wl.IE, wl.CN])
+def test_source_dirichlet_modal_closed_form(scheme):
+    p = wl.Problem(dim=1, M=(40, 1), bc=wl.DIRICHLET, nu=0.05, react=0.4, T=0.8, N=5, m=9,
+                   fine=scheme, c=1, coarse=wl.IE)
+    x = wl.grid_1d(p)
+    h = 1.0 / 41
+    mu = lambda k: -(4 * p.nu / h**2) * math.sin(k * math.pi * h / 2) ** 2 - p.react
+    modes = {1: (1.0, 0.7), 2: (0.0, -1.3), 3: (0.5, 0.0)}  # k: (u0 coefficient, source coefficient)
+    u0 = sum(c0 * np.sin(k * math.pi * x) for k, (c0, _) in modes.items())
+    f = sum(ph * np.sin(k * math.pi * x) for k, (_, ph) in modes.items())
+    o = orc.Oracle(**p.oracle_kwargs(), source=f)
+    dt = p.T / p.N / p.m
+    coefs = {k: modal_serial(scheme, dt, p.m, p.N, mu(k), c0, ph) for k, (c0, ph) in modes.items()}
+    ref = np.concatenate([sum(coefs[k][n] * np.sin(k * math.pi * x) for k in modes) for n in range(p.N)])
+    lam, uT = o.serial(u0, want_uT=True)
+    assert relerr(lam, ref) < 1e-13
+    assert relerr(uT, sum(coefs[k][p.N] * np.sin(k * math.pi * x) for k in modes)) < 1e-13
+    b = sum(modal_serial(scheme, dt, p.m, 1, mu(k), 0.0, ph)[1] * np.sin(k * math.pi * x)
+            for k, (_, ph) in modes.items())
+    assert relerr(o.forced(), b) < 1e-13
+    # F is affine and G, the preconditioner's propagator, stays linear
+    assert relerr(o.F(u0) - o.F(np.zeros_like(u0)), make(p).F(u0)) < 1e-13
+    assert np.all(o.G(np.zeros_like(u0)) == 0.0)
+
+
+def test_source_periodic_advection_modal_closed_form():
+    p = wl.Problem(dim=1, M=(48, 1), bc=wl.PERIODIC, nu=3e-3, adv=(0.8, 0.0), react=0.3, T=0.5, N=4,
+                   m=11, fine=wl.CN, c=2, coarse=wl.IE)
+    x = wl.grid_1d(p)
+    # complex mode coefficients on e^{2 pi i k x}; k = 0 is the constant mode
+    modes = {0: (0.2, 0.5), 1: (1.0 - 0.5j, 0.3j), 3: (0.0, 0.8 - 0.1j), 5: (0.25j, 0.0)}
+    field = lambda cs: sum((cs[k] * np.exp(2j * math.pi * k * x)).real for k in cs)
+    u0 = field({k: c0 for k, (c0, _) in modes.items()})
+    f = field({k: ph for k, (_, ph) in modes.items()})
+    o = orc.Oracle(**p.oracle_kwargs(), source=f)
+    dt = p.T / p.N / p.m
+    coefs = {k: modal_serial(wl.CN, dt, p.m, p.N, periodic_symbol(p, k), c0, ph) for k, (c0, ph) in modes.items()}
+    ref = np.concatenate([field({k: coefs[k][n] for k in modes}) for n in range(p.N)])
+    assert relerr(o.serial(u0), ref) < 1e-13
+
+
+def test_source_adi_2d_modal_closed_form():
+    p = wl.Problem(dim=2, M=(18, 14), length=(1.0, 1.3), bc=wl.DIRICHLET, nu=0.05, react=0.2,
+                   T=0.3, N=3, m=5, fine=wl.ADI, c=1, coarse=wl.ADI)
+    X, Y = wl.grid_2d(p)
+    hx, hy = 1.0 / 19, 1.3 / 15
+    mx = lambda k: -(4 * p.nu / hx**2) * math.sin(k * math.pi * hx / 2.0) ** 2 - 0.5 * p.react
+    my = lambda l: -(4 * p.nu / hy**2) * math.sin(l * math.pi * (hy / 1.3) / 2.0) ** 2 - 0.5 * p.react
+    modes = {(1, 1): (1.0, 0.6), (2, 3): (0.5, 0.0), (3, 1): (0.0, -0.9)}
+    mode = lambda k, l: (np.sin(k * math.pi * X / 1.0) * np.sin(l * math.pi * Y / 1.3)).reshape(-1)
+    u0 = sum(c0 * mode(k, l) for (k, l), (c0, _) in modes.items())
+    f = sum(ph * mode(k, l) for (k, l), (_, ph) in modes.items())
+    o = orc.Oracle(**p.oracle_kwargs(), source=f)
+    th = 0.5 * p.T / p.N / p.m
+
+    def F_coef(k, l, c, ph):
+        for _ in range(p.m):
+            cs = ((1 + th * my(l)) * c + th * ph) / (1 - th * mx(k))
+            c = ((1 + th * mx(k)) * cs + th * ph) / (1 - th * my(l))
+        return c
+
+    ref = sum(F_coef(k, l, c0, ph) * mode(k, l) for (k, l), (c0, ph) in modes.items())
+    assert relerr(o.F(u0), ref) < 1e-13
+    assert relerr(o.forced(), sum(F_coef(k, l, 0.0, ph) * mode(k, l) for (k, l), (_, ph) in modes.items())) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_source_all_at_once_system_and_solvers(dim):
+    """The serial trajectory solves F Lambda = B with B = (u0, b, .., b);
+    Algorithm 1 and both parareal forms reach it."""
+    if dim == 1:
+        p = wl.Problem(dim=1, M=(30, 1), bc=wl.PERIODIC, nu=2e-3, adv=(0.6, 0.0), react=0.1, T=0.6, N=6,
+                       m=5, fine=wl.CN, c=2, coarse=wl.IE)
+        x = wl.grid_1d(p)
+        u0 = np.sin(2 * math.pi * x) + 0.2
+        f = np.exp(-((x - 0.4) ** 2) / 0.01) - 0.3 * np.cos(4 * math.pi * x)
+    else:
+        p = wl.Problem(dim=2, M=(9, 7), bc=wl.DIRICHLET, nu=0.05, react=0.2, T=0.3, N=5, m=4,
+                       fine=wl.ADI, c=1, coarse=wl.ADI)
+        X, Y = wl.grid_2d(p)
+        u0 = (np.sin(math.pi * X) * np.sin(2 * math.pi * Y)).reshape(-1)
+        f = (X * (1 - X) * Y + 0.5).reshape(-1)
+    o = orc.Oracle(**p.oracle_kwargs(), source=f)
+    lam = o.serial(u0)
+    b = o.forced()
+    B = np.concatenate([u0] + [b] * (p.N - 1))
+    assert relerr(o.apply(lam), B) < 1e-13
+    Xs, info = o.pitsbicg(u0, tol=1e-13)
+    assert info.status == orc.OK and relerr(Xs, lam) < 1e-10
+    Xr, _ = o.parareal_richardson(u0, p.N)
+    assert relerr(Xr, lam) < 1e-12
+    Xp = o.parareal_pc(u0, np.zeros(p.N * o.npts), p.N)
+    assert relerr(Xp, lam) < 1e-12
