@@ -167,6 +167,26 @@ size_t pit_workspace_bytes(const pit_ctx *ctx);
  * PIT_EHIP. */
 int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes);
 
+/* Source term constant in time: the problem becomes u_t = L u + f(x) (the
+ * source f of the Cauchy problem, Sec. 2, eq. (Cauchy)).  Each step adds it:
+ * IE  (I - dt L) u' = u + dt f;  CN  (I - dt/2 L) u' = (I + dt/2 L) u + dt f;
+ * PR-ADI  dt/2 f in each half-step.  The slice propagator is then affine,
+ * F(u) = F0(u) + b with b = F(0) the forced response of one slice, and the
+ * all-at-once system of Sec. 2, eq. (algebraiclinearsystem) keeps its linear
+ * operator with B = (u0, b, .., b), whose solution is again the serial
+ * trajectory.  f: host array of npts values in slice layout, copied; NULL
+ * removes the source.  If the workspace is bound, f is uploaded and b computed
+ * at once (synchronous, null stream, with the context's block vectors as
+ * scratch: no other call on the context may be in flight), otherwise at
+ * pit_bind_workspace.
+ * Effects: pit_solve and pit_parareal (and batched solves of the context) use
+ * B = (u0, b, .., b); pit_apply_F with PIT_APPLY_RAW or PIT_APPLY_LAST returns
+ * the affine F(lam_n); the plain pit_apply_F (the system operator) and
+ * pit_coarse_sweep (the preconditioner, linear G) are unchanged.  Requests to
+ * a server carry no source.  Errors: PIT_EINVAL (NULL ctx, non-finite value),
+ * PIT_EHIP. */
+int pit_set_source(pit_ctx *ctx, const double *f);
+
 /* ---- operators ------------------------------------------------------------ */
 
 /* All-at-once operator (Sec. 2, eq. (algebraiclinearsystem)):

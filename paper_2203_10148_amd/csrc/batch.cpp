@@ -584,6 +584,7 @@ class Engine {
         if (ph == PH_INIT) {
             PIT_HIP(launch_fill0(in->v(VEC_S), n, st));
             PIT_HIP(launch_copy(in->v(VEC_S), in->u0, c->npts, st));
+            PIT_HIP(fill_forced(c, in->v(VEC_S), st));
             PIT_HIP(launch_fill0(in->v(VEC_X), n, st));
         }
         if (ph == PH_A && in->pend_p) {
@@ -660,6 +661,7 @@ class Engine {
             plan.push_back([=] {
                 return launch_to_chunked(in->u0, in->v(VEC_S), 1, c->npts, c->lf.sh.NT, c->lf.sh.C, st);
             });
+            plan.push_back([=] { return fill_forced(c, in->v(VEC_S), st); });
             plan.push_back([=] { return launch_fill0(in->v(VEC_X), in->n(), st); });
         }
         // vector updates: deferred new direction (A), S = R - alpha D (B), X and R updates (C)

@@ -25,6 +25,10 @@ void set_last_hip(int code);
         }                                     \
     } while (0)
 
+// One slice of `len` values written (add = 0) or added (add = 1) into `count`
+// consecutive slices (krylov.hip).
+hipError_t launch_repeat(double *dst, const double *src, long len, long count, int add, hipStream_t st);
+
 constexpr size_t kAlign = 256;
 constexpr int kSolveVectors = 8;  // R, shadow R, P, D, S, K, temporary, iterate
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -75,6 +79,15 @@ struct pit_ctx {
     double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
     size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
     int adi_R = 32;  // rows per wavefront in the fine x half step
+    // Source constant in time (host copy; empty: none) and, in the workspace,
+    // the source (natural layout) and the forced response b = F(0) of one
+    // slice in the working layout (1D chunked) and in the natural layout.
+    std::vector<double> src;
+    size_t off_src = 0, off_bf = 0, off_bfn = 0;
+    bool has_src() const { return !src.empty(); }
+    double *srcdev() const { return reinterpret_cast<double *>(ws + off_src); }
+    double *bf() const { return reinterpret_cast<double *>(ws + off_bf); }
+    double *bfn() const { return reinterpret_cast<double *>(ws + off_bfn); }
     // 2D: the launch sequences of the fine apply (2m launches) and of the
     // coarse sweep (2(N-1)c launches) captured as HIP graphs, one per
     // (operation, input, output), replayed on the caller's stream
@@ -137,5 +150,7 @@ namespace pit {
 // The operators on block vectors of stride ld (chunked inside the solvers in 1D).
 hipError_t op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal, hipStream_t st);
 hipError_t op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st);
+// With a source: slices 1..N-1 of B (working layout) become b.  No-op without one.
+hipError_t fill_forced(const pit_ctx *c, double *B, hipStream_t st);
 
 }  // namespace pit

@@ -309,6 +309,24 @@ hipError_t launch_b_minus(double *out, const double *in, const double *u0, long 
     return hipGetLastError();
 }
 
+// dst[i] = src[i % len] (add = 0) or dst[i] += src[i % len] (add = 1), i < len*count:
+// one slice repeated over `count` slices.
+__global__ void k_repeat(double *__restrict__ dst, const double *__restrict__ src, long len, long n, int add)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = src[i % len];
+        dst[i] = add ? dst[i] + v : v;
+    }
+}
+
+hipError_t launch_repeat(double *dst, const double *src, long len, long count, int add, hipStream_t st)
+{
+    const long n = len * count;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_repeat, vec_grid(n), dim3(kVecThreads), 0, st, dst, src, len, n, add);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_copy, vec_grid(n), dim3(kVecThreads), 0, st, dst, src, n);

@@ -463,7 +463,109 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
     return hipSuccess;
 }
 
+// Workspace of the source term: the source and the forced response (working
+// and natural layouts); reserved for every context, a few slices at most.
+size_t source_slots(pit_ctx &c, size_t o)
+{
+    c.off_src = o;
+    o = align_up(o + (size_t)c.npts * sizeof(double));
+    c.off_bf = o;
+    o = align_up(o + (size_t)std::max<long>(c.ld, c.npts) * sizeof(double));
+    c.off_bfn = o;
+    return align_up(o + (size_t)c.npts * sizeof(double));
+}
+
+// The forced response b = F(0) of one slice for the source f (constant in
+// time), into bfn() (natural) and bf() (working layout), FP64.  F is affine,
+// F(u) = S^m u + b with S one fine step, and b = sum_{i<m} S^i c where c is
+// the response of one step from 0:
+//   IE and CN: c = A^{-1} (dt f)  (A = I - theta dt L, the step's matrix);
+//   PR-ADI:    c = dt Y^{-1} X^{-1} f  (X, Y the half-step matrices: the
+//              source's dt/2 f enters both half-steps, and (I + th Lx) X^{-1}
+//              = 2 X^{-1} - I).
+// 1D sums by doubling, b(2k) = b(k) + S^k b(k), b(k+1) = S b(k) + c, with
+// S^k one fine launch of k steps; 2D sums step by step.  Uses the context's
+// block vectors as scratch (at bind, no solve runs).
+hipError_t compute_forced(pit_ctx *c, hipStream_t st)
+{
+    const long np = c->npts;
+    const double dt = c->DT / c->m;
+    double *h = c->vec(0), *t = c->vec(1), *cc = c->vec(2), *g = c->vec(3);
+    hipError_t e;
+#define FH(x)                              \
+    if ((e = (x)) != hipSuccess) return e
+    FH(hipMemcpyAsync(c->srcdev(), c->src.data(), np * sizeof(double), hipMemcpyHostToDevice, st));
+    if (!c->dim2()) {
+        const LineTab<double> tb = c->tab(c->lf, c->off_tf);
+        auto steps = [&](const double *in, double *out, int k, int scheme) {
+            return launch_fine1d_f64(c->lf.sh, tb, in, out, 1, c->npts, k, scheme, 1, 0, false, st);
+        };
+        FH(launch_axpby(g, c->srcdev(), dt, c->srcdev(), 0.0, np, st));
+        FH(steps(g, cc, 1, SCHEME_IE));  // one solve with A: A^{-1} (dt f)
+        FH(launch_copy(h, cc, np, st));
+        int top = 0;
+        while ((c->m >> (top + 1)) != 0) ++top;
+        int count = 1;
+        for (int bit = top - 1; bit >= 0; --bit) {
+            FH(steps(h, t, count, c->fine.scheme));
+            FH(launch_axpby(h, t, 1.0, h, 1.0, np, st));
+            count *= 2;
+            if ((c->m >> bit) & 1) {
+                FH(steps(h, t, 1, c->fine.scheme));
+                FH(launch_axpby(h, t, 1.0, cc, 1.0, np, st));
+                count += 1;
+            }
+        }
+        FH(launch_copy(c->bfn(), h, np, st));
+        FH(launch_to_chunked(h, c->bf(), 1, c->npts, c->lf.sh.NT, c->lf.sh.C, st));
+        return hipSuccess;
+    }
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64 * c->ash.xw, c->ash.cx);
+    tx.cyclic = 0;
+    tx.M = Mx;
+    const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy * c->ash.seg);
+    auto B = [](double *p) { return AdiBuf{nullptr, p, false}; };
+    auto half_x = [&](const double *in, double *out, double ex, double ed) {
+        return launch_adi_x(c->ash, tx, B(const_cast<double *>(in)), 0, B(out), 0, 1, Mx, My, 1, ex, ed, st);
+    };
+    auto half_y = [&](const double *in, double *out, double ex, double ed) {
+        return launch_adi_y(c->ash, ty, B(const_cast<double *>(in)), 0, B(out), 0, nullptr, 0, 0.0, 1, Mx, My, ex,
+                            ed, st);
+    };
+    FH(half_x(c->srcdev(), t, 0.0, 1.0));  // X^{-1} f (explicit part off)
+    FH(half_y(t, g, 0.0, 1.0));            // Y^{-1} X^{-1} f
+    FH(launch_axpby(cc, g, dt, g, 0.0, np, st));
+    FH(launch_copy(h, cc, np, st));
+    for (int k = 1; k < c->m; ++k) {
+        FH(half_x(h, t, c->fx_ex, c->fx_ed));
+        FH(half_y(t, g, c->fy_ex, c->fy_ed));
+        FH(launch_axpby(h, g, 1.0, cc, 1.0, np, st));
+    }
+    FH(launch_copy(c->bfn(), h, np, st));
+    FH(launch_copy(c->bf(), h, np, st));
+#undef FH
+    return hipSuccess;
+}
+
+// With a source: upload it and compute the forced response (synchronous, on
+// the null stream, like the table uploads of pit_bind_workspace).
+int bind_source(pit_ctx *ctx)
+{
+    if (!ctx->has_src()) return PIT_OK;
+    PIT_HIP(compute_forced(ctx, nullptr));
+    PIT_HIP(hipStreamSynchronize(nullptr));
+    return PIT_OK;
+}
+
 }  // namespace
+
+hipError_t pit::fill_forced(const pit_ctx *c, double *B, hipStream_t st)
+{
+    if (!c->has_src() || c->N < 2) return hipSuccess;
+    const long len = c->dim2() ? c->npts : c->ld;
+    return launch_repeat(B + len, c->bf(), len, c->N - 1, 0, st);
+}
 
 void pit_ctx::drop_graphs() const
 {
@@ -609,6 +711,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
         c->off_red = o;
         o = align_up(o + sizeof(RedOut));
+        o = source_slots(*c, o);
         c->total = o;
         *out = c;
         return PIT_OK;
@@ -654,6 +757,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
     c->off_red = o;
     o = align_up(o + sizeof(RedOut));
+    o = source_slots(*c, o);
     c->total = o;
     *out = c;
     return PIT_OK;
@@ -710,7 +814,7 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
                           hipMemcpyHostToDevice));
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_ayc, ctx->ayc.data(), ctx->ayc.size() * sizeof(double),
                           hipMemcpyHostToDevice));
-        return PIT_OK;
+        return bind_source(ctx);
     }
     PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf, ctx->lf.blob.data(), ctx->lf.blob.size() * sizeof(double),
                       hipMemcpyHostToDevice));
@@ -719,7 +823,20 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
     if (ctx->fine32())
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf32, ctx->lf.blob32.data(), ctx->lf.blob32.size() * sizeof(float),
                           hipMemcpyHostToDevice));
-    return PIT_OK;
+    return bind_source(ctx);
+}
+
+int pit_set_source(pit_ctx *ctx, const double *f)
+{
+    if (!ctx) return PIT_EINVAL;
+    if (!f) {
+        ctx->src.clear();
+        return PIT_OK;
+    }
+    for (int j = 0; j < ctx->npts; ++j)
+        if (!std::isfinite(f[j])) return PIT_EINVAL;
+    ctx->src.assign(f, f + ctx->npts);
+    return ctx->ws ? bind_source(ctx) : PIT_OK;
 }
 
 int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void *stream)
@@ -739,9 +856,15 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
         PIT_HIP(op_apply(ctx, a, b, raw, last, true, st));
         if (last) PIT_HIP(launch_from_chunked(b + n1 * ctx->ld, y + n1 * ctx->npts, 1, ctx->npts, NT, C, st));
         else PIT_HIP(launch_from_chunked(b, y, ctx->N, ctx->npts, NT, C, st));
-        return PIT_OK;
+    } else {
+        PIT_HIP(op_apply(ctx, lam, y, raw, last, false, st));
     }
-    PIT_HIP(op_apply(ctx, lam, y, raw, last, false, st));
+    // with a source F is affine: F(lam_n) = F0(lam_n) + b
+    if (ctx->has_src() && (raw || last)) {
+        const long np = ctx->npts;
+        if (last) PIT_HIP(launch_repeat(y + (long)(ctx->N - 1) * np, ctx->bfn(), np, 1, 1, st));
+        else PIT_HIP(launch_repeat(y, ctx->bfn(), np, ctx->N, 1, st));
+    }
     return PIT_OK;
 }
 
@@ -896,10 +1019,11 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     int rc;
     RedOut h{};
 
-    // initial residual R^0 = G^{-1}(B - F X^0), B = (u0, 0, .., 0)
+    // initial residual R^0 = G^{-1}(B - F X^0), B = (u0, b, .., b) (b = 0 without a source)
     PIT_HIP(launch_fill0(s.S, n, st));
     if (ctx->dim2()) PIT_HIP(launch_copy(s.S, u0, ctx->npts, st));  // S holds B for now
     else PIT_HIP(launch_to_chunked(u0, s.S, 1, ctx->npts, NT, C, st));
+    PIT_HIP(fill_forced(ctx, s.S, st));
     if (o.x0_mode == PIT_X0_ZERO) {
         PIT_HIP(launch_fill0(X, n, st));
         if ((rc = s.sweep(s.S, s.R))) return rc;
@@ -1189,10 +1313,11 @@ extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit
     hipStream_t st = s.st;
     double *const Xu = X;
     double *const Xc = ctx->vec(7), *const R = ctx->vec(0), *const U0 = ctx->vec(1);
-    // u0 in the working layout (slice 0 of B)
+    // B in the working layout: u0 in slice 0, b (or 0) in the others
     PIT_HIP(launch_fill0(U0, n, st));
     if (ctx->dim2()) PIT_HIP(launch_copy(U0, u0, ctx->npts, st));
     else PIT_HIP(launch_to_chunked(u0, U0, 1, ctx->npts, NT, C, st));
+    PIT_HIP(fill_forced(ctx, U0, st));
     int rc;
     if (o.x0_mode == PIT_X0_ZERO) {
         PIT_HIP(launch_fill0(Xc, n, st));
@@ -1209,7 +1334,8 @@ extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit
     for (; k < o.max_iter; ++k) {
         // R = G^{-1}(B - F X)
         if ((rc = s.apply(Xc, R))) return rc;
-        PIT_HIP(launch_b_minus(R, R, U0, ctx->ld, n, st));
+        if (ctx->has_src()) PIT_HIP(launch_axpby(R, U0, 1.0, R, -1.0, n, st));
+        else PIT_HIP(launch_b_minus(R, R, U0, ctx->ld, n, st));
         if ((rc = s.sweep(R, R))) return rc;
         s.matvecs++;
         {

@@ -83,7 +83,7 @@ EXPORTS = (
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
     "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
-    "pit_parareal",
+    "pit_parareal", "pit_set_source",
 )
 
 _lib = None
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.pit_workspace_bytes.argtypes = [vp]
     lib.pit_workspace_bytes.restype = sz
     lib.pit_bind_workspace.argtypes = [vp, vp, sz]
+    lib.pit_set_source.argtypes = [vp, ct.POINTER(ct.c_double)]
     lib.pit_apply_F.argtypes = [vp, vp, vp, i32, vp]
     lib.pit_coarse_sweep.argtypes = [vp, vp, vp, vp]
     lib.pit_solve.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
@@ -216,6 +217,16 @@ class Context:
     @property
     def workspace_bytes(self) -> int:
         return int(load().pit_workspace_bytes(self._h))
+
+    def set_source(self, f):
+        """Source constant in time (one slice of values, host), or None to remove it."""
+        if f is None:
+            _check(load().pit_set_source(self._h, None), "pit_set_source")
+            return
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+        if f.size != self.p.npts:
+            raise ValueError("set_source: one slice of npts values expected")
+        _check(load().pit_set_source(self._h, f.ctypes.data_as(ct.POINTER(ct.c_double))), "pit_set_source")
 
     def kernel_shape(self):
         out = (ct.c_int32 * 4)()

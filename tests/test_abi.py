@@ -100,6 +100,22 @@ def test_unbound_context_and_null_pointers_are_rejected():
     lib.pit_destroy(h)
 
 
+def test_set_source_validates_on_the_host():
+    """pit_set_source on an unbound context only keeps a host copy."""
+    import numpy as np
+    lib = P.load()
+    _, h = create(wl.C1)
+    dp = ct.POINTER(ct.c_double)
+    f = np.linspace(0.0, 1.0, wl.C1.npts)
+    assert lib.pit_set_source(None, f.ctypes.data_as(dp)) == P.EINVAL
+    bad = f.copy()
+    bad[3] = np.nan
+    assert lib.pit_set_source(h, bad.ctypes.data_as(dp)) == P.EINVAL
+    assert lib.pit_set_source(h, f.ctypes.data_as(dp)) == P.OK
+    assert lib.pit_set_source(h, None) == P.OK
+    lib.pit_destroy(h)
+
+
 def test_strerror_covers_codes():
     for code in (P.OK, P.EINVAL, P.ENOMEM, P.EHIP, P.ENOCONV, P.EBREAKDOWN, P.EAGAIN):
         assert P.strerror(code) and P.strerror(code) != "unknown status"
