@@ -168,13 +168,13 @@ def workload(name, prec, side=None):
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
 
 
-def cpu_baseline(p, u0, seconds):
+def cpu_baseline(p, u0, seconds, source=None):
     """Oracle PiTSBiCG on the host cores, truncated to a few iterations."""
     import oracle as orc
 
     threads = max(1, min(16, os.cpu_count() or 1))
     orc.set_threads(threads)
-    o = orc.Oracle(**p.oracle_kwargs())
+    o = orc.Oracle(**p.oracle_kwargs(), source=source)
     iters = 1
     while True:
         t0 = time.perf_counter()
@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-singles", action="store_true", help="c4: skip the single-instance baseline solves")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
+    ap.add_argument("--source", type=int, default=None, metavar="SEED",
+                    help="c1-c3: add a seeded source term constant in time (pit_set_source)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["apply", "sweep", "solve"], default=None,
@@ -253,6 +255,14 @@ def main():
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
     ctx = P.Context(p, device=dev)
+    source_f, src_ms = None, None
+    if args.source is not None:
+        # the forced response is computed at pit_set_source (setup, not timed)
+        source_f = wl.source_bumps(p, args.source)
+        t0 = time.perf_counter()
+        ctx.set_source(source_f)
+        src_ms = 1e3 * (time.perf_counter() - t0)
+        log(f"[bench] source (seed {args.source}): forced response set up in {src_ms:.2f} ms")
     if args.probe:
         lam = torch.as_tensor(wl.random_block(p, 1), dtype=torch.float64, device=dev)
         out = torch.empty_like(lam)
@@ -371,12 +381,18 @@ def main():
         "fine_kernel_stream_equiv_hbm_frac": fine_cu_s * (16 if args.prec == "f64" else 8) / (PEAK["hbm_GBs"] * 1e9),
         "kernel_shape": ctx.kernel_shape(),
     }
+    if source_f is not None:
+        out["config"]["source_seed"] = args.source
+        out["source"] = {"setup_ms": src_ms, "note": "forced response b = F(0) of one slice, computed on the "
+                                                    "device at pit_set_source; B = (u0, b, .., b)"}
     # the other fine-propagator form on the same input (FP32 fine with FP64
     # reductions vs plain FP64), outside the timed region
     if p.dim == 1 and not args.no_compare:
         other = wl.F64 if p.prec == wl.F32 else wl.F32
         po = p.with_(prec=other)
         co = P.Context(po, device=dev)
+        if source_f is not None:
+            co.set_source(source_f)
         Xo = torch.empty_like(X)
         so = 10 if other == wl.F32 else 0
         co.solve(u0, Xo, tol=p.tol, stall_window=so)
@@ -411,7 +427,7 @@ def main():
             f"vs PiTSBiCG {matvecs} products")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f)
     print(json.dumps(out), flush=True)
 
 

@@ -137,6 +137,31 @@ def u0_bumps(p: Problem, seed: int, nbumps: int = 8) -> np.ndarray:
     return u.reshape(-1)
 
 
+def source_bumps(p: Problem, seed: int, nbumps: int = 4) -> np.ndarray:
+    """A seeded source field (constant in time): Gaussian bumps, A ~ U[-1,1],
+    centres ~ U[0,1) of each axis, sigma ~ U[0.03,0.1]; the distance wraps on
+    a periodic axis."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(-1.0, 1.0, nbumps)
+    cx = rng.uniform(0.0, 1.0, nbumps) * p.length[0]
+    cy = rng.uniform(0.0, 1.0, nbumps) * p.length[1]
+    sg = rng.uniform(0.03, 0.1, nbumps)
+    if p.dim == 1:
+        x = grid_1d(p)
+        f = np.zeros_like(x)
+        for i in range(nbumps):
+            d = x - cx[i]
+            if p.bc == PERIODIC:
+                d = (d + 0.5 * p.length[0]) % p.length[0] - 0.5 * p.length[0]
+            f += A[i] * np.exp(-d ** 2 / (2.0 * sg[i] ** 2))
+        return f
+    X, Y = grid_2d(p)
+    f = np.zeros_like(X)
+    for i in range(nbumps):
+        f += A[i] * np.exp(-((X - cx[i]) ** 2 + (Y - cy[i]) ** 2) / (2.0 * sg[i] ** 2))
+    return f.reshape(-1)
+
+
 def random_block(p: Problem, seed: int) -> np.ndarray:
     """A seeded N x npts block vector of standard normals (operator parity inputs)."""
     return np.random.default_rng(seed).standard_normal(p.N * p.npts)
