@@ -69,7 +69,7 @@ def _load():
     lib.orc_create.restype = ct.c_void_p
     lib.orc_create.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double, ct.c_double,
                                ct.c_double, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
-                               ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int]
+                               ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double]
     lib.orc_destroy.argtypes = [ct.c_void_p]
     lib.orc_set_source.argtypes = [ct.c_void_p, _D]
     lib.orc_forced.argtypes = [ct.c_void_p, _D]
@@ -142,13 +142,13 @@ class Oracle:
     """One PiT problem: a grid, an operator, N slices, fine and coarse steppers."""
 
     def __init__(self, *, dim=1, M=(64, 1), bc=DIRICHLET, length=(1.0, 1.0), nu=1.0,
-                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None):
+                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None, rot=0.0):
         lib = _load()
         Mx, My = (M, 1) if isinstance(M, int) else (int(M[0]), int(M[1]))
         self.dim, self.Mx, self.My, self.N = dim, Mx, (My if dim == 2 else 1), N
         h = lib.orc_create(dim, Mx, My, bc, float(length[0]), float(length[1]), float(nu),
                            float(adv[0]), float(adv[1]), float(react), float(T), N, m, fine, c,
-                           coarse)
+                           coarse, float(rot))
         if not h:
             raise ValueError("oracle: invalid problem description")
         self._h = h

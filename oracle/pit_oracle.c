@@ -34,7 +34,14 @@
  *   CN:  (I - dt/2 L) u' = (I + dt/2 L) u + dt f
  *   PR-ADI (2D): (I - dt/2 Lx) u* = (I + dt/2 Ly) u + dt/2 f,
  *                (I - dt/2 Ly) u' = (I + dt/2 Lx) u* + dt/2 f,
- *       with Lx = nu*D2x - ax*D1x - r/2 and Ly = nu*D2y - ay*D1y - r/2.
+ *       with Lx = nu*D2x - ux(y)*D1x - r/2 and Ly = nu*D2y - uy(x)*D1y - r/2;
+ *       the velocity is a constant (ax, ay) plus a rigid rotation of rate rot
+ *       about the centre (xc, yc) of the domain:
+ *           ux = ax - rot*(y - yc),  uy = ay + rot*(x - xc)
+ *       (rot = 1 with the centre at the origin is the u = [-y, x] of the
+ *       advection-diffusion-reaction test of Sec. 4).  ux is constant along a
+ *       row and uy along a column, so every line is a constant-stencil
+ *       tridiagonal system, one per row or column.
  * f is an optional source, constant in time (the source term of Sec. 2, eq.
  * (Cauchy)); without it f = 0.  With a source the slice propagator is affine,
  * F(u) = F0(u) + b with b = F(0), the forced response of one slice.  The
@@ -65,7 +72,7 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOCONV = -4, ORC_EBREAKDOWN = -5 };
 
 typedef struct {
     int dim, Mx, My, bc;
-    double Lx, Ly, nu, ax, ay, react, T;
+    double Lx, Ly, nu, ax, ay, react, T, rot;
     int N, m, fine_scheme, c, coarse_scheme;
     /* derived */
     int npts;      /* points per slice */
@@ -185,6 +192,17 @@ static void implicit_line(int n, int bc, double th, double lo, double di, double
         thomas(n, a, b, c, d, x, w, w + n);
 }
 
+/* 2D velocity: x-component on row j (constant along the row), y-component on
+ * column i; interior points x_i = (i+1) hx, y_j = (j+1) hy. */
+static double ux_at(const orc_ctx *C, int j)
+{
+    return C->ax - C->rot * ((j + 1) * C->hy - 0.5 * C->Ly);
+}
+static double uy_at(const orc_ctx *C, int i)
+{
+    return C->ay + C->rot * ((i + 1) * C->hx - 0.5 * C->Lx);
+}
+
 /* Work size in doubles needed by one_step. */
 static size_t step_work(const orc_ctx *C)
 {
@@ -227,11 +245,10 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
         }
         return;
     }
-    /* 2D Peaceman-Rachford ADI, Dirichlet-0. */
+    /* 2D Peaceman-Rachford ADI, Dirichlet-0.  Row j: x-operator with velocity
+     * ux(y_j); column i: y-operator with velocity uy(x_i). */
     int nx = C->Mx, ny = C->My;
     double xlo, xdi, xup, ylo, ydi, yup;
-    op1d(C->nu, C->ax, 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
-    op1d(C->nu, C->ay, 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
     int nmax = nx > ny ? nx : ny;
     double *star = work;           /* npts */
     double *line = work + C->npts; /* nmax */
@@ -241,24 +258,28 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
     /* half-step 1: rhs = (I + th*Ly) u + th*f, then (I - th*Lx) u* = rhs row by row */
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
+            op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
             double c0 = u[j * nx + i];
             double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
             double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
             line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
             if (f) line[i] += th * f[j * nx + i];
         }
+        op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
         implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
         for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
     }
     /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column */
     for (int i = 0; i < nx; ++i) {
         for (int j = 0; j < ny; ++j) {
+            op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
             double c0 = star[j * nx + i];
             double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
             double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
             line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
             if (f) line[j] += th * f[j * nx + i];
         }
+        op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
         implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
         for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
     }
@@ -290,12 +311,12 @@ static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, con
 
 orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, double nu, double ax,
                     double ay, double react, double T, int N, int m, int fine_scheme, int c,
-                    int coarse_scheme)
+                    int coarse_scheme, double rot)
 {
     if (dim != 1 && dim != 2) return NULL;
     if (Mx < 3 || N < 1 || m < 1 || c < 1) return NULL;
     if (dim == 2 && (My < 3 || bc != ORC_DIRICHLET)) return NULL;
-    if (dim == 2 && (ax != 0.0 || ay != 0.0)) return NULL; /* 2D: diffusion-reaction only */
+    if (dim == 1 && rot != 0.0) return NULL; /* rotation: 2D only */
     if (dim == 1 && (fine_scheme == ORC_ADI || coarse_scheme == ORC_ADI)) return NULL;
     if (dim == 2 && (fine_scheme != ORC_ADI || coarse_scheme != ORC_ADI)) return NULL;
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
@@ -310,6 +331,7 @@ orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, doubl
     C->ay = ay;
     C->react = react;
     C->T = T;
+    C->rot = rot;
     C->N = N;
     C->m = m;
     C->fine_scheme = fine_scheme;

@@ -50,6 +50,7 @@ class Problem:
     prec: int = F64             # fine-propagator precision
     tol: float = 1e-10
     name: str = "custom"
+    rot: float = 0.0            # 2D: rate of a rigid rotation about the domain centre
 
     @property
     def npts(self) -> int:
@@ -63,7 +64,7 @@ class Problem:
     def oracle_kwargs(self) -> dict:
         return dict(dim=self.dim, M=self.M, bc=self.bc, length=self.length, nu=self.nu,
                     adv=self.adv, react=self.react, T=self.T, N=self.N, m=self.m,
-                    fine=self.fine, c=self.c, coarse=self.coarse)
+                    fine=self.fine, c=self.c, coarse=self.coarse, rot=self.rot)
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)

@@ -66,10 +66,18 @@ def dense_step(p: wl.Problem, scheme, dt):
         return np.linalg.solve(I - 0.5 * dt * L, I + 0.5 * dt * L)
     Mx, My = p.M
     hx, hy = p.length[0] / (Mx + 1), p.length[1] / (My + 1)
-    Dx = dense_L1(Mx, hx, p.nu, 0.0, 0.5 * p.react, False)
-    Dy = dense_L1(My, hy, p.nu, 0.0, 0.5 * p.react, False)
-    Lx = np.kron(np.eye(My), Dx)  # acts along x (fastest index)
-    Ly = np.kron(Dy, np.eye(Mx))
+    # velocity: constant plus a rigid rotation about the centre, so row j has
+    # its own x-operator and column i its own y-operator
+    ux = [p.adv[0] - p.rot * ((j + 1) * hy - 0.5 * p.length[1]) for j in range(My)]
+    uy = [p.adv[1] + p.rot * ((i + 1) * hx - 0.5 * p.length[0]) for i in range(Mx)]
+    n = Mx * My
+    Lx = np.zeros((n, n))
+    Ly = np.zeros((n, n))
+    for j in range(My):  # x is the fastest index
+        Lx[j * Mx:(j + 1) * Mx, j * Mx:(j + 1) * Mx] = dense_L1(Mx, hx, p.nu, ux[j], 0.5 * p.react, False)
+    for i in range(Mx):
+        idx = np.arange(My) * Mx + i
+        Ly[np.ix_(idx, idx)] = dense_L1(My, hy, p.nu, uy[i], 0.5 * p.react, False)
     I = np.eye(Mx * My)
     th = 0.5 * dt
     half1 = np.linalg.solve(I - th * Lx, I + th * Ly)
@@ -241,12 +249,14 @@ def test_adi_2d_closed_form_rectangle():
     assert relerr(o.G(u0), field(cstep)) < 1e-13
 
 
-@pytest.mark.parametrize("case", ["d_ie_adv", "d_cn_adv", "p_cn", "adi"])
+@pytest.mark.parametrize("case", ["d_ie_adv", "d_cn_adv", "p_cn", "adi", "adi_rot"])
 def test_one_step_vs_dense(case):
     """One step of each scheme against the dense matrix solved by LAPACK."""
-    if case == "adi":
+    if case.startswith("adi"):
+        rot = case == "adi_rot"
         p = wl.Problem(dim=2, M=(5, 4), length=(1.0, 0.7), nu=0.3, react=0.5, T=1.0, N=1, m=1,
-                       fine=wl.ADI, coarse=wl.ADI)
+                       fine=wl.ADI, coarse=wl.ADI, adv=(0.4, -0.2) if rot else (0.0, 0.0),
+                       rot=1.3 if rot else 0.0)
         scheme = wl.ADI
     else:
         bc = wl.PERIODIC if case.startswith("p") else wl.DIRICHLET
@@ -270,10 +280,12 @@ TINY = [
                fine=wl.CN, c=2, coarse=wl.IE),
     wl.Problem(dim=2, M=(4, 3), length=(1.0, 0.8), nu=0.05, T=0.5, N=4, m=3, fine=wl.ADI, c=1,
                coarse=wl.ADI),
+    wl.Problem(dim=2, M=(5, 4), length=(1.0, 1.0), nu=0.02, react=0.5, rot=1.0, T=0.5, N=4, m=3,
+               fine=wl.ADI, c=1, coarse=wl.ADI),
 ]
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
 def test_apply_and_sweep_vs_dense(p):
     o = make(p)
     SF, SG = dense_props(p)
@@ -286,7 +298,7 @@ def test_apply_and_sweep_vs_dense(p):
         assert relerr(raw[n], SF @ v.reshape(p.N, -1)[n]) < 1e-13
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
 def test_serial_is_exact_solution(p):
     """The serial fine trajectory solves F Lambda = B with B = (u0, 0, .., 0)."""
     o = make(p)
@@ -349,7 +361,7 @@ def bicgstab_textbook(A, b, weight, N, iters):
     return xs, np.array(norms)
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
 def test_pitsbicg_matches_textbook_bicgstab_and_dense_solution(p):
     o = make(p)
     u0 = np.random.default_rng(9).standard_normal(p.npts)
@@ -618,3 +630,22 @@ def test_source_all_at_once_system_and_solvers(dim):
     assert relerr(Xr, lam) < 1e-12
     Xp = o.parareal_pc(u0, np.zeros(p.N * o.npts), p.N)
     assert relerr(Xp, lam) < 1e-12
+
+
+def test_rotation_turns_a_bump_counterclockwise_about_the_centre():
+    """u = [-(y - yc), x - xc] (rate 1): a bump a quarter of the side east of
+    the centre is, after a quarter turn (t = pi/2), north of it; after a half
+    turn, west.  This fixes the signs and the centre independently of the
+    formula."""
+    p = wl.Problem(dim=2, M=(71, 71), bc=wl.DIRICHLET, nu=1e-5, rot=1.0, T=math.pi / 2, N=1, m=600,
+                   fine=wl.ADI, c=1, coarse=wl.ADI)
+    o = make(p)
+    X, Y = wl.grid_2d(p)
+    u0 = np.exp(-((X - 0.75) ** 2 + (Y - 0.5) ** 2) / (2 * 0.05 ** 2)).reshape(-1)
+    u1 = o.F(u0)
+    k = int(np.argmax(u1))
+    assert abs(X.reshape(-1)[k] - 0.5) < 0.03 and abs(Y.reshape(-1)[k] - 0.75) < 0.03
+    u2 = o.F(u1)
+    k = int(np.argmax(u2))
+    assert abs(X.reshape(-1)[k] - 0.25) < 0.03 and abs(Y.reshape(-1)[k] - 0.5) < 0.03
+    assert abs(u2.max() / u0.max() - 1.0) < 0.1  # little damping at nu = 1e-5
