@@ -159,7 +159,7 @@ def algorithmic_bytes(p, prec, unit):
 def workload(name, prec, side=None):
     from paper_2203_10148_amd import workloads as wl
 
-    p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3}[name]
+    p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3, "f2": wl.F2}[name]
     if side and p.dim == 2 and side != p.M[0]:
         # the same 2D recipe on a larger square (its working set beyond the 256 MiB MALL)
         p = p.with_(M=(side, side), name=f"{p.name}_{side}")
@@ -196,7 +196,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2"],
                     help="c1-c3: one solve per step; c4: the 64-instance batch per step; c5: a served "
                          "Poisson stream (one pass of --requests requests)")
     ap.add_argument("--requests", type=int, default=120, help="c5: how many requests of the stream to serve")

@@ -86,6 +86,9 @@ typedef struct {
     double adv[2];     /* advection velocity (1D uses adv[0])          */
     double react;      /* reaction coefficient                         */
     double T;          /* final time (> 0)                             */
+    double rot;        /* 2D: rate of a rigid rotation about the domain
+                          centre added to adv, 0 in 1D (the u = [-y, x]
+                          of the advection test of Sec. 4)             */
 } pit_problem;
 
 /* A time stepper over one slice: `substeps` steps of length DT/substeps.

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "pit_internal.hpp"
+#include "vel2d.hpp"
 
 namespace pit {
 
@@ -88,6 +89,20 @@ struct pit_ctx {
     double *srcdev() const { return reinterpret_cast<double *>(ws + off_src); }
     double *bf() const { return reinterpret_cast<double *>(ws + off_bf); }
     double *bfn() const { return reinterpret_cast<double *>(ws + off_bfn); }
+    // 2D with a velocity field: per-line tables of the fine and coarse PR-ADI
+    // steps (layout of vel_tab_view), the y half-step's forward values for
+    // all slices (wbuf) and for one slice (vwk).
+    bool vel = false;
+    std::vector<double> vtf, vtc;
+    double vf_xdi = 0, vf_ydi = 0, vc_xdi = 0, vc_ydi = 0;
+    size_t off_vtf = 0, off_vtc = 0, off_wbuf = 0, off_vwk = 0;
+    VelTab vtab(bool fine_step) const
+    {
+        const double *b = reinterpret_cast<const double *>(ws + (fine_step ? off_vtf : off_vtc));
+        return vel_tab_view(b, pb.M[0], pb.M[1], fine_step ? vf_xdi : vc_xdi, fine_step ? vf_ydi : vc_ydi);
+    }
+    double *wbuf() const { return reinterpret_cast<double *>(ws + off_wbuf); }
+    double *vwk() const { return reinterpret_cast<double *>(ws + off_vwk); }
     // 2D: the launch sequences of the fine apply (2m launches) and of the
     // coarse sweep (2(N-1)c launches) captured as HIP graphs, one per
     // (operation, input, output), replayed on the caller's stream

@@ -357,19 +357,75 @@ bool setup_2d(pit_ctx &c)
            tables(thc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed);
 }
 
+// Per-line tables of one PR-ADI step with a velocity field (theta = th):
+// row j's x-operator Lx_j = nu D2x - ux(y_j) D1x - r/2, column i's
+// Ly_i = nu D2y - uy(x_i) D1y - r/2, with ux = adv0 - rot (y - Ly/2) and
+// uy = adv1 + rot (x - Lx/2) (a rigid rotation about the domain centre);
+// Thomas pivots of I - th L per line, layout of vel_tab_view.
+bool vel_tables(const pit_ctx &c, double th, std::vector<double> &v, double &xdi, double &ydi)
+{
+    const int Mx = c.pb.M[0], My = c.pb.M[1];
+    const double nu = c.pb.nu, r = c.pb.react, hx = c.hx, hy = c.hy;
+    const size_t np = (size_t)Mx * My;
+    v.assign(vel_tab_elems(Mx, My), 0.0);
+    double *xw = v.data(), *xc = xw + np, *yw = xw + 2 * np, *yc = xw + 3 * np;
+    double *xa = xw + 4 * np, *xlo = xa + My, *xup = xa + 2 * My;
+    double *ya = xa + 3 * My, *ylo = ya + Mx, *yup = ya + 2 * Mx;
+    const double dix = -2.0 * nu / (hx * hx) - 0.5 * r, diy = -2.0 * nu / (hy * hy) - 0.5 * r;
+    xdi = th * dix;
+    ydi = th * diy;
+    for (int j = 0; j < My; ++j) {
+        const double ux = c.pb.adv[0] - c.pb.rot * ((j + 1) * hy - 0.5 * c.pb.length[1]);
+        const double lo = nu / (hx * hx) + ux / (2.0 * hx), up = nu / (hx * hx) - ux / (2.0 * hx);
+        xlo[j] = th * lo;
+        xup[j] = th * up;
+        xa[j] = -th * lo;
+        const double b = 1.0 - th * dix, cc = -th * up;
+        double cp = 0.0;
+        for (int i = 0; i < Mx; ++i) {
+            const double piv = b - (i > 0 ? xa[j] * cp : 0.0);
+            const size_t q = (size_t)j * Mx + i;
+            xw[q] = 1.0 / piv;
+            cp = xc[q] = cc / piv;
+        }
+    }
+    for (int i = 0; i < Mx; ++i) {
+        const double uy = c.pb.adv[1] + c.pb.rot * ((i + 1) * hx - 0.5 * c.pb.length[0]);
+        const double lo = nu / (hy * hy) + uy / (2.0 * hy), up = nu / (hy * hy) - uy / (2.0 * hy);
+        ylo[i] = th * lo;
+        yup[i] = th * up;
+        ya[i] = -th * lo;
+        const double b = 1.0 - th * diy, cc = -th * up;
+        double cp = 0.0;
+        for (int j = 0; j < My; ++j) {
+            const double piv = b - (j > 0 ? ya[i] * cp : 0.0);
+            const size_t q = (size_t)j * Mx + i;
+            yw[q] = 1.0 / piv;
+            cp = yc[q] = cc / piv;
+        }
+    }
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
 int validate(const pit_problem *p, int N, int m, const pit_stepper &f, const pit_stepper &g)
 {
     if (!p || N < 1 || m < 1) return PIT_EINVAL;
     if (p->dim != 1 && p->dim != 2) return PIT_EINVAL;
     if (!(p->length[0] > 0.0) || !(p->T > 0.0) || !(p->nu >= 0.0)) return PIT_EINVAL;
-    if (!std::isfinite(p->adv[0]) || !std::isfinite(p->react)) return PIT_EINVAL;
+    if (!std::isfinite(p->adv[0]) || !std::isfinite(p->adv[1]) || !std::isfinite(p->react) ||
+        !std::isfinite(p->rot))
+        return PIT_EINVAL;
     if (p->dim == 2) {
         if (p->M[0] < 3 || p->M[1] < 3 || p->M[0] > kMaxAdi || p->M[1] > kMaxAdi) return PIT_EINVAL;
-        if (p->bc != PIT_DIRICHLET0 || p->adv[0] != 0.0 || p->adv[1] != 0.0) return PIT_EINVAL;
+        if (p->bc != PIT_DIRICHLET0) return PIT_EINVAL;
+        // a velocity field runs the per-line FP64 half-steps
+        if ((p->adv[0] != 0.0 || p->adv[1] != 0.0 || p->rot != 0.0) && f.prec != PIT_F64) return PIT_EINVAL;
         if (!(p->length[1] > 0.0)) return PIT_EINVAL;
         if (f.scheme != PIT_ADI_PR || g.scheme != PIT_ADI_PR) return PIT_EINVAL;
     } else {
-        if (p->M[0] < 3 || p->M[0] > kMaxLine) return PIT_EINVAL;
+        if (p->M[0] < 3 || p->M[0] > kMaxLine || p->rot != 0.0) return PIT_EINVAL;
         if (p->bc != PIT_DIRICHLET0 && p->bc != PIT_PERIODIC) return PIT_EINVAL;
         if (f.scheme != PIT_IE && f.scheme != PIT_CN) return PIT_EINVAL;
         if (g.scheme != PIT_IE && g.scheme != PIT_CN) return PIT_EINVAL;
@@ -429,6 +485,57 @@ hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int
         else
             e = launch_adi_y(c->ash, ty, sb, 0, ub, 0, nullptr, 0, 0.0, ns, Mx, My, c->fy_ex, c->fy_ed, st);
         if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// 2D all-at-once apply with a velocity field: the per-line half-steps.
+hipError_t apply_2dv(const pit_ctx *c, const double *lam, double *y, int raw, int last, hipStream_t st)
+{
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    const long np = c->npts;
+    if (last) raw = 1;
+    const int ns = last ? 1 : (raw ? c->N : c->N - 1);
+    const long in_off = last ? c->N - 1 : 0;
+    const long out_off = last ? c->N - 1 : (raw ? 0 : 1);
+    hipError_t e;
+    if (!raw && (e = launch_copy(y, lam, np, st)) != hipSuccess) return e;  // y_0 = lam_0
+    if (ns == 0) return hipSuccess;
+    const VelTab t = c->vtab(true);
+    double *ub = reinterpret_cast<double *>(c->ws + c->off_ubuf), *sb = reinterpret_cast<double *>(c->ws + c->off_sbuf);
+    for (int step = 0; step < c->m; ++step) {
+        const bool first = step == 0, fin = step == c->m - 1;
+        if ((e = launch_vel_x(t, first ? lam : ub, first ? in_off : 0, sb, 0, ns, Mx, My, 1, st)) != hipSuccess)
+            return e;
+        if (fin)
+            e = launch_vel_y(t, sb, 0, y, out_off, raw ? nullptr : lam, out_off, -1.0, c->wbuf(), ns, Mx, My, 1, st);
+        else
+            e = launch_vel_y(t, sb, 0, ub, 0, nullptr, 0, 0.0, c->wbuf(), ns, Mx, My, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// 2D coarse sweep with a velocity field, one slice at a time.
+hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t st)
+{
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    const long np = c->npts;
+    hipError_t e;
+    if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
+    const VelTab t = c->vtab(false);
+    double *ta = c->ctmp(0), *tb = c->ctmp(1);
+    const int cs = c->coarse.substeps;
+    for (int n = 1; n < c->N; ++n) {
+        for (int s = 0; s < cs; ++s) {
+            if ((e = launch_vel_x(t, s == 0 ? z : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, st)) != hipSuccess)
+                return e;
+            if (s == cs - 1)
+                e = launch_vel_y(t, ta, 0, z, n, v, n, 1.0, c->vwk(), 1, Mx, My, 1, st);
+            else
+                e = launch_vel_y(t, ta, 0, tb, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 1, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -521,6 +628,21 @@ hipError_t compute_forced(pit_ctx *c, hipStream_t st)
         return hipSuccess;
     }
     const int Mx = c->pb.M[0], My = c->pb.M[1];
+    if (c->vel) {  // per-line half-steps
+        const VelTab vt = c->vtab(true);
+        FH(launch_vel_x(vt, c->srcdev(), 0, t, 0, 1, Mx, My, 0, st));             // X^{-1} f
+        FH(launch_vel_y(vt, t, 0, g, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 0, st));  // Y^{-1} X^{-1} f
+        FH(launch_axpby(cc, g, dt, g, 0.0, np, st));
+        FH(launch_copy(h, cc, np, st));
+        for (int k = 1; k < c->m; ++k) {
+            FH(launch_vel_x(vt, h, 0, t, 0, 1, Mx, My, 1, st));
+            FH(launch_vel_y(vt, t, 0, g, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 1, st));
+            FH(launch_axpby(h, g, 1.0, cc, 1.0, np, st));
+        }
+        FH(launch_copy(c->bfn(), h, np, st));
+        FH(launch_copy(c->bf(), h, np, st));
+        return hipSuccess;
+    }
     LineTab<double> tx = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64 * c->ash.xw, c->ash.cx);
     tx.cyclic = 0;
     tx.M = Mx;
@@ -625,13 +747,17 @@ hipError_t pit::op_apply(const pit_ctx *c, const double *lam, double *y, int raw
                          hipStream_t st)
 {
     if (c->dim2())
-        return replay(c, 0, lam, y, raw, last, st, [&](hipStream_t s) { return apply_2d(c, lam, y, raw, last, s); });
+        return replay(c, 0, lam, y, raw, last, st, [&](hipStream_t s) {
+            return c->vel ? apply_2dv(c, lam, y, raw, last, s) : apply_2d(c, lam, y, raw, last, s);
+        });
     return fine_launch(c, lam, y, raw, last, internal, st);
 }
 
 hipError_t pit::op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
 {
-    if (c->dim2()) return replay(c, 1, v, z, 0, 0, st, [&](hipStream_t s) { return sweep_2d(c, v, z, s); });
+    if (c->dim2())
+        return replay(c, 1, v, z, 0, 0, st,
+                      [&](hipStream_t s) { return c->vel ? sweep_2dv(c, v, z, s) : sweep_2d(c, v, z, s); });
     return launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), v, z, c->N, c->npts, c->coarse.substeps,
                               c->coarse.scheme, internal, st);
 }
@@ -686,6 +812,12 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
             delete c;
             return PIT_EINVAL;
         }
+        c->vel = problem->adv[0] != 0.0 || problem->adv[1] != 0.0 || problem->rot != 0.0;
+        if (c->vel && (!vel_tables(*c, 0.5 * c->DT / m, c->vtf, c->vf_xdi, c->vf_ydi) ||
+                       !vel_tables(*c, 0.5 * c->DT / coarse.substeps, c->vtc, c->vc_xdi, c->vc_ydi))) {
+            delete c;
+            return PIT_EINVAL;
+        }
         if (const char *e = std::getenv("PIT_ADI_ROWS")) c->adi_R = std::max(1, std::atoi(e));
         c->ld = c->npts;
         c->bps = (int)std::min<long>(64, std::max<long>(1, (c->ld + 4095) / 4096));
@@ -712,6 +844,16 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         c->off_red = o;
         o = align_up(o + sizeof(RedOut));
         o = source_slots(*c, o);
+        if (c->vel) {
+            c->off_vtf = o;
+            o = align_up(o + c->vtf.size() * sizeof(double));
+            c->off_vtc = o;
+            o = align_up(o + c->vtc.size() * sizeof(double));
+            c->off_wbuf = o;
+            o = align_up(o + (size_t)N * c->npts * sizeof(double));
+            c->off_vwk = o;
+            o = align_up(o + (size_t)c->npts * sizeof(double));
+        }
         c->total = o;
         *out = c;
         return PIT_OK;
@@ -814,6 +956,12 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
                           hipMemcpyHostToDevice));
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_ayc, ctx->ayc.data(), ctx->ayc.size() * sizeof(double),
                           hipMemcpyHostToDevice));
+        if (ctx->vel) {
+            PIT_HIP(hipMemcpy(ctx->ws + ctx->off_vtf, ctx->vtf.data(), ctx->vtf.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+            PIT_HIP(hipMemcpy(ctx->ws + ctx->off_vtc, ctx->vtc.data(), ctx->vtc.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+        }
         return bind_source(ctx);
     }
     PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf, ctx->lf.blob.data(), ctx->lf.blob.size() * sizeof(double),

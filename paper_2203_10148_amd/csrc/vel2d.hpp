@@ -1,0 +1,62 @@
+// 2D PR-ADI with a velocity field (constant plus a rigid rotation about the
+// domain centre): every row has its own x-operator and every column its own
+// y-operator (the advection-diffusion-reaction test of Sec. 4 with
+// u = [-y, x]).  Private to libpitsbicg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pit {
+
+// Tables of one propagator (fine or coarse) with theta = dt/2 folded in.
+// Row j's x-solve (I - th Lx_j) x = r is a constant-stencil tridiagonal
+// system (sub xa[j], diagonal, super): the Thomas forward pass is
+//   d_0 = r_0 xw_0,  d_i = (r_i - xa[j] d_{i-1}) xw_i,
+// and the backward pass x_{M-1} = d_{M-1}, x_i = d_i - xc_i x_{i+1}, where
+// xw = 1/pivot and xc = super/pivot are stored per point [My][Mx]; column
+// i's y-solve likewise with ya[i], yw, yc.  The explicit parts:
+//   x half-step: (I + th Ly_i) u = u + ylo[i] u(j-1) + ydi u + yup[i] u(j+1)
+//   y half-step: (I + th Lx_j) u = u + xlo[j] u(i-1) + xdi u + xup[j] u(i+1)
+// (Dirichlet 0 outside).
+struct VelTab {
+    const double *xw, *xc, *yw, *yc;      // [My][Mx]
+    const double *xa, *xlo, *xup;         // [My]
+    const double *ya, *ylo, *yup;         // [Mx]
+    double xdi, ydi;
+};
+
+// Doubles of one VelTab in the workspace, and its view.
+inline size_t vel_tab_elems(int Mx, int My) { return 4 * (size_t)Mx * My + 3 * (size_t)My + 3 * (size_t)Mx; }
+inline VelTab vel_tab_view(const double *b, int Mx, int My, double xdi, double ydi)
+{
+    const size_t np = (size_t)Mx * My;
+    VelTab t{};
+    t.xw = b;
+    t.xc = b + np;
+    t.yw = b + 2 * np;
+    t.yc = b + 3 * np;
+    const double *r = b + 4 * np;
+    t.xa = r;
+    t.xlo = r + My;
+    t.xup = r + 2 * My;
+    const double *c = r + 3 * My;
+    t.ya = c;
+    t.ylo = c + Mx;
+    t.yup = c + 2 * Mx;
+    t.xdi = xdi;
+    t.ydi = ydi;
+    return t;
+}
+
+// x half-step on `ns` slices: out_{s+out_off} = X^{-1} E u,  u = in_{s+in_off},
+// E = (I + th Ly) (expl != 0) or I.  in and out must not overlap.
+hipError_t launch_vel_x(const VelTab &t, const double *in, long in_off, double *out, long out_off, int ns,
+                        int Mx, int My, int expl, hipStream_t st);
+// y half-step: x = Y^{-1} E u (E = (I + th Lx) or I), then
+// out = base + sign x (base != NULL) or x; wk (ns slices) holds the forward
+// values, so base may be out itself.  in must not overlap out or wk.
+hipError_t launch_vel_y(const VelTab &t, const double *in, long in_off, double *out, long out_off,
+                        const double *base, long base_off, double sign, double *wk, int ns, int Mx, int My,
+                        int expl, hipStream_t st);
+
+}  // namespace pit

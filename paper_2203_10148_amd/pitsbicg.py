@@ -36,7 +36,7 @@ class PitError(RuntimeError):
 class pit_problem(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("M", ct.c_int32 * 2), ("bc", ct.c_int32),
                 ("length", ct.c_double * 2), ("nu", ct.c_double), ("adv", ct.c_double * 2),
-                ("react", ct.c_double), ("T", ct.c_double)]
+                ("react", ct.c_double), ("T", ct.c_double), ("rot", ct.c_double)]
 
 
 class pit_stepper(ct.Structure):
@@ -159,6 +159,7 @@ def make_problem(p) -> pit_problem:
     pb.adv[0], pb.adv[1] = float(p.adv[0]), float(p.adv[1])
     pb.react = float(p.react)
     pb.T = float(p.T)
+    pb.rot = float(getattr(p, "rot", 0.0))
     return pb
 
 

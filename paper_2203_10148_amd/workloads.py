@@ -180,10 +180,27 @@ C3 = Problem(dim=2, M=(512, 512), bc=DIRICHLET, nu=0.05, T=0.5, N=128, m=64, fin
              coarse=ADI, prec=F32, tol=1e-8, name="c3_heat2d")
 
 
+# The advection-diffusion-reaction test of Sec. 4 (rotating velocity
+# u = [-y, x] about the centre of the unit square, mu = 0.1, r = 0.5, h = 0.02
+# (49 interior points per axis), dt = 1e-3, T = 6.4) as a PR-ADI problem:
+# 64 slices of 100 fine steps, coarse one PR-ADI step per slice.
+F2 = Problem(dim=2, M=(49, 49), bc=DIRICHLET, nu=0.1, react=0.5, rot=1.0, T=6.4, N=64, m=100, fine=ADI, c=1,
+             coarse=ADI, prec=F64, tol=1e-8, name="f2_rotating_adr")
+
+
+def u0_gaussian(p: Problem, centre=(0.75, 0.5), sigma=0.1) -> np.ndarray:
+    """A Gaussian (2D) at `centre` (fractions of the side lengths)."""
+    X, Y = grid_2d(p)
+    cx, cy = centre[0] * p.length[0], centre[1] * p.length[1]
+    return np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * sigma ** 2)).reshape(-1)
+
+
 def u0_for(p: Problem, seed: int | None = None) -> np.ndarray:
     """The initial condition a named configuration uses."""
     if p.name.startswith("c1"):
         return u0_sines(p)
+    if p.name.startswith("f2"):
+        return u0_gaussian(p)
     if p.dim == 2:
         return u0_bumps(p, 3 if seed is None else seed)
     return u0_fourier(p, 2 if seed is None else seed)

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes fixed by the header's field list (int32 / double / pointer, natural alignment)
-    assert ct.sizeof(P.pit_problem) == 4 * 4 + 8 * 7
+    assert ct.sizeof(P.pit_problem) == 4 * 4 + 8 * 8
     assert ct.sizeof(P.pit_stepper) == 16
     assert ct.sizeof(P.pit_solve_opts) == 8 * 2 + 4 * 6
     assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 3
@@ -98,6 +98,24 @@ def test_unbound_context_and_null_pointers_are_rejected():
     assert lib.pit_bind_workspace(h, ct.c_void_p(256 * 1000 + 8), 1 << 30) == P.EINVAL  # misaligned
     assert lib.pit_bind_workspace(h, ct.c_void_p(256 * 1000), 16) == P.ENOMEM
     lib.pit_destroy(h)
+
+
+def test_velocity_fields_validate_on_the_host():
+    """2D velocity (constant and rotation): FP64 fine only; 1D takes no rotation."""
+    lib = P.load()
+    p2 = wl.F2.with_(N=4, m=5)
+    rc, h = create(p2)
+    assert rc == P.OK
+    lib.pit_destroy(h)
+    rc, h = create(p2.with_(rot=0.0, adv=(0.3, -0.2)))
+    assert rc == P.OK
+    lib.pit_destroy(h)
+    rc, _ = create(p2.with_(prec=wl.F32))
+    assert rc == P.EINVAL
+    rc, _ = create(wl.C1.with_(rot=1.0))
+    assert rc == P.EINVAL
+    rc, _ = create(p2.with_(rot=float("nan")))
+    assert rc == P.EINVAL
 
 
 def test_set_source_validates_on_the_host():
