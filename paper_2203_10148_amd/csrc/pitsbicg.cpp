@@ -489,6 +489,13 @@ hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int
     return hipSuccess;
 }
 
+// Whole slices in LDS when they fit (PIT_VEL_LDS=0 keeps the half-step kernels).
+bool vel_lds(const pit_ctx *c)
+{
+    const char *e = std::getenv("PIT_VEL_LDS");
+    return !(e && e[0] == '0') && vel_lds_mode(c->pb.M[0], c->pb.M[1]) > 0;
+}
+
 // 2D all-at-once apply with a velocity field: the per-line half-steps.
 hipError_t apply_2dv(const pit_ctx *c, const double *lam, double *y, int raw, int last, hipStream_t st)
 {
@@ -502,6 +509,9 @@ hipError_t apply_2dv(const pit_ctx *c, const double *lam, double *y, int raw, in
     if (!raw && (e = launch_copy(y, lam, np, st)) != hipSuccess) return e;  // y_0 = lam_0
     if (ns == 0) return hipSuccess;
     const VelTab t = c->vtab(true);
+    if (vel_lds(c))
+        return launch_vel_apply_lds(t, lam, in_off, y, out_off, raw ? nullptr : lam, out_off, -1.0, ns, c->m, Mx, My,
+                                    st);
     double *ub = reinterpret_cast<double *>(c->ws + c->off_ubuf), *sb = reinterpret_cast<double *>(c->ws + c->off_sbuf);
     for (int step = 0; step < c->m; ++step) {
         const bool first = step == 0, fin = step == c->m - 1;
@@ -522,8 +532,9 @@ hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t s
     const int Mx = c->pb.M[0], My = c->pb.M[1];
     const long np = c->npts;
     hipError_t e;
-    if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
     const VelTab t = c->vtab(false);
+    if (vel_lds(c)) return launch_vel_sweep_lds(t, v, z, c->N, c->coarse.substeps, Mx, My, st);
+    if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
     double *ta = c->ctmp(0), *tb = c->ctmp(1);
     const int cs = c->coarse.substeps;
     for (int n = 1; n < c->N; ++n) {

@@ -59,4 +59,22 @@ hipError_t launch_vel_y(const VelTab &t, const double *in, long in_off, double *
                         const double *base, long base_off, double sign, double *wk, int ns, int Mx, int My,
                         int expl, hipStream_t st);
 
+// Slices small enough for LDS run whole on chip: the apply with one
+// workgroup per slice for all m steps, the sweep with one workgroup marching
+// the slices.  Same arithmetic, in the same order, as the half-step kernels.
+// vel_lds_mode: 2 when three FP64 fields and the tables fit in kVelLdsMax
+// bytes, 1 when the fields alone fit (tables read from global memory), 0
+// otherwise (or more than 512 lines on an axis).
+constexpr size_t kVelLdsMax = 160 * 1024;
+size_t vel_lds_bytes(int Mx, int My, bool tab);
+int vel_lds_mode(int Mx, int My);
+// out_{s+out_off} = base_{s+out_off} + sign F(in_{s+in_off}) (base NULL: F(in)),
+// s < ns, F = m steps; in must not overlap out.
+hipError_t launch_vel_apply_lds(const VelTab &t, const double *in, long in_off, double *out, long out_off,
+                                const double *base, long base_off, double sign, int ns, int m, int Mx, int My,
+                                hipStream_t st);
+// z_0 = v_0, z_n = v_n + G(z_{n-1}), G = c steps; v == z allowed.
+hipError_t launch_vel_sweep_lds(const VelTab &t, const double *v, double *z, int N, int c, int Mx, int My,
+                                hipStream_t st);
+
 }  // namespace pit

@@ -67,14 +67,23 @@ CASES = {
     # more lines than one 64-thread block along both axes, ragged
     "wide": wl.Problem(dim=2, M=(130, 70), bc=wl.DIRICHLET, nu=0.02, react=0.5, rot=1.0, T=0.3, N=3, m=4,
                        fine=wl.ADI, c=1, coarse=wl.ADI, name="wide"),
+    # fields in LDS, tables read from global memory
+    "mid": wl.Problem(dim=2, M=(80, 66), bc=wl.DIRICHLET, nu=0.02, adv=(-0.1, 0.2), react=0.5, rot=1.0, T=0.3,
+                      N=3, m=3, fine=wl.ADI, c=2, coarse=wl.ADI, name="mid"),
+    # too large for a slice in LDS: the half-step kernels
+    "big": wl.Problem(dim=2, M=(150, 100), bc=wl.DIRICHLET, nu=0.02, adv=(0.2, 0.1), react=0.5, rot=1.0, T=0.3,
+                      N=3, m=3, fine=wl.ADI, c=2, coarse=wl.ADI, name="big"),
 }
 
 
+@pytest.mark.parametrize("lds", ["1", "0"], ids=["lds", "halfsteps"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_velocity_operators_match_oracle(case):
+def test_velocity_operators_match_oracle(case, lds, monkeypatch):
+    """Whole slices in LDS (when they fit) and the half-step kernels."""
     P = P_()
     p = CASES[case]
-    say(f"velocity operators {case}")
+    monkeypatch.setenv("PIT_VEL_LDS", lds)
+    say(f"velocity operators {case} lds={lds}")
     o = orc.Oracle(**p.oracle_kwargs())
     c = P.Context(p)
     lam = wl.random_block(p, 17)
