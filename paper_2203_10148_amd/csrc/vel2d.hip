@@ -105,132 +105,158 @@ __global__ __launch_bounds__(kVelThreads) void k_vel_y(VelTab t, const double *_
 
 // ---------------------------------------------------------------------------
 // Slices that fit in LDS: one workgroup keeps a whole slice on chip for all
-// its steps.  LDS holds the fields U, S and W and, when they fit as well,
-// the four point tables and the six line vectors (copied in once per launch).
-// Each field has a ring of zero ghost points (point (i, j) at (j+1) P + i+1,
-// odd pitch P >= Mx + 2, so that row threads at stride P hit distinct banks):
-// the explicit part then reads its neighbours without masks.  A step is the
-// x half-step (row threads: U -> S, the forward values in W), a barrier, the
-// y half-step (column threads: S -> U) and a barrier.  No walk reads a field
-// it writes, so the loads of an unrolled stretch issue ahead of the
-// recurrence; one wavefront does all the walks of a slice of up to 64 lines
-// per axis, so the step is bound by its instruction count per point.
+// its steps.  LDS holds three fields and, when they fit as well, the four
+// point tables and the six line vectors (copied in once per launch):
+//   U   the slice, row-major: point (i, j) at (j+1) P + i+1;
+//   S   the x half-step's result, transposed: point (i, j) at (i+1) Q + j+1;
+//   W   the forward values of the walk in progress (either layout);
+// with a ring of zero ghost points around U and S, so the explicit parts read
+// their neighbours without masks, and odd pitches P >= Mx + 2, Q >= My + 2,
+// so that threads at stride P or Q hit distinct banks.  Row thread j reads
+// rows j-1, j, j+1 of U and column thread i rows i-1, i, i+1 of S: every
+// load of a walk is contiguous along the walk (immediate offsets, paired
+// loads) and only the solution is stored across the other layout.  The y
+// tables are staged transposed for the same reason.  A step is the x
+// half-step (row threads: U -> S), a barrier, the y half-step (column
+// threads: S -> U) and a barrier.  One wavefront does all the walks of a
+// slice of up to 64 lines per axis, so a step is bound by its instruction
+// count per point.
 // ---------------------------------------------------------------------------
 
 // At most this many lines per axis (one thread per line, one workgroup).
 constexpr int kVelLdsLines = 512;
 
-// Where the walks read their tables (point tables with row pitch tp).
-struct VelView {
-    const double *xw, *xc, *yw, *yc;
-    const double *xa, *xlo, *xup, *ya, *ylo, *yup;
-    int tp;
+// LDS layout of one slice, in doubles.
+struct VelLds {
+    int P, Q;      // row pitch of U (and the x tables), of S (and the y tables)
+    int s, w, t;   // offsets of S, W, the tables (U at 0)
+    int total;     // doubles without tables (fields only) or with them
 };
-
-__host__ __device__ inline int vel_pitch(int Mx) { return (Mx + 2) | 1; }
-__host__ __device__ inline long vel_field(int Mx, int My) { return (long)(My + 2) * vel_pitch(Mx); }
-// LDS index of interior point q = j Mx + i (slices of at most 512 x 512
-// points: 32-bit arithmetic).
+__host__ __device__ inline VelLds vel_lds_layout(int Mx, int My, bool tab)
+{
+    VelLds l;
+    l.P = (Mx + 2) | 1;
+    l.Q = (My + 2) | 1;
+    const int fu = (My + 2) * l.P, fs = (Mx + 2) * l.Q;
+    l.s = fu;
+    l.w = fu + fs;
+    l.t = l.w + (fu > fs ? fu : fs);
+    l.total = l.t + (tab ? 2 * My * l.P + 2 * Mx * l.Q + 3 * (Mx + My) : 0);
+    return l;
+}
+// LDS index in U of interior point q = j Mx + i (32-bit: slices of at most
+// 512 x 512 points).
 __device__ __forceinline__ int vel_at(int q, int Mx, int P)
 {
     const int j = q / Mx;
     return (j + 1) * P + (q - j * Mx) + 1;
 }
 
-// One line: n points at field stride fs and table stride ts.  The explicit
-// part at point e is c + lo[e] cm + di c + up[e] cq (cm, cq the neighbours
-// across the line, ghosts outside), then the Thomas passes with pivots w,
-// cc; the forward values go to fw, the solution to o.
+// Where the walks read their tables: x tables of row j at xw + j tp + i,
+// y tables of column i at yw + i yq + j ys.
+struct VelView {
+    const double *xw, *xc, *yw, *yc;
+    const double *xa, *xlo, *xup, *ya, *ylo, *yup;
+    int tp, yq, ys;
+};
+
+// One line of n points: the explicit part at point e is
+// c + lo[e] cm + di c + up[e] cq (cp, mp, qp the line and its two neighbour
+// lines, contiguous), then the Thomas passes with pivots w, cc (table
+// stride ts); the forward values go to fw (contiguous), the solution to o
+// at stride fo.
 __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const double *__restrict__ mp,
                                          const double *__restrict__ qp, double *__restrict__ fw,
                                          double *__restrict__ o, const double *__restrict__ w,
                                          const double *__restrict__ cc, const double *__restrict__ lo,
-                                         const double *__restrict__ up, double a, double di, int n, int fs, int ts)
+                                         const double *__restrict__ up, double a, double di, int n, int fo, int ts)
 {
     double d = 0.0;
 #pragma unroll 8
     for (int e = 0; e < n; ++e) {
-        const double c0 = cp[e * fs];
-        const double r = c0 + lo[e] * mp[e * fs] + di * c0 + up[e] * qp[e * fs];
+        const double c0 = cp[e];
+        const double r = c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e];
         d = (r - a * d) * w[e * ts];
-        fw[e * fs] = d;
+        fw[e] = d;
     }
     double x = d;
-    o[(n - 1) * fs] = x;
+    o[(n - 1) * fo] = x;
 #pragma unroll 8
     for (int e = n - 2; e >= 0; --e) {
-        x = fw[e * fs] - cc[e * ts] * x;
-        o[e * fs] = x;
+        x = fw[e] - cc[e * ts] * x;
+        o[e * fo] = x;
     }
 }
 
 __device__ __forceinline__ void vel_step_lds(const VelView &v, double xdi, double ydi, double *U, double *S,
-                                             double *W, int Mx, int My, int P)
+                                             double *W, int Mx, int My, int P, int Q)
 {
-    // The line index and the pitch pass through an empty asm once per step:
-    // otherwise the compiler hoists every address of both walks out of the
-    // loop over steps and keeps them all live (register spills).
+    // The line index and the pitches pass through an empty asm once per
+    // step: otherwise the compiler hoists every address of both walks out
+    // of the loop over steps and keeps them all live (register spills).
     int k = threadIdx.x;
     asm volatile("" : "+v"(k));
     asm volatile("" : "+s"(P));
+    asm volatile("" : "+s"(Q));
     if (k < My) {  // row k: S = X^{-1} (I + th Ly) U
         const int j = k;
-        const long r0 = (long)(j + 1) * P + 1;
-        vel_walk(U + r0, U + r0 - P, U + r0 + P, W + r0, S + r0, v.xw + j * v.tp, v.xc + j * v.tp, v.ylo, v.yup,
-                 v.xa[j], ydi, Mx, 1, 1);
+        const int r0 = (j + 1) * P + 1;
+        vel_walk(U + r0, U + r0 - P, U + r0 + P, W + r0, S + Q + j + 1, v.xw + j * v.tp, v.xc + j * v.tp, v.ylo,
+                 v.yup, v.xa[j], ydi, Mx, Q, 1);
     }
     __syncthreads();
     if (k < Mx) {  // column k: U = Y^{-1} (I + th Lx) S
         const int i = k;
-        const long c0 = P + i + 1;
-        vel_walk(S + c0, S + c0 - 1, S + c0 + 1, W + c0, U + c0, v.yw + i, v.yc + i, v.xlo, v.xup, v.ya[i], xdi, My,
-                 P, v.tp);
+        const int c0 = (i + 1) * Q + 1;
+        vel_walk(S + c0, S + c0 - Q, S + c0 + Q, W + c0, U + P + i + 1, v.yw + i * v.yq, v.yc + i * v.yq, v.xlo,
+                 v.xup, v.ya[i], xdi, My, P, v.ys);
     }
     __syncthreads();
 }
 
-// TAB: copy the tables into LDS behind the three fields (the caller's
-// barrier publishes them); else read them in place.
+// TAB: copy the tables into LDS behind the fields (the y tables
+// transposed; the caller's barrier publishes them); else read them in place.
 template <bool TAB>
-__device__ __forceinline__ VelView vel_stage(const VelTab &t, double *sh, int Mx, int My, int P)
+__device__ __forceinline__ VelView vel_stage(const VelTab &t, double *sh, int Mx, int My, const VelLds &L)
 {
     if constexpr (!TAB) {
-        return VelView{t.xw, t.xc, t.yw, t.yc, t.xa, t.xlo, t.xup, t.ya, t.ylo, t.yup, Mx};
+        return VelView{t.xw, t.xc, t.yw, t.yc, t.xa, t.xlo, t.xup, t.ya, t.ylo, t.yup, Mx, 1, Mx};
     } else {
-        const int tpl = My * P, np = Mx * My;
-        double *T = sh + 3 * vel_field(Mx, My);
+        const int P = L.P, Q = L.Q, np = Mx * My;
+        double *XW = sh + L.t, *XC = XW + My * P, *YW = XC + My * P, *YC = YW + Mx * Q;
         for (int q = threadIdx.x; q < np; q += blockDim.x) {
-            const int jq = q / Mx, l = jq * P + (q - jq * Mx);
-            T[l] = t.xw[q];
-            T[tpl + l] = t.xc[q];
-            T[2 * tpl + l] = t.yw[q];
-            T[3 * tpl + l] = t.yc[q];
+            const int j = q / Mx, i = q - j * Mx;
+            XW[j * P + i] = t.xw[q];
+            XC[j * P + i] = t.xc[q];
+            YW[i * Q + j] = t.yw[q];
+            YC[i * Q + j] = t.yc[q];
         }
-        double *L = T + 4 * tpl, *C = L + 3 * My;
+        double *R = YC + Mx * Q, *C = R + 3 * My;
         for (int q = threadIdx.x; q < My; q += blockDim.x) {
-            L[q] = t.xa[q];
-            L[My + q] = t.xlo[q];
-            L[2 * My + q] = t.xup[q];
+            R[q] = t.xa[q];
+            R[My + q] = t.xlo[q];
+            R[2 * My + q] = t.xup[q];
         }
         for (int q = threadIdx.x; q < Mx; q += blockDim.x) {
             C[q] = t.ya[q];
             C[Mx + q] = t.ylo[q];
             C[2 * Mx + q] = t.yup[q];
         }
-        return VelView{T, T + tpl, T + 2 * tpl, T + 3 * tpl, L, L + My, L + 2 * My, C, C + Mx, C + 2 * Mx, P};
+        return VelView{XW, XC, YW, YC, R, R + My, R + 2 * My, C, C + Mx, C + 2 * Mx, P, Q, 1};
     }
 }
 
-// U = slice u (interior), ghosts of U and S zero.
-__device__ __forceinline__ void vel_load_field(double *U, double *S, const double *u, int Mx, int My, int P)
+// U = slice u (interior) with zero ghosts; S all zero (its ghosts stay so).
+__device__ __forceinline__ void vel_load_field(double *U, double *S, const double *u, int Mx, int My,
+                                               const VelLds &L)
 {
-    const int fp = (int)vel_field(Mx, My);
-    for (int l = threadIdx.x; l < fp; l += blockDim.x) {
+    const int P = L.P, fu = (My + 2) * P, fs = (Mx + 2) * L.Q;
+    for (int l = threadIdx.x; l < fu; l += blockDim.x) {
         const int jj = l / P - 1, ii = l - (jj + 1) * P - 1;
         const bool in = jj >= 0 && jj < My && ii >= 0 && ii < Mx;
-        U[l] = in ? u[(long)jj * Mx + ii] : 0.0;
-        S[l] = 0.0;
+        U[l] = in ? u[jj * Mx + ii] : 0.0;
     }
+    for (int l = threadIdx.x; l < fs; l += blockDim.x) S[l] = 0.0;
 }
 
 // All-at-once apply on `ns` slices: out_{s+out_off} = base_{s+out_off} + sign F(in_{s+in_off})
@@ -241,18 +267,17 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_apply_lds(VelTab t, const 
                                                                  long base_off, double sign, int m, int Mx, int My)
 {
     extern __shared__ double sh[];
-    const int P = vel_pitch(Mx);
-    const long fp = vel_field(Mx, My);
-    double *U = sh, *S = sh + fp, *W = sh + 2 * fp;
-    const VelView v = vel_stage<TAB>(t, sh, Mx, My, P);
+    const VelLds L = vel_lds_layout(Mx, My, TAB);
+    double *U = sh, *S = sh + L.s, *W = sh + L.w;
+    const VelView v = vel_stage<TAB>(t, sh, Mx, My, L);
     const int np = Mx * My;
-    vel_load_field(U, S, in + (in_off + blockIdx.x) * np, Mx, My, P);
+    vel_load_field(U, S, in + (in_off + blockIdx.x) * np, Mx, My, L);
     __syncthreads();
-    for (int s = 0; s < m; ++s) vel_step_lds(v, t.xdi, t.ydi, U, S, W, Mx, My, P);
+    for (int s = 0; s < m; ++s) vel_step_lds(v, t.xdi, t.ydi, U, S, W, Mx, My, L.P, L.Q);
     double *o = out + (out_off + blockIdx.x) * np;
     const double *b = base ? base + (base_off + blockIdx.x) * np : nullptr;
     for (int q = threadIdx.x; q < np; q += blockDim.x) {
-        const double x = U[vel_at(q, Mx, P)];
+        const double x = U[vel_at(q, Mx, L.P)];
         o[q] = b ? b[q] + sign * x : x;
     }
 }
@@ -269,12 +294,12 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const 
                                                                  int Mx, int My)
 {
     extern __shared__ double sh[];
-    const int P = vel_pitch(Mx);
-    const long fp = vel_field(Mx, My);
-    double *U = sh, *S = sh + fp, *W = sh + 2 * fp;
-    const VelView w = vel_stage<TAB>(t, sh, Mx, My, P);
+    const VelLds L = vel_lds_layout(Mx, My, TAB);
+    const int P = L.P;
+    double *U = sh, *S = sh + L.s, *W = sh + L.w;
+    const VelView w = vel_stage<TAB>(t, sh, Mx, My, L);
     const int np = Mx * My, bd = blockDim.x, tid = threadIdx.x;
-    vel_load_field(U, S, v, Mx, My, P);
+    vel_load_field(U, S, v, Mx, My, L);
     if (z != v)
         for (int q = tid; q < np; q += bd) z[q] = v[q];
     // this thread's first kVelPre points and their LDS indices
@@ -301,7 +326,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const 
 #pragma unroll
         for (int k = 0; k < kVelPre; ++k) pre[k] = vn[min(tid + k * bd, np - 1)];
         if (n > 1) store(z + (long)(n - 1) * np);
-        for (int s = 0; s < c; ++s) vel_step_lds(w, t.xdi, t.ydi, U, S, W, Mx, My, P);
+        for (int s = 0; s < c; ++s) vel_step_lds(w, t.xdi, t.ydi, U, S, W, Mx, My, P, L.Q);
 #pragma unroll
         for (int k = 0; k < kVelPre; ++k)
             if (tid + k * bd < np) U[at[k]] += pre[k];
@@ -311,11 +336,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const 
     if (N > 1) store(z + (long)(N - 1) * np);
 }
 
-size_t vel_lds_bytes(int Mx, int My, bool tab)
-{
-    const size_t fp = (size_t)vel_field(Mx, My), tpl = (size_t)My * vel_pitch(Mx);
-    return sizeof(double) * (3 * fp + (tab ? 4 * tpl + 3 * ((size_t)Mx + My) : 0));
-}
+size_t vel_lds_bytes(int Mx, int My, bool tab) { return sizeof(double) * (size_t)vel_lds_layout(Mx, My, tab).total; }
 
 // Lines per axis fit one workgroup; at least four wavefronts for the copies.
 static int vel_lds_threads(int Mx, int My)
