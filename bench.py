@@ -34,6 +34,11 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_vec_TFs": 78.6, "fp32_vec_TFs": 157.3, "cus": 2
 # Sherman-Morrison correction 2 (periodic), CN combination 2u - A^{-1}... 2.
 FLOPS_PER_CU = {("ie", 0): 5, ("ie", 1): 7, ("cn", 0): 7, ("cn", 1): 9}
 
+# Algorithmic FLOPs per point of one PR-ADI step with a velocity field, per
+# half-step: explicit part u + lo u_m + di u + up u_q (6), forward
+# elimination (r - a d) w (3), back substitution d - c x (2).
+VEL_FLOPS_PER_POINT_STEP = 2 * (6 + 3 + 2)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -328,6 +333,18 @@ def main():
             "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
                              "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
         }
+    elif ctx.kernel_shape()[2] > 0 and (p.rot != 0.0 or any(a != 0.0 for a in p.adv)):
+        # 2D with a velocity field, slices held in LDS for all their steps:
+        # HBM sees each slice once per launch, the steps are FP64 arithmetic.
+        scheme, cscheme = "adi", "adi"
+        fl_fine = p.cells_per_apply * VEL_FLOPS_PER_POINT_STEP
+        fl_coarse = (p.N - 1) * p.c * p.npts * VEL_FLOPS_PER_POINT_STEP + (p.N - 1) * p.npts
+        kern = {
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "alu",
+                           "work_per_launch": fl_fine, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
+                             "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
+        }
     else:
         # 2D: the fine apply streams the field through HBM twice per PR-ADI step
         # (x half step: read + write, y half step: read + write).
@@ -350,8 +367,8 @@ def main():
     achieved = rate(k)
     roofline = {"bound": k["bound"], "kernel": dom, "achieved": achieved, "peak": k["peak"], "unit": k["unit"],
                 "frac": achieved / k["peak"], "traffic": None}
-    if p.dim == 1 and dom == "coarse_sweep":
-        # The 1D sweep is sequential by construction and runs on one CU: its
+    if k["bound"] == "alu" and dom == "coarse_sweep":
+        # The sweep is sequential by construction and runs on one CU: its
         # ceiling is one CU's share of the FP64 vector peak (context only; the
         # fields above keep the chip's peak).
         roofline["peak_one_cu"] = k["peak"] / PEAK["cus"]

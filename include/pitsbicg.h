@@ -371,8 +371,13 @@ const char *pit_strerror(int code);
 /* The hipError_t of the last failing HIP call in this thread (0 if none). */
 int pit_last_hip_error(void);
 
-/* Kernel shape the context chose (for reports): threads per line and points
- * per thread of the fine and coarse line solvers (1D), 0 where unused. */
+/* Kernel shape the context chose (for reports).  1D: threads per line and
+ * points per thread of the fine and coarse line solvers.  2D: lanes and
+ * points per lane of the x half-step, lanes and rows per lane of the y
+ * half-step.  2D with a velocity field: {1, 0, L, 0}, one thread per line,
+ * where L says where a slice lives during its steps: 2 = its fields and
+ * tables in LDS, 1 = its fields in LDS, 0 = HBM (one launch per half-step).
+ * PIT_EINVAL on a NULL argument. */
 int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4]);
 
 #ifdef __cplusplus

@@ -937,6 +937,13 @@ size_t pit_workspace_bytes(const pit_ctx *ctx) { return ctx ? ctx->total : 0; }
 int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4])
 {
     if (!ctx || !out) return PIT_EINVAL;
+    if (ctx->dim2() && ctx->vel) {  // one thread per line; where a slice lives
+        out[0] = 1;
+        out[1] = 0;
+        out[2] = vel_lds(ctx) ? vel_lds_mode(ctx->pb.M[0], ctx->pb.M[1]) : 0;
+        out[3] = 0;
+        return PIT_OK;
+    }
     if (ctx->dim2()) {  // 2D: 64 lanes x cx points per row; wy waves x cy rows per column
         out[0] = 64 * ctx->ash.xw;
         out[1] = ctx->ash.cx;

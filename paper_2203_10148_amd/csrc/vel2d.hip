@@ -1,13 +1,15 @@
-// 2D PR-ADI half-steps with per-line operators (velocity field), FP64.
+// 2D PR-ADI with per-line operators (velocity field), FP64.
 //
-// One thread per line (row for the x half-step, column for the y half-step,
-// grid.y = slice) runs the Thomas recurrences of its line with the
-// precomputed pivots.  Column threads of a wavefront touch consecutive
-// addresses at every point of their walk; row threads touch one point of 64
-// rows per step and reuse each fetched 128-byte line over the next 15 steps
-// from L1.  The walks are unrolled so that the loads of several points
-// (which depend on the index only) are in flight at once; on small grids the
-// launches are bound by that latency.
+// One thread per line (row for the x half-step, column for the y half-step)
+// runs the Thomas recurrences of its line with the precomputed pivots.  Two
+// forms: slices that fit in LDS run whole on chip for all their steps (the
+// kernels at the end of this file); larger slices take one launch per
+// half-step over all slices (grid.y = slice) with the fields in HBM, where
+// column threads of a wavefront touch consecutive addresses at every point
+// of their walk and row threads touch one point of 64 rows per step and
+// reuse each fetched 128-byte line over the next 15 steps from L1.  The walks
+// are unrolled so that the loads of several points (which depend on the
+// index only) are in flight at once.
 #include "vel2d.hpp"
 
 namespace pit {

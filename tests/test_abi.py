@@ -151,6 +151,23 @@ def test_kernel_shapes_cover_the_line():
         lib.pit_destroy(h)
 
 
+def test_velocity_kernel_shape_reports_where_a_slice_lives(monkeypatch):
+    """One thread per line; 2 = fields and tables in LDS (the 49x49 case),
+    1 = fields only, 0 = per-half-step kernels (too large, or switched off)."""
+    lib = P.load()
+    for M, want in (((49, 49), 2), ((80, 66), 1), ((130, 70), 0)):
+        rc, h = create(wl.F2.with_(M=M, N=4, m=2))
+        assert rc == P.OK
+        out = (ct.c_int32 * 4)()
+        assert lib.pit_kernel_shape(h, out) == P.OK
+        assert list(out) == [1, 0, want, 0], (M, list(out))
+        monkeypatch.setenv("PIT_VEL_LDS", "0")
+        lib.pit_kernel_shape(h, out)
+        assert out[2] == 0
+        monkeypatch.delenv("PIT_VEL_LDS")
+        lib.pit_destroy(h)
+
+
 def test_batch_and_server_validate_on_the_host():
     lib = P.load()
     h = ct.c_void_p()
