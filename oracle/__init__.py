@@ -14,9 +14,11 @@ Bi-Conjugate Gradient Algorithm"):
   * ``pitsbicg``        -- Algorithm 1 (Sec. 3);
   * ``parareal_*``      -- Sec. 2, eqs. (pararealAlgebraic) and (pararealscheme);
   * ``serial``          -- the serial fine trajectory, the exact solution;
-  * ``source``/``forced`` -- an optional source constant in time (Sec. 2, eq.
-                           (Cauchy)): F becomes affine, B = (u0, b, .., b) with
-                           b = F(0) the forced response of one slice.
+  * ``source``/``forced`` -- an optional source (Sec. 2, eq. (Cauchy)), constant
+                           in time or separable, f(t, x) = g(t) h(x): the
+                           propagator of slice n becomes affine, F_n(u) =
+                           F0(u) + b_n, and B = (u0, b_0, .., b_{N-2}) with
+                           b_n = F_n(0) the forced response of slice n.
 """
 from __future__ import annotations
 
@@ -72,7 +74,10 @@ def _load():
                                ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_double]
     lib.orc_destroy.argtypes = [ct.c_void_p]
     lib.orc_set_source.argtypes = [ct.c_void_p, _D]
+    lib.orc_set_source_t.argtypes = [ct.c_void_p, _D, _D]
     lib.orc_forced.argtypes = [ct.c_void_p, _D]
+    lib.orc_forced_slice.argtypes = [ct.c_void_p, ct.c_int, _D]
+    lib.orc_F_slice.argtypes = [ct.c_void_p, ct.c_int, _D, _D]
     lib.orc_npts.argtypes = [ct.c_void_p]
     lib.orc_npts.restype = ct.c_int
     lib.orc_weight.argtypes = [ct.c_void_p]
@@ -145,7 +150,7 @@ class Oracle:
                  adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None, rot=0.0):
         lib = _load()
         Mx, My = (M, 1) if isinstance(M, int) else (int(M[0]), int(M[1]))
-        self.dim, self.Mx, self.My, self.N = dim, Mx, (My if dim == 2 else 1), N
+        self.dim, self.Mx, self.My, self.N, self.m = dim, Mx, (My if dim == 2 else 1), N, m
         h = lib.orc_create(dim, Mx, My, bc, float(length[0]), float(length[1]), float(nu),
                            float(adv[0]), float(adv[1]), float(react), float(T), N, m, fine, c,
                            coarse, float(rot))
@@ -157,20 +162,28 @@ class Oracle:
         if source is not None:
             self.set_source(source)
 
-    def set_source(self, f):
-        """Set the source f (one slice of values), or remove it with None."""
+    def set_source(self, f, g=None):
+        """Set the source f (one slice of values), or remove it with None.
+        With g (N m + 1 values, g(t_j) at the fine step times t_j = j dt) the
+        source is f(t, x) = g(t) f(x)."""
         if f is None:
             _lib.orc_set_source(self._h, None)
             return
         f = self._c(f)
         if f.size != self.npts:
             raise ValueError("oracle: source size")
-        _lib.orc_set_source(self._h, _p(f))
+        if g is None:
+            _lib.orc_set_source(self._h, _p(f))
+            return
+        g = self._c(g)
+        if g.size != self.N * self.m + 1:
+            raise ValueError("oracle: time profile size")
+        _lib.orc_set_source_t(self._h, _p(f), _p(g))
 
-    def forced(self):
-        """b = F(0): the forced response of one slice."""
+    def forced(self, n=0):
+        """b_n = F_n(0): the forced response of slice n."""
         b = self._slice()
-        _lib.orc_forced(self._h, _p(b))
+        _lib.orc_forced_slice(self._h, int(n), _p(b))
         return b
 
     def __del__(self):
@@ -188,9 +201,11 @@ class Oracle:
     def _c(a):
         return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
 
-    def F(self, u):
+    def F(self, u, n=0):
+        """The fine propagator of slice n (the source's slice n with a
+        time-dependent source)."""
         u = self._c(u); out = self._slice()
-        _lib.orc_F(self._h, _p(u), _p(out)); return out
+        _lib.orc_F_slice(self._h, int(n), _p(u), _p(out)); return out
 
     def G(self, u):
         u = self._c(u); out = self._slice()

@@ -42,12 +42,18 @@
  *       advection-diffusion-reaction test of Sec. 4).  ux is constant along a
  *       row and uy along a column, so every line is a constant-stencil
  *       tridiagonal system, one per row or column.
- * f is an optional source, constant in time (the source term of Sec. 2, eq.
- * (Cauchy)); without it f = 0.  With a source the slice propagator is affine,
- * F(u) = F0(u) + b with b = F(0), the forced response of one slice.  The
- * all-at-once system keeps its linear operator (F0 below the diagonal) and
- * gets B = (u0, b, .., b): its solution is again the serial trajectory
- * lambda_{n+1} = F(lambda_n) (the middle entries of B in Sec. 2, eq.
+ * f is an optional source (the source term of Sec. 2, eq. (Cauchy)); without
+ * it f = 0.  It is either constant in time or separable, f(t, x) = g(t) h(x),
+ * with g given at the fine step times t_j = j dt, j = 0..N m.  Fine step j
+ * (from t_j to t_{j+1}) takes f(t_{j+1}) under IE, the trapezoidal mean
+ * (f(t_j) + f(t_{j+1}))/2 under CN, and the midpoint value, read as that same
+ * mean, in both PR-ADI half-steps.  With a source the propagator of slice n
+ * is affine, F_n(u) = F0(u) + b_n with b_n = F_n(0), the forced response of
+ * slice n (one b for all slices when f is constant).  The all-at-once system
+ * keeps its linear operator (F0 below the diagonal) and gets
+ * B = (u0, b_0, .., b_{N-2}) (eq. (Cauchyn): slice n carries f restricted to
+ * [T_n, T_{n+1}]): its solution is again the serial trajectory
+ * lambda_{n+1} = F_n(lambda_n) (the middle entries of B in Sec. 2, eq.
  * (algebraiclinearsystem)).  The preconditioner uses the linear coarse
  * propagator G0.
  * Tridiagonal systems: Thomas algorithm without pivoting.  Periodic (cyclic)
@@ -79,7 +85,8 @@ typedef struct {
     double hx, hy; /* grid spacing */
     double w;      /* L2 quadrature weight h^d */
     double DT;     /* slice length T/N */
-    double *src;   /* source f (npts values, owned) or NULL */
+    double *src;   /* source f, or its profile h (npts values, owned), or NULL */
+    double *gt;    /* g(t_j), j = 0..N m (owned), or NULL: f constant in time */
 } orc_ctx;
 
 static int g_threads = 1;
@@ -211,9 +218,9 @@ static size_t step_work(const orc_ctx *C)
 }
 
 /* out = one step of `scheme` with time step dt applied to u (no aliasing);
- * f is the source (NULL: none). */
+ * the source of the step is wf * f (f NULL: none). */
 static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, double *out,
-                     double *work, const double *f)
+                     double *work, const double *f, double wf)
 {
     if (C->dim == 1) {
         int n = C->Mx;
@@ -222,7 +229,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
         double *rhs = work, *lw = work + n;
         if (scheme == ORC_IE) {
             if (f) { /* rhs = u + dt f */
-                for (int j = 0; j < n; ++j) rhs[j] = u[j] + dt * f[j];
+                for (int j = 0; j < n; ++j) rhs[j] = u[j] + dt * (wf * f[j]);
                 implicit_line(n, C->bc, dt, lo, di, up, rhs, out, lw);
             } else {
                 implicit_line(n, C->bc, dt, lo, di, up, u, out, lw);
@@ -239,7 +246,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
                     uq = (j < n - 1) ? u[j + 1] : 0.0;
                 }
                 rhs[j] = u[j] + th * (lo * um + di * u[j] + up * uq);
-                if (f) rhs[j] += dt * f[j];
+                if (f) rhs[j] += dt * (wf * f[j]);
             }
             implicit_line(n, C->bc, th, lo, di, up, rhs, out, lw);
         }
@@ -263,7 +270,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
             double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
             double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
             line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
-            if (f) line[i] += th * f[j * nx + i];
+            if (f) line[i] += th * (wf * f[j * nx + i]);
         }
         op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
         implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
@@ -277,7 +284,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
             double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
             double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
             line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
-            if (f) line[j] += th * f[j * nx + i];
+            if (f) line[j] += th * (wf * f[j * nx + i]);
         }
         op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
         implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
@@ -285,10 +292,20 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
     }
 }
 
+/* Weight of the source profile in global fine step j (from t_j to t_{j+1}),
+ * 1 when the source is constant in time or j < 0. */
+static double src_weight(const orc_ctx *C, int scheme, int j)
+{
+    if (!C->gt || j < 0) return 1.0;
+    return scheme == ORC_IE ? C->gt[j + 1] : 0.5 * (C->gt[j] + C->gt[j + 1]);
+}
+
 /* Apply `nsteps` steps of `scheme`, each of length span/nsteps, with source f
- * (NULL: none): out = step^nsteps(in).  in and out may alias. */
+ * (NULL: none): out = step^nsteps(in).  j0 is the global index of the first
+ * step (for the weights of a time-dependent source), -1 for none.  in and
+ * out may alias. */
 static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
-                      double *out, const double *f)
+                      double *out, const double *f, int j0)
 {
     size_t np = (size_t)C->npts;
     double dt = span / nsteps;
@@ -296,7 +313,7 @@ static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, con
     double *a = base, *b = base + np, *work = base + 2 * np;
     memcpy(a, in, sizeof(double) * np);
     for (int s = 0; s < nsteps; ++s) {
-        one_step(C, scheme, dt, a, b, work, f);
+        one_step(C, scheme, dt, a, b, work, f, src_weight(C, scheme, j0 < 0 ? -1 : j0 + s));
         double *t = a;
         a = b;
         b = t;
@@ -348,59 +365,84 @@ orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, doubl
 
 void orc_destroy(orc_ctx *C)
 {
-    if (C) free(C->src);
+    if (C) {
+        free(C->src);
+        free(C->gt);
+    }
     free(C);
 }
 
-/* Set (a copy of) the source f, npts values in slice layout; NULL removes it. */
+/* Set (a copy of) the source f, constant in time, npts values in slice
+ * layout; NULL removes it. */
 void orc_set_source(orc_ctx *C, const double *f)
 {
     free(C->src);
+    free(C->gt);
     C->src = NULL;
+    C->gt = NULL;
     if (f) {
         C->src = (double *)malloc(sizeof(double) * (size_t)C->npts);
         memcpy(C->src, f, sizeof(double) * (size_t)C->npts);
     }
 }
 
+/* Set the separable source f(t, x) = g(t) h(x): h npts values, g its values
+ * at the fine step times t_j = j dt, j = 0..N m (N m + 1 values). */
+void orc_set_source_t(orc_ctx *C, const double *h, const double *g)
+{
+    orc_set_source(C, h);
+    size_t ng = (size_t)C->N * (size_t)C->m + 1;
+    C->gt = (double *)malloc(sizeof(double) * ng);
+    memcpy(C->gt, g, sizeof(double) * ng);
+}
+
 /* The linear part F0 of the fine propagator (no source). */
 static void F_lin(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL);
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL, -1);
 }
 
-/* b = F(0): the forced response of one slice (0 without a source). */
-void orc_forced(const orc_ctx *C, double *b)
+/* b_n = F_n(0): the forced response of slice n (0 without a source). */
+void orc_forced_slice(const orc_ctx *C, int n, double *b)
 {
     memset(b, 0, sizeof(double) * (size_t)C->npts);
-    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src);
+    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src, n * C->m);
 }
 
-/* B = (u0, b, .., b) (Sec. 2, eq. (algebraiclinearsystem)). */
+/* The forced response of slice 0 (of every slice when f is constant). */
+void orc_forced(const orc_ctx *C, double *b) { orc_forced_slice(C, 0, b); }
+
+/* B = (u0, b_0, .., b_{N-2}) (Sec. 2, eq. (algebraiclinearsystem)). */
 static void build_B(const orc_ctx *C, const double *u0, double *B)
 {
     size_t np = (size_t)C->npts;
     memcpy(B, u0, sizeof(double) * np);
     if (C->N > 1) {
-        orc_forced(C, B + np);
-        for (int n = 2; n < C->N; ++n) memcpy(B + (size_t)n * np, B + np, sizeof(double) * np);
+        orc_forced_slice(C, 0, B + np);
+        for (int n = 2; n < C->N; ++n) {
+            if (C->gt) orc_forced_slice(C, n - 1, B + (size_t)n * np);
+            else memcpy(B + (size_t)n * np, B + np, sizeof(double) * np);
+        }
     }
 }
 int orc_npts(const orc_ctx *C) { return C->npts; }
 double orc_weight(const orc_ctx *C) { return C->w; }
 
-/* Fine propagator over one slice: m steps of dt = DT/m (Sec. 2), with the
+/* Fine propagator over slice n: m steps of dt = DT/m (Sec. 2), with the
  * source if one is set (affine). */
-void orc_F(const orc_ctx *C, const double *in, double *out)
+void orc_F_slice(const orc_ctx *C, int n, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src);
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src, n * C->m);
 }
+
+/* The fine propagator of slice 0 (of every slice when f is constant). */
+void orc_F(const orc_ctx *C, const double *in, double *out) { orc_F_slice(C, 0, in, out); }
 
 /* Coarse propagator over one slice: c steps of DT/c, linear (the
  * preconditioner's G; a source cancels from the parareal corrections). */
 void orc_G(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL);
+    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL, -1);
 }
 
 /* One step of `scheme` with step dt and the source if set (exported for the
@@ -408,7 +450,7 @@ void orc_G(const orc_ctx *C, const double *in, double *out)
 void orc_step(const orc_ctx *C, int scheme, double dt, const double *in, double *out)
 {
     double *work = (double *)malloc(sizeof(double) * step_work(C));
-    one_step(C, scheme, dt, in, out, work, C->src);
+    one_step(C, scheme, dt, in, out, work, C->src, 1.0);
     free(work);
 }
 
@@ -431,13 +473,13 @@ void orc_apply(const orc_ctx *C, const double *lam, double *y)
     }
 }
 
-/* y_n = F(lam_n) for n = 0..N-1, the source included (the last row gives
- * u(T) = F(lam_{N-1})). */
+/* y_n = F_n(lam_n) for n = 0..N-1, the source included (the last row gives
+ * u(T) = F_{N-1}(lam_{N-1})). */
 void orc_apply_raw(const orc_ctx *C, const double *lam, double *y)
 {
     size_t np = (size_t)C->npts;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
-    for (int n = 0; n < C->N; ++n) orc_F(C, lam + (size_t)n * np, y + (size_t)n * np);
+    for (int n = 0; n < C->N; ++n) orc_F_slice(C, n, lam + (size_t)n * np, y + (size_t)n * np);
 }
 
 /* z = G^{-1} v by forward substitution: z_0 = v_0, z_n = v_n + G(z_{n-1}).
@@ -454,13 +496,13 @@ void orc_sweep(const orc_ctx *C, const double *v, double *z)
     free(g);
 }
 
-/* Serial fine trajectory: lam_0 = u0, lam_{n+1} = F(lam_n); uT = F(lam_{N-1}) if non-NULL. */
+/* Serial fine trajectory: lam_0 = u0, lam_{n+1} = F_n(lam_n); uT = F_{N-1}(lam_{N-1}) if non-NULL. */
 void orc_serial(const orc_ctx *C, const double *u0, double *lam, double *uT)
 {
     size_t np = (size_t)C->npts;
     memcpy(lam, u0, sizeof(double) * np);
-    for (int n = 1; n < C->N; ++n) orc_F(C, lam + (size_t)(n - 1) * np, lam + (size_t)n * np);
-    if (uT) orc_F(C, lam + (size_t)(C->N - 1) * np, uT);
+    for (int n = 1; n < C->N; ++n) orc_F_slice(C, n - 1, lam + (size_t)(n - 1) * np, lam + (size_t)n * np);
+    if (uT) orc_F_slice(C, C->N - 1, lam + (size_t)(C->N - 1) * np, uT);
 }
 
 /* Block inner product <U,V> = sum_n h^d sum_j u_{n,j} v_{n,j}, summed per
@@ -543,7 +585,7 @@ int orc_pitsbicg(const orc_ctx *C, const double *u0, double *X, double tol, doub
     int status = ORC_ENOCONV, k = 0, matvecs = 0, restarts = 0, hl = 0;
     double nrm = 0.0;
 
-    build_B(C, u0, B); /* B = (lambda_0, b, ..., b), b = 0 without a source */
+    build_B(C, u0, B); /* B = (lambda_0, b_0, ..., b_{N-2}), b = 0 without a source */
 
     /* initial residual R^0 = G^{-1}(B - F X^0) */
     if (x0_mode == ORC_X0_ZERO) {
@@ -718,7 +760,7 @@ void orc_parareal_pc(const orc_ctx *C, const double *u0, double *Lam, int iters)
         memcpy(old, Lam, sizeof(double) * nt);
         /* fine and old-coarse corrections of all slices (the parallel part) */
         for (int n = 0; n + 1 < C->N; ++n) {
-            orc_F(C, old + (size_t)n * np, f + (size_t)n * np);
+            orc_F_slice(C, n, old + (size_t)n * np, f + (size_t)n * np);
             orc_G(C, old + (size_t)n * np, g);
             for (size_t j = 0; j < np; ++j) f[(size_t)n * np + j] -= g[j];
         }

@@ -163,6 +163,22 @@ def source_bumps(p: Problem, seed: int, nbumps: int = 4) -> np.ndarray:
     return f.reshape(-1)
 
 
+def source_profile(p: Problem, seed: int, nwaves: int = 3) -> np.ndarray:
+    """A seeded time profile g(t_j) at the fine step times t_j = j T/(N m),
+    j = 0..N m, for a separable source g(t) h(x): 1 plus a few sine waves,
+    amplitudes ~ U[-0.5,0.5], angular frequencies ~ U[0,4 pi/T] (up to two
+    periods over the horizon), phases ~ U[0,2 pi)."""
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(-0.5, 0.5, nwaves)
+    om = rng.uniform(0.0, 4.0 * np.pi / p.T, nwaves)
+    ph = rng.uniform(0.0, 2.0 * np.pi, nwaves)
+    t = (p.T / (p.N * p.m)) * np.arange(p.N * p.m + 1)
+    g = np.ones_like(t)
+    for i in range(nwaves):
+        g += amp[i] * np.sin(om[i] * t + ph[i])
+    return g
+
+
 def random_block(p: Problem, seed: int) -> np.ndarray:
     """A seeded N x npts block vector of standard normals (operator parity inputs)."""
     return np.random.default_rng(seed).standard_normal(p.N * p.npts)

@@ -632,6 +632,167 @@ def test_source_all_at_once_system_and_solvers(dim):
     assert relerr(Xp, lam) < 1e-12
 
 
+# ---------------------------------------------------------------------------
+# A separable source f(t, x) = g(t) h(x), g given at the fine step times
+# t_j = j dt (eq. (Cauchyn): slice n carries f on [T_n, T_{n+1}]).  Step j
+# takes g(t_{j+1}) under IE and (g(t_j) + g(t_{j+1}))/2 under CN and in both
+# PR-ADI half-steps, so that on a mode of coefficient c with source
+# coefficient phi:
+#   IE:     c' = (c + dt g_{j+1} phi) / (1 - dt mu)
+#   CN:     c' = ((1 + dt/2 mu) c + dt (g_j + g_{j+1})/2 phi) / (1 - dt/2 mu)
+#   PR-ADI: as above with th (g_j + g_{j+1})/2 phi in both half-steps.
+# ---------------------------------------------------------------------------
+
+def profile(p, a=0.5, w=3.0):
+    dt = p.T / p.N / p.m
+    t = dt * np.arange(p.N * p.m + 1)
+    return 1.0 + a * np.sin(w * t) + t * t
+
+
+def modal_step_t(scheme, dt, mu, c, phi, g0, g1):
+    if scheme == wl.IE:
+        return (c + dt * g1 * phi) / (1 - dt * mu)
+    return ((1 + 0.5 * dt * mu) * c + dt * 0.5 * (g0 + g1) * phi) / (1 - 0.5 * dt * mu)
+
+
+@pytest.mark.parametrize("scheme", [wl.IE, wl.CN])
+def test_source_t_dirichlet_modal_recursion(scheme):
+    p = wl.Problem(dim=1, M=(40, 1), bc=wl.DIRICHLET, nu=0.05, react=0.4, T=0.8, N=5, m=9,
+                   fine=scheme, c=1, coarse=wl.IE)
+    x = wl.grid_1d(p)
+    h = 1.0 / 41
+    mu = lambda k: -(4 * p.nu / h**2) * math.sin(k * math.pi * h / 2) ** 2 - p.react
+    modes = {1: (1.0, 0.7), 2: (0.0, -1.3), 3: (0.5, 0.0)}
+    u0 = sum(c0 * np.sin(k * math.pi * x) for k, (c0, _) in modes.items())
+    f = sum(ph * np.sin(k * math.pi * x) for k, (_, ph) in modes.items())
+    g = profile(p)
+    o = orc.Oracle(**p.oracle_kwargs())
+    o.set_source(f, g)
+    dt = p.T / p.N / p.m
+
+    def run(k, c, ph, j0, steps):
+        for j in range(j0, j0 + steps):
+            c = modal_step_t(scheme, dt, mu(k), c, ph, g[j], g[j + 1])
+        return c
+
+    field = lambda cs: sum(cs[k] * np.sin(k * math.pi * x) for k in modes)
+    lam_ref, cs = [], {k: c0 for k, (c0, _) in modes.items()}
+    for n in range(p.N):
+        lam_ref.append(field(cs))
+        cs = {k: run(k, cs[k], modes[k][1], n * p.m, p.m) for k in modes}
+    lam_ref.append(field(cs))
+    lam, uT = o.serial(u0, want_uT=True)
+    assert relerr(lam, np.concatenate(lam_ref[: p.N])) < 1e-13
+    assert relerr(uT, lam_ref[p.N]) < 1e-13
+    for n in range(p.N):
+        b = field({k: run(k, 0.0, modes[k][1], n * p.m, p.m) for k in modes})
+        assert relerr(o.forced(n), b) < 1e-13
+        Fu = field({k: run(k, modes[k][0], modes[k][1], n * p.m, p.m) for k in modes})
+        assert relerr(o.F(u0, n), Fu) < 1e-13
+    # the slices differ: the source is not the constant one
+    assert relerr(o.forced(0), o.forced(p.N - 1)) > 1e-2
+
+
+def test_source_t_ie_geometric_closed_form():
+    """g_j = rho^j under IE: the forced response of slice n on one mode is
+    dt rho^(n m) q rho (q^m - rho^m) / (q - rho), q = 1/(1 - dt mu), a closed
+    form of the sum of the step responses."""
+    p = wl.Problem(dim=1, M=(32, 1), bc=wl.DIRICHLET, nu=0.03, react=0.1, T=0.5, N=4, m=7,
+                   fine=wl.IE, c=1, coarse=wl.IE)
+    x = wl.grid_1d(p)
+    h = 1.0 / 33
+    k = 2
+    mu = -(4 * p.nu / h**2) * math.sin(k * math.pi * h / 2) ** 2 - p.react
+    dt = p.T / p.N / p.m
+    rho = 1.03
+    g = rho ** np.arange(p.N * p.m + 1)
+    v = np.sin(k * math.pi * x)
+    o = orc.Oracle(**p.oracle_kwargs())
+    o.set_source(0.9 * v, g)
+    q = 1.0 / (1.0 - dt * mu)
+    for n in range(p.N):
+        coef = 0.9 * dt * rho ** (n * p.m) * q * rho * (q**p.m - rho**p.m) / (q - rho)
+        assert relerr(o.forced(n), coef * v) < 1e-12
+
+
+def test_source_t_adi_2d_modal_recursion():
+    p = wl.Problem(dim=2, M=(18, 14), length=(1.0, 1.3), bc=wl.DIRICHLET, nu=0.05, react=0.2,
+                   T=0.3, N=3, m=5, fine=wl.ADI, c=1, coarse=wl.ADI)
+    X, Y = wl.grid_2d(p)
+    hx, hy = 1.0 / 19, 1.3 / 15
+    mx = lambda k: -(4 * p.nu / hx**2) * math.sin(k * math.pi * hx / 2.0) ** 2 - 0.5 * p.react
+    my = lambda l: -(4 * p.nu / hy**2) * math.sin(l * math.pi * (hy / 1.3) / 2.0) ** 2 - 0.5 * p.react
+    modes = {(1, 1): (1.0, 0.6), (2, 3): (0.5, 0.0), (3, 1): (0.0, -0.9)}
+    mode = lambda k, l: (np.sin(k * math.pi * X / 1.0) * np.sin(l * math.pi * Y / 1.3)).reshape(-1)
+    u0 = sum(c0 * mode(k, l) for (k, l), (c0, _) in modes.items())
+    f = sum(ph * mode(k, l) for (k, l), (_, ph) in modes.items())
+    g = profile(p, a=0.8, w=7.0)
+    o = orc.Oracle(**p.oracle_kwargs())
+    o.set_source(f, g)
+    th = 0.5 * p.T / p.N / p.m
+
+    def F_coef(k, l, c, ph, n):
+        for j in range(n * p.m, (n + 1) * p.m):
+            w = 0.5 * (g[j] + g[j + 1]) * ph
+            cs = ((1 + th * my(l)) * c + th * w) / (1 - th * mx(k))
+            c = ((1 + th * mx(k)) * cs + th * w) / (1 - th * my(l))
+        return c
+
+    for n in range(p.N):
+        ref = sum(F_coef(k, l, c0, ph, n) * mode(k, l) for (k, l), (c0, ph) in modes.items())
+        assert relerr(o.F(u0, n), ref) < 1e-13
+        b = sum(F_coef(k, l, 0.0, ph, n) * mode(k, l) for (k, l), (_, ph) in modes.items())
+        assert relerr(o.forced(n), b) < 1e-13
+
+
+@pytest.mark.parametrize("fine", [wl.IE, wl.CN, wl.ADI])
+def test_source_t_constant_profile_is_the_constant_source(fine):
+    if fine == wl.ADI:
+        p = wl.Problem(dim=2, M=(9, 7), bc=wl.DIRICHLET, nu=0.05, react=0.2, rot=0.5, T=0.3, N=4, m=3,
+                       fine=wl.ADI, c=1, coarse=wl.ADI)
+    else:
+        p = wl.Problem(dim=1, M=(20, 1), bc=wl.PERIODIC, nu=0.01, adv=(0.4, 0.0), T=0.4, N=4, m=6,
+                       fine=fine, c=1, coarse=wl.IE)
+    f = np.cos(np.arange(p.npts) * 0.37) + 0.1
+    u0 = np.sin(np.arange(p.npts) * 0.11)
+    a, b = orc.Oracle(**p.oracle_kwargs()), orc.Oracle(**p.oracle_kwargs())
+    a.set_source(f)
+    b.set_source(f, np.ones(p.N * p.m + 1))
+    assert np.array_equal(a.serial(u0), b.serial(u0))
+    for n in range(p.N):
+        assert np.array_equal(a.forced(), b.forced(n))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_source_t_all_at_once_system_and_solvers(dim):
+    """With a time-dependent source the serial trajectory solves
+    F Lambda = B with B = (u0, b_0, .., b_{N-2}); Algorithm 1 and both
+    parareal forms reach it."""
+    if dim == 1:
+        p = wl.Problem(dim=1, M=(30, 1), bc=wl.PERIODIC, nu=2e-3, adv=(0.6, 0.0), react=0.1, T=0.6, N=6,
+                       m=5, fine=wl.CN, c=2, coarse=wl.IE)
+        x = wl.grid_1d(p)
+        u0 = np.sin(2 * math.pi * x) + 0.2
+        f = np.exp(-((x - 0.4) ** 2) / 0.01) - 0.3 * np.cos(4 * math.pi * x)
+    else:
+        p = wl.Problem(dim=2, M=(9, 7), bc=wl.DIRICHLET, nu=0.05, react=0.2, rot=1.0, T=0.3, N=5, m=4,
+                       fine=wl.ADI, c=1, coarse=wl.ADI)
+        X, Y = wl.grid_2d(p)
+        u0 = (np.sin(math.pi * X) * np.sin(2 * math.pi * Y)).reshape(-1)
+        f = (X * (1 - X) * Y + 0.5).reshape(-1)
+    o = orc.Oracle(**p.oracle_kwargs())
+    o.set_source(f, profile(p, a=0.9, w=11.0))
+    lam = o.serial(u0)
+    B = np.concatenate([u0] + [o.forced(n) for n in range(p.N - 1)])
+    assert relerr(o.apply(lam), B) < 1e-13
+    Xs, info = o.pitsbicg(u0, tol=1e-13)
+    assert info.status == orc.OK and relerr(Xs, lam) < 1e-10
+    Xr, _ = o.parareal_richardson(u0, p.N)
+    assert relerr(Xr, lam) < 1e-12
+    Xp = o.parareal_pc(u0, np.zeros(p.N * o.npts), p.N)
+    assert relerr(Xp, lam) < 1e-12
+
+
 def test_rotation_turns_a_bump_counterclockwise_about_the_centre():
     """u = [-(y - yc), x - xc] (rate 1): a bump a quarter of the side east of
     the centre is, after a quarter turn (t = pi/2), north of it; after a half
