@@ -190,6 +190,32 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes);
  * PIT_EHIP. */
 int pit_set_source(pit_ctx *ctx, const double *f);
 
+/* Source term separable in time, f(t, x) = g(t) h(x): slice n carries f on
+ * [T_n, T_{n+1}] (Sec. 2, eq. (Cauchyn)).  Fine step j, from t_j = j dt to
+ * t_{j+1}, adds the source as in pit_set_source with f = w_j h, where w_j =
+ * g(t_{j+1}) under IE and (g(t_j) + g(t_{j+1}))/2 under CN and in both PR-ADI
+ * half-steps (the midpoint value, read as the mean of the two ends).  The
+ * propagator of slice n is affine, F_n(u) = F0(u) + b_n with b_n = F_n(0),
+ * and the all-at-once system keeps its linear operator with
+ * B = (u0, b_0, .., b_{N-2}).
+ * h: npts values in slice layout; g: the profile at the N m + 1 fine step
+ * times t_0 .. t_{N m}; both copied.  NULL g sets the constant source h
+ * (pit_set_source), NULL h removes the source.
+ * Workspace: the context then needs N slices and N m values more, behind
+ * the rest: pit_workspace_bytes reports the size for the source set.  If a
+ * workspace is bound and smaller, the source is set, the context is left
+ * unbound and the call returns PIT_ENOMEM: bind a workspace of
+ * pit_workspace_bytes.  b_0 .. b_{N-1} are computed for all slices at once
+ * (m fine steps of every slice, synchronous, null stream, the context's
+ * block vectors as scratch) as soon as both the workspace and the source
+ * are set.
+ * Effects as pit_set_source, with b_n in place of b: pit_solve and
+ * pit_parareal use B = (u0, b_0, .., b_{N-2}), and pit_apply_F with
+ * PIT_APPLY_RAW or PIT_APPLY_LAST returns F_n(lam_n).  pit_set_source
+ * replaces a separable source.  Errors: PIT_EINVAL (NULL ctx, non-finite
+ * value), PIT_ENOMEM, PIT_EHIP. */
+int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g);
+
 /* ---- operators ------------------------------------------------------------ */
 
 /* All-at-once operator (Sec. 2, eq. (algebraiclinearsystem)):

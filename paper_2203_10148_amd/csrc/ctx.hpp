@@ -29,6 +29,9 @@ void set_last_hip(int code);
 // One slice of `len` values written (add = 0) or added (add = 1) into `count`
 // consecutive slices (krylov.hip).
 hipError_t launch_repeat(double *dst, const double *src, long len, long count, int add, hipStream_t st);
+// X_s += w[s * wstride] c for the N slices (len points each) of X.
+hipError_t launch_slice_axpy(double *X, const double *c, const double *w, long wstride, long len, int N,
+                             hipStream_t st);
 
 constexpr size_t kAlign = 256;
 constexpr int kSolveVectors = 8;  // R, shadow R, P, D, S, K, temporary, iterate
@@ -89,6 +92,15 @@ struct pit_ctx {
     double *srcdev() const { return reinterpret_cast<double *>(ws + off_src); }
     double *bf() const { return reinterpret_cast<double *>(ws + off_bf); }
     double *bfn() const { return reinterpret_cast<double *>(ws + off_bfn); }
+    // Separable source g(t) h(x) (src holds h): g at the fine step times
+    // (N m + 1 values; empty: f constant in time) and, behind the base
+    // workspace (base_total bytes), the forced responses b_n of all N slices
+    // (natural layout) and the per-step source weights (N m values).
+    std::vector<double> gt;
+    size_t base_total = 0, off_bft = 0, off_gw = 0;
+    bool src_t() const { return has_src() && !gt.empty(); }
+    double *bft() const { return reinterpret_cast<double *>(ws + off_bft); }
+    double *gw() const { return reinterpret_cast<double *>(ws + off_gw); }
     // 2D with a velocity field: per-line tables of the fine and coarse PR-ADI
     // steps (layout of vel_tab_view), the y half-step's forward values for
     // all slices (wbuf) and for one slice (vwk).

@@ -5,6 +5,7 @@
 // with the L2 product approximated by h^d * sum_j; the stopping norm is the
 // maximum over slices of the discrete L2 norm.  Both come out of one pass that
 // produces per-slice sums.
+#include <algorithm>
 #include "pit_internal.hpp"
 
 namespace pit {
@@ -324,6 +325,26 @@ hipError_t launch_repeat(double *dst, const double *src, long len, long count, i
     const long n = len * count;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_repeat, vec_grid(n), dim3(kVecThreads), 0, st, dst, src, len, n, add);
+    return hipGetLastError();
+}
+
+// X_s += w[s * wstride] c for slices s < N of len points (grid.y = slice).
+__global__ void k_slice_axpy(double *__restrict__ X, const double *__restrict__ c, const double *__restrict__ w,
+                             long wstride, long len)
+{
+    const double a = w[(long)blockIdx.y * wstride];
+    double *x = X + (long)blockIdx.y * len;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long)gridDim.x * blockDim.x)
+        x[i] += a * c[i];
+}
+
+hipError_t launch_slice_axpy(double *X, const double *c, const double *w, long wstride, long len, int N,
+                             hipStream_t st)
+{
+    if (len <= 0 || N <= 0) return hipSuccess;
+    const long blocks = std::min<long>((len + kVecThreads - 1) / kVecThreads, 1024);
+    hipLaunchKernelGGL(k_slice_axpy, dim3((unsigned)blocks, (unsigned)N), dim3(kVecThreads), 0, st, X, c, w,
+                       wstride, len);
     return hipGetLastError();
 }
 

@@ -593,6 +593,78 @@ size_t source_slots(pit_ctx &c, size_t o)
     return align_up(o + (size_t)c.npts * sizeof(double));
 }
 
+// The workspace with or without the slots of a time-dependent source: the
+// forced responses of all N slices and the N m per-step weights, behind the
+// base workspace.
+void size_source_t(pit_ctx *c)
+{
+    if (c->gt.empty()) {
+        c->total = c->base_total;
+        return;
+    }
+    size_t o = align_up(c->base_total);
+    c->off_bft = o;
+    o = align_up(o + (size_t)c->N * c->npts * sizeof(double));
+    c->off_gw = o;
+    c->total = align_up(o + (size_t)c->N * c->m * sizeof(double));
+}
+
+// One fine step of every slice: out_n = S in_n, n < N (natural layout,
+// FP64; tmp is a block vector for the 2D half-steps).
+hipError_t step_all(pit_ctx *c, const double *in, double *out, double *tmp, hipStream_t st)
+{
+    const int N = c->N;
+    if (!c->dim2())
+        return launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), in, out, N, c->npts, 1, c->fine.scheme, 1, 0,
+                                 false, st);
+    const int Mx = c->pb.M[0], My = c->pb.M[1];
+    hipError_t e;
+    if (c->vel) {
+        const VelTab vt = c->vtab(true);
+        if (vel_lds(c)) return launch_vel_apply_lds(vt, in, 0, out, 0, nullptr, 0, 0.0, N, 1, Mx, My, st);
+        if ((e = launch_vel_x(vt, in, 0, tmp, 0, N, Mx, My, 1, st)) != hipSuccess) return e;
+        return launch_vel_y(vt, tmp, 0, out, 0, nullptr, 0, 0.0, c->wbuf(), N, Mx, My, 1, st);
+    }
+    LineTab<double> tx =
+        line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64 * c->ash.xw, c->ash.cx);
+    tx.cyclic = 0;
+    tx.M = Mx;
+    const ColTab ty =
+        col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy * c->ash.seg);
+    auto B = [](const double *p) { return AdiBuf{nullptr, const_cast<double *>(p), false}; };
+    if ((e = launch_adi_x(c->ash, tx, B(in), 0, B(tmp), 0, N, Mx, My, c->adi_R, c->fx_ex, c->fx_ed, st)) !=
+        hipSuccess)
+        return e;
+    return launch_adi_y(c->ash, ty, B(tmp), 0, B(out), 0, nullptr, 0, 0.0, N, Mx, My, c->fy_ex, c->fy_ed, st);
+}
+
+// Time-dependent source: the forced responses of all N slices at once into
+// bft(): from 0, u_{j+1} = S u_j + w_j c over the m steps of each slice, c
+// the response of one step to the profile h, w_j the profile's weight in
+// global step j (g(t_{j+1}) under IE, the mean of g(t_j) and g(t_{j+1})
+// under CN and PR-ADI).  One fine step of every slice per launch, then one
+// per-slice axpy.
+hipError_t forced_t(pit_ctx *c, const double *cc, hipStream_t st)
+{
+    const long np = c->npts;
+    const int N = c->N, m = c->m;
+    std::vector<double> w((size_t)N * m);
+    const bool ie = !c->dim2() && c->fine.scheme == SCHEME_IE;
+    for (size_t j = 0; j < w.size(); ++j) w[j] = ie ? c->gt[j + 1] : 0.5 * (c->gt[j] + c->gt[j + 1]);
+    hipError_t e;
+    if ((e = hipMemcpy(c->gw(), w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    double *X = c->vec(4), *Y = c->vec(5), *T = c->vec(6);
+    if ((e = launch_fill0(X, (long)N * np, st)) != hipSuccess) return e;
+    if ((e = launch_slice_axpy(X, cc, c->gw(), m, np, N, st)) != hipSuccess) return e;
+    for (int k = 1; k < m; ++k) {
+        if ((e = step_all(c, X, Y, T, st)) != hipSuccess) return e;
+        if ((e = launch_slice_axpy(Y, cc, c->gw() + k, m, np, N, st)) != hipSuccess) return e;
+        std::swap(X, Y);
+    }
+    return launch_copy(c->bft(), X, (long)N * np, st);
+}
+
 // The forced response b = F(0) of one slice for the source f (constant in
 // time), into bfn() (natural) and bf() (working layout), FP64.  F is affine,
 // F(u) = S^m u + b with S one fine step, and b = sum_{i<m} S^i c where c is
@@ -620,6 +692,7 @@ hipError_t compute_forced(pit_ctx *c, hipStream_t st)
         };
         FH(launch_axpby(g, c->srcdev(), dt, c->srcdev(), 0.0, np, st));
         FH(steps(g, cc, 1, SCHEME_IE));  // one solve with A: A^{-1} (dt f)
+        if (c->src_t()) return forced_t(c, cc, st);
         FH(launch_copy(h, cc, np, st));
         int top = 0;
         while ((c->m >> (top + 1)) != 0) ++top;
@@ -644,6 +717,7 @@ hipError_t compute_forced(pit_ctx *c, hipStream_t st)
         FH(launch_vel_x(vt, c->srcdev(), 0, t, 0, 1, Mx, My, 0, st));             // X^{-1} f
         FH(launch_vel_y(vt, t, 0, g, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 0, st));  // Y^{-1} X^{-1} f
         FH(launch_axpby(cc, g, dt, g, 0.0, np, st));
+        if (c->src_t()) return forced_t(c, cc, st);
         FH(launch_copy(h, cc, np, st));
         for (int k = 1; k < c->m; ++k) {
             FH(launch_vel_x(vt, h, 0, t, 0, 1, Mx, My, 1, st));
@@ -669,6 +743,7 @@ hipError_t compute_forced(pit_ctx *c, hipStream_t st)
     FH(half_x(c->srcdev(), t, 0.0, 1.0));  // X^{-1} f (explicit part off)
     FH(half_y(t, g, 0.0, 1.0));            // Y^{-1} X^{-1} f
     FH(launch_axpby(cc, g, dt, g, 0.0, np, st));
+    if (c->src_t()) return forced_t(c, cc, st);
     FH(launch_copy(h, cc, np, st));
     for (int k = 1; k < c->m; ++k) {
         FH(half_x(h, t, c->fx_ex, c->fx_ed));
@@ -696,6 +771,10 @@ int bind_source(pit_ctx *ctx)
 hipError_t pit::fill_forced(const pit_ctx *c, double *B, hipStream_t st)
 {
     if (!c->has_src() || c->N < 2) return hipSuccess;
+    if (c->src_t()) {  // b_0 .. b_{N-2} into slices 1 .. N-1
+        if (c->dim2()) return launch_copy(B + c->npts, c->bft(), (long)(c->N - 1) * c->npts, st);
+        return launch_to_chunked(c->bft(), B + c->ld, c->N - 1, c->npts, c->lf.sh.NT, c->lf.sh.C, st);
+    }
     const long len = c->dim2() ? c->npts : c->ld;
     return launch_repeat(B + len, c->bf(), len, c->N - 1, 0, st);
 }
@@ -865,7 +944,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
             c->off_vwk = o;
             o = align_up(o + (size_t)c->npts * sizeof(double));
         }
-        c->total = o;
+        c->total = c->base_total = o;
         *out = c;
         return PIT_OK;
     }
@@ -911,7 +990,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->off_red = o;
     o = align_up(o + sizeof(RedOut));
     o = source_slots(*c, o);
-    c->total = o;
+    c->total = c->base_total = o;
     *out = c;
     return PIT_OK;
 }
@@ -995,13 +1074,37 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
 int pit_set_source(pit_ctx *ctx, const double *f)
 {
     if (!ctx) return PIT_EINVAL;
+    if (f)
+        for (int j = 0; j < ctx->npts; ++j)
+            if (!std::isfinite(f[j])) return PIT_EINVAL;
+    ctx->gt.clear();
+    size_source_t(ctx);
     if (!f) {
         ctx->src.clear();
         return PIT_OK;
     }
-    for (int j = 0; j < ctx->npts; ++j)
-        if (!std::isfinite(f[j])) return PIT_EINVAL;
     ctx->src.assign(f, f + ctx->npts);
+    return ctx->ws ? bind_source(ctx) : PIT_OK;
+}
+
+int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g)
+{
+    if (!ctx) return PIT_EINVAL;
+    if (!h || !g) return pit_set_source(ctx, h);
+    const size_t ng = (size_t)ctx->N * ctx->m + 1;
+    for (int j = 0; j < ctx->npts; ++j)
+        if (!std::isfinite(h[j])) return PIT_EINVAL;
+    for (size_t j = 0; j < ng; ++j)
+        if (!std::isfinite(g[j])) return PIT_EINVAL;
+    ctx->gt.assign(g, g + ng);
+    ctx->src.assign(h, h + ctx->npts);
+    size_source_t(ctx);
+    if (ctx->ws && ctx->ws_bytes < ctx->total) {  // the bound workspace is too small: unbind
+        ctx->drop_graphs();
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+        return PIT_ENOMEM;
+    }
     return ctx->ws ? bind_source(ctx) : PIT_OK;
 }
 
@@ -1025,11 +1128,17 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
     } else {
         PIT_HIP(op_apply(ctx, lam, y, raw, last, false, st));
     }
-    // with a source F is affine: F(lam_n) = F0(lam_n) + b
+    // with a source F is affine: F_n(lam_n) = F0(lam_n) + b_n
     if (ctx->has_src() && (raw || last)) {
-        const long np = ctx->npts;
-        if (last) PIT_HIP(launch_repeat(y + (long)(ctx->N - 1) * np, ctx->bfn(), np, 1, 1, st));
-        else PIT_HIP(launch_repeat(y, ctx->bfn(), np, ctx->N, 1, st));
+        const long np = ctx->npts, l0 = (long)(ctx->N - 1) * np;
+        if (ctx->src_t()) {
+            if (last) PIT_HIP(launch_axpby(y + l0, ctx->bft() + l0, 1.0, y + l0, 1.0, np, st));
+            else PIT_HIP(launch_axpby(y, ctx->bft(), 1.0, y, 1.0, (long)ctx->N * np, st));
+        } else if (last) {
+            PIT_HIP(launch_repeat(y + l0, ctx->bfn(), np, 1, 1, st));
+        } else {
+            PIT_HIP(launch_repeat(y, ctx->bfn(), np, ctx->N, 1, st));
+        }
     }
     return PIT_OK;
 }

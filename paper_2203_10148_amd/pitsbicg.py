@@ -83,7 +83,7 @@ EXPORTS = (
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
     "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
-    "pit_parareal", "pit_set_source",
+    "pit_parareal", "pit_set_source", "pit_set_source_t",
 )
 
 _lib = None
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.pit_workspace_bytes.restype = sz
     lib.pit_bind_workspace.argtypes = [vp, vp, sz]
     lib.pit_set_source.argtypes = [vp, ct.POINTER(ct.c_double)]
+    lib.pit_set_source_t.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     lib.pit_apply_F.argtypes = [vp, vp, vp, i32, vp]
     lib.pit_coarse_sweep.argtypes = [vp, vp, vp, vp]
     lib.pit_solve.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
@@ -219,15 +220,29 @@ class Context:
     def workspace_bytes(self) -> int:
         return int(load().pit_workspace_bytes(self._h))
 
-    def set_source(self, f):
-        """Source constant in time (one slice of values, host), or None to remove it."""
+    def set_source(self, f, g=None):
+        """Source constant in time (one slice of values, host), or None to
+        remove it; with g (N m + 1 values at the fine step times) the source
+        g(t) f(x).  A bound workspace that is too small for g is replaced by
+        one of the new size."""
         if f is None:
             _check(load().pit_set_source(self._h, None), "pit_set_source")
             return
         f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
         if f.size != self.p.npts:
             raise ValueError("set_source: one slice of npts values expected")
-        _check(load().pit_set_source(self._h, f.ctypes.data_as(ct.POINTER(ct.c_double))), "pit_set_source")
+        fp = f.ctypes.data_as(ct.POINTER(ct.c_double))
+        if g is None:
+            _check(load().pit_set_source(self._h, fp), "pit_set_source")
+            return
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+        if g.size != self.p.N * self.p.m + 1:
+            raise ValueError("set_source: N m + 1 profile values expected")
+        rc = load().pit_set_source_t(self._h, fp, g.ctypes.data_as(ct.POINTER(ct.c_double)))
+        if rc == ENOMEM and self.ws is not None:  # unbound: bind one of the new size
+            self.bind(self.ws.device)
+            return
+        _check(rc, "pit_set_source_t")
 
     def kernel_shape(self):
         out = (ct.c_int32 * 4)()

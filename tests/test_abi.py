@@ -4,6 +4,7 @@ import ctypes as ct
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2203_10148_amd import pitsbicg as P
@@ -166,6 +167,33 @@ def test_velocity_kernel_shape_reports_where_a_slice_lives(monkeypatch):
         assert out[2] == 0
         monkeypatch.delenv("PIT_VEL_LDS")
         lib.pit_destroy(h)
+
+
+def test_time_dependent_source_sizes_the_workspace_on_the_host():
+    """pit_set_source_t on an unbound context: validation, and the workspace
+    grows by the N forced responses and N m weights (256-byte aligned), and
+    shrinks back when the source becomes constant or goes."""
+    lib = P.load()
+    p = wl.C1.with_(N=8, m=16)
+    rc, h = create(p)
+    assert rc == P.OK
+    dp = ct.POINTER(ct.c_double)
+    base = lib.pit_workspace_bytes(h)
+    f = np.linspace(0.0, 1.0, p.npts)
+    g = np.ones(p.N * p.m + 1)
+    assert lib.pit_set_source_t(h, f.ctypes.data_as(dp), g.ctypes.data_as(dp)) == P.OK
+    up = lambda n: (n + 255) // 256 * 256
+    assert lib.pit_workspace_bytes(h) == up(up(base + p.N * p.npts * 8) + p.N * p.m * 8)
+    bad = g.copy()
+    bad[5] = np.nan
+    assert lib.pit_set_source_t(h, f.ctypes.data_as(dp), bad.ctypes.data_as(dp)) == P.EINVAL
+    assert lib.pit_set_source_t(None, f.ctypes.data_as(dp), g.ctypes.data_as(dp)) == P.EINVAL
+    assert lib.pit_set_source_t(h, f.ctypes.data_as(dp), None) == P.OK  # constant source
+    assert lib.pit_workspace_bytes(h) == base
+    assert lib.pit_set_source_t(h, f.ctypes.data_as(dp), g.ctypes.data_as(dp)) == P.OK
+    assert lib.pit_set_source(h, None) == P.OK  # removed
+    assert lib.pit_workspace_bytes(h) == base
+    lib.pit_destroy(h)
 
 
 def test_batch_and_server_validate_on_the_host():
