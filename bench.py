@@ -173,13 +173,15 @@ def workload(name, prec, side=None):
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
 
 
-def cpu_baseline(p, u0, seconds, source=None):
+def cpu_baseline(p, u0, seconds, source=None, profile=None):
     """Oracle PiTSBiCG on the host cores, truncated to a few iterations."""
     import oracle as orc
 
     threads = max(1, min(16, os.cpu_count() or 1))
     orc.set_threads(threads)
-    o = orc.Oracle(**p.oracle_kwargs(), source=source)
+    o = orc.Oracle(**p.oracle_kwargs())
+    if source is not None:
+        o.set_source(source, profile)
     iters = 1
     while True:
         t0 = time.perf_counter()
@@ -214,7 +216,9 @@ def main():
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
     ap.add_argument("--source", type=int, default=None, metavar="SEED",
-                    help="c1-c3: add a seeded source term constant in time (pit_set_source)")
+                    help="c1-c3, f2: add a seeded source term constant in time (pit_set_source)")
+    ap.add_argument("--source-profile", action="store_true",
+                    help="with --source: make it g(t) h(x), g a seeded time profile (pit_set_source_t)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["apply", "sweep", "solve"], default=None,
@@ -260,14 +264,18 @@ def main():
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
     ctx = P.Context(p, device=dev)
-    source_f, src_ms = None, None
+    source_f, source_g, src_ms = None, None, None
     if args.source is not None:
-        # the forced response is computed at pit_set_source (setup, not timed)
+        # the forced responses are computed at pit_set_source(_t) (setup, not timed)
         source_f = wl.source_bumps(p, args.source)
+        if args.source_profile:
+            source_g = wl.source_profile(p, args.source + 1)
         t0 = time.perf_counter()
-        ctx.set_source(source_f)
+        ctx.set_source(source_f, source_g)
+        torch.cuda.synchronize()
         src_ms = 1e3 * (time.perf_counter() - t0)
-        log(f"[bench] source (seed {args.source}): forced response set up in {src_ms:.2f} ms")
+        what = "all N slices' forced responses" if source_g is not None else "forced response"
+        log(f"[bench] source (seed {args.source}): {what} set up in {src_ms:.2f} ms")
     if args.probe:
         lam = torch.as_tensor(wl.random_block(p, 1), dtype=torch.float64, device=dev)
         out = torch.empty_like(lam)
@@ -400,8 +408,13 @@ def main():
     }
     if source_f is not None:
         out["config"]["source_seed"] = args.source
-        out["source"] = {"setup_ms": src_ms, "note": "forced response b = F(0) of one slice, computed on the "
-                                                    "device at pit_set_source; B = (u0, b, .., b)"}
+        if source_g is not None:
+            out["config"]["source_profile"] = True
+            note = ("forced responses b_n = F_n(0) of all N slices for g(t) h(x), computed on the device at "
+                    "pit_set_source_t; B = (u0, b_0, .., b_{N-2})")
+        else:
+            note = "forced response b = F(0) of one slice, computed on the device at pit_set_source; B = (u0, b, .., b)"
+        out["source"] = {"setup_ms": src_ms, "note": note}
     # the other fine-propagator form on the same input (FP32 fine with FP64
     # reductions vs plain FP64), outside the timed region
     if p.dim == 1 and not args.no_compare:
@@ -409,7 +422,7 @@ def main():
         po = p.with_(prec=other)
         co = P.Context(po, device=dev)
         if source_f is not None:
-            co.set_source(source_f)
+            co.set_source(source_f, source_g)
         Xo = torch.empty_like(X)
         so = 10 if other == wl.F32 else 0
         co.solve(u0, Xo, tol=p.tol, stall_window=so)
@@ -444,7 +457,7 @@ def main():
             f"vs PiTSBiCG {matvecs} products")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f)
+        out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f, source_g)
     print(json.dumps(out), flush=True)
 
 
