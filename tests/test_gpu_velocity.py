@@ -67,6 +67,14 @@ CASES = {
     # more lines than one 64-thread block along both axes, ragged
     "wide": wl.Problem(dim=2, M=(130, 70), bc=wl.DIRICHLET, nu=0.02, react=0.5, rot=1.0, T=0.3, N=3, m=4,
                        fine=wl.ADI, c=1, coarse=wl.ADI, name="wide"),
+    # degenerate sizes: the smallest grid, one slice (the apply has no
+    # slice to propagate, the sweep copies)
+    "tiny": wl.Problem(dim=2, M=(3, 3), bc=wl.DIRICHLET, nu=0.05, adv=(0.3, -0.1), react=0.5, rot=1.0, T=0.2,
+                       N=3, m=2, fine=wl.ADI, c=1, coarse=wl.ADI, name="tiny"),
+    "one_slice": wl.F2.with_(T=0.1, N=1, m=10, name="one_slice"),
+    # column walks over two wavefronts, fields and tables in LDS
+    "cols70": wl.Problem(dim=2, M=(70, 20), bc=wl.DIRICHLET, nu=0.02, adv=(0.1, 0.2), react=0.3, rot=1.5, T=0.3,
+                         N=4, m=3, fine=wl.ADI, c=2, coarse=wl.ADI, name="cols70"),
     # fields in LDS, tables read from global memory
     "mid": wl.Problem(dim=2, M=(80, 66), bc=wl.DIRICHLET, nu=0.02, adv=(-0.1, 0.2), react=0.5, rot=1.0, T=0.3,
                       N=3, m=3, fine=wl.ADI, c=2, coarse=wl.ADI, name="mid"),
