@@ -164,7 +164,7 @@ def algorithmic_bytes(p, prec, unit):
 def workload(name, prec, side=None):
     from paper_2203_10148_amd import workloads as wl
 
-    p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3, "f2": wl.F2}[name]
+    p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3, "f2": wl.F2, "f3d": wl.F3_DIFF, "f3r": wl.F3_DR}[name]
     if side and p.dim == 2 and side != p.M[0]:
         # the same 2D recipe on a larger square (its working set beyond the 256 MiB MALL)
         p = p.with_(M=(side, side), name=f"{p.name}_{side}")
@@ -203,9 +203,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2"],
-                    help="c1-c3: one solve per step; c4: the 64-instance batch per step; c5: a served "
-                         "Poisson stream (one pass of --requests requests)")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2", "f3d", "f3r"],
+                    help="c1-c3, f2, f3d (diffusion), f3r (diffusion-reaction): one solve per step; c4: the "
+                         "64-instance batch per step; c5: a served Poisson stream (one pass of --requests "
+                         "requests)")
+    ap.add_argument("--paper-cases", action="store_true",
+                    help="the experiment of Sec. 4: the diffusion, diffusion-reaction and rotating "
+                         "advection-diffusion-reaction cases on 4..64 slices, PiTSBiCG against parareal by "
+                         "preconditioned products to tol (one JSON line)")
     ap.add_argument("--requests", type=int, default=120, help="c5: how many requests of the stream to serve")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: arrival rate (requests/s)")
     ap.add_argument("--arena-gib", type=float, default=160.0, help="c5: HBM budget of the server (GiB)")
@@ -255,6 +260,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.paper_cases:
+        return bench_paper_cases(args, dev)
     if args.workload == "c4":
         return bench_batch(args, dev)
     if args.workload == "c5":
@@ -341,8 +348,8 @@ def main():
             "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
                              "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
         }
-    elif ctx.kernel_shape()[2] > 0 and (p.rot != 0.0 or any(a != 0.0 for a in p.adv)):
-        # 2D with a velocity field, slices held in LDS for all their steps:
+    elif ctx.kernel_shape()[0] == 1 and ctx.kernel_shape()[2] > 0:
+        # 2D on per-line tables with the slices held in LDS for all their steps:
         # HBM sees each slice once per launch, the steps are FP64 arithmetic.
         scheme, cscheme = "adi", "adi"
         fl_fine = p.cells_per_apply * VEL_FLOPS_PER_POINT_STEP
@@ -459,6 +466,42 @@ def main():
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f, source_g)
     print(json.dumps(out), flush=True)
+
+
+def bench_paper_cases(args, dev):
+    """Sec. 4's experiment on the synthetic stand-ins: each case on N = 4..64
+    slices with the fine step fixed (N m = 6400), PiTSBiCG and parareal to the
+    same tolerance on the preconditioned residual (parareal's update is that
+    residual), compared by preconditioned products and by time (second of two
+    runs of each)."""
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    rows = []
+    for case in wl.PAPER_CASES:
+        for N in wl.PAPER_SLICES:
+            p = wl.paper_case(case, N)
+            ctx = P.Context(p, device=dev)
+            u0 = torch.as_tensor(wl.u0_for(p), dtype=torch.float64, device=dev)
+            X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)
+            for _ in range(2):
+                _, si = ctx.solve(u0, X, tol=p.tol)
+            for _ in range(2):
+                _, pi = ctx.parareal(u0, X, tol=p.tol)
+            row = {"case": case.name, "N": N, "m": p.m,
+                   "pitsbicg": {"status": si.status, "iters": si.iters, "products": si.matvecs,
+                                "ms": si.ms_total, "res_norm": si.res_norm},
+                   "parareal": {"status": pi.status, "iters": pi.iters, "products": pi.matvecs,
+                                "ms": pi.ms_total, "res_norm": pi.res_norm}}
+            rows.append(row)
+            log(f"[bench] {case.name} N={N} m={p.m}: PiTSBiCG {si.matvecs} products {si.ms_total:.1f} ms "
+                f"(status {si.status}); parareal {pi.matvecs} products {pi.ms_total:.1f} ms (status {pi.status})")
+            del ctx
+    print(json.dumps({"metric": "preconditioned products to tol, PiTSBiCG vs parareal (Sec. 4)",
+                      "unit": "products", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+                      "data": "synthetic", "tol": wl.F2.tol, "rows": rows}), flush=True)
 
 
 def bench_batch(args, dev):

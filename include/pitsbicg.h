@@ -400,9 +400,10 @@ int pit_last_hip_error(void);
 /* Kernel shape the context chose (for reports).  1D: threads per line and
  * points per thread of the fine and coarse line solvers.  2D: lanes and
  * points per lane of the x half-step, lanes and rows per lane of the y
- * half-step.  2D with a velocity field: {1, 0, L, 0}, one thread per line,
- * where L says where a slice lives during its steps: 2 = its fields and
- * tables in LDS, 1 = its fields in LDS, 0 = HBM (one launch per half-step).
+ * half-step.  2D on per-line tables (a velocity field, or FP64 slices small
+ * enough for LDS): {1, 0, L, 0}, one thread per line, where L says where a
+ * slice lives during its steps: 2 = its fields and tables in LDS, 1 = its
+ * fields in LDS, 0 = HBM (one launch per half-step).
  * PIT_EINVAL on a NULL argument. */
 int pit_kernel_shape(const pit_ctx *ctx, int32_t out[4]);
 

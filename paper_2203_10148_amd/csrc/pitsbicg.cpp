@@ -902,7 +902,14 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
             delete c;
             return PIT_EINVAL;
         }
-        c->vel = problem->adv[0] != 0.0 || problem->adv[1] != 0.0 || problem->rot != 0.0;
+        // Per-line tables: with a velocity field, and also without one for FP64
+        // slices small enough for LDS, where the whole-slice kernels beat two
+        // launches per step (PIT_VEL_LDS=0 keeps the shared-table kernels).
+        const bool velocity = problem->adv[0] != 0.0 || problem->adv[1] != 0.0 || problem->rot != 0.0;
+        const char *lds_env = std::getenv("PIT_VEL_LDS");
+        const bool lds_small = !c->fine32() && !(lds_env && lds_env[0] == '0') &&
+                               vel_lds_mode(problem->M[0], problem->M[1]) > 0;
+        c->vel = velocity || lds_small;
         if (c->vel && (!vel_tables(*c, 0.5 * c->DT / m, c->vtf, c->vf_xdi, c->vf_ydi) ||
                        !vel_tables(*c, 0.5 * c->DT / coarse.substeps, c->vtc, c->vc_xdi, c->vc_ydi))) {
             delete c;

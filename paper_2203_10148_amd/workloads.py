@@ -203,6 +203,22 @@ C3 = Problem(dim=2, M=(512, 512), bc=DIRICHLET, nu=0.05, T=0.5, N=128, m=64, fin
 F2 = Problem(dim=2, M=(49, 49), bc=DIRICHLET, nu=0.1, react=0.5, rot=1.0, T=6.4, N=64, m=100, fine=ADI, c=1,
              coarse=ADI, prec=F64, tol=1e-8, name="f2_rotating_adr")
 
+# The other two cases of Sec. 4 on the same grid and time line: diffusion
+# (mu = 1) and diffusion-reaction (mu = 1, r = 1.5); Gaussian u0 at the centre.
+F3_DIFF = Problem(dim=2, M=(49, 49), bc=DIRICHLET, nu=1.0, T=6.4, N=64, m=100, fine=ADI, c=1, coarse=ADI,
+                  prec=F64, tol=1e-8, name="f3_diffusion")
+F3_DR = F3_DIFF.with_(react=1.5, name="f3_diffusion_reaction")
+
+# Sec. 4 runs each case on 2^n slices, n = 2..6, with the fine step fixed.
+PAPER_CASES = (F3_DIFF, F3_DR, F2)
+PAPER_SLICES = (4, 8, 16, 32, 64)
+
+
+def paper_case(p: Problem, N: int) -> Problem:
+    """Case p on N slices with the same fine step (N m = 6400 steps over T)."""
+    steps = p.N * p.m
+    return p.with_(N=N, m=steps // N)
+
 
 def u0_gaussian(p: Problem, centre=(0.75, 0.5), sigma=0.1) -> np.ndarray:
     """A Gaussian (2D) at `centre` (fractions of the side lengths)."""
@@ -217,6 +233,8 @@ def u0_for(p: Problem, seed: int | None = None) -> np.ndarray:
         return u0_sines(p)
     if p.name.startswith("f2"):
         return u0_gaussian(p)
+    if p.name.startswith("f3"):
+        return u0_gaussian(p, centre=(0.5, 0.5))
     if p.dim == 2:
         return u0_bumps(p, 3 if seed is None else seed)
     return u0_fourier(p, 2 if seed is None else seed)

@@ -196,6 +196,28 @@ def test_time_dependent_source_sizes_the_workspace_on_the_host():
     lib.pit_destroy(h)
 
 
+def test_small_fp64_2d_problems_take_the_lds_kernels(monkeypatch):
+    """Without a velocity, an FP64 2D slice that fits in LDS takes the
+    per-line path as well; FP32 fields, larger slices or PIT_VEL_LDS=0 at
+    creation keep the shared-table kernels (64-lane strips)."""
+    lib = P.load()
+    out = (ct.c_int32 * 4)()
+
+    def shape(p):
+        rc, h = create(p)
+        assert rc == P.OK
+        lib.pit_kernel_shape(h, out)
+        lib.pit_destroy(h)
+        return list(out)
+
+    small = wl.F3_DIFF.with_(N=4, m=2)
+    assert shape(small) == [1, 0, 2, 0]
+    assert shape(small.with_(prec=wl.F32))[0] >= 64
+    assert shape(small.with_(M=(300, 200)))[0] >= 64
+    monkeypatch.setenv("PIT_VEL_LDS", "0")
+    assert shape(small)[0] >= 64
+
+
 def test_batch_and_server_validate_on_the_host():
     lib = P.load()
     h = ct.c_void_p()

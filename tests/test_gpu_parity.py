@@ -508,6 +508,22 @@ def test_adi_other_y_shapes_on_a_short_column(yshape, reported, monkeypatch):
     assert relerr(host(c.coarse_sweep(dev(lam))), o.sweep(lam)) < 1e-12
 
 
+def test_adi_shared_tables_on_a_small_fp64_slice(monkeypatch):
+    """The shared-table kernels on a slice that would otherwise take the LDS
+    path (PIT_VEL_LDS=0 at creation), against the oracle."""
+    monkeypatch.setenv("PIT_VEL_LDS", "0")
+    p = adi_problem(24, 20, 1.0, 1.3, 4, 3, 1, wl.F64)
+    say("adi shared tables 24x20")
+    c = ctx(p)
+    assert c.kernel_shape()[0] >= 64
+    o = make_oracle(p)
+    lam = wl.random_block(p, 19)
+    d = dev(lam)
+    assert relerr(host(c.apply_F(d)), o.apply(lam)) < 1e-12
+    assert relerr(host(c.apply_F(d, raw=True)), o.apply_raw(lam)) < 1e-12
+    assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
+
+
 def test_adi_graph_replays_equal_eager_launches(monkeypatch):
     """The 2D apply and sweep run as captured HIP graphs; every replay, with
     other work and synchronisations in between, gives the bits of the eager
@@ -535,11 +551,15 @@ def test_adi_graph_replays_equal_eager_launches(monkeypatch):
         del scratch
 
 
-@pytest.mark.parametrize("prec", [wl.F64, wl.F32])
-def test_adi_small_solve_matches_oracle(prec):
+@pytest.mark.parametrize("prec,lds", [(wl.F64, "1"), (wl.F64, "0"), (wl.F32, "1")],
+                         ids=["f64_lds", "f64_shared_tables", "f32"])
+def test_adi_small_solve_matches_oracle(prec, lds, monkeypatch):
+    """FP64 slices that fit in LDS take the per-line whole-slice kernels;
+    PIT_VEL_LDS=0 at creation keeps the shared-table kernels."""
+    monkeypatch.setenv("PIT_VEL_LDS", lds)
     p = wl.Problem(dim=2, M=(40, 33), length=(1.0, 1.0), nu=0.05, T=0.5, N=8, m=8, fine=wl.ADI, c=1,
                    coarse=wl.ADI, prec=prec)
-    say(f"adi small solve prec={prec}")
+    say(f"adi small solve prec={prec} lds={lds}")
     o = make_oracle(p)
     u0 = wl.u0_bumps(p, 3)
     Xo, io = o.pitsbicg(u0, tol=1e-10)
