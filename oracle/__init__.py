@@ -34,7 +34,7 @@ _SRC = os.path.join(_HERE, "pit_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 DIRICHLET, PERIODIC = 0, 1
-IE, CN, ADI = 0, 1, 2
+IE, CN, ADI, ADI_IE = 0, 1, 2, 3  # ADI_IE: the 2D backward-Euler splitting
 ABS, REL = 0, 1
 X0_ZERO, X0_GIVEN, X0_COARSE = 0, 1, 2
 OK, EINVAL, ENOCONV, EBREAKDOWN = 0, -1, -4, -5

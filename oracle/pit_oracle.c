@@ -35,6 +35,8 @@
  *   PR-ADI (2D): (I - dt/2 Lx) u* = (I + dt/2 Ly) u + dt/2 f,
  *                (I - dt/2 Ly) u' = (I + dt/2 Lx) u* + dt/2 f,
  *       with Lx = nu*D2x - ux(y)*D1x - r/2 and Ly = nu*D2y - uy(x)*D1y - r/2;
+ *   backward-Euler splitting (2D): (I - dt Lx) u* = u + dt f,
+ *                                  (I - dt Ly) u' = u*  (same Lx, Ly);
  *       the velocity is a constant (ax, ay) plus a rigid rotation of rate rot
  *       about the centre (xc, yc) of the domain:
  *           ux = ax - rot*(y - yc),  uy = ay + rot*(x - xc)
@@ -45,7 +47,8 @@
  * f is an optional source (the source term of Sec. 2, eq. (Cauchy)); without
  * it f = 0.  It is either constant in time or separable, f(t, x) = g(t) h(x),
  * with g given at the fine step times t_j = j dt, j = 0..N m.  Fine step j
- * (from t_j to t_{j+1}) takes f(t_{j+1}) under IE, the trapezoidal mean
+ * (from t_j to t_{j+1}) takes f(t_{j+1}) under IE and the backward-Euler
+ * splitting, the trapezoidal mean
  * (f(t_j) + f(t_{j+1}))/2 under CN, and the midpoint value, read as that same
  * mean, in both PR-ADI half-steps.  With a source the propagator of slice n
  * is affine, F_n(u) = F0(u) + b_n with b_n = F_n(0), the forced response of
@@ -71,7 +74,7 @@
 #endif
 
 enum { ORC_DIRICHLET = 0, ORC_PERIODIC = 1 };
-enum { ORC_IE = 0, ORC_CN = 1, ORC_ADI = 2 };
+enum { ORC_IE = 0, ORC_CN = 1, ORC_ADI = 2, ORC_ADI_IE = 3 };
 enum { ORC_ABS = 0, ORC_REL = 1 };
 enum { ORC_X0_ZERO = 0, ORC_X0_GIVEN = 1, ORC_X0_COARSE = 2 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOCONV = -4, ORC_EBREAKDOWN = -5 };
@@ -262,6 +265,25 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
     double *sol = line + nmax;     /* nmax */
     double *lw = sol + nmax;       /* 9*nmax */
     double th = 0.5 * dt;
+    if (scheme == ORC_ADI_IE) {
+        /* (I - dt*Lx) u* = u + dt*f row by row, then (I - dt*Ly) u' = u* column by column */
+        for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                line[i] = u[j * nx + i];
+                if (f) line[i] += dt * (wf * f[j * nx + i]);
+            }
+            op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
+            implicit_line(nx, ORC_DIRICHLET, dt, xlo, xdi, xup, line, sol, lw);
+            for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
+        }
+        for (int i = 0; i < nx; ++i) {
+            for (int j = 0; j < ny; ++j) line[j] = star[j * nx + i];
+            op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
+            implicit_line(ny, ORC_DIRICHLET, dt, ylo, ydi, yup, line, sol, lw);
+            for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+        }
+        return;
+    }
     /* half-step 1: rhs = (I + th*Ly) u + th*f, then (I - th*Lx) u* = rhs row by row */
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
@@ -297,7 +319,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
 static double src_weight(const orc_ctx *C, int scheme, int j)
 {
     if (!C->gt || j < 0) return 1.0;
-    return scheme == ORC_IE ? C->gt[j + 1] : 0.5 * (C->gt[j] + C->gt[j + 1]);
+    return (scheme == ORC_IE || scheme == ORC_ADI_IE) ? C->gt[j + 1] : 0.5 * (C->gt[j] + C->gt[j + 1]);
 }
 
 /* Apply `nsteps` steps of `scheme`, each of length span/nsteps, with source f
@@ -334,8 +356,10 @@ orc_ctx *orc_create(int dim, int Mx, int My, int bc, double Lx, double Ly, doubl
     if (Mx < 3 || N < 1 || m < 1 || c < 1) return NULL;
     if (dim == 2 && (My < 3 || bc != ORC_DIRICHLET)) return NULL;
     if (dim == 1 && rot != 0.0) return NULL; /* rotation: 2D only */
-    if (dim == 1 && (fine_scheme == ORC_ADI || coarse_scheme == ORC_ADI)) return NULL;
-    if (dim == 2 && (fine_scheme != ORC_ADI || coarse_scheme != ORC_ADI)) return NULL;
+    if (dim == 1 && (fine_scheme >= ORC_ADI || coarse_scheme >= ORC_ADI)) return NULL;
+    if (dim == 2 && ((fine_scheme != ORC_ADI && fine_scheme != ORC_ADI_IE) ||
+                     (coarse_scheme != ORC_ADI && coarse_scheme != ORC_ADI_IE)))
+        return NULL;
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     C->dim = dim;
     C->Mx = Mx;

@@ -27,7 +27,7 @@ from dataclasses import dataclass, field, replace
 import numpy as np
 
 DIRICHLET, PERIODIC = 0, 1
-IE, CN, ADI = 0, 1, 2
+IE, CN, ADI, ADI_IE = 0, 1, 2, 3  # ADI_IE: the 2D backward-Euler splitting
 F64, F32 = 0, 1
 
 

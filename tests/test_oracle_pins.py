@@ -79,6 +79,8 @@ def dense_step(p: wl.Problem, scheme, dt):
         idx = np.arange(My) * Mx + i
         Ly[np.ix_(idx, idx)] = dense_L1(My, hy, p.nu, uy[i], 0.5 * p.react, False)
     I = np.eye(Mx * My)
+    if scheme == wl.ADI_IE:  # backward-Euler splitting: x-implicit, then y-implicit, full dt each
+        return np.linalg.solve(I - dt * Ly, I) @ np.linalg.solve(I - dt * Lx, I)
     th = 0.5 * dt
     half1 = np.linalg.solve(I - th * Lx, I + th * Ly)
     half2 = np.linalg.solve(I - th * Ly, I + th * Lx)
@@ -249,15 +251,15 @@ def test_adi_2d_closed_form_rectangle():
     assert relerr(o.G(u0), field(cstep)) < 1e-13
 
 
-@pytest.mark.parametrize("case", ["d_ie_adv", "d_cn_adv", "p_cn", "adi", "adi_rot"])
+@pytest.mark.parametrize("case", ["d_ie_adv", "d_cn_adv", "p_cn", "adi", "adi_rot", "adi_ie", "adi_ie_rot"])
 def test_one_step_vs_dense(case):
     """One step of each scheme against the dense matrix solved by LAPACK."""
     if case.startswith("adi"):
-        rot = case == "adi_rot"
+        rot = case.endswith("rot")
+        scheme = wl.ADI_IE if case.startswith("adi_ie") else wl.ADI
         p = wl.Problem(dim=2, M=(5, 4), length=(1.0, 0.7), nu=0.3, react=0.5, T=1.0, N=1, m=1,
-                       fine=wl.ADI, coarse=wl.ADI, adv=(0.4, -0.2) if rot else (0.0, 0.0),
+                       fine=scheme, coarse=scheme, adv=(0.4, -0.2) if rot else (0.0, 0.0),
                        rot=1.3 if rot else 0.0)
-        scheme = wl.ADI
     else:
         bc = wl.PERIODIC if case.startswith("p") else wl.DIRICHLET
         scheme = wl.IE if "ie" in case else wl.CN
@@ -282,10 +284,14 @@ TINY = [
                coarse=wl.ADI),
     wl.Problem(dim=2, M=(5, 4), length=(1.0, 1.0), nu=0.02, react=0.5, rot=1.0, T=0.5, N=4, m=3,
                fine=wl.ADI, c=1, coarse=wl.ADI),
+    wl.Problem(dim=2, M=(4, 5), length=(1.0, 1.2), nu=0.05, react=1.5, T=0.5, N=4, m=3,
+               fine=wl.ADI_IE, c=1, coarse=wl.ADI_IE),
+    wl.Problem(dim=2, M=(5, 4), length=(1.0, 1.0), nu=0.1, react=0.5, rot=1.0, T=0.5, N=5, m=2,
+               fine=wl.ADI, c=2, coarse=wl.ADI_IE),
 ]
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot", "adi_ie", "adi_mixed"])
 def test_apply_and_sweep_vs_dense(p):
     o = make(p)
     SF, SG = dense_props(p)
@@ -298,7 +304,7 @@ def test_apply_and_sweep_vs_dense(p):
         assert relerr(raw[n], SF @ v.reshape(p.N, -1)[n]) < 1e-13
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot", "adi_ie", "adi_mixed"])
 def test_serial_is_exact_solution(p):
     """The serial fine trajectory solves F Lambda = B with B = (u0, 0, .., 0)."""
     o = make(p)
@@ -361,7 +367,7 @@ def bicgstab_textbook(A, b, weight, N, iters):
     return xs, np.array(norms)
 
 
-@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot"])
+@pytest.mark.parametrize("p", TINY, ids=["dir_ie", "per_cn", "adi", "adi_rot", "adi_ie", "adi_mixed"])
 def test_pitsbicg_matches_textbook_bicgstab_and_dense_solution(p):
     o = make(p)
     u0 = np.random.default_rng(9).standard_normal(p.npts)
@@ -601,6 +607,43 @@ def test_source_adi_2d_modal_closed_form():
     ref = sum(F_coef(k, l, c0, ph) * mode(k, l) for (k, l), (c0, ph) in modes.items())
     assert relerr(o.F(u0), ref) < 1e-13
     assert relerr(o.forced(), sum(F_coef(k, l, 0.0, ph) * mode(k, l) for (k, l), (_, ph) in modes.items())) < 1e-13
+
+
+def test_adi_ie_modal_closed_form_with_source():
+    """Backward-Euler splitting on sin(k pi x) sin(l pi y): the two factors
+    scale a mode by 1/(1 - dt mx) and 1/(1 - dt my), the source entering the
+    first: c' = (c + dt phi) / ((1 - dt mx)(1 - dt my))."""
+    p = wl.Problem(dim=2, M=(18, 14), length=(1.0, 1.3), bc=wl.DIRICHLET, nu=0.05, react=1.5,
+                   T=0.3, N=3, m=5, fine=wl.ADI_IE, c=1, coarse=wl.ADI_IE)
+    X, Y = wl.grid_2d(p)
+    hx, hy = 1.0 / 19, 1.3 / 15
+    mx = lambda k: -(4 * p.nu / hx**2) * math.sin(k * math.pi * hx / 2.0) ** 2 - 0.5 * p.react
+    my = lambda l: -(4 * p.nu / hy**2) * math.sin(l * math.pi * (hy / 1.3) / 2.0) ** 2 - 0.5 * p.react
+    modes = {(1, 1): (1.0, 0.6), (2, 3): (0.5, 0.0), (3, 1): (0.0, -0.9)}
+    mode = lambda k, l: (np.sin(k * math.pi * X / 1.0) * np.sin(l * math.pi * Y / 1.3)).reshape(-1)
+    u0 = sum(c0 * mode(k, l) for (k, l), (c0, _) in modes.items())
+    f = sum(ph * mode(k, l) for (k, l), (_, ph) in modes.items())
+    o = orc.Oracle(**p.oracle_kwargs(), source=f)
+    dt = p.T / p.N / p.m
+
+    def F_coef(k, l, c, ph, wts):
+        for w in wts:
+            c = (c + dt * w * ph) / ((1 - dt * mx(k)) * (1 - dt * my(l)))
+        return c
+
+    ref = sum(F_coef(k, l, c0, ph, [1.0] * p.m) * mode(k, l) for (k, l), (c0, ph) in modes.items())
+    assert relerr(o.F(u0), ref) < 1e-13
+    # the coarse propagator (one step of DT, linear) on the same modes
+    G = sum(c0 / ((1 - p.T / p.N * mx(k)) * (1 - p.T / p.N * my(l))) * mode(k, l)
+            for (k, l), (c0, _) in modes.items())
+    assert relerr(o.G(u0), G) < 1e-13
+    # a time-dependent profile enters step j with g(t_{j+1})
+    g = profile(p, a=0.7, w=9.0)
+    o.set_source(f, g)
+    for n in range(p.N):
+        wts = [g[j + 1] for j in range(n * p.m, (n + 1) * p.m)]
+        b = sum(F_coef(k, l, 0.0, ph, wts) * mode(k, l) for (k, l), (_, ph) in modes.items())
+        assert relerr(o.forced(n), b) < 1e-13
 
 
 @pytest.mark.parametrize("dim", [1, 2])
