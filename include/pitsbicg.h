@@ -54,6 +54,9 @@ extern "C" {
 #define PIT_IE 0     /* implicit Euler: (I - dt L) u' = u                        */
 #define PIT_CN 1     /* Crank-Nicolson: (I - dt/2 L) u' = (I + dt/2 L) u         */
 #define PIT_ADI_PR 2 /* Peaceman-Rachford ADI (2D): x-implicit then y-implicit  */
+#define PIT_ADI_IE 3 /* backward-Euler splitting (2D): (I - dt Lx) u* = u,       */
+                     /* (I - dt Ly) u' = u*, the reaction split r/2 per factor;  */
+                     /* a source enters the first factor (u + dt f)              */
 
 #define PIT_F64 0 /* FP64 state and arithmetic                                 */
 #define PIT_F32 1 /* fine propagator only: FP32 state (see pit_stepper.prec)    */
@@ -100,7 +103,7 @@ typedef struct {
  * the ADI half steps, FP64 arithmetic); the coarse sweep, the dot products and
  * the BiCGStab scalars are always FP64. */
 typedef struct {
-    int32_t scheme;   /* PIT_IE, PIT_CN (1D) or PIT_ADI_PR (2D) */
+    int32_t scheme;   /* PIT_IE, PIT_CN (1D); PIT_ADI_PR, PIT_ADI_IE (2D) */
     int32_t substeps; /* m (fine) or c (coarse)                */
     int32_t prec;     /* PIT_F64 or PIT_F32                     */
     int32_t reserved; /* must be 0                              */

@@ -306,8 +306,19 @@ bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &
     return build_line(c.pb.M[0], c.pb.bc == PIT_PERIODIC, -th * lo, 1.0 - th * di, -th * up, sh, out);
 }
 
+// theta of the fine or coarse 2D step: dt/2 (PR-ADI) or dt (backward-Euler
+// splitting).
+double adi_theta(const pit_ctx &c, bool fine_step)
+{
+    const pit_stepper &s = fine_step ? c.fine : c.coarse;
+    const double dt = c.DT / (fine_step ? c.m : c.coarse.substeps);
+    return s.scheme == PIT_ADI_PR ? 0.5 * dt : dt;
+}
+
 // 2D setup: shapes, x and y tables and explicit coefficients for the fine
-// (theta = dt/2) and coarse (theta = DT/(2c)) PR-ADI steps.
+// and coarse steps: theta = dt/2 with the explicit halves (I + theta L) for
+// PR-ADI, theta = dt with identity explicit parts for the backward-Euler
+// splitting.
 bool setup_2d(pit_ctx &c)
 {
     const int Mx = c.pb.M[0], My = c.pb.M[1];
@@ -341,28 +352,29 @@ bool setup_2d(pit_ctx &c)
     c.ash = sh;
     const double nu = c.pb.nu, r = c.pb.react;
     const double kx = nu / (c.hx * c.hx), ky = nu / (c.hy * c.hy);
-    auto tables = [&](double th, LineHost &ax, std::vector<double> &ay, double &xex, double &xed, double &yex,
-                      double &yed) {
-        xex = th * ky;                      // x half step: (I + th Ly)
-        xed = 1.0 - 2.0 * th * ky - 0.5 * th * r;
-        yex = th * kx;                      // y half step: (I + th Lx)
-        yed = 1.0 - 2.0 * th * kx - 0.5 * th * r;
+    auto tables = [&](double th, bool pr, LineHost &ax, std::vector<double> &ay, double &xex, double &xed,
+                      double &yex, double &yed) {
+        xex = pr ? th * ky : 0.0;  // x half step: (I + th Ly), or I
+        xed = pr ? 1.0 - 2.0 * th * ky - 0.5 * th * r : 1.0;
+        yex = pr ? th * kx : 0.0;  // y half step: (I + th Lx), or I
+        yed = pr ? 1.0 - 2.0 * th * kx - 0.5 * th * r : 1.0;
         const bool okx = build_line(Mx, false, -th * kx, 1.0 + 2.0 * th * kx + 0.5 * th * r, -th * kx,
                                     LineShape{64 * xw, cx}, ax);
         const bool oky = build_col(My, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, sh.wy * sh.seg, sh.cy, ay);
         return okx && oky;
     };
-    const double thf = 0.5 * c.DT / c.m, thc = 0.5 * c.DT / c.coarse.substeps;
-    return tables(thf, c.axf, c.ayf, c.fx_ex, c.fx_ed, c.fy_ex, c.fy_ed) &&
-           tables(thc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed);
+    const bool prf = c.fine.scheme == PIT_ADI_PR, prc = c.coarse.scheme == PIT_ADI_PR;
+    return tables(adi_theta(c, true), prf, c.axf, c.ayf, c.fx_ex, c.fx_ed, c.fy_ex, c.fy_ed) &&
+           tables(adi_theta(c, false), prc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed);
 }
 
-// Per-line tables of one PR-ADI step with a velocity field (theta = th):
+// Per-line tables of one 2D step with a velocity field (theta = th; pr:
+// the PR-ADI explicit halves, else identity explicit parts):
 // row j's x-operator Lx_j = nu D2x - ux(y_j) D1x - r/2, column i's
 // Ly_i = nu D2y - uy(x_i) D1y - r/2, with ux = adv0 - rot (y - Ly/2) and
 // uy = adv1 + rot (x - Lx/2) (a rigid rotation about the domain centre);
 // Thomas pivots of I - th L per line, layout of vel_tab_view.
-bool vel_tables(const pit_ctx &c, double th, std::vector<double> &v, double &xdi, double &ydi)
+bool vel_tables(const pit_ctx &c, double th, bool pr, std::vector<double> &v, double &xdi, double &ydi)
 {
     const int Mx = c.pb.M[0], My = c.pb.M[1];
     const double nu = c.pb.nu, r = c.pb.react, hx = c.hx, hy = c.hy;
@@ -372,13 +384,13 @@ bool vel_tables(const pit_ctx &c, double th, std::vector<double> &v, double &xdi
     double *xa = xw + 4 * np, *xlo = xa + My, *xup = xa + 2 * My;
     double *ya = xa + 3 * My, *ylo = ya + Mx, *yup = ya + 2 * Mx;
     const double dix = -2.0 * nu / (hx * hx) - 0.5 * r, diy = -2.0 * nu / (hy * hy) - 0.5 * r;
-    xdi = th * dix;
-    ydi = th * diy;
+    xdi = pr ? th * dix : 0.0;
+    ydi = pr ? th * diy : 0.0;
     for (int j = 0; j < My; ++j) {
         const double ux = c.pb.adv[0] - c.pb.rot * ((j + 1) * hy - 0.5 * c.pb.length[1]);
         const double lo = nu / (hx * hx) + ux / (2.0 * hx), up = nu / (hx * hx) - ux / (2.0 * hx);
-        xlo[j] = th * lo;
-        xup[j] = th * up;
+        xlo[j] = pr ? th * lo : 0.0;
+        xup[j] = pr ? th * up : 0.0;
         xa[j] = -th * lo;
         const double b = 1.0 - th * dix, cc = -th * up;
         double cp = 0.0;
@@ -392,8 +404,8 @@ bool vel_tables(const pit_ctx &c, double th, std::vector<double> &v, double &xdi
     for (int i = 0; i < Mx; ++i) {
         const double uy = c.pb.adv[1] + c.pb.rot * ((i + 1) * hx - 0.5 * c.pb.length[0]);
         const double lo = nu / (hy * hy) + uy / (2.0 * hy), up = nu / (hy * hy) - uy / (2.0 * hy);
-        ylo[i] = th * lo;
-        yup[i] = th * up;
+        ylo[i] = pr ? th * lo : 0.0;
+        yup[i] = pr ? th * up : 0.0;
         ya[i] = -th * lo;
         const double b = 1.0 - th * diy, cc = -th * up;
         double cp = 0.0;
@@ -423,7 +435,8 @@ int validate(const pit_problem *p, int N, int m, const pit_stepper &f, const pit
         // a velocity field runs the per-line FP64 half-steps
         if ((p->adv[0] != 0.0 || p->adv[1] != 0.0 || p->rot != 0.0) && f.prec != PIT_F64) return PIT_EINVAL;
         if (!(p->length[1] > 0.0)) return PIT_EINVAL;
-        if (f.scheme != PIT_ADI_PR || g.scheme != PIT_ADI_PR) return PIT_EINVAL;
+        if ((f.scheme != PIT_ADI_PR && f.scheme != PIT_ADI_IE) || (g.scheme != PIT_ADI_PR && g.scheme != PIT_ADI_IE))
+            return PIT_EINVAL;
     } else {
         if (p->M[0] < 3 || p->M[0] > kMaxLine || p->rot != 0.0) return PIT_EINVAL;
         if (p->bc != PIT_DIRICHLET0 && p->bc != PIT_PERIODIC) return PIT_EINVAL;
@@ -649,7 +662,7 @@ hipError_t forced_t(pit_ctx *c, const double *cc, hipStream_t st)
     const long np = c->npts;
     const int N = c->N, m = c->m;
     std::vector<double> w((size_t)N * m);
-    const bool ie = !c->dim2() && c->fine.scheme == SCHEME_IE;
+    const bool ie = c->dim2() ? c->fine.scheme == PIT_ADI_IE : c->fine.scheme == SCHEME_IE;
     for (size_t j = 0; j < w.size(); ++j) w[j] = ie ? c->gt[j + 1] : 0.5 * (c->gt[j] + c->gt[j + 1]);
     hipError_t e;
     if ((e = hipMemcpy(c->gw(), w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
@@ -910,8 +923,9 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         const bool lds_small = !c->fine32() && !(lds_env && lds_env[0] == '0') &&
                                vel_lds_mode(problem->M[0], problem->M[1]) > 0;
         c->vel = velocity || lds_small;
-        if (c->vel && (!vel_tables(*c, 0.5 * c->DT / m, c->vtf, c->vf_xdi, c->vf_ydi) ||
-                       !vel_tables(*c, 0.5 * c->DT / coarse.substeps, c->vtc, c->vc_xdi, c->vc_ydi))) {
+        if (c->vel && (!vel_tables(*c, adi_theta(*c, true), fine.scheme == PIT_ADI_PR, c->vtf, c->vf_xdi, c->vf_ydi) ||
+                       !vel_tables(*c, adi_theta(*c, false), coarse.scheme == PIT_ADI_PR, c->vtc, c->vc_xdi,
+                                   c->vc_ydi))) {
             delete c;
             return PIT_EINVAL;
         }

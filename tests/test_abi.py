@@ -218,6 +218,17 @@ def test_small_fp64_2d_problems_take_the_lds_kernels(monkeypatch):
     assert shape(small)[0] >= 64
 
 
+def test_backward_euler_splitting_is_2d_only():
+    """PIT_ADI_IE (3) is a 2D scheme, as fine or coarse; 1D takes IE/CN."""
+    for p in (wl.F2.with_(fine=wl.ADI_IE, coarse=wl.ADI_IE, N=4, m=2), wl.F2.with_(coarse=wl.ADI_IE, N=4, m=2)):
+        rc, h = create(p)
+        assert rc == P.OK
+        P.load().pit_destroy(h)
+    assert create(wl.C1.with_(fine=wl.ADI_IE, N=4, m=2))[0] == P.EINVAL
+    assert create(wl.C1.with_(coarse=wl.ADI_IE, N=4, m=2))[0] == P.EINVAL
+    assert create(wl.F2.with_(fine=wl.IE, N=4, m=2))[0] == P.EINVAL
+
+
 def test_batch_and_server_validate_on_the_host():
     lib = P.load()
     h = ct.c_void_p()
