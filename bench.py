@@ -34,10 +34,11 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_vec_TFs": 78.6, "fp32_vec_TFs": 157.3, "cus": 2
 # Sherman-Morrison correction 2 (periodic), CN combination 2u - A^{-1}... 2.
 FLOPS_PER_CU = {("ie", 0): 5, ("ie", 1): 7, ("cn", 0): 7, ("cn", 1): 9}
 
-# Algorithmic FLOPs per point of one PR-ADI step with a velocity field, per
-# half-step: explicit part u + lo u_m + di u + up u_q (6), forward
-# elimination (r - a d) w (3), back substitution d - c x (2).
-VEL_FLOPS_PER_POINT_STEP = 2 * (6 + 3 + 2)
+# Algorithmic FLOPs per point of one 2D step on per-line tables, per
+# half-step: explicit part u + lo u_m + di u + up u_q (6, PR-ADI only; the
+# backward-Euler splitting has none), forward elimination (r - a d) w (3),
+# back substitution d - c x (2).
+VEL_FLOPS_PER_POINT_STEP = {"adi": 2 * (6 + 3 + 2), "adi_ie": 2 * (3 + 2)}
 
 
 def log(msg):
@@ -161,13 +162,15 @@ def algorithmic_bytes(p, prec, unit):
     return (p.N - 1) * p.c * p.npts * 40
 
 
-def workload(name, prec, side=None):
+def workload(name, prec, side=None, time_scheme="pr"):
     from paper_2203_10148_amd import workloads as wl
 
     p = {"c1": wl.C1, "c2": wl.C2, "c3": wl.C3, "f2": wl.F2, "f3d": wl.F3_DIFF, "f3r": wl.F3_DR}[name]
     if side and p.dim == 2 and side != p.M[0]:
         # the same 2D recipe on a larger square (its working set beyond the 256 MiB MALL)
         p = p.with_(M=(side, side), name=f"{p.name}_{side}")
+    if time_scheme == "ie" and p.dim == 2:
+        p = p.with_(fine=wl.ADI_IE, coarse=wl.ADI_IE, name=f"{p.name}_ie")
     if prec is None:
         return p
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
@@ -207,6 +210,9 @@ def main():
                     help="c1-c3, f2, f3d (diffusion), f3r (diffusion-reaction): one solve per step; c4: the "
                          "64-instance batch per step; c5: a served Poisson stream (one pass of --requests "
                          "requests)")
+    ap.add_argument("--time-scheme", choices=["pr", "ie"], default="pr",
+                    help="2D workloads: Peaceman-Rachford ADI (pr) or the backward-Euler splitting (ie, the "
+                         "paper's time marching) as fine and coarse stepper")
     ap.add_argument("--paper-cases", action="store_true",
                     help="the experiment of Sec. 4: the diffusion, diffusion-reaction and rotating "
                          "advection-diffusion-reaction cases on 4..64 slices, PiTSBiCG against parareal by "
@@ -241,7 +247,7 @@ def main():
         summarize_stats(*args.stats_summary)
         return
     if args.pmc_summary:
-        p = workload(args.workload, args.prec, args.side)
+        p = workload(args.workload, args.prec, args.side, args.time_scheme)
         from paper_2203_10148_amd import workloads as wl
         prec = "f32" if p.prec == wl.F32 else "f64"
         fc, wc, out, unit, rx, units, cf, cw = args.pmc_summary
@@ -266,7 +272,7 @@ def main():
         return bench_batch(args, dev)
     if args.workload == "c5":
         return bench_serve(args, dev)
-    p = workload(args.workload, args.prec, args.side)
+    p = workload(args.workload, args.prec, args.side, args.time_scheme)
     args.prec = "f32" if p.prec == wl.F32 else "f64"
     u0h = wl.u0_for(p)
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
@@ -351,9 +357,10 @@ def main():
     elif ctx.kernel_shape()[0] == 1 and ctx.kernel_shape()[2] > 0:
         # 2D on per-line tables with the slices held in LDS for all their steps:
         # HBM sees each slice once per launch, the steps are FP64 arithmetic.
-        scheme, cscheme = "adi", "adi"
-        fl_fine = p.cells_per_apply * VEL_FLOPS_PER_POINT_STEP
-        fl_coarse = (p.N - 1) * p.c * p.npts * VEL_FLOPS_PER_POINT_STEP + (p.N - 1) * p.npts
+        scheme = "adi_ie" if p.fine == wl.ADI_IE else "adi"
+        cscheme = "adi_ie" if p.coarse == wl.ADI_IE else "adi"
+        fl_fine = p.cells_per_apply * VEL_FLOPS_PER_POINT_STEP[scheme]
+        fl_coarse = (p.N - 1) * p.c * p.npts * VEL_FLOPS_PER_POINT_STEP[cscheme] + (p.N - 1) * p.npts
         kern = {
             "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "alu",
                            "work_per_launch": fl_fine, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
@@ -363,7 +370,8 @@ def main():
     else:
         # 2D: the fine apply streams the field through HBM twice per PR-ADI step
         # (x half step: read + write, y half step: read + write).
-        scheme, cscheme = "adi", "adi"
+        scheme = "adi_ie" if p.fine == wl.ADI_IE else "adi"
+        cscheme = "adi_ie" if p.coarse == wl.ADI_IE else "adi"
         by_fine = algorithmic_bytes(p, args.prec, "fine_apply")
         by_coarse = algorithmic_bytes(p, args.prec, "coarse_sweep")
         kern = {
@@ -481,6 +489,8 @@ def bench_paper_cases(args, dev):
 
     rows = []
     for case in wl.PAPER_CASES:
+        if args.time_scheme == "ie":
+            case = case.with_(fine=wl.ADI_IE, coarse=wl.ADI_IE)
         for N in wl.PAPER_SLICES:
             p = wl.paper_case(case, N)
             ctx = P.Context(p, device=dev)
@@ -501,7 +511,9 @@ def bench_paper_cases(args, dev):
             del ctx
     print(json.dumps({"metric": "preconditioned products to tol, PiTSBiCG vs parareal (Sec. 4)",
                       "unit": "products", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
-                      "data": "synthetic", "tol": wl.F2.tol, "rows": rows}), flush=True)
+                      "data": "synthetic", "tol": wl.F2.tol,
+                      "time_scheme": "backward-Euler splitting" if args.time_scheme == "ie" else "PR-ADI",
+                      "rows": rows}), flush=True)
 
 
 def bench_batch(args, dev):
