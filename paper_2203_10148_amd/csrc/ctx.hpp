@@ -111,7 +111,8 @@ struct pit_ctx {
     VelTab vtab(bool fine_step) const
     {
         const double *b = reinterpret_cast<const double *>(ws + (fine_step ? off_vtf : off_vtc));
-        return vel_tab_view(b, pb.M[0], pb.M[1], fine_step ? vf_xdi : vc_xdi, fine_step ? vf_ydi : vc_ydi);
+        return vel_tab_view(b, pb.M[0], pb.M[1], fine_step ? vf_xdi : vc_xdi, fine_step ? vf_ydi : vc_ydi,
+                            (fine_step ? fine.scheme : coarse.scheme) == PIT_ADI_PR);
     }
     double *wbuf() const { return reinterpret_cast<double *>(ws + off_wbuf); }
     double *vwk() const { return reinterpret_cast<double *>(ws + off_vwk); }

@@ -528,12 +528,13 @@ hipError_t apply_2dv(const pit_ctx *c, const double *lam, double *y, int raw, in
     double *ub = reinterpret_cast<double *>(c->ws + c->off_ubuf), *sb = reinterpret_cast<double *>(c->ws + c->off_sbuf);
     for (int step = 0; step < c->m; ++step) {
         const bool first = step == 0, fin = step == c->m - 1;
-        if ((e = launch_vel_x(t, first ? lam : ub, first ? in_off : 0, sb, 0, ns, Mx, My, 1, st)) != hipSuccess)
+        if ((e = launch_vel_x(t, first ? lam : ub, first ? in_off : 0, sb, 0, ns, Mx, My, t.expl, st)) != hipSuccess)
             return e;
         if (fin)
-            e = launch_vel_y(t, sb, 0, y, out_off, raw ? nullptr : lam, out_off, -1.0, c->wbuf(), ns, Mx, My, 1, st);
+            e = launch_vel_y(t, sb, 0, y, out_off, raw ? nullptr : lam, out_off, -1.0, c->wbuf(), ns, Mx, My, t.expl,
+                             st);
         else
-            e = launch_vel_y(t, sb, 0, ub, 0, nullptr, 0, 0.0, c->wbuf(), ns, Mx, My, 1, st);
+            e = launch_vel_y(t, sb, 0, ub, 0, nullptr, 0, 0.0, c->wbuf(), ns, Mx, My, t.expl, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -552,12 +553,12 @@ hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t s
     const int cs = c->coarse.substeps;
     for (int n = 1; n < c->N; ++n) {
         for (int s = 0; s < cs; ++s) {
-            if ((e = launch_vel_x(t, s == 0 ? z : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, st)) != hipSuccess)
+            if ((e = launch_vel_x(t, s == 0 ? z : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, t.expl, st)) != hipSuccess)
                 return e;
             if (s == cs - 1)
-                e = launch_vel_y(t, ta, 0, z, n, v, n, 1.0, c->vwk(), 1, Mx, My, 1, st);
+                e = launch_vel_y(t, ta, 0, z, n, v, n, 1.0, c->vwk(), 1, Mx, My, t.expl, st);
             else
-                e = launch_vel_y(t, ta, 0, tb, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 1, st);
+                e = launch_vel_y(t, ta, 0, tb, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, t.expl, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -635,8 +636,8 @@ hipError_t step_all(pit_ctx *c, const double *in, double *out, double *tmp, hipS
     if (c->vel) {
         const VelTab vt = c->vtab(true);
         if (vel_lds(c)) return launch_vel_apply_lds(vt, in, 0, out, 0, nullptr, 0, 0.0, N, 1, Mx, My, st);
-        if ((e = launch_vel_x(vt, in, 0, tmp, 0, N, Mx, My, 1, st)) != hipSuccess) return e;
-        return launch_vel_y(vt, tmp, 0, out, 0, nullptr, 0, 0.0, c->wbuf(), N, Mx, My, 1, st);
+        if ((e = launch_vel_x(vt, in, 0, tmp, 0, N, Mx, My, vt.expl, st)) != hipSuccess) return e;
+        return launch_vel_y(vt, tmp, 0, out, 0, nullptr, 0, 0.0, c->wbuf(), N, Mx, My, vt.expl, st);
     }
     LineTab<double> tx =
         line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_axf), 64 * c->ash.xw, c->ash.cx);
@@ -733,8 +734,8 @@ hipError_t compute_forced(pit_ctx *c, hipStream_t st)
         if (c->src_t()) return forced_t(c, cc, st);
         FH(launch_copy(h, cc, np, st));
         for (int k = 1; k < c->m; ++k) {
-            FH(launch_vel_x(vt, h, 0, t, 0, 1, Mx, My, 1, st));
-            FH(launch_vel_y(vt, t, 0, g, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, 1, st));
+            FH(launch_vel_x(vt, h, 0, t, 0, 1, Mx, My, vt.expl, st));
+            FH(launch_vel_y(vt, t, 0, g, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, vt.expl, st));
             FH(launch_axpby(h, g, 1.0, cc, 1.0, np, st));
         }
         FH(launch_copy(c->bfn(), h, np, st));

@@ -164,9 +164,10 @@ struct VelView {
 
 // One line of n points: the explicit part at point e is
 // c + lo[e] cm + di c + up[e] cq (cp, mp, qp the line and its two neighbour
-// lines, contiguous), then the Thomas passes with pivots w, cc (table
-// stride ts); the forward values go to fw (contiguous), the solution to o
-// at stride fo.
+// lines, contiguous; EXPL false: just c), then the Thomas passes with pivots
+// w, cc (table stride ts); the forward values go to fw (contiguous), the
+// solution to o at stride fo.
+template <bool EXPL>
 __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const double *__restrict__ mp,
                                          const double *__restrict__ qp, double *__restrict__ fw,
                                          double *__restrict__ o, const double *__restrict__ w,
@@ -177,7 +178,8 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
 #pragma unroll 8
     for (int e = 0; e < n; ++e) {
         const double c0 = cp[e];
-        const double r = c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e];
+        double r = c0;
+        if constexpr (EXPL) r = c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e];
         d = (r - a * d) * w[e * ts];
         fw[e] = d;
     }
@@ -190,6 +192,7 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
     }
 }
 
+template <bool EXPL>
 __device__ __forceinline__ void vel_step_lds(const VelView &v, double xdi, double ydi, double *U, double *S,
                                              double *W, int Mx, int My, int P, int Q)
 {
@@ -203,14 +206,14 @@ __device__ __forceinline__ void vel_step_lds(const VelView &v, double xdi, doubl
     if (k < My) {  // row k: S = X^{-1} (I + th Ly) U
         const int j = k;
         const int r0 = (j + 1) * P + 1;
-        vel_walk(U + r0, U + r0 - P, U + r0 + P, W + r0, S + Q + j + 1, v.xw + j * v.tp, v.xc + j * v.tp, v.ylo,
+        vel_walk<EXPL>(U + r0, U + r0 - P, U + r0 + P, W + r0, S + Q + j + 1, v.xw + j * v.tp, v.xc + j * v.tp, v.ylo,
                  v.yup, v.xa[j], ydi, Mx, Q, 1);
     }
     __syncthreads();
     if (k < Mx) {  // column k: U = Y^{-1} (I + th Lx) S
         const int i = k;
         const int c0 = (i + 1) * Q + 1;
-        vel_walk(S + c0, S + c0 - Q, S + c0 + Q, W + c0, U + P + i + 1, v.yw + i * v.yq, v.yc + i * v.yq, v.xlo,
+        vel_walk<EXPL>(S + c0, S + c0 - Q, S + c0 + Q, W + c0, U + P + i + 1, v.yw + i * v.yq, v.yc + i * v.yq, v.xlo,
                  v.xup, v.ya[i], xdi, My, P, v.ys);
     }
     __syncthreads();
@@ -263,7 +266,7 @@ __device__ __forceinline__ void vel_load_field(double *U, double *S, const doubl
 
 // All-at-once apply on `ns` slices: out_{s+out_off} = base_{s+out_off} + sign F(in_{s+in_off})
 // (base NULL: F(in)), F = m steps, one workgroup per slice.
-template <bool TAB>
+template <bool TAB, bool EXPL>
 __global__ __launch_bounds__(kVelLdsLines) void k_vel_apply_lds(VelTab t, const double *__restrict__ in, long in_off,
                                                                  double *out, long out_off, const double *base,
                                                                  long base_off, double sign, int m, int Mx, int My)
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_apply_lds(VelTab t, const 
     const int np = Mx * My;
     vel_load_field(U, S, in + (in_off + blockIdx.x) * np, Mx, My, L);
     __syncthreads();
-    for (int s = 0; s < m; ++s) vel_step_lds(v, t.xdi, t.ydi, U, S, W, Mx, My, L.P, L.Q);
+    for (int s = 0; s < m; ++s) vel_step_lds<EXPL>(v, t.xdi, t.ydi, U, S, W, Mx, My, L.P, L.Q);
     double *o = out + (out_off + blockIdx.x) * np;
     const double *b = base ? base + (base_off + blockIdx.x) * np : nullptr;
     for (int q = threadIdx.x; q < np; q += blockDim.x) {
@@ -291,7 +294,7 @@ constexpr int kVelPre = 16;
 // workgroup marching the slices; v == z is allowed.  Each slice first issues
 // the loads of v_n and the stores of z_{n-1} (from LDS), then walks: both
 // transfers overlap the walks.
-template <bool TAB>
+template <bool TAB, bool EXPL>
 __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const double *v, double *z, int N, int c,
                                                                  int Mx, int My)
 {
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const 
 #pragma unroll
         for (int k = 0; k < kVelPre; ++k) pre[k] = vn[min(tid + k * bd, np - 1)];
         if (n > 1) store(z + (long)(n - 1) * np);
-        for (int s = 0; s < c; ++s) vel_step_lds(w, t.xdi, t.ydi, U, S, W, Mx, My, P, L.Q);
+        for (int s = 0; s < c; ++s) vel_step_lds<EXPL>(w, t.xdi, t.ydi, U, S, W, Mx, My, P, L.Q);
 #pragma unroll
         for (int k = 0; k < kVelPre; ++k)
             if (tid + k * bd < np) U[at[k]] += pre[k];
@@ -356,19 +359,42 @@ int vel_lds_mode(int Mx, int My)
 }
 
 // Raise the dynamic LDS limit of a kernel once.
-template <bool TAB>
+template <bool TAB, bool EXPL>
 static hipError_t apply_lds_attr()
 {
-    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vel_apply_lds<TAB>),
+    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vel_apply_lds<TAB, EXPL>),
                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kVelLdsMax);
     return e;
 }
-template <bool TAB>
+template <bool TAB, bool EXPL>
 static hipError_t sweep_lds_attr()
 {
-    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vel_sweep_lds<TAB>),
+    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_vel_sweep_lds<TAB, EXPL>),
                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kVelLdsMax);
     return e;
+}
+
+template <bool TAB, bool EXPL>
+static hipError_t apply_lds(const VelTab &t, const double *in, long in_off, double *out, long out_off,
+                            const double *base, long base_off, double sign, int ns, int m, int Mx, int My,
+                            hipStream_t st)
+{
+    const hipError_t e = apply_lds_attr<TAB, EXPL>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_vel_apply_lds<TAB, EXPL>), dim3(ns), dim3(vel_lds_threads(Mx, My)),
+                       vel_lds_bytes(Mx, My, TAB), st, t, in, in_off, out, out_off, base, base_off, sign, m, Mx, My);
+    return hipGetLastError();
+}
+
+template <bool TAB, bool EXPL>
+static hipError_t sweep_lds(const VelTab &t, const double *v, double *z, int N, int c, int Mx, int My,
+                            hipStream_t st)
+{
+    const hipError_t e = sweep_lds_attr<TAB, EXPL>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_vel_sweep_lds<TAB, EXPL>), dim3(1), dim3(vel_lds_threads(Mx, My)),
+                       vel_lds_bytes(Mx, My, TAB), st, t, v, z, N, c, Mx, My);
+    return hipGetLastError();
 }
 
 hipError_t launch_vel_apply_lds(const VelTab &t, const double *in, long in_off, double *out, long out_off,
@@ -378,18 +404,11 @@ hipError_t launch_vel_apply_lds(const VelTab &t, const double *in, long in_off, 
     if (ns <= 0) return hipSuccess;
     const int mode = vel_lds_mode(Mx, My);
     if (mode == 0) return hipErrorInvalidValue;
-    const bool tab = mode == 2;
-    const hipError_t e = tab ? apply_lds_attr<true>() : apply_lds_attr<false>();
-    if (e != hipSuccess) return e;
-    const dim3 grid(ns), block(vel_lds_threads(Mx, My));
-    const size_t lds = vel_lds_bytes(Mx, My, tab);
-    if (tab)
-        hipLaunchKernelGGL(k_vel_apply_lds<true>, grid, block, lds, st, t, in, in_off, out, out_off, base, base_off,
-                           sign, m, Mx, My);
-    else
-        hipLaunchKernelGGL(k_vel_apply_lds<false>, grid, block, lds, st, t, in, in_off, out, out_off, base, base_off,
-                           sign, m, Mx, My);
-    return hipGetLastError();
+    if (mode == 2)
+        return t.expl ? apply_lds<true, true>(t, in, in_off, out, out_off, base, base_off, sign, ns, m, Mx, My, st)
+                      : apply_lds<true, false>(t, in, in_off, out, out_off, base, base_off, sign, ns, m, Mx, My, st);
+    return t.expl ? apply_lds<false, true>(t, in, in_off, out, out_off, base, base_off, sign, ns, m, Mx, My, st)
+                  : apply_lds<false, false>(t, in, in_off, out, out_off, base, base_off, sign, ns, m, Mx, My, st);
 }
 
 hipError_t launch_vel_sweep_lds(const VelTab &t, const double *v, double *z, int N, int c, int Mx, int My,
@@ -398,14 +417,9 @@ hipError_t launch_vel_sweep_lds(const VelTab &t, const double *v, double *z, int
     if (N <= 0) return hipSuccess;
     const int mode = vel_lds_mode(Mx, My);
     if (mode == 0) return hipErrorInvalidValue;
-    const bool tab = mode == 2;
-    const hipError_t e = tab ? sweep_lds_attr<true>() : sweep_lds_attr<false>();
-    if (e != hipSuccess) return e;
-    const dim3 block(vel_lds_threads(Mx, My));
-    const size_t lds = vel_lds_bytes(Mx, My, tab);
-    if (tab) hipLaunchKernelGGL(k_vel_sweep_lds<true>, dim3(1), block, lds, st, t, v, z, N, c, Mx, My);
-    else hipLaunchKernelGGL(k_vel_sweep_lds<false>, dim3(1), block, lds, st, t, v, z, N, c, Mx, My);
-    return hipGetLastError();
+    if (mode == 2)
+        return t.expl ? sweep_lds<true, true>(t, v, z, N, c, Mx, My, st) : sweep_lds<true, false>(t, v, z, N, c, Mx, My, st);
+    return t.expl ? sweep_lds<false, true>(t, v, z, N, c, Mx, My, st) : sweep_lds<false, false>(t, v, z, N, c, Mx, My, st);
 }
 
 hipError_t launch_vel_x(const VelTab &t, const double *in, long in_off, double *out, long out_off, int ns,

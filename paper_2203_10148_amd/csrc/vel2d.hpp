@@ -23,11 +23,12 @@ struct VelTab {
     const double *xa, *xlo, *xup;         // [My]
     const double *ya, *ylo, *yup;         // [Mx]
     double xdi, ydi;
+    int expl;  // 1: the PR-ADI explicit halves; 0: identity (backward-Euler splitting)
 };
 
 // Doubles of one VelTab in the workspace, and its view.
 inline size_t vel_tab_elems(int Mx, int My) { return 4 * (size_t)Mx * My + 3 * (size_t)My + 3 * (size_t)Mx; }
-inline VelTab vel_tab_view(const double *b, int Mx, int My, double xdi, double ydi)
+inline VelTab vel_tab_view(const double *b, int Mx, int My, double xdi, double ydi, int expl)
 {
     const size_t np = (size_t)Mx * My;
     VelTab t{};
@@ -45,6 +46,7 @@ inline VelTab vel_tab_view(const double *b, int Mx, int My, double xdi, double y
     t.yup = c + 2 * Mx;
     t.xdi = xdi;
     t.ydi = ydi;
+    t.expl = expl;
     return t;
 }
 
