@@ -128,6 +128,9 @@ struct pit_ctx {
     };
     mutable std::vector<Graph> graphs;
     mutable hipStream_t capture = nullptr;
+    // pinned host copy of the reduction results read by pit_solve and
+    // pit_parareal (allocated at the first solve)
+    RedOut *red_pin = nullptr;
     void drop_graphs() const;
     ~pit_ctx();
     bool dim2() const { return pb.dim == 2; }

@@ -803,6 +803,7 @@ pit_ctx::~pit_ctx()
 {
     drop_graphs();
     if (capture) (void)hipStreamDestroy(capture);
+    if (red_pin) (void)hipHostFree(red_pin);
 }
 
 namespace {
@@ -1272,8 +1273,11 @@ struct Solver {
             pr.b[q] = b[q];
         }
         PIT_HIP(launch_seg_dots(pr, nq, c->N, c->ld, c->bps, c->part(), c->w, c->red(), st));
-        PIT_HIP(hipMemcpyAsync(&h, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
+        if (!c->red_pin)
+            PIT_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->red_pin), sizeof(RedOut), hipHostMallocDefault));
+        PIT_HIP(hipMemcpyAsync(c->red_pin, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
         PIT_HIP(hipStreamSynchronize(st));
+        h = *c->red_pin;
         return PIT_OK;
     }
 };
