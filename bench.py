@@ -213,6 +213,10 @@ def main():
     ap.add_argument("--time-scheme", choices=["pr", "ie"], default="pr",
                     help="2D workloads: Peaceman-Rachford ADI (pr) or the backward-Euler splitting (ie, the "
                          "paper's time marching) as fine and coarse stepper")
+    ap.add_argument("--restart-study", action="store_true",
+                    help="Algorithm 1's restart threshold epsilon_0 (|<R, R~>| <= epsilon_0 restarts the shadow "
+                         "residual) swept over C1, C2 and the cases of Sec. 4 at N = 64: iterations, products, "
+                         "restarts and time per value (one JSON line)")
     ap.add_argument("--paper-cases", action="store_true",
                     help="the experiment of Sec. 4: the diffusion, diffusion-reaction and rotating "
                          "advection-diffusion-reaction cases on 4..64 slices, PiTSBiCG against parareal by "
@@ -268,6 +272,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.paper_cases:
         return bench_paper_cases(args, dev)
+    if args.restart_study:
+        return bench_restart_study(args, dev)
     if args.workload == "c4":
         return bench_batch(args, dev)
     if args.workload == "c5":
@@ -514,6 +520,38 @@ def bench_paper_cases(args, dev):
                       "data": "synthetic", "tol": wl.F2.tol,
                       "time_scheme": "backward-Euler splitting" if args.time_scheme == "ie" else "PR-ADI",
                       "rows": rows}), flush=True)
+
+
+def bench_restart_study(args, dev):
+    """Algorithm 1 with the restart threshold epsilon_0 swept (the paper fixes
+    no value): each workload solved to its tolerance from X0 = 0, second of
+    two runs timed."""
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    cases = [wl.C1, wl.C2.with_(prec=wl.F64)]
+    for case in wl.PAPER_CASES:
+        cases.append(case)
+        cases.append(case.with_(fine=wl.ADI_IE, coarse=wl.ADI_IE, name=case.name + "_ie"))
+    eps0 = [1e-30, 1e-14, 1e-12, 1e-10, 1e-8, 1e-6]
+    rows = []
+    for p in cases:
+        ctx = P.Context(p, device=dev)
+        u0 = torch.as_tensor(wl.u0_for(p), dtype=torch.float64, device=dev)
+        X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)
+        for e0 in eps0:
+            for _ in range(2):
+                _, si = ctx.solve(u0, X, tol=p.tol, restart_tol=e0)
+            rows.append({"case": p.name, "tol": p.tol, "eps0": e0, "status": si.status, "iters": si.iters,
+                         "products": si.matvecs, "restarts": si.restarts, "ms": si.ms_total,
+                         "res_norm": si.res_norm})
+            log(f"[bench] {p.name} eps0={e0:g}: status {si.status}, {si.iters} iterations, {si.matvecs} "
+                f"products, {si.restarts} restarts, {si.ms_total:.1f} ms")
+        del ctx
+    print(json.dumps({"metric": "Algorithm 1 against its restart threshold epsilon_0", "n_gpus": 1,
+                      "dtype": "f64", "data": "synthetic", "rows": rows}), flush=True)
 
 
 def bench_batch(args, dev):
