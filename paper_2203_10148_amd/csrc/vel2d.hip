@@ -166,7 +166,9 @@ struct VelView {
 // c + lo[e] cm + di c + up[e] cq (cp, mp, qp the line and its two neighbour
 // lines, contiguous; EXPL false: just c), then the Thomas passes with pivots
 // w, cc (table stride ts); the forward values go to fw (contiguous), the
-// solution to o at stride fo.
+// solution to o at stride fo.  Both passes go in blocks of KB points with two
+// register sets used in turn: the loads of one block are issued before the
+// recurrence of the other runs, so their latency is hidden behind it.
 template <bool EXPL>
 __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const double *__restrict__ mp,
                                          const double *__restrict__ qp, double *__restrict__ fw,
@@ -174,21 +176,79 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
                                          const double *__restrict__ cc, const double *__restrict__ lo,
                                          const double *__restrict__ up, double a, double di, int n, int fo, int ts)
 {
+    constexpr int KB = EXPL ? 4 : 8;
+    // ---- forward: r_e (explicit part), d_e = (r_e - a d_{e-1}) w_e
     double d = 0.0;
-#pragma unroll 8
-    for (int e = 0; e < n; ++e) {
-        const double c0 = cp[e];
-        double r = c0;
-        if constexpr (EXPL) r = c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e];
-        d = (r - a * d) * w[e * ts];
-        fw[e] = d;
+    {
+        double ra[KB], wa[KB], rb[KB], wb[KB];
+        // block at e0 into (r, wv): the explicit part needs only loads
+        auto load = [&](int e0, double (&r)[KB], double (&wv)[KB]) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int e = e0 + k;
+                const double c0 = cp[e];
+                r[k] = EXPL ? c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e] : c0;
+                wv[k] = w[e * ts];
+            }
+        };
+        auto run = [&](int e0, const double (&r)[KB], const double (&wv)[KB]) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                d = (r[k] - a * d) * wv[k];
+                fw[e0 + k] = d;
+            }
+        };
+        const int nb = n / KB;
+        if (nb > 0) load(0, ra, wa);
+        int b = 0;
+        for (; b + 1 < nb; b += 2) {
+            load((b + 1) * KB, rb, wb);
+            run(b * KB, ra, wa);
+            if (b + 2 < nb) load((b + 2) * KB, ra, wa);
+            run((b + 1) * KB, rb, wb);
+        }
+        if (b < nb) run(b * KB, ra, wa);
+        for (int e = nb * KB; e < n; ++e) {
+            const double c0 = cp[e];
+            const double r = EXPL ? c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e] : c0;
+            d = (r - a * d) * w[e * ts];
+            fw[e] = d;
+        }
     }
+    // ---- backward over e = n-2 .. 0: x_e = d_e - cc_e x_{e+1}
     double x = d;
     o[(n - 1) * fo] = x;
-#pragma unroll 8
-    for (int e = n - 2; e >= 0; --e) {
-        x = fw[e] - cc[e * ts] * x;
-        o[e * fo] = x;
+    {
+        constexpr int KBB = 8;
+        double fa[KBB], ca[KBB], fb[KBB], cb[KBB];
+        auto load = [&](int e0, double (&f)[KBB], double (&cv)[KBB]) {
+#pragma unroll
+            for (int k = 0; k < KBB; ++k) {
+                f[k] = fw[e0 - k];
+                cv[k] = cc[(e0 - k) * ts];
+            }
+        };
+        auto run = [&](int e0, const double (&f)[KBB], const double (&cv)[KBB]) {
+#pragma unroll
+            for (int k = 0; k < KBB; ++k) {
+                x = f[k] - cv[k] * x;
+                o[(e0 - k) * fo] = x;
+            }
+        };
+        const int nb = (n - 1) / KBB;
+        if (nb > 0) load(n - 2, fa, ca);
+        int b = 0;
+        for (; b + 1 < nb; b += 2) {
+            load(n - 2 - (b + 1) * KBB, fb, cb);
+            run(n - 2 - b * KBB, fa, ca);
+            if (b + 2 < nb) load(n - 2 - (b + 2) * KBB, fa, ca);
+            run(n - 2 - (b + 1) * KBB, fb, cb);
+        }
+        if (b < nb) run(n - 2 - b * KBB, fa, ca);
+        for (int e = n - 2 - nb * KBB; e >= 0; --e) {
+            x = fw[e] - cc[e * ts] * x;
+            o[e * fo] = x;
+        }
     }
 }
 
