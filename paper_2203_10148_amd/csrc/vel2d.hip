@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_apply_lds(VelTab t, const 
 }
 
 // Values of v_n each thread loads ahead of the walks of slice n.
-constexpr int kVelPre = 16;
+constexpr int kVelPre = 8;
 
 // Coarse sweep z_0 = v_0, z_n = v_n + G(z_{n-1}) (G = c steps) by one
 // workgroup marching the slices; v == z is allowed.  Each slice first issues
@@ -411,6 +411,10 @@ static int vel_lds_threads(int Mx, int My)
     return t < 256 ? 256 : t;
 }
 
+// The sweep adds v_n and stores z_n every slice: all kVelLdsLines threads
+// share that work (the walks use one thread per line).
+static int vel_sweep_threads(int Mx, int My) { return kVelLdsLines > vel_lds_threads(Mx, My) ? kVelLdsLines : vel_lds_threads(Mx, My); }
+
 int vel_lds_mode(int Mx, int My)
 {
     if (Mx < 1 || My < 1 || (Mx > My ? Mx : My) > kVelLdsLines) return 0;
@@ -452,7 +456,7 @@ static hipError_t sweep_lds(const VelTab &t, const double *v, double *z, int N, 
 {
     const hipError_t e = sweep_lds_attr<TAB, EXPL>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vel_sweep_lds<TAB, EXPL>), dim3(1), dim3(vel_lds_threads(Mx, My)),
+    hipLaunchKernelGGL((k_vel_sweep_lds<TAB, EXPL>), dim3(1), dim3(vel_sweep_threads(Mx, My)),
                        vel_lds_bytes(Mx, My, TAB), st, t, v, z, N, c, Mx, My);
     return hipGetLastError();
 }
