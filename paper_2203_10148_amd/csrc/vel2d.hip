@@ -176,7 +176,7 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
                                          const double *__restrict__ cc, const double *__restrict__ lo,
                                          const double *__restrict__ up, double a, double di, int n, int fo, int ts)
 {
-    constexpr int KB = EXPL ? 4 : 8;
+    constexpr int KB = 8;
     // ---- forward: r_e (explicit part), d_e = (r_e - a d_{e-1}) w_e
     double d = 0.0;
     {
