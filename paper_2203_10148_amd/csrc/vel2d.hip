@@ -162,33 +162,27 @@ struct VelView {
     int tp, yq, ys;
 };
 
-// One line of n points: the explicit part at point e is
-// c + lo[e] cm + di c + up[e] cq (cp, mp, qp the line and its two neighbour
-// lines, contiguous; EXPL false: just c), then the Thomas passes with pivots
-// w, cc (table stride ts); the forward values go to fw (contiguous), the
-// solution to o at stride fo.  Both passes go in blocks of KB points with two
-// register sets used in turn: the loads of one block are issued before the
-// recurrence of the other runs, so their latency is hidden behind it.
-template <bool EXPL>
-__device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const double *__restrict__ mp,
-                                         const double *__restrict__ qp, double *__restrict__ fw,
-                                         double *__restrict__ o, const double *__restrict__ w,
-                                         const double *__restrict__ cc, const double *__restrict__ lo,
-                                         const double *__restrict__ up, double a, double di, int n, int fo, int ts)
+// One line of n points: the Thomas passes with pivots w, cc (table stride
+// ts) on the right-hand side rp (contiguous); the forward values go to fw
+// (contiguous; fw may be rp itself), the solution to o at stride fo.  Both
+// passes go in blocks of KB points with two register sets used in turn: the
+// loads of one block are issued before the recurrence of the other runs, so
+// their latency is hidden behind it.  In that order every right-hand-side
+// value is read a block before its forward value overwrites it.
+__device__ __forceinline__ void vel_walk(const double *rp, double *fw, double *__restrict__ o,
+                                         const double *__restrict__ w, const double *__restrict__ cc, double a,
+                                         int n, int fo, int ts)
 {
     constexpr int KB = 8;
-    // ---- forward: r_e (explicit part), d_e = (r_e - a d_{e-1}) w_e
+    // ---- forward: d_e = (r_e - a d_{e-1}) w_e
     double d = 0.0;
     {
         double ra[KB], wa[KB], rb[KB], wb[KB];
-        // block at e0 into (r, wv): the explicit part needs only loads
         auto load = [&](int e0, double (&r)[KB], double (&wv)[KB]) {
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
-                const int e = e0 + k;
-                const double c0 = cp[e];
-                r[k] = EXPL ? c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e] : c0;
-                wv[k] = w[e * ts];
+                r[k] = rp[e0 + k];
+                wv[k] = w[(e0 + k) * ts];
             }
         };
         auto run = [&](int e0, const double (&r)[KB], const double (&wv)[KB]) {
@@ -209,9 +203,7 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
         }
         if (b < nb) run(b * KB, ra, wa);
         for (int e = nb * KB; e < n; ++e) {
-            const double c0 = cp[e];
-            const double r = EXPL ? c0 + lo[e] * mp[e] + di * c0 + up[e] * qp[e] : c0;
-            d = (r - a * d) * w[e * ts];
+            d = (rp[e] - a * d) * w[e * ts];
             fw[e] = d;
         }
     }
@@ -219,39 +211,73 @@ __device__ __forceinline__ void vel_walk(const double *__restrict__ cp, const do
     double x = d;
     o[(n - 1) * fo] = x;
     {
-        constexpr int KBB = 8;
-        double fa[KBB], ca[KBB], fb[KBB], cb[KBB];
-        auto load = [&](int e0, double (&f)[KBB], double (&cv)[KBB]) {
+        double fa[KB], ca[KB], fb[KB], cb[KB];
+        auto load = [&](int e0, double (&f)[KB], double (&cv)[KB]) {
 #pragma unroll
-            for (int k = 0; k < KBB; ++k) {
+            for (int k = 0; k < KB; ++k) {
                 f[k] = fw[e0 - k];
                 cv[k] = cc[(e0 - k) * ts];
             }
         };
-        auto run = [&](int e0, const double (&f)[KBB], const double (&cv)[KBB]) {
+        auto run = [&](int e0, const double (&f)[KB], const double (&cv)[KB]) {
 #pragma unroll
-            for (int k = 0; k < KBB; ++k) {
+            for (int k = 0; k < KB; ++k) {
                 x = f[k] - cv[k] * x;
                 o[(e0 - k) * fo] = x;
             }
         };
-        const int nb = (n - 1) / KBB;
+        const int nb = (n - 1) / KB;
         if (nb > 0) load(n - 2, fa, ca);
         int b = 0;
         for (; b + 1 < nb; b += 2) {
-            load(n - 2 - (b + 1) * KBB, fb, cb);
-            run(n - 2 - b * KBB, fa, ca);
-            if (b + 2 < nb) load(n - 2 - (b + 2) * KBB, fa, ca);
-            run(n - 2 - (b + 1) * KBB, fb, cb);
+            load(n - 2 - (b + 1) * KB, fb, cb);
+            run(n - 2 - b * KB, fa, ca);
+            if (b + 2 < nb) load(n - 2 - (b + 2) * KB, fa, ca);
+            run(n - 2 - (b + 1) * KB, fb, cb);
         }
-        if (b < nb) run(n - 2 - b * KBB, fa, ca);
-        for (int e = n - 2 - nb * KBB; e >= 0; --e) {
+        if (b < nb) run(n - 2 - b * KB, fa, ca);
+        for (int e = n - 2 - nb * KB; e >= 0; --e) {
             x = fw[e] - cc[e * ts] * x;
             o[e * fo] = x;
         }
     }
 }
 
+// The explicit parts of a PR-ADI step, by all threads (wavefronts over the
+// lines, lanes along them), into W in the layout the next walk reads:
+//   x half-step, row-major:  W(i, j) = U + ylo[i] U(i, j-1) + ydi U + yup[i] U(i, j+1)
+//   y half-step, transposed: W(i, j) = S + xlo[j] S(i-1, j) + xdi S + xup[j] S(i+1, j)
+// (the ghost rows of U and S supply the zeros outside).
+__device__ __forceinline__ void vel_rhs_x(const VelView &v, double ydi, const double *__restrict__ U,
+                                          double *__restrict__ W, int Mx, int My, int P)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll 2
+    for (int j = threadIdx.x >> 6; j < My; j += nw)
+        for (int i = lane; i < Mx; i += 64) {
+            const int l = (j + 1) * P + i + 1;
+            const double c0 = U[l];
+            W[l] = c0 + v.ylo[i] * U[l - P] + ydi * c0 + v.yup[i] * U[l + P];
+        }
+}
+
+__device__ __forceinline__ void vel_rhs_y(const VelView &v, double xdi, const double *__restrict__ S,
+                                          double *__restrict__ W, int Mx, int My, int Q)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll 2
+    for (int i = threadIdx.x >> 6; i < Mx; i += nw)
+        for (int j = lane; j < My; j += 64) {
+            const int l = (i + 1) * Q + j + 1;
+            const double c0 = S[l];
+            W[l] = c0 + v.xlo[j] * S[l - Q] + xdi * c0 + v.xup[j] * S[l + Q];
+        }
+}
+
+// One step: x half-step (row threads: the right-hand side -> S), barrier,
+// y half-step (column threads: -> U), barrier.  EXPL: the PR-ADI explicit
+// parts go first into W (a parallel pass and a barrier each) and the walks
+// solve in place on W; else the walks read U and S directly.
 template <bool EXPL>
 __device__ __forceinline__ void vel_step_lds(const VelView &v, double xdi, double ydi, double *U, double *S,
                                              double *W, int Mx, int My, int P, int Q)
@@ -263,18 +289,26 @@ __device__ __forceinline__ void vel_step_lds(const VelView &v, double xdi, doubl
     asm volatile("" : "+v"(k));
     asm volatile("" : "+s"(P));
     asm volatile("" : "+s"(Q));
+    if constexpr (EXPL) {
+        vel_rhs_x(v, ydi, U, W, Mx, My, P);
+        __syncthreads();
+    }
     if (k < My) {  // row k: S = X^{-1} (I + th Ly) U
         const int j = k;
         const int r0 = (j + 1) * P + 1;
-        vel_walk<EXPL>(U + r0, U + r0 - P, U + r0 + P, W + r0, S + Q + j + 1, v.xw + j * v.tp, v.xc + j * v.tp, v.ylo,
-                 v.yup, v.xa[j], ydi, Mx, Q, 1);
+        vel_walk(EXPL ? W + r0 : U + r0, W + r0, S + Q + j + 1, v.xw + j * v.tp, v.xc + j * v.tp, v.xa[j], Mx, Q,
+                 1);
     }
     __syncthreads();
+    if constexpr (EXPL) {
+        vel_rhs_y(v, xdi, S, W, Mx, My, Q);
+        __syncthreads();
+    }
     if (k < Mx) {  // column k: U = Y^{-1} (I + th Lx) S
         const int i = k;
         const int c0 = (i + 1) * Q + 1;
-        vel_walk<EXPL>(S + c0, S + c0 - Q, S + c0 + Q, W + c0, U + P + i + 1, v.yw + i * v.yq, v.yc + i * v.yq, v.xlo,
-                 v.xup, v.ya[i], xdi, My, P, v.ys);
+        vel_walk(EXPL ? W + c0 : S + c0, W + c0, U + P + i + 1, v.yw + i * v.yq, v.yc + i * v.yq, v.ya[i], My, P,
+                 v.ys);
     }
     __syncthreads();
 }
@@ -411,9 +445,13 @@ static int vel_lds_threads(int Mx, int My)
     return t < 256 ? 256 : t;
 }
 
-// The sweep adds v_n and stores z_n every slice: all kVelLdsLines threads
+// The sweep adds v_n and stores z_n every slice, and a PR-ADI step has its
+// explicit parts computed by all threads: there all kVelLdsLines threads
 // share that work (the walks use one thread per line).
-static int vel_sweep_threads(int Mx, int My) { return kVelLdsLines > vel_lds_threads(Mx, My) ? kVelLdsLines : vel_lds_threads(Mx, My); }
+static int vel_wide_threads(int Mx, int My)
+{
+    return kVelLdsLines > vel_lds_threads(Mx, My) ? kVelLdsLines : vel_lds_threads(Mx, My);
+}
 
 int vel_lds_mode(int Mx, int My)
 {
@@ -445,7 +483,7 @@ static hipError_t apply_lds(const VelTab &t, const double *in, long in_off, doub
 {
     const hipError_t e = apply_lds_attr<TAB, EXPL>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vel_apply_lds<TAB, EXPL>), dim3(ns), dim3(vel_lds_threads(Mx, My)),
+    hipLaunchKernelGGL((k_vel_apply_lds<TAB, EXPL>), dim3(ns), dim3(EXPL ? vel_wide_threads(Mx, My) : vel_lds_threads(Mx, My)),
                        vel_lds_bytes(Mx, My, TAB), st, t, in, in_off, out, out_off, base, base_off, sign, m, Mx, My);
     return hipGetLastError();
 }
@@ -456,7 +494,7 @@ static hipError_t sweep_lds(const VelTab &t, const double *v, double *z, int N, 
 {
     const hipError_t e = sweep_lds_attr<TAB, EXPL>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_vel_sweep_lds<TAB, EXPL>), dim3(1), dim3(vel_sweep_threads(Mx, My)),
+    hipLaunchKernelGGL((k_vel_sweep_lds<TAB, EXPL>), dim3(1), dim3(vel_wide_threads(Mx, My)),
                        vel_lds_bytes(Mx, My, TAB), st, t, v, z, N, c, Mx, My);
     return hipGetLastError();
 }
