@@ -823,7 +823,9 @@ template <class F>
 hipError_t replay(const pit_ctx *c, int op, const void *in, void *out, int raw, int last, hipStream_t st,
                   F &&launches)
 {
-    if (!graphs_enabled()) return launches(st);
+    // graphs pay off for the many launches of the half-step kernels; the
+    // whole-slice LDS kernels are one launch (two for an apply) anyway
+    if (!graphs_enabled() || (c->vel && vel_lds(c))) return launches(st);
     for (const auto &g : c->graphs)
         if (g.op == op && g.in == in && g.out == out && g.raw == raw && g.last == last)
             return hipGraphLaunch(g.exec, st);

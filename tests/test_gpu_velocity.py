@@ -141,9 +141,12 @@ def test_velocity_with_source_and_parareal():
 
 
 def test_velocity_graphs_equal_eager_launches(monkeypatch):
+    """The per-half-step kernels run as captured HIP graphs (the whole-slice
+    LDS kernels launch directly): replays give the bits of eager launches."""
     P = P_()
     p = CASES["rect"]
     say("velocity graphs vs eager")
+    monkeypatch.setenv("PIT_VEL_LDS", "0")
     lam = dev(wl.random_block(p, 5))
     c = P.Context(p)
     ys = [host(c.apply_F(lam)) for _ in range(3)]
