@@ -176,6 +176,62 @@ def workload(name, prec, side=None, time_scheme="pr"):
     return p.with_(prec=wl.F64 if prec == "f64" else wl.F32)
 
 
+def gpu_serial(p, u0, dev):
+    """The sequential method on the same GPU kernels: one slice of all N m fine
+    steps (same fine step), u(T) = F^{N m}(u0) by one RAW apply; the 2D
+    half-step launches go eagerly (no graph of that many nodes).  Second of
+    two runs."""
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+
+    q = p.with_(N=1, m=p.N * p.m)
+    ctx = P.Context(q, device=dev)
+    u = torch.as_tensor(u0, dtype=torch.float64, device=dev)
+    y = torch.empty_like(u)
+    old = os.environ.get("PIT_GRAPHS")
+    os.environ["PIT_GRAPHS"] = "0"
+    try:
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.apply_F(u, y, raw=True)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+    finally:
+        if old is None:
+            del os.environ["PIT_GRAPHS"]
+        else:
+            os.environ["PIT_GRAPHS"] = old
+    return {"ms": ms, "steps": p.N * p.m, "kind": "the fine propagator over all N m steps of one slice, "
+            "the sequential method on the same kernels (u(T) only)"}
+
+
+def cpu_serial(p, u0, seconds=1.0):
+    """The oracle's serial fine solve (the sequential time stepping that the
+    parallel-in-time method replaces) on one core: the first k slices of the
+    same workload (same fine step), k doubled until about `seconds` of work,
+    and the full serial time to solution estimated from that rate."""
+    import oracle as orc
+
+    orc.set_threads(1)
+    k = 1
+    while True:
+        q = p.with_(N=k, T=p.T * k / p.N)
+        o = orc.Oracle(**q.oracle_kwargs())
+        t0 = time.perf_counter()
+        o.serial(u0, want_uT=True)  # lambda_1 .. lambda_{k-1} and u(T_k): k slices of m steps
+        dt = time.perf_counter() - t0
+        if dt >= seconds or k >= p.N:
+            break
+        k = min(p.N, 2 * k)
+    cells = k * p.m * p.npts
+    rate = cells / dt
+    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle serial fine solve",
+            "sample": f"first {k} of {p.N} slices ({cells} cell-updates, {dt:.2f} s)",
+            "time_to_solution_s_est": p.N * p.m * p.npts / rate}
+
+
 def cpu_baseline(p, u0, seconds, source=None, profile=None):
     """Oracle PiTSBiCG on the host cores, truncated to a few iterations."""
     import oracle as orc
@@ -476,9 +532,20 @@ def main():
                                    "pitsbicg_matvecs": matvecs}
         log(f"[bench] parareal: {float(np.median(times)):.2f} ms, {ip.iters} iterations ({ip.matvecs} products) "
             f"vs PiTSBiCG {matvecs} products")
+    # the sequential method on the same GPU (context, not the timed region)
+    if args.workload in ("c1", "c2", "c3", "f2", "f3d", "f3r") and source_f is None:
+        gs = gpu_serial(p, u0h, dev)
+        gs["pit_speedup"] = gs["ms"] / ms_per_step
+        out["gpu_serial"] = gs
+        log(f"[bench] gpu serial fine solve: {gs['ms']:.2f} ms for {gs['steps']} steps; PiTSBiCG {ms_per_step:.2f} ms "
+            f"({gs['pit_speedup']:.2f}x)")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f, source_g)
+        if source_f is None:
+            out["cpu_serial"] = cpu_serial(p, u0h)
+            log(f"[bench] cpu serial fine solve: {out['cpu_serial']['value']:.3g} cell-updates/s on one core, "
+                f"{out['cpu_serial']['time_to_solution_s_est']:.2f} s to solution (estimated)")
     print(json.dumps(out), flush=True)
 
 
