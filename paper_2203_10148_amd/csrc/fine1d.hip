@@ -20,14 +20,31 @@ namespace pit {
 //            line and padding points j >= M are zeroed where the value is
 //            used, so a prefetched register is not merged across control
 //            flow (that would force an early wait on the load).
-//   chunked  (TR = true):  point t*C+k at k*NT+t, slice stride NT*C, padding
-//            stored as zeros.  Every load and store is coalesced across the
-//            wavefront; pit_solve keeps its block vectors in this layout.
+//   chunked  (TR = true):  point t*C+k at chunk_pos(NT, C, t, k): the
+//            thread's points in pairs, pair g of all threads side by side
+//            (C = 1: point t at t).  Slice stride NT*C, padding stored as
+//            zeros.  Every load and store moves 16 bytes per lane and is
+//            contiguous across the wavefront; pit_solve keeps its block
+//            vectors in this layout.  On one CU the cost of a slice's loads
+//            and stores is set by the number of memory instructions, not by
+//            bytes, so the pairs halve it against one point per access.
+typedef double pit_d2 __attribute__((ext_vector_type(2)));
+
 template <int NT, int C, bool TR>
 __device__ __forceinline__ void load_chunk(const double *__restrict__ src, int t, int M, double (&u)[C])
 {
+    if constexpr (TR && chunk_width(C) == 2) {
+        const pit_d2 *s2 = reinterpret_cast<const pit_d2 *>(src);
 #pragma unroll
-    for (int k = 0; k < C; ++k) u[k] = TR ? src[k * NT + t] : src[min(t * C + k, M - 1)];
+        for (int g = 0; g < C / 2; ++g) {
+            const pit_d2 x = s2[g * NT + t];
+            u[2 * g] = x.x;
+            u[2 * g + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < C; ++k) u[k] = TR ? src[k * NT + t] : src[min(t * C + k, M - 1)];
+    }
 }
 
 template <int C>
@@ -41,7 +58,16 @@ __device__ __forceinline__ void zero_pads(int t, int M, double (&u)[C])
 template <int NT, int C, bool TR>
 __device__ __forceinline__ void store_chunk(double *__restrict__ dst, int t, int M, const double (&u)[C])
 {
-    if constexpr (TR) {
+    if constexpr (TR && chunk_width(C) == 2) {
+        pit_d2 *d2 = reinterpret_cast<pit_d2 *>(dst);
+#pragma unroll
+        for (int g = 0; g < C / 2; ++g) {
+            pit_d2 x;
+            x.x = u[2 * g];
+            x.y = u[2 * g + 1];
+            d2[g * NT + t] = x;
+        }
+    } else if constexpr (TR) {
 #pragma unroll
         for (int k = 0; k < C; ++k) dst[k * NT + t] = u[k];
     } else {
@@ -192,14 +218,14 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
     if constexpr (line_compact(NT, C)) {
         // 16 FP64 points per lane at 1024 threads leave no registers for a
         // prefetch buffer.  Instead, while step n-1 runs, every thread touches
-        // one element per 128-byte line of v_n (chunked: line k = t mod 16 of
-        // its 16-thread group; natural: its own first point), so the loads
-        // after the c solves of step n hit L2.
+        // one element of v_n at offset t*C (16 points = one 128-byte line per
+        // thread in either layout), so the loads after the c solves of step n
+        // hit L2.
         double u[C];
         load_chunk<NT, C, TR>(v, t, M, u);
         zero_pads<C>(t, M, u);
         store_chunk<NT, C, TR>(z, t, M, u);
-        const long tofs = TR ? (long)(t & 15) * NT + t : (long)min(t * C, M - 1);
+        const long tofs = min(t * C, TR ? NT * C - 1 : M - 1);
         for (int n = 1; n < N; ++n) {
             const double touch = v[(size_t)n * ld + tofs];
             for (int s = 0; s < c; ++s) {
@@ -224,18 +250,25 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
         }
         return;
     }
-    // With 1024 threads (128 registers per lane) and 8 points per thread a
-    // second prefetch buffer does not fit; one is enough there, since v_n is
-    // only needed after the c solves of the step.
-    constexpr bool kTwoBuffers = NT * C <= 4096;
+    // A second prefetch buffer does not fit in the registers at 16 points per
+    // thread (with the solver's four per-point tables the compiler parks the
+    // buffers in AGPRs, and its copies then wait on loads just issued), nor
+    // at 1024 threads (128 registers per lane).  One buffer is enough there:
+    // v_{n+1} is loaded at the end of step n and needed only after the c
+    // solves of step n+1, and a touch of v_{n+2} (one element per 128-byte
+    // line, as above) a step earlier makes that load an L2 hit.
+    constexpr bool kTwoBuffers = C <= 8 && NT * C <= 4096;
     double u[C], va[C];
     load_chunk<NT, C, TR>(v, t, M, u);
     zero_pads<C>(t, M, u);
     load_chunk<NT, C, TR>(v + (size_t)min(1, N - 1) * ld, t, M, va);
     store_chunk<NT, C, TR>(z, t, M, u);
     if constexpr (!kTwoBuffers) {
+        const long tofs = min(t * C, TR ? NT * C - 1 : M - 1);
         for (int n = 1; n < N; ++n) {
+            const double touch = v[(size_t)min(n + 2, N - 1) * ld + tofs];
             coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
+            asm volatile("" ::"v"(touch));  // consumed a whole step after it was issued
             load_chunk<NT, C, TR>(v + (size_t)min(n + 1, N - 1) * ld, t, M, va);
             store_chunk<NT, C, TR>(z + (size_t)n * ld, t, M, u);
         }

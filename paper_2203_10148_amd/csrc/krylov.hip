@@ -247,14 +247,16 @@ __global__ void k_fill0(double *__restrict__ dst, long n)
         dst[i] = 0.0;
 }
 
-// natural [N][M] <-> chunked [N][NT*C]: point j = t*C + k sits at k*NT + t.
+// natural [N][M] <-> chunked [N][NT*C]: point j = t*C + k sits at
+// chunk_pos(NT, C, t, k) (pairs of points, see pit_internal.hpp).
 __global__ void k_to_chunked(const double *__restrict__ nat, double *__restrict__ chk, int N, int M, int NT,
                              int C)
 {
-    const long S = (long)NT * C, tot = (long)N * S;
+    const long S = (long)NT * C, tot = (long)N * S, P = chunk_width(C);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
         const long n = i / S, r = i % S;
-        const long k = r / NT, t = r % NT, j = t * C + k;
+        const long g = r / (P * NT), q = r % (P * NT);
+        const long t = q / P, k = g * P + q % P, j = t * C + k;
         chk[i] = (j < M) ? nat[n * M + j] : 0.0;
     }
 }
@@ -265,8 +267,7 @@ __global__ void k_from_chunked(const double *__restrict__ chk, double *__restric
     const long S = (long)NT * C, tot = (long)N * M;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
         const long n = i / M, j = i % M;
-        const long t = j / C, k = j % C;
-        nat[i] = chk[n * S + k * NT + t];
+        nat[i] = chk[n * S + chunk_pos(NT, C, j / C, j % C)];
     }
 }
 

@@ -107,7 +107,17 @@ struct LineShape {
 enum { SCHEME_IE = 0, SCHEME_CN = 1, SCHEME_ADI = 2 };
 
 // Slice layouts of the 1D kernels: natural (point j at j, stride M) or
-// chunked (point t*C+k at k*NT+t, stride NT*C, zero padding), see fine1d.hip.
+// chunked (stride NT*C, zero padding), see fine1d.hip.  In the chunked layout
+// thread t's points t*C .. t*C+C-1 are stored in groups of P = chunk_width(C)
+// consecutive points, group g of every thread side by side:
+//   point t*C + k  at  (k / P) * P * NT + P * t + k % P.
+// With P = 2 every access moves 16 bytes per lane and a wavefront's accesses
+// are contiguous.
+constexpr int chunk_width(int C) { return C % 2 == 0 ? 2 : 1; }
+constexpr long chunk_pos(int NT, int C, long t, long k)
+{
+    return (k / chunk_width(C)) * chunk_width(C) * NT + chunk_width(C) * t + k % chunk_width(C);
+}
 //
 // Fine apply, 1D, FP64 state.  y_0 = lam_0, y_n = lam_n - F(lam_{n-1}); raw: y_n = F(lam_n);
 // last_only: y_{N-1} = F(lam_{N-1}) only.

@@ -137,11 +137,16 @@ def test_every_line_shape(shape, monkeypatch):
     assert relerr(host(c.coarse_sweep(d)), o.sweep(lam)) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(64, 2), (128, 8), (256, 4), (512, 8), (1024, 4), (1024, 16)],
+@pytest.mark.parametrize("shape", [(64, 1), (64, 2), (128, 8), (256, 4), (256, 16), (512, 8), (512, 16), (1024, 4),
+                                   (1024, 8), (1024, 16)],
                          ids=lambda s: f"NT{s[0]}_C{s[1]}")
 def test_solve_every_layout(shape, monkeypatch):
     """pit_solve keeps its vectors in the chunked layout of the line shape
-    (padded to NT*C points); a ragged line exercises the padding."""
+    (pairs of points per lane, single points at C = 1, padded to NT*C
+    points); a ragged line exercises the padding.  The shapes cover the
+    sweep's two-buffer prefetch (C <= 8, NT*C <= 4096), its one-buffer
+    prefetch with an L2 touch (C = 16, or 1024 threads) and the compact
+    solver tables (1024 x 16)."""
     NT, C = shape
     M = NT * C - 5
     monkeypatch.setenv("PIT_LINE_SHAPE", f"{NT},{C}")
