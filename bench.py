@@ -51,6 +51,12 @@ KERNEL_SOURCES = {1: ["fine1d.hip", "line1d.hpp", "pit_internal.hpp"],
                   2: ["adi2d.hip", "line1d.hpp", "pit_internal.hpp"]}
 CSRC = os.path.join(ROOT, "paper_2203_10148_amd", "csrc")
 CAL_BYTES = 1 << 30  # the probe's device copy (read 1 GiB, write 1 GiB)
+# The timed solves time one fine apply and one coarse sweep in KERNEL_SAMPLE
+# of each with HIP events (the first of a solve and every KERNEL_SAMPLE-th
+# after it): an event pair around every launch put a 10 us gap between each
+# apply and its sweep, 0.5 ms of a 4096-point solve.  Launches of one kernel
+# in a solve do the same work (rocprofv3 min/max within 3%).
+KERNEL_SAMPLE = 7
 
 
 def sources_sha(dim):
@@ -374,7 +380,7 @@ def main():
     stall = 10 if args.prec == "f32" else 0
 
     def step(timing):
-        _, info = ctx.solve(u0, X, tol=p.tol, stall_window=stall, timing=timing)
+        _, info = ctx.solve(u0, X, tol=p.tol, stall_window=stall, timing=KERNEL_SAMPLE if timing else 0)
         ctx.apply_F(X, uT, last=True)
         return info
 
@@ -401,8 +407,10 @@ def main():
     ms_fine = sum(i.ms_fine for i in infos)
     ms_coarse = sum(i.ms_coarse for i in infos)
     n_coarse = sum(i.n_coarse for i in infos)
-    avg_fine = ms_fine / max(n_apply, 1)
-    avg_coarse = ms_coarse / max(n_coarse, 1)
+    n_fine_timed = sum(i.n_fine_timed for i in infos)
+    n_coarse_timed = sum(i.n_coarse_timed for i in infos)
+    avg_fine = ms_fine / max(n_fine_timed, 1)
+    avg_coarse = ms_coarse / max(n_coarse_timed, 1)
     periodic = 1 if p.bc == wl.PERIODIC else 0
     if p.dim == 1:
         scheme = "cn" if p.fine == wl.CN else "ie"
@@ -411,9 +419,11 @@ def main():
         fl_coarse = (p.N - 1) * p.c * p.npts * FLOPS_PER_CU[(cscheme, periodic)] + (p.N - 1) * p.npts
         peak = PEAK["fp64_vec_TFs"] if args.prec == "f64" else PEAK["fp32_vec_TFs"]
         kern = {
-            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "alu",
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": avg_fine * n_apply, "launches": n_apply,
+                           "timed_ms": ms_fine, "timed_launches": n_fine_timed, "bound": "alu",
                            "work_per_launch": fl_fine, "unit": "TFLOP/s", "peak": peak},
-            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": avg_coarse * n_coarse, "launches": n_coarse,
+                             "timed_ms": ms_coarse, "timed_launches": n_coarse_timed, "bound": "alu",
                              "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
         }
     elif ctx.kernel_shape()[0] == 1 and ctx.kernel_shape()[2] > 0:
@@ -424,9 +434,11 @@ def main():
         fl_fine = p.cells_per_apply * VEL_FLOPS_PER_POINT_STEP[scheme]
         fl_coarse = (p.N - 1) * p.c * p.npts * VEL_FLOPS_PER_POINT_STEP[cscheme] + (p.N - 1) * p.npts
         kern = {
-            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "alu",
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": avg_fine * n_apply, "launches": n_apply,
+                           "timed_ms": ms_fine, "timed_launches": n_fine_timed, "bound": "alu",
                            "work_per_launch": fl_fine, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
-            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "alu",
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": avg_coarse * n_coarse, "launches": n_coarse,
+                             "timed_ms": ms_coarse, "timed_launches": n_coarse_timed, "bound": "alu",
                              "work_per_launch": fl_coarse, "unit": "TFLOP/s", "peak": PEAK["fp64_vec_TFs"]},
         }
     else:
@@ -437,9 +449,11 @@ def main():
         by_fine = algorithmic_bytes(p, args.prec, "fine_apply")
         by_coarse = algorithmic_bytes(p, args.prec, "coarse_sweep")
         kern = {
-            "fine_apply": {"avg_ms": avg_fine, "total_ms": ms_fine, "launches": n_apply, "bound": "hbm",
+            "fine_apply": {"avg_ms": avg_fine, "total_ms": avg_fine * n_apply, "launches": n_apply,
+                           "timed_ms": ms_fine, "timed_launches": n_fine_timed, "bound": "hbm",
                            "work_per_launch": by_fine, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
-            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": ms_coarse, "launches": n_coarse, "bound": "hbm",
+            "coarse_sweep": {"avg_ms": avg_coarse, "total_ms": avg_coarse * n_coarse, "launches": n_coarse,
+                             "timed_ms": ms_coarse, "timed_launches": n_coarse_timed, "bound": "hbm",
                              "work_per_launch": by_coarse, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
         }
     scale = {"TFLOP/s": 1e12, "GB/s": 1e9}

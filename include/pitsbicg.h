@@ -120,8 +120,13 @@ typedef struct {
     int32_t half_step_check; /* !=0: also stop after S = R - alpha D if ||S|| <= tol */
     int32_t stall_window;    /* >0: PIT_ENOCONV when ||R|| has not halved in this
                                 many iterations (for FP32 fine propagators)         */
-    int32_t timing;          /* !=0: time every fine apply and coarse sweep with HIP
-                                events on `stream` (fills ms_fine / ms_coarse)      */
+    int32_t timing;          /* >0: time launches with HIP events on `stream`: the
+                                first fine apply and coarse sweep and then every
+                                timing-th one of each (1: every launch).  Fills
+                                ms_fine / ms_coarse and n_fine_timed /
+                                n_coarse_timed.  Each timed launch adds two event
+                                records, and with them a gap, to the stream.
+                                <0 is PIT_EINVAL.                                   */
 } pit_solve_opts;
 
 /* Result of pit_solve.  history (host, optional, capacity history_cap)
@@ -136,11 +141,12 @@ typedef struct {
     int32_t history_cap;
     int32_t history_len;
     float ms_total;   /* wall time of the call, milliseconds                  */
-    float ms_fine;    /* summed duration of the fine-apply launches (timing)  */
-    float ms_coarse;  /* summed duration of the coarse-sweep launches (timing) */
+    float ms_fine;    /* summed duration of the timed fine-apply launches     */
+    float ms_coarse;  /* summed duration of the timed coarse-sweep launches   */
     int32_t n_fine;   /* fine-apply launches in the call                      */
     int32_t n_coarse; /* coarse-sweep launches in the call                    */
-    int32_t reserved;
+    int32_t n_fine_timed;   /* of those, timed (opts->timing); 0 in batches   */
+    int32_t n_coarse_timed;
 } pit_solve_info;
 
 typedef struct pit_ctx pit_ctx;

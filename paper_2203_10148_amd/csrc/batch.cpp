@@ -872,6 +872,7 @@ void fill_info(const Inst *in, pit_solve_info *info)
     info->n_fine = in->n_fine;
     info->n_coarse = in->n_coarse;
     info->ms_fine = info->ms_coarse = 0.0f;
+    info->n_fine_timed = info->n_coarse_timed = 0;
     info->ms_total = (float)(in->t_done - in->t_admit);
 }
 

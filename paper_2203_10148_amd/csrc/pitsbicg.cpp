@@ -1205,7 +1205,7 @@ struct Solver {
     long n;
     int matvecs = 0;
     int n_fine = 0, n_coarse = 0;
-    bool timing = false;
+    int timing = 0;  // > 0: time the first launch of each kind and every timing-th after it
     std::vector<EventPair> ev_fine, ev_coarse;
 
     ~Solver()
@@ -1228,9 +1228,10 @@ struct Solver {
     int apply(const double *in, double *out)
     {
         int rc;
-        if (timing && (rc = begin(ev_fine))) return rc;
+        const bool timed = timing > 0 && n_fine % timing == 0;
+        if (timed && (rc = begin(ev_fine))) return rc;
         PIT_HIP(op_apply(c, in, out, 0, 0, true, st));
-        if (timing) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
+        if (timed) PIT_HIP(hipEventRecord(ev_fine.back().b, st));
         ++n_fine;
         return PIT_OK;
     }
@@ -1238,9 +1239,10 @@ struct Solver {
     int sweep(const double *in, double *out)
     {
         int rc;
-        if (timing && (rc = begin(ev_coarse))) return rc;
+        const bool timed = timing > 0 && n_coarse % timing == 0;
+        if (timed && (rc = begin(ev_coarse))) return rc;
         PIT_HIP(op_sweep(c, in, out, true, st));
-        if (timing) PIT_HIP(hipEventRecord(ev_coarse.back().b, st));
+        if (timed) PIT_HIP(hipEventRecord(ev_coarse.back().b, st));
         ++n_coarse;
         return PIT_OK;
     }
@@ -1313,7 +1315,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     s.Tm = ctx->vec(6);
     s.Xc = ctx->vec(7);
     s.n = ctx->ntc();
-    s.timing = o.timing != 0;
+    if (o.timing < 0) return PIT_EINVAL;
+    s.timing = o.timing;
     const long n = s.n;
     const int NT = ctx->lf.sh.NT, C = ctx->lf.sh.C;
     hipStream_t st = s.st;
@@ -1477,8 +1480,10 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         info->history_len = hl;
         info->n_fine = s.n_fine;
         info->n_coarse = s.n_coarse;
-        info->ms_fine = s.timing ? Solver::total_ms(s.ev_fine) : 0.0f;
-        info->ms_coarse = s.timing ? Solver::total_ms(s.ev_coarse) : 0.0f;
+        info->ms_fine = Solver::total_ms(s.ev_fine);
+        info->ms_coarse = Solver::total_ms(s.ev_coarse);
+        info->n_fine_timed = (int)s.ev_fine.size();
+        info->n_coarse_timed = (int)s.ev_coarse.size();
         info->ms_total =
             std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -1610,7 +1615,8 @@ extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit
     Solver s{};
     s.c = ctx;
     s.st = static_cast<hipStream_t>(stream);
-    s.timing = o.timing != 0;
+    if (o.timing < 0) return PIT_EINVAL;
+    s.timing = o.timing;
     const long n = ctx->ntc();
     const int NT = ctx->lf.sh.NT, C = ctx->lf.sh.C;
     hipStream_t st = s.st;
@@ -1673,8 +1679,10 @@ extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit
         info->history_len = hl;
         info->n_fine = s.n_fine;
         info->n_coarse = s.n_coarse;
-        info->ms_fine = s.timing ? Solver::total_ms(s.ev_fine) : 0.0f;
-        info->ms_coarse = s.timing ? Solver::total_ms(s.ev_coarse) : 0.0f;
+        info->ms_fine = Solver::total_ms(s.ev_fine);
+        info->ms_coarse = Solver::total_ms(s.ev_coarse);
+        info->n_fine_timed = (int)s.ev_fine.size();
+        info->n_coarse_timed = (int)s.ev_coarse.size();
         info->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;

@@ -57,7 +57,7 @@ class pit_solve_info(ct.Structure):
                 ("history", ct.POINTER(ct.c_double)), ("history_cap", ct.c_int32),
                 ("history_len", ct.c_int32), ("ms_total", ct.c_float),
                 ("ms_fine", ct.c_float), ("ms_coarse", ct.c_float), ("n_fine", ct.c_int32),
-                ("n_coarse", ct.c_int32), ("reserved", ct.c_int32)]
+                ("n_coarse", ct.c_int32), ("n_fine_timed", ct.c_int32), ("n_coarse_timed", ct.c_int32)]
 
 
 class pit_server_cfg(ct.Structure):
@@ -198,6 +198,8 @@ class SolveInfo:
     ms_coarse: float = 0.0
     n_fine: int = 0
     n_coarse: int = 0
+    n_fine_timed: int = 0
+    n_coarse_timed: int = 0
 
 
 class Context:
@@ -293,13 +295,15 @@ class Context:
 
     def solve(self, u0, X=None, *, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS,
               x0_mode=X0_ZERO, half_step_check=0, stall_window=0, hist_cap=4096, stream=None,
-              timing=False, raise_on_error=False):
+              timing=0, raise_on_error=False):
+        # timing: 0 off; k > 0 times the first fine apply and coarse sweep and every k-th
+        # after them with HIP events (1: every launch), see pit_solve_opts.timing
         import torch
 
         if X is None:
             X = torch.empty(self.p.N * self.p.npts, dtype=torch.float64, device=u0.device)
         o = pit_solve_opts(self.p.tol if tol is None else tol, restart_tol, max_iter, norm_mode,
-                           x0_mode, half_step_check, stall_window, 1 if timing else 0)
+                           x0_mode, half_step_check, stall_window, int(timing))
         hist = np.zeros(hist_cap, dtype=np.float64)
         info = pit_solve_info()
         info.history = hist.ctypes.data_as(ct.POINTER(ct.c_double))
@@ -311,16 +315,17 @@ class Context:
             raise PitError(rc, "pit_solve")
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
-                            info.ms_coarse, info.n_fine, info.n_coarse)
+                            info.ms_coarse, info.n_fine, info.n_coarse, info.n_fine_timed,
+                            info.n_coarse_timed)
 
     def parareal(self, u0, X=None, *, tol=0.0, max_iter=0, norm_mode=ABS, x0_mode=X0_ZERO, hist_cap=4096,
-                 stream=None, timing=False):
+                 stream=None, timing=0):
         """Parareal (Richardson form) with the library's apply and sweep; returns (X, SolveInfo)."""
         import torch
 
         if X is None:
             X = torch.empty(self.p.N * self.p.npts, dtype=torch.float64, device=u0.device)
-        o = pit_solve_opts(tol, 0.0, max_iter, norm_mode, x0_mode, 0, 0, 1 if timing else 0)
+        o = pit_solve_opts(tol, 0.0, max_iter, norm_mode, x0_mode, 0, 0, int(timing))
         hist = np.zeros(hist_cap, dtype=np.float64)
         info = pit_solve_info()
         info.history = hist.ctypes.data_as(ct.POINTER(ct.c_double))
@@ -331,7 +336,8 @@ class Context:
             raise PitError(rc, "pit_parareal")
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
-                            info.ms_coarse, info.n_fine, info.n_coarse)
+                            info.ms_coarse, info.n_fine, info.n_coarse, info.n_fine_timed,
+                            info.n_coarse_timed)
 
 
 def autotune(p, device=None, stream=None):

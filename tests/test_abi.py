@@ -33,11 +33,40 @@ def test_struct_layouts_match_header():
     assert ct.sizeof(P.pit_problem) == 4 * 4 + 8 * 8
     assert ct.sizeof(P.pit_stepper) == 16
     assert ct.sizeof(P.pit_solve_opts) == 8 * 2 + 4 * 6
-    assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 3
+    assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 4 + 4  # + tail padding to 8
     assert ct.sizeof(P.pit_server_cfg) == 8 + 8 + 4 * 4
     assert ct.sizeof(P.pit_request) == ct.sizeof(P.pit_problem) + 4 * 2 + 16 * 2 + 8 * 2 + ct.sizeof(P.pit_solve_opts)
     assert ct.sizeof(P.pit_result) == 4 * 4 + 8 * 4 + 8 + 4 * 2
 
+
+
+def test_struct_sizes_and_offsets_match_the_c_header(tmp_path):
+    """The ctypes mirrors against the header itself: a C program built with
+    gcc prints sizeof and every field's offsetof."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = [P.pit_problem, P.pit_stepper, P.pit_solve_opts, P.pit_solve_info, P.pit_server_cfg,
+               P.pit_request, P.pit_result]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pitsbicg.h"', "int main(void) {"]
+    for st in structs:
+        lines.append(f'printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
+        for f in st._fields_:
+            lines.append(f'printf("{st.__name__}.{f[0]} %zu\\n", offsetof({st.__name__}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for st in structs:
+        assert int(got[st.__name__]) == ct.sizeof(st), st.__name__
+        for f in st._fields_:
+            assert int(got[f"{st.__name__}.{f[0]}"]) == getattr(st, f[0]).offset, (st.__name__, f[0])
 
 def create(p, fine=None, coarse=None, N=None, m=None):
     lib = P.load()
