@@ -148,7 +148,7 @@ struct pit_ctx {
     long ntc() const { return (long)N * ld; }
     double *vec(int i) const { return reinterpret_cast<double *>(ws + off_vec) + (size_t)i * ntc(); }
     double *part() const { return reinterpret_cast<double *>(ws + off_part); }
-    RedOut *red() const { return reinterpret_cast<RedOut *>(ws + off_red); }
+    RedOut *red(int slot = 0) const { return reinterpret_cast<RedOut *>(ws + off_red) + slot; }
     LineTab<float> tab32(const LineHost &L, size_t off) const
     {
         LineTab<float> t = line_tab_view<float>(reinterpret_cast<const float *>(ws + off), L.sh.NT, L.sh.C);

@@ -304,6 +304,83 @@ hipError_t launch_update_p(double *P, const double *R, const double *D, double b
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The same three updates with Algorithm 1's scalars taken from reduction
+// outputs in device memory, so that an iteration needs no host round trip
+// between its reductions.  Every thread forms the scalars with the host's
+// operations and in its order (alpha = rho / dr, omega = ks / kk,
+// beta = (alpha / omega) * (rho_new / rho)), so the results are the bits of
+// the host-scalar kernels.  A step that meets one of the algorithm's special
+// cases (dr, kk or omega exactly 0) changes nothing in X, R, P: the host
+// reads the outputs afterwards and takes that branch itself.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool dev_scalars(const DevScalars &s, double &alpha, double &omega)
+{
+    const double dr = s.A->dot[0];
+    if (dr == 0.0) return false;
+    alpha = s.rho->dot[s.rho_idx] / dr;
+    const double kk = s.B->dot[1];
+    if (kk == 0.0) return false;
+    omega = s.B->dot[0] / kk;
+    return omega != 0.0;
+}
+
+// `one` is 1.0, passed at run time as k_axpby's coefficient is: with a
+// literal 1 the compiler folds fma(1, R, b D) into R + b D and may then
+// contract that into one fma, which rounds b D differently.
+__global__ void k_axpby_dev(double *__restrict__ S, const double *__restrict__ R, const double *__restrict__ D,
+                            DevScalars s, double one, long n)
+{
+    const double dr = s.A->dot[0];
+    const double alpha = s.rho->dot[s.rho_idx] / dr;  // dr == 0: S is not used
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        S[i] = axpby_elem(one, R[i], -alpha, D[i]);
+}
+
+__global__ void k_update_xr_dev(double *__restrict__ X, double *__restrict__ R, const double *__restrict__ P,
+                                const double *__restrict__ S, const double *__restrict__ K, DevScalars s, long n)
+{
+    double alpha, omega;
+    if (!dev_scalars(s, alpha, omega)) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double x = X[i], r;
+        update_xr_elem(x, r, P[i], S[i], K[i], alpha, omega);
+        X[i] = x;
+        R[i] = r;
+    }
+}
+
+__global__ void k_update_p_dev(double *__restrict__ P, const double *__restrict__ R, const double *__restrict__ D,
+                               DevScalars s, long n)
+{
+    double alpha, omega;
+    if (!dev_scalars(s, alpha, omega)) return;
+    const double beta = (alpha / omega) * (s.C->dot[0] / s.rho->dot[s.rho_idx]);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        P[i] = update_p_elem(P[i], R[i], D[i], beta, omega);
+}
+
+hipError_t launch_axpby_dev(double *S, const double *R, const double *D, const DevScalars &s, long n,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby_dev, vec_grid(n), dim3(kVecThreads), 0, st, S, R, D, s, 1.0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xr_dev(double *X, double *R, const double *P, const double *S, const double *K,
+                                const DevScalars &s, long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_xr_dev, vec_grid(n), dim3(kVecThreads), 0, st, X, R, P, S, K, s, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_p_dev(double *P, const double *R, const double *D, const DevScalars &s, long n,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_p_dev, vec_grid(n), dim3(kVecThreads), 0, st, P, R, D, s, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_b_minus(double *out, const double *in, const double *u0, long npts, long n,
                           hipStream_t st)
 {

@@ -183,6 +183,10 @@ struct RedOut {
     double dot[4];   // w * sum over slices (fixed order)
     double nmax[4];  // max over slices of sqrt(w * slice sum)
 };
+// A context's reduction outputs: slot 0 for reductions read back one by one,
+// slots 1..4 for pit_solve's one-sync iteration (dr; ks, kk, |S|; rho_new and
+// |R| in two alternating slots), slot 5 for a rho set by the host.
+constexpr int kRedSlots = 6;
 hipError_t launch_seg_dots(const DotPairs &pr, int nq, int N, long npts, int bps, double *part,
                            double w, RedOut *out, hipStream_t st);
 // S = R - alpha*D
@@ -194,6 +198,21 @@ hipError_t launch_update_xr(double *X, double *R, const double *P, const double 
 // P = R + beta*(P - omega*D)
 hipError_t launch_update_p(double *P, const double *R, const double *D, double beta, double omega,
                            long n, hipStream_t st);
+// The same updates with the scalars read on the device from reduction outputs:
+// rho = rho->dot[rho_idx], dr = A->dot[0], ks = B->dot[0], kk = B->dot[1],
+// rho_new = C->dot[0].  update_xr / update_p change nothing when dr, kk or
+// omega is exactly 0 (the host takes those branches).
+struct DevScalars {
+    const RedOut *rho;
+    int rho_idx;
+    const RedOut *A, *B, *C;
+};
+hipError_t launch_axpby_dev(double *S, const double *R, const double *D, const DevScalars &s, long n,
+                            hipStream_t st);
+hipError_t launch_update_xr_dev(double *X, double *R, const double *P, const double *S, const double *K,
+                                const DevScalars &s, long n, hipStream_t st);
+hipError_t launch_update_p_dev(double *P, const double *R, const double *D, const DevScalars &s, long n,
+                               hipStream_t st);
 // out = B - in, B = (u0, 0, ..); first slice uses u0
 hipError_t launch_b_minus(double *out, const double *in, const double *u0, long npts, long n,
                           hipStream_t st);

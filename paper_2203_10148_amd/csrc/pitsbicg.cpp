@@ -815,6 +815,14 @@ bool graphs_enabled()
     return !(e && e[0] == '0');
 }
 
+// pit_solve's one-sync iteration is on unless PIT_DEV_SCALARS=0 (a host round
+// trip after every reduction, for comparison).
+bool dev_scalars_enabled()
+{
+    const char *e = std::getenv("PIT_DEV_SCALARS");
+    return !(e && e[0] == '0');
+}
+
 // Run the launch sequence `launches` as a HIP graph: captured once per
 // (op, in, out, flags) on the context's own capture stream (a capture cannot
 // run on the legacy null stream), then replayed on `st`.  The sequences hold
@@ -957,7 +965,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         c->off_part = o;
         o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
         c->off_red = o;
-        o = align_up(o + sizeof(RedOut));
+        o = align_up(o + kRedSlots * sizeof(RedOut));
         o = source_slots(*c, o);
         if (c->vel) {
             c->off_vtf = o;
@@ -1013,7 +1021,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
     c->off_part = o;
     o = align_up(o + 4 * (size_t)N * c->bps * sizeof(double));
     c->off_red = o;
-    o = align_up(o + sizeof(RedOut));
+    o = align_up(o + kRedSlots * sizeof(RedOut));
     o = source_slots(*c, o);
     c->total = c->base_total = o;
     *out = c;
@@ -1277,11 +1285,50 @@ struct Solver {
             pr.b[q] = b[q];
         }
         PIT_HIP(launch_seg_dots(pr, nq, c->N, c->ld, c->bps, c->part(), c->w, c->red(), st));
-        if (!c->red_pin)
-            PIT_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->red_pin), sizeof(RedOut), hipHostMallocDefault));
+        if (int e = pin()) return e;
         PIT_HIP(hipMemcpyAsync(c->red_pin, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
         PIT_HIP(hipStreamSynchronize(st));
         h = *c->red_pin;
+        return PIT_OK;
+    }
+
+    int pin()
+    {
+        if (!c->red_pin)
+            PIT_HIP(hipHostMalloc(reinterpret_cast<void **>(&c->red_pin), kRedSlots * sizeof(RedOut),
+                                  hipHostMallocDefault));
+        return PIT_OK;
+    }
+
+    // nq inner products into `out` on the device, not read back
+    int dots(int nq, const double *const *a, const double *const *b, RedOut *out)
+    {
+        DotPairs pr{};
+        for (int q = 0; q < nq; ++q) {
+            pr.a[q] = a[q];
+            pr.b[q] = b[q];
+        }
+        PIT_HIP(launch_seg_dots(pr, nq, c->N, c->ld, c->bps, c->part(), c->w, out, st));
+        return PIT_OK;
+    }
+
+    // slots 1..4 to the host, after everything queued so far
+    int fetch(RedOut (&h)[kRedSlots])
+    {
+        if (int e = pin()) return e;
+        PIT_HIP(hipMemcpyAsync(c->red_pin + 1, c->red(1), 4 * sizeof(RedOut), hipMemcpyDeviceToHost, st));
+        PIT_HIP(hipStreamSynchronize(st));
+        for (int i = 1; i <= 4; ++i) h[i] = c->red_pin[i];
+        return PIT_OK;
+    }
+
+    // rho as the host holds it, into slot 5 (the device-scalar kernels read it there)
+    int set_rho(double rho)
+    {
+        if (int e = pin()) return e;
+        c->red_pin[5].dot[0] = rho;
+        PIT_HIP(hipMemcpyAsync(c->red(5), c->red_pin + 5, sizeof(double), hipMemcpyHostToDevice, st));
+        PIT_HIP(hipStreamSynchronize(st));
         return PIT_OK;
     }
 };
@@ -1357,6 +1404,15 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     const double scale = (o.norm_mode == PIT_REL && h.nmax[1] > 0.0) ? h.nmax[1] : 1.0;
     double best = nrm;
     int best_at = 0, k = 0, restarts = 0, status = PIT_ENOCONV, hl = 0;
+    // One host round trip per iteration: the update kernels read alpha, omega
+    // and beta from the reductions' device outputs, and the host reads all of
+    // them once, at the end (see launch_update_xr_dev).  rho_src[rho_idx]
+    // holds the host's rho bit for bit: the previous iteration's slot 3 or 4,
+    // or slot 5 after the host changed rho itself.
+    const bool one_sync = !o.half_step_check && dev_scalars_enabled();
+    const RedOut *rho_src = nullptr;
+    int rho_idx = 0;
+    double rho_dev = 0.0;
 
     for (;;) {
         if (info && info->history && hl < info->history_cap) info->history[hl++] = nrm;
@@ -1379,6 +1435,77 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             } else if (k - best_at >= o.stall_window) {
                 status = PIT_ENOCONV;
                 break;
+            }
+        }
+        if (one_sync) {
+            if (!rho_src || std::memcmp(&rho, &rho_dev, sizeof(double)) != 0) {
+                if ((rc = s.set_rho(rho))) return rc;
+                rho_src = ctx->red(5);
+                rho_idx = 0;
+                rho_dev = rho;
+            }
+            RedOut *const A = ctx->red(1), *const Bq = ctx->red(2);
+            RedOut *const Cn = ctx->red(rho_src == ctx->red(3) ? 4 : 3);
+            const DevScalars ds{rho_src, rho_idx, A, Bq, Cn};
+            if ((rc = s.matvec(s.P, s.D))) return rc;
+            {
+                const double *a[1] = {s.D}, *b[1] = {s.Rt};
+                if ((rc = s.dots(1, a, b, A))) return rc;
+            }
+            PIT_HIP(launch_axpby_dev(s.S, s.R, s.D, ds, n, st));  // S = R - alpha D
+            if ((rc = s.matvec(s.S, s.K))) return rc;
+            {
+                const double *a[3] = {s.K, s.K, s.S}, *b[3] = {s.S, s.K, s.S};
+                if ((rc = s.dots(3, a, b, Bq))) return rc;
+            }
+            PIT_HIP(launch_update_xr_dev(X, s.R, s.P, s.S, s.K, ds, n, st));
+            {
+                const double *a[2] = {s.R, s.R}, *b[2] = {s.Rt, s.R};
+                if ((rc = s.dots(2, a, b, Cn))) return rc;
+            }
+            PIT_HIP(launch_update_p_dev(s.P, s.R, s.D, ds, n, st));
+            RedOut hs[kRedSlots];
+            if ((rc = s.fetch(hs))) return rc;
+            const double dr = hs[1].dot[0];
+            if (dr != 0.0) {  // (dr == 0: the iteration is redone below, restart first)
+                const double alpha = rho / dr;
+                const double ks = hs[2].dot[0], kk = hs[2].dot[1], snorm = hs[2].nmax[2];
+                if (kk == 0.0) {  // S = 0: the half step solved the system
+                    PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
+                    PIT_HIP(launch_copy(s.R, s.S, n, st));
+                    nrm = snorm;
+                    k++;
+                    continue;
+                }
+                const double omega = ks / kk;
+                if (omega == 0.0) {
+                    PIT_HIP(launch_axpby(X, X, 1.0, s.P, alpha, n, st));
+                    PIT_HIP(launch_copy(s.R, s.S, n, st));
+                    PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+                    PIT_HIP(launch_copy(s.P, s.R, n, st));
+                    const double *a[1] = {s.R}, *b[1] = {s.R};
+                    if ((rc = s.reduce(1, a, b, h))) return rc;
+                    rho = h.dot[0];
+                    nrm = h.nmax[0];
+                    restarts++;
+                    k++;
+                    continue;
+                }
+                const RedOut &hc = hs[Cn == ctx->red(3) ? 3 : 4];
+                double rho_new = hc.dot[0];
+                nrm = hc.nmax[1];
+                rho_src = Cn;
+                rho_idx = 0;
+                if (std::fabs(rho_new) <= o.restart_tol) {  // restart test with epsilon_0
+                    PIT_HIP(launch_copy(s.Rt, s.R, n, st));
+                    PIT_HIP(launch_copy(s.P, s.R, n, st));
+                    rho_new = hc.dot[1];
+                    rho_idx = 1;
+                    restarts++;
+                }
+                rho = rho_dev = rho_new;
+                k++;
+                continue;
             }
         }
         // D = G^{-1} F P

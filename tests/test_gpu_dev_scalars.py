@@ -1,0 +1,111 @@
+"""GPU: pit_solve's one-sync iteration (alpha, omega, beta formed on the device
+from the reductions' outputs, one host read-back per iteration) against the
+iteration that reads every reduction back before going on (PIT_DEV_SCALARS=0).
+Both evaluate the same FP64 operations in the same order, so the iterates,
+the residual history and the counters must agree bit for bit.  The cases
+cover the regular path, the half step that solves the system (one slice:
+S = 0 exactly, kk = 0), the restart test of Algorithm 1 firing at the end of
+every iteration (rho then comes from the second inner product), an FP32 fine
+propagator, a 2D problem and a source term, and one oracle check of the
+solution.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2203_10148_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_10148_amd import pitsbicg as P
+
+    P.load()  # fail loudly if the HIP library is missing
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+HEAT1D = wl.Problem(dim=1, M=(300, 1), bc=wl.DIRICHLET, nu=0.05, T=0.5, N=12, m=20, fine=wl.CN, c=2,
+                    coarse=wl.IE, prec=wl.F64, tol=1e-10, name="heat1d_300")
+CASES = {
+    "c2": (wl.C2, {}),
+    "c2_f32": (wl.C2.with_(prec=wl.F32), {"stall_window": 10}),
+    "heat1d": (HEAT1D, {}),
+    "one_slice": (HEAT1D.with_(N=1, m=30), {}),
+    "restart_every_iteration": (HEAT1D, {"restart_tol": 1e300}),
+    "heat2d": (wl.Problem(dim=2, M=(40, 30), bc=wl.DIRICHLET, nu=0.05, T=0.3, N=8, m=6, fine=wl.ADI, c=1,
+                          coarse=wl.ADI, prec=wl.F64, tol=1e-10, name="heat2d_40x30"), {}),
+    "f2_short": (wl.F2.with_(T=0.4, N=4, m=25), {}),
+}
+
+
+def solve(p, u0, monkeypatch, flag, source=None, **kw):
+    from paper_2203_10148_amd import pitsbicg as P
+
+    monkeypatch.setenv("PIT_DEV_SCALARS", flag)
+    c = P.Context(p)
+    if source is not None:
+        c.set_source(source)
+    kw.setdefault("tol", p.tol)
+    X, info = c.solve(dev(u0), **kw)
+    return host(X), info
+
+
+def u0_of(p):
+    return wl.u0_gaussian(p) if p.dim == 2 else wl.u0_for(p)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_sync_iteration_equals_read_back_iteration(case, monkeypatch):
+    p, kw = CASES[case]
+    say(f"one-sync vs read-back {case}")
+    u0 = u0_of(p)
+    Xa, ia = solve(p, u0, monkeypatch, "1", **kw)
+    Xb, ib = solve(p, u0, monkeypatch, "0", **kw)
+    print(f"status {ia.status}/{ib.status} iters {ia.iters}/{ib.iters} restarts {ia.restarts}/{ib.restarts}",
+          flush=True)
+    assert (ia.status, ia.iters, ia.matvecs, ia.restarts) == (ib.status, ib.iters, ib.matvecs, ib.restarts)
+    assert np.array_equal(ia.history, ib.history)
+    assert ia.res_norm == ib.res_norm or (np.isnan(ia.res_norm) and np.isnan(ib.res_norm))
+    assert np.array_equal(Xa, Xb)
+    if case == "restart_every_iteration":
+        assert ia.restarts >= ia.iters - 1 > 0
+    if case == "one_slice":
+        assert ia.status == orc.OK and ia.iters == 1
+
+
+def test_one_sync_iteration_with_a_source_matches_the_oracle(monkeypatch):
+    p = HEAT1D
+    say("one-sync with a source vs oracle")
+    x = wl.grid_1d(p)
+    f = np.sin(np.pi * x) * (1.0 + x)
+    u0 = u0_of(p)
+    Xa, ia = solve(p, u0, monkeypatch, "1", source=f, tol=1e-12)
+    Xb, ib = solve(p, u0, monkeypatch, "0", source=f, tol=1e-12)
+    assert ia.iters == ib.iters and np.array_equal(Xa, Xb)
+    serial = orc.Oracle(**p.oracle_kwargs(), source=f).serial(u0)
+    err = float(np.linalg.norm(Xa - serial) / np.linalg.norm(serial))
+    assert ia.status == orc.OK and err < 1e-10
