@@ -109,3 +109,33 @@ def test_one_sync_iteration_with_a_source_matches_the_oracle(monkeypatch):
     serial = orc.Oracle(**p.oracle_kwargs(), source=f).serial(u0)
     err = float(np.linalg.norm(Xa - serial) / np.linalg.norm(serial))
     assert ia.status == orc.OK and err < 1e-10
+
+
+@pytest.mark.parametrize("stride", [0, 1, 3, 7])
+def test_timing_stride_counts_and_averages(stride):
+    """pit_solve_opts.timing = k times the first fine apply and coarse sweep
+    and every k-th after them: the info counts the timed launches, and the
+    timing leaves the iterates alone."""
+    from paper_2203_10148_amd import pitsbicg as P
+
+    p = HEAT1D
+    say(f"timing stride {stride}")
+    c = P.Context(p)
+    u0 = dev(u0_of(p))
+    X0, i0 = c.solve(u0, tol=p.tol)
+    X, info = c.solve(u0, tol=p.tol, timing=stride)
+    assert np.array_equal(host(X), host(X0)) and info.iters == i0.iters
+    if stride == 0:
+        assert info.n_fine_timed == info.n_coarse_timed == 0 and info.ms_fine == info.ms_coarse == 0.0
+        return
+    assert info.n_fine_timed == -(-info.n_fine // stride)
+    assert info.n_coarse_timed == -(-info.n_coarse // stride)
+    assert info.ms_fine > 0.0 and info.ms_coarse > 0.0
+
+
+def test_negative_timing_stride_is_rejected():
+    from paper_2203_10148_amd import pitsbicg as P
+
+    c = P.Context(HEAT1D)
+    with pytest.raises(P.PitError):
+        c.solve(dev(u0_of(HEAT1D)), timing=-1)
