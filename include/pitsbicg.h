@@ -256,8 +256,12 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
  * (tol 1e-10, restart_tol 1e-30, max_iter 2N, PIT_ABS, PIT_X0_ZERO).
  * info may be NULL.  Inner products are the block L2 product of Sec. 3; the
  * stopping norm is max over slices of the discrete L2 norm.  Host-synchronous
- * (the stopping test needs the norm).  Returns PIT_OK, PIT_ENOCONV,
- * PIT_EBREAKDOWN, PIT_EINVAL or PIT_EHIP. */
+ * (the stopping test needs the norm): one read-back of the iteration's FP64
+ * reduction outputs per iteration, with alpha, omega and beta formed on the
+ * device by the host's operations in the host's order (without
+ * half_step_check; the environment variable PIT_DEV_SCALARS=0 selects a
+ * read-back after every reduction, which gives the same bits).  Returns
+ * PIT_OK, PIT_ENOCONV, PIT_EBREAKDOWN, PIT_EINVAL or PIT_EHIP. */
 int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *opts,
               pit_solve_info *info, void *stream);
 
