@@ -213,6 +213,19 @@ static double uy_at(const orc_ctx *C, int i)
     return C->ay + C->rot * ((i + 1) * C->hx - 0.5 * C->Lx);
 }
 
+/* True when a 2D step should share its lines among the threads: called
+ * outside a parallel region (slices already running in parallel keep one
+ * thread each) on a slice large enough to pay for it. */
+static int lines_in_parallel(const orc_ctx *C)
+{
+#ifdef _OPENMP
+    return g_threads > 1 && !omp_in_parallel() && C->npts >= 4096;
+#else
+    (void)C;
+    return 0;
+#endif
+}
+
 /* Work size in doubles needed by one_step. */
 static size_t step_work(const orc_ctx *C)
 {
@@ -256,61 +269,80 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
         return;
     }
     /* 2D Peaceman-Rachford ADI, Dirichlet-0.  Row j: x-operator with velocity
-     * ux(y_j); column i: y-operator with velocity uy(x_i). */
+     * ux(y_j); column i: y-operator with velocity uy(x_i).  The lines of a
+     * half step are independent; outside a parallel region (one slice at a
+     * time, as in the serial trajectory) they are shared among the threads,
+     * each line computed exactly as by one thread. */
     int nx = C->Mx, ny = C->My;
-    double xlo, xdi, xup, ylo, ydi, yup;
     int nmax = nx > ny ? nx : ny;
-    double *star = work;           /* npts */
-    double *line = work + C->npts; /* nmax */
-    double *sol = line + nmax;     /* nmax */
-    double *lw = sol + nmax;       /* 9*nmax */
-    double th = 0.5 * dt;
+    double *star = work; /* npts */
+    int par = lines_in_parallel(C);
     if (scheme == ORC_ADI_IE) {
         /* (I - dt*Lx) u* = u + dt*f row by row, then (I - dt*Ly) u' = u* column by column */
-        for (int j = 0; j < ny; ++j) {
-            for (int i = 0; i < nx; ++i) {
-                line[i] = u[j * nx + i];
-                if (f) line[i] += dt * (wf * f[j * nx + i]);
+#pragma omp parallel num_threads(g_threads) if (par)
+        {
+            double *line = (double *)malloc(sizeof(double) * 11 * (size_t)nmax);
+            double *sol = line + nmax, *lw = sol + nmax;
+            double xlo, xdi, xup, ylo, ydi, yup;
+#pragma omp for schedule(static)
+            for (int j = 0; j < ny; ++j) {
+                for (int i = 0; i < nx; ++i) {
+                    line[i] = u[j * nx + i];
+                    if (f) line[i] += dt * (wf * f[j * nx + i]);
+                }
+                op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
+                implicit_line(nx, ORC_DIRICHLET, dt, xlo, xdi, xup, line, sol, lw);
+                for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
             }
-            op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
-            implicit_line(nx, ORC_DIRICHLET, dt, xlo, xdi, xup, line, sol, lw);
-            for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
-        }
-        for (int i = 0; i < nx; ++i) {
-            for (int j = 0; j < ny; ++j) line[j] = star[j * nx + i];
-            op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
-            implicit_line(ny, ORC_DIRICHLET, dt, ylo, ydi, yup, line, sol, lw);
-            for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+#pragma omp for schedule(static)
+            for (int i = 0; i < nx; ++i) {
+                for (int j = 0; j < ny; ++j) line[j] = star[j * nx + i];
+                op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
+                implicit_line(ny, ORC_DIRICHLET, dt, ylo, ydi, yup, line, sol, lw);
+                for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+            }
+            free(line);
         }
         return;
     }
-    /* half-step 1: rhs = (I + th*Ly) u + th*f, then (I - th*Lx) u* = rhs row by row */
-    for (int j = 0; j < ny; ++j) {
-        for (int i = 0; i < nx; ++i) {
-            op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
-            double c0 = u[j * nx + i];
-            double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
-            double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
-            line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
-            if (f) line[i] += th * (wf * f[j * nx + i]);
-        }
-        op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
-        implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
-        for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
-    }
-    /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column */
-    for (int i = 0; i < nx; ++i) {
+    double th = 0.5 * dt;
+#pragma omp parallel num_threads(g_threads) if (par)
+    {
+        double *line = (double *)malloc(sizeof(double) * 11 * (size_t)nmax);
+        double *sol = line + nmax, *lw = sol + nmax;
+        double xlo, xdi, xup, ylo, ydi, yup;
+        /* half-step 1: rhs = (I + th*Ly) u + th*f, then (I - th*Lx) u* = rhs row by row */
+#pragma omp for schedule(static)
         for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
+                double c0 = u[j * nx + i];
+                double cm = (j > 0) ? u[(j - 1) * nx + i] : 0.0;
+                double cq = (j < ny - 1) ? u[(j + 1) * nx + i] : 0.0;
+                line[i] = c0 + th * (ylo * cm + ydi * c0 + yup * cq);
+                if (f) line[i] += th * (wf * f[j * nx + i]);
+            }
             op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
-            double c0 = star[j * nx + i];
-            double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
-            double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
-            line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
-            if (f) line[j] += th * (wf * f[j * nx + i]);
+            implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
+            for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
         }
-        op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
-        implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
-        for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+        /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column
+         * (the implicit barrier of the loop above orders the two halves) */
+#pragma omp for schedule(static)
+        for (int i = 0; i < nx; ++i) {
+            for (int j = 0; j < ny; ++j) {
+                op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
+                double c0 = star[j * nx + i];
+                double cm = (i > 0) ? star[j * nx + i - 1] : 0.0;
+                double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
+                line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
+                if (f) line[j] += th * (wf * f[j * nx + i]);
+            }
+            op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
+            implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
+            for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+        }
+        free(line);
     }
 }
 

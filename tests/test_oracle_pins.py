@@ -465,6 +465,186 @@ def test_x0_given_and_coarse():
 
 
 # ---------------------------------------------------------------------------
+# Algorithm 1: the restart, breakdown and stall branches
+# ---------------------------------------------------------------------------
+
+def bicgstab_from(A, b, x0, weight, N, iters, restart_each=False):
+    """van der Vorst's BiCGStab (1992) on a dense matrix from x0, with the
+    shadow residual r~ = r0.  restart_each: every iteration starts afresh from
+    the current x (r~ = r, p = r).  Returns the iterates and the N,inf norms of
+    the residuals, both from x0 on."""
+    x = x0.copy(); r = b - A @ x
+    norm = lambda z: np.sqrt(weight * (z.reshape(N, -1) ** 2).sum(1)).max()
+    xs, norms = [x.copy()], [norm(r)]
+
+    def fresh(r):
+        return r.copy(), 1.0, 1.0, 1.0, np.zeros_like(r), np.zeros_like(r)
+
+    rh, rho_old, alpha, omega, v, pvec = fresh(r)
+    for _ in range(iters):
+        rho = rh @ r
+        beta = (rho / rho_old) * (alpha / omega)
+        pvec = r + beta * (pvec - omega * v)
+        v = A @ pvec
+        alpha = rho / (rh @ v)
+        s = r - alpha * v
+        t = A @ s
+        omega = (t @ s) / (t @ t)
+        x = x + alpha * pvec + omega * s
+        r = s - omega * t
+        rho_old = rho
+        xs.append(x.copy()); norms.append(norm(r))
+        if restart_each:
+            rh, rho_old, alpha, omega, v, pvec = fresh(r)
+    return xs, np.array(norms)
+
+
+def dense_system(p, u0):
+    SF, SG = dense_props(p)
+    Fb, Gb = block_lower(SF, p.N), block_lower(SG, p.N)
+    B = np.zeros(p.N * p.npts); B[: p.npts] = u0
+    return np.linalg.solve(Gb, Fb), np.linalg.solve(Gb, B)
+
+
+def test_restart_every_iteration_matches_restarted_bicgstab():
+    """epsilon_0 = 1e30 restarts after every iteration (Alg. 1, restart test):
+    each iteration is then the first step of a fresh BiCGStab from the current
+    iterate, with R~ = P = R and rho = <R, R>.  Iterate by iterate."""
+    p = TINY[1]
+    o = make(p)
+    u0 = np.random.default_rng(11).standard_normal(p.npts)
+    A, b = dense_system(p, u0)
+    X, info = o.pitsbicg(u0, tol=1e-12, eps0=1e30, max_iter=80)
+    assert info.status == orc.OK and info.restarts == info.iters
+    xs, norms = bicgstab_from(A, b, np.zeros_like(b), o.weight, p.N, info.iters, restart_each=True)
+    h = info.history
+    for k in range(len(h)):
+        if norms[k] < 1e-9 * norms[0]:
+            break
+        assert abs(h[k] - norms[k]) <= 1e-9 * norms[0], k
+    assert relerr(X, xs[info.iters]) < 1e-9
+    # without the restarts the iterates differ (the restart is not a no-op here)
+    X2, info2 = o.pitsbicg(u0, tol=1e-12, eps0=1e-30, max_iter=80)
+    assert info2.restarts == 0 and abs(info2.history[2] - h[2]) > 1e-6 * h[0]
+
+
+def stall_stop(norms, tol, window):
+    """The stall reading: stop (without convergence) at the first k at which
+    ||R^k|| has not fallen to half of the last norm that did halve, for
+    `window` iterations.  Returns (k, smallest distance of a halving decision
+    from its threshold, relative) or (None, margin) if tol is met first."""
+    ref, ref_at, margin = norms[0], 0, np.inf
+    for k, nk in enumerate(norms):
+        if not nk > tol:
+            return None, margin
+        margin = min(margin, abs(nk - 0.5 * ref) / ref)
+        if nk <= 0.5 * ref:
+            ref, ref_at = nk, k
+        elif k - ref_at >= window:
+            return k, margin
+    raise AssertionError("sequence too short")
+
+
+@pytest.mark.parametrize("window", [1, 2, 3])
+def test_stall_rule_stops_where_the_reading_says(window):
+    """The stall window (the reading for an FP32 fine propagator's residual
+    floor): the oracle stops with ENOCONV at the iteration the textbook
+    BiCGStab's residual norms predict, with the textbook's iterate there.  An
+    advection-dominated periodic case whose residual does not halve every
+    iteration (CN fine, one IE coarse step)."""
+    p = wl.Problem(dim=1, M=(10, 1), bc=wl.PERIODIC, nu=1e-3, adv=(1.0, 0.0), T=4.0, N=10, m=6,
+                   fine=wl.CN, c=1, coarse=wl.IE)
+    o = make(p)
+    u0 = np.random.default_rng(5).standard_normal(p.npts)
+    A, b = dense_system(p, u0)
+    xs, norms = bicgstab_from(A, b, np.zeros_like(b), o.weight, p.N, 40)
+    k, margin = stall_stop(norms, 1e-13, window)
+    assert k is not None and margin > 1e-6  # the case decides every halving clearly
+    X, info = o.pitsbicg(u0, tol=1e-13, eps0=0.0, max_iter=80, stall_window=window)
+    assert info.status == orc.ENOCONV and info.iters == k and info.matvecs == 2 * k
+    # this strongly non-normal operator amplifies rounding differences between
+    # the two BiCGStabs to ~1e-9 within a few iterations
+    assert relerr(X, xs[k]) < 1e-8
+    # a window it never reaches: the solve converges
+    X, info = o.pitsbicg(u0, tol=1e-13, eps0=0.0, max_iter=80, stall_window=1000)
+    assert info.status == orc.OK
+
+
+def test_exact_cases_point_operator_is_the_dense_operator():
+    """The per-point factors of the exact branch cases (f, g over a slice) give
+    the dense G^{-1} F of the finite-difference definition."""
+    import exact_cases as ec
+
+    for p, (f, g) in ((ec.OMEGA_ZERO, ec.OMEGA_ZERO_FG), (ec.SHADOW_ZERO, ec.SHADOW_ZERO_FG)):
+        A, _ = dense_system(p, np.ones(p.npts))
+        assert np.array_equal(A, ec.block_operator(p, f, g)) or np.abs(A - ec.block_operator(p, f, g)).max() < 1e-15
+
+
+def test_omega_zero_branch():
+    """omega = 0 with K != 0 (Alg. 1, omega): X += alpha P, R = S, restart.  The
+    restart makes R~ = R = S, so the next <D, R~> = <K, S> = 0: the
+    shadow-product restart cannot help and the solve ends in a breakdown.
+    Everything here is exact (dyadic data), so the checks are equalities."""
+    import exact_cases as ec
+
+    p = ec.OMEGA_ZERO
+    o = make(p)
+    u0, X0, R0 = ec.omega_zero_data()
+    A = ec.block_operator(p, *ec.OMEGA_ZERO_FG)
+    # the construction: R^0 is what the oracle's initial residual gives, and
+    # the textbook first half step has alpha = 1/2 and <K, S> = 0
+    B = np.zeros_like(R0); B[: p.npts] = u0
+    assert np.array_equal(o.sweep(B - o.apply(X0)), R0)
+    D = A @ R0
+    alpha = (R0 @ R0) / (D @ R0)
+    S = R0 - alpha * D
+    K = A @ S
+    assert alpha == 0.5 and K @ S == 0.0 and K @ K > 0.0
+    X, info = o.pitsbicg(u0, tol=1e-12, x0_mode=orc.X0_GIVEN, X0=X0)
+    assert info.status == orc.EBREAKDOWN
+    assert info.iters == 1 and info.restarts == 2
+    assert info.matvecs == 1 + 2 + 2  # X^0's residual; D, K; D, and D again after the restart
+    assert np.array_equal(X, X0 + alpha * R0)
+    assert info.history[1] == o.norm(S)
+
+
+def test_shadow_product_zero_restarts_with_the_current_residual():
+    """<D, R~> = 0 with R~ != R (Alg. 1, alpha): the restart sets R~ = P = R,
+    rho = <R, R>, recomputes D and goes on; from there the iterates are those
+    of a fresh BiCGStab started from the current iterate."""
+    import exact_cases as ec
+
+    p = ec.SHADOW_ZERO
+    o = make(p)
+    u, X0, R0 = ec.shadow_zero_data()
+    A = ec.block_operator(p, *ec.SHADOW_ZERO_FG)
+    B = np.zeros_like(R0); B[: p.npts] = u
+    b = A @ B  # G^{-1} B, since F = 0 makes the all-at-once operator the identity
+    assert np.array_equal(o.sweep(B - o.apply(X0)), R0)
+    # the first iteration by the textbook, exactly: alpha = 1, omega = 3/4,
+    # R^1 orthogonal to R~ = R^0 (beta = 0), then <A R^1, R^0> = 0
+    xs, norms = bicgstab_from(A, b, X0, o.weight, p.N, 1)
+    X1 = xs[1]
+    R1 = b - A @ X1
+    assert R1 @ R0 == 0.0 and (A @ R1) @ R0 == 0.0 and np.abs(R1).max() > 0
+    X, info = o.pitsbicg(u, tol=1e-13, eps0=-1.0, max_iter=20, x0_mode=orc.X0_GIVEN, X0=X0)
+    assert info.status == orc.OK and info.restarts == 1
+    # X^0's residual; D, K; D, D again after the restart, K; then D, K per iteration
+    assert info.matvecs == 1 + 2 + 3 + 2 * (info.iters - 2)
+    # from X^1 on: a fresh BiCGStab (R~ = R^1)
+    xf, nf = bicgstab_from(A, b, X1, o.weight, p.N, info.iters - 1)
+    h = info.history
+    assert h[1] == nf[0]
+    for k in range(1, len(h)):
+        if nf[k - 1] < 1e-9 * nf[0]:
+            break
+        assert abs(h[k] - nf[k - 1]) <= 1e-9 * nf[0], k
+    assert relerr(X, xf[info.iters - 1]) < 1e-9
+    # the exact solution of the all-at-once system: X = B (F = 0)
+    assert relerr(X, B) < 1e-11
+
+
+# ---------------------------------------------------------------------------
 # parareal
 # ---------------------------------------------------------------------------
 
@@ -853,3 +1033,18 @@ def test_rotation_turns_a_bump_counterclockwise_about_the_centre():
     k = int(np.argmax(u2))
     assert abs(X.reshape(-1)[k] - 0.25) < 0.03 and abs(Y.reshape(-1)[k] - 0.5) < 0.03
     assert abs(u2.max() / u0.max() - 1.0) < 0.1  # little damping at nu = 1e-5
+
+
+@pytest.mark.parametrize("inst", [0, 14, 31, 50, 63])
+def test_c4_fourier_closed_form_is_the_oracle_serial(inst):
+    """The modal closed form that checks whole batched trajectories on the GPU
+    (every instance, every slice) agrees with the oracle's serial fine solve on
+    the first slices of batch instances (same fine step)."""
+    from closed_forms import fourier_serial
+
+    p, seed = wl.c4_batch()[inst]
+    q = p.with_(N=5, T=p.T * 5 / p.N, prec=wl.F64)
+    o = make(q)
+    ref = o.serial(wl.u0_fourier(q, seed)).reshape(q.N, -1)
+    cf = fourier_serial(q, seed)
+    assert relerr(cf, ref) < 1e-11, relerr(cf, ref)
