@@ -12,7 +12,13 @@ region record HIP events around every fine apply and coarse sweep on the
 solve's stream.  The CPU baseline is the oracle (plain C, FP64) running the
 same solve truncated to a bounded number of iterations on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--prec f64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3] [--prec f32]
+
+The default line is the 512 x 512 heat workload (128 slices, 64 PR-ADI fine steps
+per slice, FP32 fine fields, FP64 Krylov), whose fine apply is bound by HBM
+bandwidth.  It also carries the same fine apply on a 1024 x 1024 grid (a working
+set beyond the 256 MiB Infinity Cache) and the 4096-point advection-diffusion
+workload (FP64 and FP32 fine) as extra keys.
 """
 import argparse
 import csv
@@ -157,15 +163,26 @@ def stored_traffic(p, prec, unit):
 
 
 def algorithmic_bytes(p, prec, unit):
-    """Algorithmic HBM bytes of one fine apply or coarse sweep (block vectors FP64)."""
-    from paper_2203_10148_amd import workloads as wl
+    """Algorithmic HBM bytes of one fine apply or coarse sweep (block vectors FP64).
+
+    1D fine apply: each of the N-1 slices reads lam_{n-1} and lam_n (the
+    epilogue's subtraction) and writes y_n; the state stays on chip across the
+    m steps.  1D coarse sweep: v_n in, z_n out.  2D fine apply: each PR-ADI
+    half step reads and writes the field once in the fine precision, except
+    that the first reads lam_{n-1} (FP64) and the last reads lam_n and writes
+    y_n (FP64).  2D coarse sweep per slice and step: x half (read 8 + write 8),
+    y half (read 8 + base 8 + write 8).
+    """
+    ns = p.N - 1
     if p.dim == 1:
-        return 2 * p.N * p.npts * 8  # slice in, slice out; the state stays on chip across steps
+        if unit == "fine_apply":
+            return ns * p.npts * 24
+        return 2 * p.N * p.npts * 8
     if unit == "fine_apply":
-        # each PR-ADI half step reads and writes the field once
-        return p.cells_per_apply * 4 * (4 if prec == "f32" else 8)
-    # coarse sweep per slice and step: x half (read 8 + write 8), y half (read 8 + base 8 + write 8)
-    return (p.N - 1) * p.c * p.npts * 40
+        f = 4 if prec == "f32" else 8
+        per_point = 2 * p.m * 2 * f + 2 * (8 - f) + 8  # 4m field passes; FP64 first read and last write; lam_n
+        return ns * p.npts * per_point
+    return ns * p.c * p.npts * 40
 
 
 def workload(name, prec, side=None, time_scheme="pr"):
@@ -238,11 +255,22 @@ def cpu_serial(p, u0, seconds=1.0):
             "time_to_solution_s_est": p.N * p.m * p.npts / rate}
 
 
+def host_cores():
+    """Threads for the oracle: the cores this process may run on, at most 16
+    (the host share of a one-GPU job; the machine may show more cores than
+    the job is given)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(p, u0, seconds, source=None, profile=None):
     """Oracle PiTSBiCG on the host cores, truncated to a few iterations."""
     import oracle as orc
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cores()
     orc.set_threads(threads)
     o = orc.Oracle(**p.oracle_kwargs())
     if source is not None:
@@ -260,7 +288,121 @@ def cpu_baseline(p, u0, seconds, source=None, profile=None):
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle Algorithm 1 on the same {p.name} input truncated to "
                       f"{info.iters} iteration(s) ({info.matvecs} preconditioned products), "
-                      f"{dt:.1f} s, {threads} OpenMP threads over slices"}
+                      f"{dt:.1f} s, {threads} OpenMP threads over slices (over the lines of a 2D step where one slice "
+                      f"runs alone): the host cores this process may use, at most the 16 a one-GPU job is given"}
+
+
+def solve_summary(infos, P):
+    """Status, iterations and time of the timed solves; the time to tol only
+    when every timed solve reached it."""
+    import numpy as np
+
+    status = sorted({i.status for i in infos})
+    ms = float(np.median([i.ms_total for i in infos]))
+    d = {"status": status, "iters": infos[-1].iters, "matvecs": infos[-1].matvecs, "restarts": infos[-1].restarts,
+         "res_norm": infos[-1].res_norm, "reached_tol": status == [P.OK]}
+    if status == [P.OK]:
+        d["time_to_tol_ms"] = ms
+    else:
+        d["time_to_stop_ms"] = ms
+    return d
+
+
+def compare_form(p, other, u0, X, source_f, source_g, dev, reps):
+    """The same solve with the other fine precision (FP32 fine with FP64
+    reductions, or plain FP64): time, outcome and distance from the timed
+    form's solution."""
+    import numpy as np
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    po = p.with_(prec=other)
+    co = P.Context(po, device=dev)
+    if source_f is not None:
+        co.set_source(source_f, source_g)
+    Xo = torch.empty_like(X)
+    so = 10 if other == wl.F32 else 0
+    co.solve(u0, Xo, tol=p.tol, stall_window=so)
+    torch.cuda.synchronize()
+    infos = []
+    for _ in range(reps):
+        _, io = co.solve(u0, Xo, tol=p.tol, stall_window=so)
+        infos.append(io)
+    diff = float(torch.linalg.vector_norm(Xo - X) / torch.linalg.vector_norm(X))
+    d = {"form": "f32" if other == wl.F32 else "f64", "ms": float(np.median([i.ms_total for i in infos])),
+         **solve_summary(infos, P), "rel_diff_from_timed_form": diff}
+    if not d["reached_tol"]:
+        d["note"] = ("an FP32 fine propagator stops at its residual floor (stall rule, status -4) when tol is "
+                     "below it")
+    return d
+
+
+def fine_apply_rate(p, prec, dev, reps=5):
+    """Average duration (HIP events on the launching stream) and algorithmic
+    HBM rate of the fine apply of a random block on problem p."""
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    ctx = P.Context(p, device=dev)
+    g = torch.Generator(device=dev).manual_seed(1)
+    lam = torch.randn(p.N * p.npts, dtype=torch.float64, device=dev, generator=g)
+    y = torch.empty_like(lam)
+    st = torch.cuda.current_stream(dev)
+    ctx.apply_F(lam, y, stream=st)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(st)
+        ctx.apply_F(lam, y, stream=st)
+        b.record(st)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / reps
+    by = algorithmic_bytes(p, prec, "fine_apply")
+    gbs = by / (ms * 1e-3) / 1e9
+    del ctx
+    return {"workload": p.name, "M": list(p.M), "N": p.N, "m": p.m, "fine_prec": prec, "avg_ms": ms,
+            "launches": reps, "algorithmic_bytes": by, "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+            "frac": gbs / PEAK["hbm_GBs"], "cell_updates_per_s": p.cells_per_apply / (ms * 1e-3)}
+
+
+def c2_summary(dev, reps=5):
+    """The 4096-point advection-diffusion workload (N 256, m 200): time to
+    tol 1e-8 with a plain FP64 and with an FP32 fine propagator (FP64
+    reductions), whole-solve fine cell-updates/s, and the average fine apply
+    and coarse sweep (HIP events, every 7th launch)."""
+    import numpy as np
+    import torch
+
+    from paper_2203_10148_amd import pitsbicg as P
+    from paper_2203_10148_amd import workloads as wl
+
+    res = {}
+    X64 = None
+    for prec in ("f64", "f32"):
+        p = wl.C2.with_(prec=wl.F64 if prec == "f64" else wl.F32)
+        ctx = P.Context(p, device=dev)
+        u0 = torch.as_tensor(wl.u0_for(p), dtype=torch.float64, device=dev)
+        X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)
+        stall = 10 if prec == "f32" else 0
+        ctx.solve(u0, X, tol=p.tol, stall_window=stall)
+        torch.cuda.synchronize()
+        infos = [ctx.solve(u0, X, tol=p.tol, stall_window=stall, timing=KERNEL_SAMPLE)[1] for _ in range(reps)]
+        ms = float(np.median([i.ms_total for i in infos]))
+        fine = sum(i.ms_fine for i in infos) / max(sum(i.n_fine_timed for i in infos), 1)
+        sweep = sum(i.ms_coarse for i in infos) / max(sum(i.n_coarse_timed for i in infos), 1)
+        d = {"ms": ms, **solve_summary(infos, P),
+             "cell_updates_per_s": infos[-1].n_fine * p.cells_per_apply / (ms * 1e-3),
+             "fine_apply_avg_ms": fine, "coarse_sweep_avg_ms": sweep}
+        if X64 is None:
+            X64 = X.clone()
+        else:
+            d["rel_diff_from_f64"] = float(torch.linalg.vector_norm(X - X64) / torch.linalg.vector_norm(X64))
+        res[prec] = d
+    res["workload"] = wl.C2.name
+    return res
 
 
 def main():
@@ -268,7 +410,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2", "f3d", "f3r"],
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "f2", "f3d", "f3r"],
                     help="c1-c3, f2, f3d (diffusion), f3r (diffusion-reaction): one solve per step; c4: the "
                          "64-instance batch per step; c5: a served Poisson stream (one pass of --requests "
                          "requests)")
@@ -287,7 +429,7 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="c5: arrival rate (requests/s)")
     ap.add_argument("--arena-gib", type=float, default=160.0, help="c5: HBM budget of the server (GiB)")
     ap.add_argument("--no-autotune", action="store_true", help="c4: keep the default line shapes")
-    ap.add_argument("--no-compare", action="store_true", help="c1/c2: skip the solve in the other fine precision")
+    ap.add_argument("--no-compare", action="store_true", help="skip the solve in the other fine precision, parareal and (c3) the extra keys")
     ap.add_argument("--side", type=int, default=None, help="c3: grid side (default 512)")
     ap.add_argument("--no-singles", action="store_true", help="c4: skip the single-instance baseline solves")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
@@ -489,12 +631,9 @@ def main():
                    "fine": scheme, "coarse": f"{p.c}x{cscheme}", "bc": "periodic" if periodic else "dirichlet0",
                    "tol": p.tol, "fine_prec": args.prec},
         "roofline": roofline,
-        "solve": {"status": sorted(status), "iters": iters, "matvecs": matvecs,
-                  "time_to_tol_ms": float(np.median([i.ms_total for i in infos])),
-                  "restarts": infos[-1].restarts, "res_norm": infos[-1].res_norm},
+        "solve": solve_summary(infos, P),
         "kernels": {name: {**v, "achieved": rate(v)} for name, v in kern.items()},
         "fine_kernel_cell_updates_per_s": fine_cu_s,
-        "fine_kernel_stream_equiv_hbm_frac": fine_cu_s * (16 if args.prec == "f64" else 8) / (PEAK["hbm_GBs"] * 1e9),
         "kernel_shape": ctx.kernel_shape(),
     }
     if source_f is not None:
@@ -508,29 +647,12 @@ def main():
         out["source"] = {"setup_ms": src_ms, "note": note}
     # the other fine-propagator form on the same input (FP32 fine with FP64
     # reductions vs plain FP64), outside the timed region
-    if p.dim == 1 and not args.no_compare:
+    if not args.no_compare and p.dim in (1, 2) and not (p.dim == 2 and p.rot != 0.0):
         other = wl.F64 if p.prec == wl.F32 else wl.F32
-        po = p.with_(prec=other)
-        co = P.Context(po, device=dev)
-        if source_f is not None:
-            co.set_source(source_f, source_g)
-        Xo = torch.empty_like(X)
-        so = 10 if other == wl.F32 else 0
-        co.solve(u0, Xo, tol=p.tol, stall_window=so)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(3):
-            _, io = co.solve(u0, Xo, tol=p.tol, stall_window=so)
-            times.append(io.ms_total)
-        diff = float(torch.linalg.vector_norm(Xo - X) / torch.linalg.vector_norm(X))
-        out["compare"] = {"form": "f32" if other == wl.F32 else "f64", "time_to_tol_ms": float(np.median(times)),
-                          "status": io.status, "iters": io.iters, "res_norm": io.res_norm,
-                          "rel_diff_from_timed_form": diff}
-        if io.status == P.ENOCONV:
-            out["compare"]["note"] = ("an FP32 fine propagator stops at its residual floor (stall rule, status -4) "
-                                      "when tol is below it")
-        log(f"[bench] compare {out['compare']['form']}: {out['compare']['time_to_tol_ms']:.2f} ms, "
-            f"status {io.status}, iters {io.iters}, rel. diff {diff:.2e}")
+        out["compare"] = compare_form(p, other, u0, X, source_f, source_g, dev, reps=3 if p.dim == 1 else 2)
+        log(f"[bench] compare {out['compare']['form']}: {out['compare']['ms']:.2f} ms, "
+            f"status {out['compare']['status']}, iters {out['compare']['iters']}, "
+            f"rel. diff {out['compare']['rel_diff_from_timed_form']:.2e}")
     # parareal (Sec. 2, eq. (pararealAlgebraic)) on the same input and kernels,
     # to the same tolerance on its update norm: the paper's comparison
     if not args.no_compare:
@@ -553,6 +675,14 @@ def main():
         out["gpu_serial"] = gs
         log(f"[bench] gpu serial fine solve: {gs['ms']:.2f} ms for {gs['steps']} steps; PiTSBiCG {ms_per_step:.2f} ms "
             f"({gs['pit_speedup']:.2f}x)")
+    if args.workload == "c3" and not args.no_compare and source_f is None and args.time_scheme == "pr":
+        if p.M[0] == 512:
+            out["c3_1024_fine_apply"] = fine_apply_rate(p.with_(M=(1024, 1024), name=f"{p.name}_1024"),
+                                                        args.prec, dev)
+            log(f"[bench] 1024^2 fine apply: {out['c3_1024_fine_apply']['avg_ms']:.2f} ms, "
+                f"frac {out['c3_1024_fine_apply']['frac']:.3f}")
+        out["c2"] = c2_summary(dev)
+        log(f"[bench] c2 fp64: {out['c2']['f64']['ms']:.2f} ms, fp32: {out['c2']['f32']['ms']:.2f} ms")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, u0h, args.cpu_seconds, source_f, source_g)

@@ -179,20 +179,21 @@ def test_serial_trajectory_is_annihilated():
     assert np.abs(y[1:]).max() < 1e-13 * np.abs(u0).max()
 
 
-def test_c2_full_size_apply_sampled_slices():
+def test_c2_full_size_apply_all_slices():
     """The 4096-point, 256-slice advection-diffusion apply (200 CN steps),
-    checked on sampled slices."""
+    every slice against the oracle's apply."""
     p = wl.C2.with_(prec=wl.F64)
     say("c2 full apply")
     c = ctx(p)
-    o = make_oracle(p.with_(N=1, T=p.T / p.N))  # one slice of the same length DT
+    o = make_oracle(p)
     lam = wl.random_block(p, 2)
-    y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
-    L = lam.reshape(p.N, -1)
-    assert np.array_equal(y[0], L[0])
-    for n in (1, 2, 77, 128, 200, 255):
-        ref = L[n] - o.F(L[n - 1])
-        assert relerr(y[n], ref) < 1e-12, n
+    y = host(c.apply_F(dev(lam)))
+    ref = o.apply(lam)
+    Y, R = y.reshape(p.N, -1), ref.reshape(p.N, -1)
+    assert np.array_equal(Y[0], R[0])
+    worst = max(relerr(Y[n], R[n]) for n in range(1, p.N))
+    print(f"c2 apply: whole block {relerr(y, ref):.2e}, worst slice {worst:.2e}", flush=True)
+    assert relerr(y, ref) < 1e-12 and worst < 1e-12
 
 
 # ---------------------------------------------------------------------------
@@ -326,15 +327,15 @@ def test_ragged_solve_matches_oracle(M, bc, N):
 
 
 def test_c2_full_size_fp64_solve():
-    """The 4096 x 256 advection-diffusion workload, FP64.
+    """The 4096 x 256 advection-diffusion workload, FP64, against the oracle's
+    Algorithm 1 on the same input.
 
     At the workload tolerance (1e-8, absolute) two correct runs of Algorithm 1
-    that round differently agree only to the level of their remaining error,
-    so there the check is the iteration count and the distance to the exact
-    (serial fine) solution.  Below about 1e-10 the residual of this
-    non-normal operator no longer decreases monotonically and iteration
-    counts are set by rounding, so at tol 1e-12 the check is the solution:
-    within 1e-10 of the serial fine trajectory.
+    that round differently agree only to the level of their remaining error
+    (about 1e-9 relative here), so there the checks are the iteration count,
+    the stopping residual and agreement to 1e-8.  At tol 1e-12 both runs are
+    within 1e-10 of the serial fine trajectory (the exact solution) and of each
+    other.
     """
     p = wl.C2.with_(prec=wl.F64)
     say("c2 fp64 full solve")
@@ -349,14 +350,17 @@ def test_c2_full_size_fp64_solve():
           f"gpu-vs-oracle {relerr(Xg, Xo):.2e} gpu-vs-serial {relerr(Xg, serial):.2e} "
           f"oracle-vs-serial {relerr(Xo, serial):.2e}", flush=True)
     assert ig.status == io.status == orc.OK
-    assert abs(ig.iters - io.iters) <= 1
+    assert ig.iters == io.iters and ig.matvecs == io.matvecs
     assert ig.res_norm <= p.tol and io.res_norm <= p.tol
-    assert relerr(Xg, serial) < 1e-7 and relerr(Xg, Xo) < 1e-7
+    assert relerr(Xg, Xo) < 1e-8 and relerr(Xg, serial) < 1e-7
     Xg, ig = c.solve(dev(u0), tol=1e-12)
     Xg = host(Xg)
-    print(f"tol 1e-12: gpu iters={ig.iters} gpu-vs-serial {relerr(Xg, serial):.2e}", flush=True)
-    assert ig.status == orc.OK
-    assert relerr(Xg, serial) < 1e-10
+    Xo, io = o.pitsbicg(u0, tol=1e-12)
+    print(f"tol 1e-12: gpu iters={ig.iters} oracle iters={io.iters} gpu-vs-serial {relerr(Xg, serial):.2e} "
+          f"oracle-vs-serial {relerr(Xo, serial):.2e} gpu-vs-oracle {relerr(Xg, Xo):.2e}", flush=True)
+    assert ig.status == io.status == orc.OK
+    assert relerr(Xg, serial) < 1e-10 and relerr(Xo, serial) < 1e-10
+    assert relerr(Xg, Xo) < 1e-10
 
 
 # ---------------------------------------------------------------------------
@@ -583,22 +587,34 @@ def test_adi_small_solve_matches_oracle(prec, lds, monkeypatch):
 
 def test_c3_full_size_fp32():
     """The 512 x 512, 128-slice heat workload (64 PR-ADI steps, FP32 fine):
-    the apply on sampled slices, and the solve's first slices against the
-    FP64 serial fine trajectory."""
+    the apply of a random block on every slice against the oracle's apply,
+    and the solve on every slice against the FP64 serial fine trajectory, with
+    the final state u(T) = F(lambda_{N-1}) (PIT_APPLY_LAST) against the
+    oracle's.  The bar is the FP32-fine one: 1e-5 relative."""
+    from paper_2203_10148_amd import pitsbicg as P
+
     p = wl.C3
     say("c3 full size")
     c = ctx(p)
-    o1 = make_oracle(p.with_(N=1, T=p.T / p.N))  # one slice of length DT
+    o = make_oracle(p)
     lam = wl.random_block(p, 3)
-    y = host(c.apply_F(dev(lam))).reshape(p.N, -1)
-    L = lam.reshape(p.N, -1)
-    for n in (1, 64, 127):
-        assert relerr(y[n], L[n] - o1.F(L[n - 1])) < 1e-5, n
+    y = host(c.apply_F(dev(lam)))
+    ref = o.apply(lam)
+    worst = max(relerr(y.reshape(p.N, -1)[n], ref.reshape(p.N, -1)[n]) for n in range(1, p.N))
+    print(f"c3 apply: block {relerr(y, ref):.2e}, worst slice {worst:.2e}", flush=True)
+    assert relerr(y, ref) < 1e-5 and worst < 1e-5
     u0 = wl.u0_for(p)
-    Xg, ig = c.solve(dev(u0), tol=p.tol, stall_window=10)
-    Xg = host(Xg).reshape(p.N, -1)
-    print(f"c3 fp32 solve: status={ig.status} iters={ig.iters} ms={ig.ms_total:.1f}", flush=True)
-    ref = u0.copy()
-    for n in range(6):
-        assert relerr(Xg[n], ref) < 1e-5, n
-        ref = o1.F(ref)
+    Xd, ig = c.solve(dev(u0), tol=p.tol, stall_window=10)
+    Xg = host(Xd).reshape(p.N, -1)
+    uT_g = host(c.apply_F(Xd, last=True)).reshape(p.N, -1)[-1]
+    serial, uT = o.serial(u0, want_uT=True)
+    S = serial.reshape(p.N, -1)
+    errs = np.array([relerr(Xg[n], S[n]) for n in range(p.N)])
+    e_all = relerr(Xg, S)
+    print(f"c3 fp32 solve: status={ig.status} iters={ig.iters} ms={ig.ms_total:.1f} res={ig.res_norm:.2e} "
+          f"block err {e_all:.2e}, worst slice {errs.max():.2e} (slice {errs.argmax()}), "
+          f"u(T) err {relerr(uT_g, uT):.2e}", flush=True)
+    assert ig.status in (P.OK, P.ENOCONV)
+    assert ig.res_norm <= 1e-6  # converged to tol or stopped at the FP32 floor, well below the data
+    assert e_all < 1e-5 and errs.max() < 1e-5
+    assert relerr(uT_g, uT) < 1e-5
