@@ -14,6 +14,9 @@ Bi-Conjugate Gradient Algorithm"):
   * ``pitsbicg``        -- Algorithm 1 (Sec. 3);
   * ``parareal_*``      -- Sec. 2, eqs. (pararealAlgebraic) and (pararealscheme);
   * ``serial``          -- the serial fine trajectory, the exact solution;
+  * ``set_fine_f32``    -- the FP32-fine form of F, emulated (1D: FP32 increment
+                           steps with a compensated float state; 2D: FP32 field
+                           storage between half steps), to predict its accuracy;
   * ``source``/``forced`` -- an optional source (Sec. 2, eq. (Cauchy)), constant
                            in time or separable, f(t, x) = g(t) h(x): the
                            propagator of slice n becomes affine, F_n(u) =
@@ -75,6 +78,8 @@ def _load():
     lib.orc_destroy.argtypes = [ct.c_void_p]
     lib.orc_set_source.argtypes = [ct.c_void_p, _D]
     lib.orc_set_source_t.argtypes = [ct.c_void_p, _D, _D]
+    lib.orc_set_fine_f32.argtypes = [ct.c_void_p, ct.c_int]
+    lib.orc_set_fine_f32.restype = ct.c_int
     lib.orc_forced.argtypes = [ct.c_void_p, _D]
     lib.orc_forced_slice.argtypes = [ct.c_void_p, ct.c_int, _D]
     lib.orc_F_slice.argtypes = [ct.c_void_p, ct.c_int, _D, _D]
@@ -147,7 +152,8 @@ class Oracle:
     """One PiT problem: a grid, an operator, N slices, fine and coarse steppers."""
 
     def __init__(self, *, dim=1, M=(64, 1), bc=DIRICHLET, length=(1.0, 1.0), nu=1.0,
-                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None, rot=0.0):
+                 adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None, rot=0.0,
+                 fine_f32=False):
         lib = _load()
         Mx, My = (M, 1) if isinstance(M, int) else (int(M[0]), int(M[1]))
         self.dim, self.Mx, self.My, self.N, self.m = dim, Mx, (My if dim == 2 else 1), N, m
@@ -161,6 +167,17 @@ class Oracle:
         self.weight = lib.orc_weight(h)
         if source is not None:
             self.set_source(source)
+        if fine_f32:
+            self.set_fine_f32(True)
+
+    def set_fine_f32(self, on=True):
+        """The fine propagator F as the emulated FP32-fine form (1D: FP32
+        increment-form steps with a compensated float state; 2D: FP32 storage
+        of the fields between half steps), or FP64 again.  Everything else
+        (the coarse propagator, the block products, Algorithm 1) stays FP64.
+        Not with a source."""
+        if _lib.orc_set_fine_f32(self._h, 1 if on else 0) != OK:
+            raise ValueError("oracle: the FP32-fine form takes no source")
 
     def set_source(self, f, g=None):
         """Set the source f (one slice of values), or remove it with None.

@@ -90,6 +90,7 @@ typedef struct {
     double DT;     /* slice length T/N */
     double *src;   /* source f, or its profile h (npts values, owned), or NULL */
     double *gt;    /* g(t_j), j = 0..N m (owned), or NULL: f constant in time */
+    int fine_f32;  /* 1: the fine propagator is the FP32-fine form (emulated) */
 } orc_ctx;
 
 static int g_threads = 1;
@@ -233,10 +234,15 @@ static size_t step_work(const orc_ctx *C)
     return (size_t)C->npts + 12 * (size_t)nmax;
 }
 
+/* Value stored by a 2D half step: rounded to float when `rnd` says so (the
+ * FP32-fine form's field storage). */
+static double stored(double v, int rnd) { return rnd ? (double)(float)v : v; }
+
 /* out = one step of `scheme` with time step dt applied to u (no aliasing);
- * the source of the step is wf * f (f NULL: none). */
+ * the source of the step is wf * f (f NULL: none).  2D only: rnd bit 1 rounds
+ * the intermediate field to float, bit 2 the output. */
 static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, double *out,
-                     double *work, const double *f, double wf)
+                     double *work, const double *f, double wf, int rnd)
 {
     if (C->dim == 1) {
         int n = C->Mx;
@@ -292,14 +298,14 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
                 }
                 op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
                 implicit_line(nx, ORC_DIRICHLET, dt, xlo, xdi, xup, line, sol, lw);
-                for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
+                for (int i = 0; i < nx; ++i) star[j * nx + i] = stored(sol[i], rnd & 1);
             }
 #pragma omp for schedule(static)
             for (int i = 0; i < nx; ++i) {
                 for (int j = 0; j < ny; ++j) line[j] = star[j * nx + i];
                 op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
                 implicit_line(ny, ORC_DIRICHLET, dt, ylo, ydi, yup, line, sol, lw);
-                for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+                for (int j = 0; j < ny; ++j) out[j * nx + i] = stored(sol[j], rnd & 2);
             }
             free(line);
         }
@@ -324,7 +330,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
             }
             op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
             implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
-            for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
+            for (int i = 0; i < nx; ++i) star[j * nx + i] = stored(sol[i], rnd & 1);
         }
         /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column
          * (the implicit barrier of the loop above orders the two halves) */
@@ -340,7 +346,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
             }
             op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
             implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);
-            for (int j = 0; j < ny; ++j) out[j * nx + i] = sol[j];
+            for (int j = 0; j < ny; ++j) out[j * nx + i] = stored(sol[j], rnd & 2);
         }
         free(line);
     }
@@ -354,26 +360,163 @@ static double src_weight(const orc_ctx *C, int scheme, int j)
     return (scheme == ORC_IE || scheme == ORC_ADI_IE) ? C->gt[j + 1] : 0.5 * (C->gt[j] + C->gt[j + 1]);
 }
 
+static void propagate_f32_1d(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
+                             double *out);
+
 /* Apply `nsteps` steps of `scheme`, each of length span/nsteps, with source f
  * (NULL: none): out = step^nsteps(in).  j0 is the global index of the first
  * step (for the weights of a time-dependent source), -1 for none.  in and
  * out may alias. */
 static void propagate(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
-                      double *out, const double *f, int j0)
+                      double *out, const double *f, int j0, int f32)
 {
+    if (f32 && C->dim == 1 && !f) {
+        propagate_f32_1d(C, scheme, nsteps, span, in, out);
+        return;
+    }
     size_t np = (size_t)C->npts;
     double dt = span / nsteps;
     double *base = (double *)malloc(sizeof(double) * (2 * np + step_work(C)));
     double *a = base, *b = base + np, *work = base + 2 * np;
     memcpy(a, in, sizeof(double) * np);
     for (int s = 0; s < nsteps; ++s) {
-        one_step(C, scheme, dt, a, b, work, f, src_weight(C, scheme, j0 < 0 ? -1 : j0 + s));
+        one_step(C, scheme, dt, a, b, work, f, src_weight(C, scheme, j0 < 0 ? -1 : j0 + s),
+                 f32 ? 1 | (s < nsteps - 1 ? 2 : 0) : 0);
         double *t = a;
         a = b;
         b = t;
     }
     memcpy(out, a, sizeof(double) * np);
     free(base);
+}
+
+/* ------------------------------------------------------------------------- */
+/* The FP32-fine form, emulated                                               */
+/* ------------------------------------------------------------------------- */
+/* The paper fixes no precision.  The FP32-fine form (a reading: the fine
+ * propagator in FP32, everything else in FP64) is emulated here, so that the
+ * accuracy it can reach is known on the CPU.
+ *
+ * 1D (IE, CN): FP32 state and step arithmetic, in increment form:
+ *   u' = u + D,   (I - th L) D = dt L u   (th = dt for IE, dt/2 for CN),
+ * equal to the standard form in exact arithmetic; a constant field gives
+ * D = 0 exactly.  dt L u is evaluated from differences,
+ *   pd (u_{j-1} - 2 u_j + u_{j+1}) + pa (u_{j-1} - u_{j+1}) - pr u_j,
+ * with pd = dt nu/h^2, pa = dt a/(2h), pr = dt r each rounded once to float.
+ * The Thomas factors of I - th L (and, periodic, the Sherman-Morrison vector)
+ * are formed in FP64 and rounded to float; the solve runs in float.  The
+ * state is an unevaluated float pair (u, e), u + e the value, updated with
+ * Fast2Sum (Dekker 1971): y = D + e, s = u + y, e' = y - (s - u), u' = s.
+ * The slice's input and output are FP64.
+ * 2D (PR-ADI, backward-Euler splitting): FP64 arithmetic with the fields
+ * between half steps stored in FP32: every half step's output is rounded to
+ * float except the last one of the slice.
+ * No source in either. */
+typedef struct {
+    int n, cyc;
+    float *l, *ip, *cp, *z; /* multipliers, inverse pivots, c/pivot, SM vector */
+    float bg, inv_den;      /* SM: beta/gam and 1/(1 + v.z) */
+} f32_line;
+
+/* Float factors of the n x n matrix with constant sub a, diagonal b, super c
+ * (cyclic: the corners too), in the layout of thomas() and cyclic(). */
+static void f32_line_build(int n, int cyc, double a, double b, double c, f32_line *F)
+{
+    double *bb = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *piv = bb + n, *y = bb + 2 * n;
+    F->n = n;
+    F->cyc = cyc;
+    F->l = (float *)malloc(sizeof(float) * 4 * (size_t)n);
+    F->ip = F->l + n;
+    F->cp = F->l + 2 * n;
+    F->z = F->l + 3 * n;
+    double gam = -b;
+    for (int i = 0; i < n; ++i) bb[i] = b;
+    if (cyc) {
+        bb[0] = b - gam;
+        bb[n - 1] = b - c * a / gam;
+    }
+    piv[0] = bb[0];
+    F->l[0] = 0.0f;
+    for (int i = 1; i < n; ++i) {
+        double l = a / piv[i - 1];
+        piv[i] = bb[i] - l * c;
+        F->l[i] = (float)l;
+    }
+    for (int i = 0; i < n; ++i) {
+        F->ip[i] = (float)(1.0 / piv[i]);
+        F->cp[i] = (float)((i < n - 1) ? c / piv[i] : 0.0);
+        F->z[i] = 0.0f;
+    }
+    F->bg = 0.0f;
+    F->inv_den = 0.0f;
+    if (cyc) { /* z = B^{-1} (gam, 0, .., 0, c), in FP64 */
+        for (int i = 0; i < n; ++i) y[i] = (i == 0) ? gam : (i == n - 1 ? c : 0.0);
+        for (int i = 1; i < n; ++i) y[i] -= (a / piv[i - 1]) * y[i - 1];
+        y[n - 1] = y[n - 1] / piv[n - 1];
+        for (int i = n - 2; i >= 0; --i) y[i] = (y[i] - c * y[i + 1]) / piv[i];
+        for (int i = 0; i < n; ++i) F->z[i] = (float)y[i];
+        F->bg = (float)(a / gam);
+        F->inv_den = (float)(1.0 / (1.0 + y[0] + (a / gam) * y[n - 1]));
+    }
+    free(bb);
+}
+
+/* d := A^{-1} d in float with the factors of F. */
+static void f32_line_solve(const f32_line *F, float *d)
+{
+    int n = F->n;
+    for (int i = 1; i < n; ++i) d[i] = d[i] - F->l[i] * d[i - 1];
+    d[n - 1] = d[n - 1] * F->ip[n - 1];
+    for (int i = n - 2; i >= 0; --i) d[i] = d[i] * F->ip[i] - F->cp[i] * d[i + 1];
+    if (F->cyc) {
+        float fac = (d[0] + F->bg * d[n - 1]) * F->inv_den;
+        for (int i = 0; i < n; ++i) d[i] = d[i] - fac * F->z[i];
+    }
+}
+
+/* out = nsteps FP32 increment-form steps of `scheme` (IE or CN) of length
+ * span/nsteps applied to in (1D, no source); in and out may alias. */
+static void propagate_f32_1d(const orc_ctx *C, int scheme, int nsteps, double span, const double *in,
+                             double *out)
+{
+    int n = C->Mx, per = C->bc == ORC_PERIODIC;
+    double dt = span / nsteps, th = (scheme == ORC_IE) ? dt : 0.5 * dt, h = C->hx;
+    double lo, di, up;
+    op1d(C->nu, C->ax, C->react, h, &lo, &di, &up);
+    f32_line F;
+    f32_line_build(n, per, -th * lo, 1.0 - th * di, -th * up, &F);
+    float pd = (float)(dt * (C->nu / (h * h))), pa = (float)(dt * (C->ax / (2.0 * h)));
+    float pr = (float)(dt * C->react);
+    float *u = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    float *e = u + n, *d = u + 2 * n;
+    for (int j = 0; j < n; ++j) {
+        u[j] = (float)in[j];
+        e[j] = (float)(in[j] - (double)u[j]);
+    }
+    for (int s = 0; s < nsteps; ++s) {
+        for (int j = 0; j < n; ++j) {
+            float um, uq;
+            if (per) {
+                um = u[(j - 1 + n) % n];
+                uq = u[(j + 1) % n];
+            } else {
+                um = (j > 0) ? u[j - 1] : 0.0f;
+                uq = (j < n - 1) ? u[j + 1] : 0.0f;
+            }
+            d[j] = pd * ((um - u[j]) + (uq - u[j])) + pa * (um - uq) - pr * u[j];
+        }
+        f32_line_solve(&F, d);
+        for (int j = 0; j < n; ++j) {
+            float y = d[j] + e[j];
+            float sum = u[j] + y;
+            e[j] = y - (sum - u[j]);
+            u[j] = sum;
+        }
+    }
+    for (int j = 0; j < n; ++j) out[j] = (double)u[j] + (double)e[j];
+    free(u);
+    free(F.l);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -429,9 +572,10 @@ void orc_destroy(orc_ctx *C)
 }
 
 /* Set (a copy of) the source f, constant in time, npts values in slice
- * layout; NULL removes it. */
+ * layout; NULL removes it.  A source switches the FP32-fine form off. */
 void orc_set_source(orc_ctx *C, const double *f)
 {
+    if (f) C->fine_f32 = 0;
     free(C->src);
     free(C->gt);
     C->src = NULL;
@@ -452,17 +596,27 @@ void orc_set_source_t(orc_ctx *C, const double *h, const double *g)
     memcpy(C->gt, g, sizeof(double) * ng);
 }
 
+/* Switch the fine propagator to the emulated FP32-fine form (on = 1) or
+ * back to FP64 (on = 0).  Returns -1 (and changes nothing) with a source
+ * set, which the FP32 form does not take. */
+int orc_set_fine_f32(orc_ctx *C, int on)
+{
+    if (on && C->src) return ORC_EINVAL;
+    C->fine_f32 = on ? 1 : 0;
+    return ORC_OK;
+}
+
 /* The linear part F0 of the fine propagator (no source). */
 static void F_lin(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL, -1);
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL, -1, C->fine_f32);
 }
 
 /* b_n = F_n(0): the forced response of slice n (0 without a source). */
 void orc_forced_slice(const orc_ctx *C, int n, double *b)
 {
     memset(b, 0, sizeof(double) * (size_t)C->npts);
-    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src, n * C->m);
+    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src, n * C->m, 0);
 }
 
 /* The forced response of slice 0 (of every slice when f is constant). */
@@ -488,7 +642,7 @@ double orc_weight(const orc_ctx *C) { return C->w; }
  * source if one is set (affine). */
 void orc_F_slice(const orc_ctx *C, int n, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src, n * C->m);
+    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src, n * C->m, C->fine_f32);
 }
 
 /* The fine propagator of slice 0 (of every slice when f is constant). */
@@ -498,7 +652,7 @@ void orc_F(const orc_ctx *C, const double *in, double *out) { orc_F_slice(C, 0, 
  * preconditioner's G; a source cancels from the parareal corrections). */
 void orc_G(const orc_ctx *C, const double *in, double *out)
 {
-    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL, -1);
+    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL, -1, 0);
 }
 
 /* One step of `scheme` with step dt and the source if set (exported for the
@@ -506,7 +660,7 @@ void orc_G(const orc_ctx *C, const double *in, double *out)
 void orc_step(const orc_ctx *C, int scheme, double dt, const double *in, double *out)
 {
     double *work = (double *)malloc(sizeof(double) * step_work(C));
-    one_step(C, scheme, dt, in, out, work, C->src, 1.0);
+    one_step(C, scheme, dt, in, out, work, C->src, 1.0, 0);
     free(work);
 }
 

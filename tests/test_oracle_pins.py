@@ -1048,3 +1048,122 @@ def test_c4_fourier_closed_form_is_the_oracle_serial(inst):
     ref = o.serial(wl.u0_fourier(q, seed)).reshape(q.N, -1)
     cf = fourier_serial(q, seed)
     assert relerr(cf, ref) < 1e-11, relerr(cf, ref)
+
+
+# ---------------------------------------------------------------------------
+# the FP32-fine form, emulated (predicts what an FP32 fine propagator reaches)
+# ---------------------------------------------------------------------------
+
+def test_fp32_form_keeps_a_constant_field_exactly():
+    """Periodic advection-diffusion without reaction: L annihilates constants,
+    and the increment form evaluates L u from differences, so every FP32 step
+    adds exactly 0 and the slice returns its input bit for bit."""
+    p = wl.C2.with_(N=2, m=50, prec=wl.F64)
+    o = make(p)
+    o.set_fine_f32(True)
+    u = np.full(p.npts, 0.375 + 2.0 ** -40)  # exactly a float pair (value, error)
+    assert np.array_equal(o.F(u), u)
+
+
+def test_fp32_form_is_fp32_and_within_the_bound_on_the_4096_point_workload():
+    """The 4096-point advection-diffusion workload (first 32 of 256 slices,
+    6400 CN steps) in the FP32-fine form against its exact FP64 trajectory
+    (the modal closed form): far from FP64 agreement (the form really rounds
+    to FP32) and well inside the 1e-5 bar."""
+    from closed_forms import fourier_serial
+
+    p = wl.C2.with_(N=32, T=wl.C2.T * 32 / wl.C2.N, prec=wl.F64)
+    o = make(p)
+    o.set_fine_f32(True)
+    seed = 2  # the workload's initial condition
+    u0 = wl.u0_fourier(p, seed)
+    x = o.serial(u0).reshape(p.N, -1)
+    e = relerr(x, fourier_serial(p, seed))
+    assert 1e-9 < e < 2e-6, e
+
+
+@pytest.mark.parametrize("inst", [0, 16])
+def test_fp32_form_on_stiff_diffusion_with_weak_advection(inst):
+    """Batch instances where diffusion dominates the step matrix (s = nu dt/h^2
+    about 55) and the advection is weak: the FP32 stencil keeps diffusion and
+    advection coefficients apart, so the advection speed is not swamped by
+    the diffusion part's rounding (rounding nu/h^2 +- a/(2h) as wholes moves
+    this trajectory by 1e-5 .. 1e-4).  First 60 slices against the exact
+    trajectory."""
+    from closed_forms import fourier_serial
+
+    p, seed = wl.c4_batch()[inst]
+    K = 60
+    q = p.with_(N=K, T=p.T * K / p.N, prec=wl.F64)
+    o = make(q)
+    o.set_fine_f32(True)
+    x = o.serial(wl.u0_fourier(q, seed)).reshape(K, -1)
+    e = relerr(x, fourier_serial(q, seed))
+    assert e < 1e-6, e
+
+
+def test_fp32_form_dirichlet_ie_sine_mode():
+    """IE with Dirichlet-0: sin(k pi x) is an exact grid eigenvector, so the
+    FP64 trajectory of one mode is r_k^(n m) sin(k pi x); the FP32 form stays
+    within 1e-6 of it over 16 slices of 64 steps."""
+    p = wl.C1
+    o = make(p)
+    o.set_fine_f32(True)
+    x = wl.grid_1d(p)
+    k, h = 3, 1.0 / (p.M[0] + 1)
+    mu = -(4 * p.nu / h ** 2) * math.sin(k * math.pi * h / 2) ** 2
+    r = 1.0 / (1.0 - (p.T / p.N / p.m) * mu)
+    u0 = np.sin(k * math.pi * x)
+    lam = o.serial(u0).reshape(p.N, -1)
+    exact = np.array([r ** (p.m * n) * u0 for n in range(p.N)])
+    e = relerr(lam, exact)
+    assert 1e-10 < e < 1e-6, e
+
+
+def test_fp32_form_2d_rounds_the_fields_between_half_steps():
+    """2D PR-ADI: FP64 arithmetic with the fields between half steps stored in
+    FP32: the slice output differs from FP64 at the FP32 level, and equals the
+    FP64 propagator when there is only one half-step pair to round (m = 1: the
+    intermediate field is rounded, so not even then bit-equal, but within
+    FP32 rounding)."""
+    p = wl.Problem(dim=2, M=(40, 30), bc=wl.DIRICHLET, nu=0.05, T=0.2, N=4, m=8, fine=wl.ADI, c=1,
+                   coarse=wl.ADI, prec=wl.F64)
+    o64 = make(p)
+    o32 = make(p)
+    o32.set_fine_f32(True)
+    u = wl.u0_gaussian(p)
+    a, b = o64.F(u), o32.F(u)
+    e = relerr(b, a)
+    assert 1e-10 < e < 1e-6, e
+    # the coarse propagator, the sweep and the inner products stay FP64
+    assert np.array_equal(o64.G(u), o32.G(u))
+
+
+def test_fp32_form_refuses_a_source():
+    p = wl.C1
+    o = make(p)
+    o.set_source(np.ones(p.npts))
+    with pytest.raises(ValueError):
+        o.set_fine_f32(True)
+    o2 = make(p)
+    o2.set_fine_f32(True)
+    o2.set_source(np.ones(p.npts))  # a source switches the FP32 form off
+    u = wl.u0_for(p)
+    assert np.array_equal(o2.F(u), o.F(u))
+
+
+@pytest.mark.parametrize("inst", [21, 53])
+def test_fp32_form_state_is_compensated(inst):
+    """Weakly diffusive batch instances (nu 3e-3 and 2.5e-4, 12-14 thousand
+    steps): each step's increment is a small fraction of the state, so a
+    plain float state would drift by its rounding (1.5e-5 and 1.8e-5 here);
+    the compensated pair keeps the whole trajectory within 1e-6 of the exact
+    one."""
+    from closed_forms import fourier_serial
+
+    p, seed = wl.c4_batch()[inst]
+    o = make(p.with_(prec=wl.F64))
+    o.set_fine_f32(True)
+    x = o.serial(wl.u0_fourier(p, seed)).reshape(p.N, -1)
+    e = relerr(x, fourier_serial(p, seed))
+    assert e < 1e-6, e
