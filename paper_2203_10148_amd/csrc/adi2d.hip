@@ -383,6 +383,91 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 }
 
 // ---------------------------------------------------------------------------
+// y half step, one column per wavefront (few slices: the coarse sweep)
+// ---------------------------------------------------------------------------
+// grid: nslices * ceil(Mx/CW) blocks of CW waves, for columns of at most 512
+// rows.  With one slice the column-strip kernel above has only Mx/32
+// workgroups; here a block owns CW columns.  It stages columns col0-1 ..
+// col0+CW of its slice in LDS (row by row, so the loads are contiguous per
+// row), wave w then forms the right-hand side of column col0+w from its two
+// neighbours and solves it with the register-resident line solver (lane l
+// holds rows l*C .. l*C+C-1; one wave per line, so no barrier inside the
+// solve), and the solution goes back through LDS so that the stores and the
+// epilogue's base reads are row-wise again.  In LDS a column keeps row r at
+// (r % C)*64 + r / C: the 64 lanes of one access read consecutive slots.
+template <int CW, int C, typename SIN, typename SOUT, int EPI>
+__global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SIN *__restrict__ in, long in_off,
+                                                    SOUT *__restrict__ out, long out_off,
+                                                    const double *__restrict__ base, long base_off, double sign,
+                                                    int nslices, int Mx, int My, double ex, double ed)
+{
+    constexpr int L = kWave * C, TW = CW + 2, NTH = CW * kWave;
+    __shared__ double tile[TW * L];
+    const int t = threadIdx.x, lane = t & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(t / kWave);
+    const int bx = (Mx + CW - 1) / CW;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk / bx, col0 = (blk % bx) * CW;
+    if (s >= nslices) return;  // uniform per block, before any barrier
+    const long npts = (long)Mx * My;
+    const SIN *islice = in + (size_t)(s + in_off) * npts;
+    auto slot = [](int r) { return (r % C) * kWave + r / C; };
+    // stage the CW + 2 columns (zeros left and right of the slice and below
+    // its last row: the Dirichlet values and the solver's pad rows)
+    constexpr int kIn = (TW * L + NTH - 1) / NTH;
+    double v[kIn];
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+        const int i = q * NTH + t, r = i / TW, col = col0 - 1 + i % TW;
+        v[q] = (i < TW * L && r < My && col >= 0 && col < Mx) ? to_d(islice[(size_t)r * Mx + col]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+        const int i = q * NTH + t;
+        if (i < TW * L) tile[(i % TW) * L + slot(i / TW)] = v[q];
+    }
+    // the epilogue's base values, read now so that their latency hides
+    // behind the staging and the solve
+    SOUT *oslice = out + (size_t)(s + out_off) * npts;
+    const double *bslice = EPI ? base + (size_t)(s + base_off) * npts : nullptr;
+    constexpr int kOut = (CW * L + NTH - 1) / NTH;
+    double bq[EPI ? kOut : 1];
+    if constexpr (EPI) {
+#pragma unroll
+        for (int q = 0; q < kOut; ++q) {
+            const int i = q * NTH + t, r = i / CW, col = col0 + i % CW;
+            bq[q] = (r < My && col < Mx) ? bslice[(size_t)r * Mx + col] : 0.0;
+        }
+    }
+    LineSolver<double, kWave, C, false> LS;
+    LS.load(tb, nullptr);
+    __syncthreads();
+    // right-hand side (I + theta Lx) u* of column col0 + w, then the solve
+    double d[C];
+    const int cc = w + 1;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int q = k * kWave + lane;  // slot of row lane*C + k
+        const double u = fma(ed, tile[cc * L + q], ex * (tile[(cc - 1) * L + q] + tile[(cc + 1) * L + q]));
+        d[k] = (lane * C + k < My) ? u : 0.0;
+    }
+    LS.solve(d);
+    __syncthreads();  // every wave has read its neighbours' columns
+#pragma unroll
+    for (int k = 0; k < C; ++k) tile[cc * L + k * kWave + lane] = d[k];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) {
+        const int i = q * NTH + t, r = i / CW, c = i % CW, col = col0 + c;
+        if (r < My && col < Mx) {
+            double x = tile[(c + 1) * L + slot(r)];
+            if constexpr (EPI) x = fma(sign, x, bq[q]);
+            oslice[(size_t)r * Mx + col] = (SOUT)x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 #define PIT_ADI_XC(X) X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 8)
@@ -420,6 +505,41 @@ static hipError_t adi_y_t(const AdiShape &sh, const ColTab &tb, const SIN *in, l
     }
     PIT_ADI_YSHAPES(X)
 #undef X
+    return hipErrorInvalidValue;
+}
+
+template <int CW, typename SIN, typename SOUT, int EPI>
+static hipError_t adi_yc_t(int cy, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,
+                           const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
+                           double ed, hipStream_t st)
+{
+    const int blocks = nslices * ((Mx + CW - 1) / CW);
+#define X(C_)                                                                                                  \
+    if (cy == C_) {                                                                                            \
+        hipLaunchKernelGGL((k_adi_yc<CW, C_, SIN, SOUT, EPI>), dim3(blocks), dim3(CW * 64), 0, st, tb, in,     \
+                           in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);               \
+        return hipGetLastError();                                                                              \
+    }
+    X(1) X(2) X(4) X(8)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adi_yc(int cw, int cy, const LineTab<double> &tb, const double *in, long in_off, double *out,
+                         long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
+                         double ex, double ed, hipStream_t st)
+{
+    if (64 * cy < My) return hipErrorInvalidValue;
+#define Y(CW_)                                                                                                 \
+    if (cw == CW_) {                                                                                           \
+        if (base)                                                                                              \
+            return adi_yc_t<CW_, double, double, 1>(cy, tb, in, in_off, out, out_off, base, base_off, sign,     \
+                                                    nslices, Mx, My, ex, ed, st);                              \
+        return adi_yc_t<CW_, double, double, 0>(cy, tb, in, in_off, out, out_off, nullptr, 0, 0.0, nslices, Mx, \
+                                                My, ex, ed, st);                                               \
+    }
+    Y(1) Y(2) Y(4)
+#undef Y
     return hipErrorInvalidValue;
 }
 

@@ -216,8 +216,8 @@ class Engine {
             d.c = c->coarse.substeps;
             d.bps = c->bps;
             d.w = c->w;
-            d.pl = c->pl;
-            d.pu = c->pu;
+            d.pd = c->pd;
+            d.pa = c->pa;
             d.pr = c->pr;
             d.periodic = c->pb.bc == PIT_PERIODIC ? 1 : 0;
             h_inst_[in->slot] = d;

@@ -66,8 +66,9 @@ struct pit_ctx {
     LineHost lc;  // coarse step matrix
     // workspace layout (byte offsets)
     size_t off_tf = 0, off_tf32 = 0, off_tc = 0, off_vec = 0, off_part = 0, off_red = 0, total = 0;
-    // increment-form stencil (FP32 fine propagator): dt L u = pl(u_{j-1}-u_j) + pu(u_{j+1}-u_j) - pr u_j
-    float pl = 0.f, pu = 0.f, pr = 0.f;
+    // increment-form stencil of the FP32 fine propagator, each part rounded on its own:
+    // dt L u = pd (u_{j-1} - 2u_j + u_{j+1}) + pa (u_{j-1} - u_{j+1}) - pr u_j
+    float pd = 0.f, pa = 0.f, pr = 0.f;
     int bps = 1;
     // bound workspace
     char *ws = nullptr;
@@ -83,6 +84,12 @@ struct pit_ctx {
     double fx_ex = 0, fx_ed = 0, fy_ex = 0, fy_ed = 0, cx_ex = 0, cx_ed = 0, cy_ex = 0, cy_ed = 0;
     size_t off_axf = 0, off_axc = 0, off_ayf = 0, off_ayc = 0, off_ubuf = 0, off_sbuf = 0, off_ctmp = 0;
     int adi_R = 32;  // rows per wavefront in the fine x half step
+    // coarse step, columns of at most 512 rows: line tables of one column
+    // (shape {64, ycc}) for the one-column-per-wave y half step of the sweep
+    LineHost aycl;
+    int ycc = 0;  // 0: not built (taller columns, or PIT_ADI_YC=0)
+    int ycw = 4;  // columns per workgroup of that kernel
+    size_t off_aycl = 0;
     // Source constant in time (host copy; empty: none) and, in the workspace,
     // the source (natural layout) and the forced response b = F(0) of one
     // slice in the working layout (1D chunked) and in the natural layout.
@@ -181,6 +188,11 @@ namespace pit {
 // The operators on block vectors of stride ld (chunked inside the solvers in 1D).
 hipError_t op_apply(const pit_ctx *c, const double *lam, double *y, int raw, int last, bool internal, hipStream_t st);
 hipError_t op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st);
+// pit_coarse_sweep on natural-layout vectors, launched directly (no graph),
+// with every temporary taken from `stage` (sweep_staging_bytes(c) bytes,
+// 8-byte aligned): 1D the chunked copies of v and z, 2D one-slice fields.
+hipError_t sweep_staged(const pit_ctx *c, const double *v, double *z, double *stage, hipStream_t st);
+size_t sweep_staging_bytes(const pit_ctx *c);
 // With a source: slices 1..N-1 of B (working layout) become b.  No-op without one.
 hipError_t fill_forced(const pit_ctx *c, double *B, hipStream_t st);
 

@@ -141,8 +141,8 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
 // FP64.
 template <int NT, int C, bool TR>
 __device__ __forceinline__ void fine1d_f32_slice(const LineTab<float> &tb, const double *__restrict__ lam,
-                                                 double *__restrict__ y, int M, long ld, int m, float pl,
-                                                 float pu, float pr, int periodic, int raw, int n, float *lds)
+                                                 double *__restrict__ y, int M, long ld, int m, float pd,
+                                                 float pa, float pr, int periodic, int raw, int n, float *lds)
 {
     const int t = threadIdx.x;
     if (!raw && n == 0) {  // y_0 = lam_0
@@ -160,7 +160,7 @@ __device__ __forceinline__ void fine1d_f32_slice(const LineTab<float> &tb, const
         u[k] = (float)ud[k];
         lo[k] = (float)(ud[k] - (double)u[k]);
     }
-    for (int s = 0; s < m; ++s) S.step_delta(u, lo, pl, pu, pr, M, periodic);
+    for (int s = 0; s < m; ++s) S.step_delta(u, lo, pd, pa, pr, M, periodic);
 #pragma unroll
     for (int k = 0; k < C; ++k) ud[k] = (double)u[k] + (double)lo[k];
     if (!raw) {
@@ -176,10 +176,10 @@ __device__ __forceinline__ void fine1d_f32_slice(const LineTab<float> &tb, const
 template <int NT, int C, bool TR>
 __global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const double *__restrict__ lam,
                                                    double *__restrict__ y, int N, int M, long ld, int m,
-                                                   float pl, float pu, float pr, int periodic, int raw, int n0)
+                                                   float pd, float pa, float pr, int periodic, int raw, int n0)
 {
     __shared__ float lds[LineSolver<float, NT, C>::kLds];
-    fine1d_f32_slice<NT, C, TR>(tb, lam, y, M, ld, m, pl, pu, pr, periodic, raw, n0 + blockIdx.x, lds);
+    fine1d_f32_slice<NT, C, TR>(tb, lam, y, M, ld, m, pd, pa, pr, periodic, raw, n0 + blockIdx.x, lds);
 }
 
 // One coarse slice step of the sweep: u <- G(u) + v_n (pads stay 0).
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_fine1d_f32_multi(Group g)
     const int vin = g.aux[2 * k], vout = g.aux[2 * k + 1];
     const Inst1d &d = g.inst[g.list[k]];
     const long nv = (long)d.N * d.ld;
-    fine1d_f32_slice<NT, C, true>(d.tf32, d.vec + vin * nv, d.vec + vout * nv, d.M, d.ld, d.m, d.pl, d.pu, d.pr,
+    fine1d_f32_slice<NT, C, true>(d.tf32, d.vec + vin * nv, d.vec + vout * nv, d.M, d.ld, d.m, d.pd, d.pa, d.pr,
                                   d.periodic, 0, blockIdx.x - g.first[k], lds);
 }
 
@@ -367,7 +367,7 @@ hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const doub
 }
 
 hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const double *lam, double *y, int N,
-                             int M, int m, float pl, float pu, float pr, int periodic, int raw, int last_only,
+                             int M, int m, float pd, float pa, float pr, int periodic, int raw, int last_only,
                              bool chunked, hipStream_t st)
 {
     const int n0 = last_only ? N - 1 : 0;
@@ -375,7 +375,7 @@ hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const doubl
     if (last_only) raw = 1;
 #define LAUNCH(nt, c, TR)                                                                         \
     hipLaunchKernelGGL((k_fine1d_f32<nt, c, TR>), dim3(grid), dim3(nt), 0, st, tb, lam, y, N, M,   \
-                       (long)(TR ? nt * c : M), m, pl, pu, pr, periodic, raw, n0)
+                       (long)(TR ? nt * c : M), m, pd, pa, pr, periodic, raw, n0)
 #define X(nt, c)                                  \
     if (sh.NT == nt && sh.C == c) {               \
         if (chunked) LAUNCH(nt, c, true);         \

@@ -325,14 +325,19 @@ struct LineSolver {
     }
 
     // One step in increment form:  u <- u + A^{-1} r,  with
-    //   r_j = pl (u_{j-1} - u_j) + pu (u_{j+1} - u_j) - pr u_j    (= dt L u, written
-    // with differences so that a constant field gives exactly 0).  Neighbour
-    // values inside a wavefront come from DPP; the two neighbours across wave
-    // edges and the periodic wrap (point 0 <-> point M-1) are exchanged in the
-    // forward scan's LDS round and enter as late right-hand-side terms: their
-    // effect on the carries is linear (multipliers rf_t and rfw_w), so no extra
-    // barrier is needed and every copy of a neighbour value is exact.
-    __device__ __forceinline__ void step_delta(T (&u)[C], T (&lo)[C], T pl, T pu, T pr, int M, int periodic)
+    //   r_j = pd (u_{j-1} - 2 u_j + u_{j+1}) + pa (u_{j-1} - u_{j+1}) - pr u_j
+    // (= dt L u: pd = dt nu/h^2, pa = dt a/(2h), pr = dt r).  The diffusion
+    // part is written with differences, so a constant field gives exactly 0,
+    // and the advection coefficient is rounded on its own: rounded as part of
+    // dt (nu/h^2 +- a/(2h)), where the diffusion part is far larger, it would
+    // lose most of its digits and the field would be advected at a visibly
+    // wrong speed.  Neighbour values inside a wavefront come from DPP; a
+    // neighbour across a wave edge or the periodic wrap (point 0 <-> point
+    // M-1) is exchanged in the forward scan's LDS round and enters as a late
+    // right-hand-side term, itself a difference with the point's own value:
+    // its effect on the carries is linear (multipliers rf_t and rfw_w), so no
+    // extra barrier is needed.  Pads (points M..) have a zero right-hand side.
+    __device__ __forceinline__ void step_delta(T (&u)[C], T (&lo)[C], T pd, T pa, T pr, int M, int periodic)
     {
         const int t = threadIdx.x;
         const int lane = t & (kWave - 1);
@@ -340,17 +345,21 @@ struct LineSolver {
         const int j0 = t * C;
         const T uprev = dpp<0x138>(u[C - 1]);  // lane-1's last point (lane 0 reads 0)
         const T unext = dpp<0x130>(u[0]);      // lane+1's first point (lane 63 reads 0)
-        // Padding points hold exactly 0, so the only one with a nonzero
-        // right-hand side is point M, pl*u_{M-1}, when its left neighbour is
-        // in the same wave: it reaches only the pads' forward values and the
-        // forward total, which is corrected below, and the pads still solve
-        // to 0.  So no point needs a mask here.
+        // A left or right neighbour outside the wave (or across the periodic
+        // wrap) is a late term; one outside a Dirichlet line is the boundary
+        // value 0, read in-wave (DPP and the zero pads supply it).
+        const bool left_late = lane == 0 && (w > 0 || periodic);
         T d[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const T left = (k == 0) ? uprev : u[k - 1];
-            const T right = (k == C - 1) ? unext : u[k + 1];
-            d[k] = fma(pl, left - u[k], fma(pu, right - u[k], -pr * u[k]));
+            const int j = j0 + k;
+            const bool ll = k == 0 && left_late;
+            const bool rl = (periodic && j == M - 1) || (k == C - 1 && lane == kWave - 1 && j < M - 1);
+            const T left = ll ? u[k] : ((k == 0) ? uprev : u[k - 1]);
+            const T right = rl ? u[k] : ((k == C - 1) ? unext : u[k + 1]);
+            const T al = ll ? T(0) : left, ar = rl ? T(0) : right;
+            const T v = fma(pd, (left - u[k]) + (right - u[k]), fma(pa, al - ar, -pr * u[k]));
+            d[k] = (j < M) ? v : T(0);
         }
         // point M-1: its thread, its index in that thread's chunk, its wave
         // (all uniform, so u_{M-1} is read with one readlane of one register)
@@ -358,7 +367,6 @@ struct LineSolver {
         const int kk = (M - 1) - owner_last * C;
         const int wstar = owner_last / kWave;
         const int wu = __builtin_amdgcn_readfirstlane(w);
-        const bool padfix = M < NT * C && M % (kWave * C) != 0;
         const T v = fwd_scan(d);
         T cw = T(0), ytot, dL = T(0), dR = T(0), dM = T(0);
         if constexpr (W > 1) {
@@ -377,13 +385,25 @@ struct LineSolver {
             __syncthreads();
             const T u0 = sh[kUFirst];
             const T uM = sh[kUWrap];
-            if (periodic) dM = pu * u0;
+            if (periodic) dM = fma(pd, u0 - uM, -pa * u0);
+            // wave q's late terms: l at its first point Pq, r at its last Qq
+            auto late = [&](int q, T &l, T &r) {
+                const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
+                l = T(0);
+                r = T(0);
+                if (Pq < M && (q > 0 || periodic)) {
+                    const T ul = (q > 0) ? sh[kULast + q - 1] : uM;
+                    l = fma(pd, ul - sh[kUFirst + q], pa * ul);
+                }
+                if (Qq < M - 1) {
+                    const T ur = sh[kUFirst + q + 1];
+                    r = fma(pd, ur - sh[kULast + q], -pa * ur);
+                }
+            };
             if constexpr (kLaneComb) {  // lane q assembles wave q's terms
                 const int q = lane & (W - 1);
-                const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
-                T l = T(0), r = T(0);
-                if (Pq < M) l = pl * ((q > 0) ? sh[kULast + q - 1] : (periodic ? uM : T(0)));
-                if (Qq < M - 1) r = pu * sh[kUFirst + q + 1];
+                T l, r;
+                late(q, l, r);
                 T agg = sh[kAggF + q] + fma(sh[kRfw + q], l, r);
                 if (q == wstar) agg += dM;
                 const T S = lane_scan_up(agg, lane);
@@ -396,10 +416,8 @@ struct LineSolver {
                 T acc = T(0);
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
-                    const int Pq = q * kWave * C, Qq = Pq + kWave * C - 1;
-                    T l = T(0), r = T(0);
-                    if (Pq < M) l = pl * ((q > 0) ? sh[kULast + q - 1] : (periodic ? uM : T(0)));
-                    if (Qq < M - 1) r = pu * sh[kUFirst + q + 1];
+                    T l, r;
+                    late(q, l, r);
                     if (q == w) {
                         cw = acc;
                         dL = l;
@@ -411,7 +429,6 @@ struct LineSolver {
                 }
                 ytot = acc;
             }
-            if (padfix) ytot -= pl * uM;
         } else {
             const T u0 = readlane(u[0], 0);
             T uM = T(0);
@@ -419,11 +436,10 @@ struct LineSolver {
             for (int k = 0; k < C; ++k)
                 if (k == kk) uM = readlane(u[k], owner_last);
             if (periodic) {
-                dM = pu * u0;
-                dL = pl * uM;
+                dM = fma(pd, u0 - uM, -pa * u0);
+                dL = fma(pd, uM - u0, pa * uM);
             }
             ytot = readlane(v, kWave - 1) + fma(rfw0, dL, dM);
-            if (padfix) ytot -= pl * uM;
         }
         const T prev = dpp<0x138>(v);
         const T c = (lane == 0) ? cw : fma(rf, dL, fma(qf, cw, prev));

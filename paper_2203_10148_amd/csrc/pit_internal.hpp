@@ -126,9 +126,9 @@ hipError_t launch_fine1d_f64(LineShape sh, const LineTab<double> &tb, const doub
                              hipStream_t st);
 
 // Fine apply, 1D, FP32 state and arithmetic in increment form (see line1d.hpp);
-// lam and y stay FP64.  pl, pu, pr: dt L u = pl (u_{j-1}-u_j) + pu (u_{j+1}-u_j) - pr u_j.
+// lam and y stay FP64.  pd, pa, pr: dt L u = pd (u_{j-1} - 2u_j + u_{j+1}) + pa (u_{j-1} - u_{j+1}) - pr u_j.
 hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const double *lam, double *y, int N,
-                             int M, int m, float pl, float pu, float pr, int periodic, int raw, int last_only,
+                             int M, int m, float pd, float pa, float pr, int periodic, int raw, int last_only,
                              bool chunked, hipStream_t st);
 
 // Coarse sweep, 1D, FP64: z_0 = v_0, z_n = v_n + G(z_{n-1}).
@@ -168,6 +168,12 @@ struct AdiBuf {
 };
 hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in, long in_off, AdiBuf out,
                         long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st);
+// FP64 y half step with one column per wavefront (columns of at most 512
+// rows, 64*cy >= My; tb: the line tables of a column, shape {64, cy}), for
+// the single-slice steps of the coarse sweep; cw (1, 2 or 4) columns per block.
+hipError_t launch_adi_yc(int cw, int cy, const LineTab<double> &tb, const double *in, long in_off, double *out,
+                         long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
+                         double ex, double ed, hipStream_t st);
 hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
                         const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
                         double ed, hipStream_t st);
@@ -243,7 +249,7 @@ struct Inst1d {
     long ld;              // slice stride (NT*C of the fine line shape)
     int N, M, m, c, bps;
     double w;             // h^d, the weight of the discrete L2 product
-    float pl, pu, pr;     // increment-form stencil of the FP32 fine step
+    float pd, pa, pr;     // FP32 fine step: dt nu/h^2, dt a/(2h), dt r
     int periodic;
 };
 

@@ -364,8 +364,26 @@ bool setup_2d(pit_ctx &c)
         return okx && oky;
     };
     const bool prf = c.fine.scheme == PIT_ADI_PR, prc = c.coarse.scheme == PIT_ADI_PR;
-    return tables(adi_theta(c, true), prf, c.axf, c.ayf, c.fx_ex, c.fx_ed, c.fy_ex, c.fy_ed) &&
-           tables(adi_theta(c, false), prc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed);
+    if (!tables(adi_theta(c, true), prf, c.axf, c.ayf, c.fx_ex, c.fx_ed, c.fy_ex, c.fy_ed) ||
+        !tables(adi_theta(c, false), prc, c.axc, c.ayc, c.cx_ex, c.cx_ed, c.cy_ex, c.cy_ed))
+        return false;
+    // the coarse sweep's single-slice y half steps: one column per wavefront
+    // (PIT_ADI_YC=0 keeps the column-strip kernel; 1, 2, 4: columns per
+    // workgroup)
+    const char *yc = std::getenv("PIT_ADI_YC");
+    if (My <= 512 && !(yc && yc[0] == '0')) {
+        int cyc = 1;
+        while (64 * cyc < My) cyc *= 2;
+        const double th = adi_theta(c, false);
+        if (!build_line(My, false, -th * ky, 1.0 + 2.0 * th * ky + 0.5 * th * r, -th * ky, LineShape{64, cyc},
+                        c.aycl))
+            return false;
+        c.ycc = cyc;
+        // columns per workgroup: 2 (measured fastest at 512 x 512), or 1 or 4
+        // by PIT_ADI_YC
+        c.ycw = (yc && (yc[0] == '1' || yc[0] == '4')) ? yc[0] - '0' : 2;
+    }
+    return true;
 }
 
 // Per-line tables of one 2D step with a velocity field (theta = th; pr:
@@ -459,8 +477,8 @@ hipError_t fine_launch(const pit_ctx *c, const double *lam, double *y, int raw, 
                        hipStream_t st)
 {
     if (c->fine32())
-        return launch_fine1d_f32(c->lf.sh, c->tab32(c->lf, c->off_tf32), lam, y, c->N, c->npts, c->m, c->pl,
-                                 c->pu, c->pr, c->pb.bc == PIT_PERIODIC ? 1 : 0, raw, last, chunked, st);
+        return launch_fine1d_f32(c->lf.sh, c->tab32(c->lf, c->off_tf32), lam, y, c->N, c->npts, c->m, c->pd,
+                                 c->pa, c->pr, c->pb.bc == PIT_PERIODIC ? 1 : 0, raw, last, chunked, st);
     return launch_fine1d_f64(c->lf.sh, c->tab(c->lf, c->off_tf), lam, y, c->N, c->npts, c->m, c->fine.scheme,
                              raw, last, chunked, st);
 }
@@ -540,8 +558,11 @@ hipError_t apply_2dv(const pit_ctx *c, const double *lam, double *y, int raw, in
     return hipSuccess;
 }
 
-// 2D coarse sweep with a velocity field, one slice at a time.
-hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t st)
+// 2D coarse sweep with a velocity field, one slice at a time.  ta, tb: two
+// one-slice FP64 temporaries; wk: one slice of the y half-step's forward
+// values (none of them used by the whole-slice LDS kernel).
+hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, double *ta, double *tb, double *wk,
+                     hipStream_t st)
 {
     const int Mx = c->pb.M[0], My = c->pb.M[1];
     const long np = c->npts;
@@ -549,16 +570,15 @@ hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t s
     const VelTab t = c->vtab(false);
     if (vel_lds(c)) return launch_vel_sweep_lds(t, v, z, c->N, c->coarse.substeps, Mx, My, st);
     if (z != v && (e = launch_copy(z, v, np, st)) != hipSuccess) return e;
-    double *ta = c->ctmp(0), *tb = c->ctmp(1);
     const int cs = c->coarse.substeps;
     for (int n = 1; n < c->N; ++n) {
         for (int s = 0; s < cs; ++s) {
             if ((e = launch_vel_x(t, s == 0 ? z : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, t.expl, st)) != hipSuccess)
                 return e;
             if (s == cs - 1)
-                e = launch_vel_y(t, ta, 0, z, n, v, n, 1.0, c->vwk(), 1, Mx, My, t.expl, st);
+                e = launch_vel_y(t, ta, 0, z, n, v, n, 1.0, wk, 1, Mx, My, t.expl, st);
             else
-                e = launch_vel_y(t, ta, 0, tb, 0, nullptr, 0, 0.0, c->vwk(), 1, Mx, My, t.expl, st);
+                e = launch_vel_y(t, ta, 0, tb, 0, nullptr, 0, 0.0, wk, 1, Mx, My, t.expl, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -566,8 +586,9 @@ hipError_t sweep_2dv(const pit_ctx *c, const double *v, double *z, hipStream_t s
 }
 
 // 2D coarse sweep: z_0 = v_0, z_n = v_n + G(z_{n-1}), G = c PR-ADI steps of
-// DT/c, FP64, one slice at a time (one row per wavefront for latency).
-hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st)
+// DT/c, FP64, one slice at a time (one row per wavefront for latency).  ta,
+// tb: two one-slice FP64 temporaries.
+hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, double *tmpa, double *tmpb, hipStream_t st)
 {
     const int Mx = c->pb.M[0], My = c->pb.M[1];
     const long np = c->npts;
@@ -577,18 +598,28 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, hipStream_t st
     tx.cyclic = 0;
     tx.M = Mx;
     const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayc), c->ash.wy * c->ash.cy * c->ash.seg);
+    LineTab<double> tyc{};
+    if (c->ycc) {
+        tyc = line_tab_view<double>(reinterpret_cast<const double *>(c->ws + c->off_aycl), 64, c->ycc);
+        tyc.cyclic = 0;
+        tyc.M = My;
+    }
     const AdiBuf zb{nullptr, z, false};
-    const AdiBuf ta{nullptr, c->ctmp(0), false}, tb{nullptr, c->ctmp(1), false};
+    const AdiBuf ta{nullptr, tmpa, false}, tb{nullptr, tmpb, false};
     const int cs = c->coarse.substeps;
+    // y half step of slice n: one column per wavefront where the tables exist
+    auto yhalf = [&](const AdiBuf &out, long out_off, const double *base, long base_off, double sign) {
+        if (c->ycc)
+            return launch_adi_yc(c->ycw, c->ycc, tyc, tmpa, 0, out.d, out_off, base, base_off, sign, 1, Mx, My,
+                                 c->cy_ex, c->cy_ed, st);
+        return launch_adi_y(c->ash, ty, ta, 0, out, out_off, base, base_off, sign, 1, Mx, My, c->cy_ex, c->cy_ed, st);
+    };
     for (int n = 1; n < c->N; ++n) {
         for (int s = 0; s < cs; ++s) {
             if ((e = launch_adi_x(c->ash, tx, s == 0 ? zb : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, c->cx_ex,
                                   c->cx_ed, st)) != hipSuccess)
                 return e;
-            if (s == cs - 1)
-                e = launch_adi_y(c->ash, ty, ta, 0, zb, n, v, n, 1.0, 1, Mx, My, c->cy_ex, c->cy_ed, st);
-            else
-                e = launch_adi_y(c->ash, ty, ta, 0, tb, 0, nullptr, 0, 0.0, 1, Mx, My, c->cy_ex, c->cy_ed, st);
+            e = (s == cs - 1) ? yhalf(zb, n, v, n, 1.0) : yhalf(tb, 0, nullptr, 0, 0.0);
             if (e != hipSuccess) return e;
         }
     }
@@ -871,10 +902,37 @@ hipError_t pit::op_apply(const pit_ctx *c, const double *lam, double *y, int raw
 hipError_t pit::op_sweep(const pit_ctx *c, const double *v, double *z, bool internal, hipStream_t st)
 {
     if (c->dim2())
-        return replay(c, 1, v, z, 0, 0, st,
-                      [&](hipStream_t s) { return c->vel ? sweep_2dv(c, v, z, s) : sweep_2d(c, v, z, s); });
+        return replay(c, 1, v, z, 0, 0, st, [&](hipStream_t s) {
+            return c->vel ? sweep_2dv(c, v, z, c->ctmp(0), c->ctmp(1), c->vwk(), s)
+                          : sweep_2d(c, v, z, c->ctmp(0), c->ctmp(1), s);
+        });
     return launch_sweep1d_f64(c->lc.sh, c->tab(c->lc, c->off_tc), v, z, c->N, c->npts, c->coarse.substeps,
                               c->coarse.scheme, internal, st);
+}
+
+size_t pit::sweep_staging_bytes(const pit_ctx *c)
+{
+    if (!c->dim2()) return 2 * (size_t)c->ntc() * sizeof(double);
+    if (c->vel && vel_lds(c)) return 0;
+    return (c->vel ? 3 : 2) * (size_t)c->npts * sizeof(double);
+}
+
+hipError_t pit::sweep_staged(const pit_ctx *c, const double *v, double *z, double *stage, hipStream_t st)
+{
+    if (c->dim2()) {
+        const size_t np = (size_t)c->npts;
+        return c->vel ? sweep_2dv(c, v, z, stage, stage + np, stage + 2 * np, st)
+                      : sweep_2d(c, v, z, stage, stage + np, st);
+    }
+    // 1D: through the chunked layout, where every load and store of the
+    // sequential sweep is coalesced (the layout passes cost far less than the
+    // strided accesses they replace)
+    const int NT = c->lc.sh.NT, C = c->lc.sh.C;
+    double *a = stage, *b = stage + c->ntc();
+    hipError_t e;
+    if ((e = launch_to_chunked(v, a, c->N, c->npts, NT, C, st)) != hipSuccess) return e;
+    if ((e = op_sweep(c, a, b, true, st)) != hipSuccess) return e;
+    return launch_from_chunked(b, z, c->N, c->npts, NT, C, st);
 }
 
 extern "C" {
@@ -954,6 +1012,8 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         o = align_up(o + c->ayf.size() * sizeof(double));
         c->off_ayc = o;
         o = align_up(o + c->ayc.size() * sizeof(double));
+        c->off_aycl = o;
+        o = align_up(o + c->aycl.blob.size() * sizeof(double));
         c->off_ubuf = o;
         o = align_up(o + (size_t)N * c->npts * fs);
         c->off_sbuf = o;
@@ -1000,11 +1060,12 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         return PIT_EINVAL;
     }
     {
-        double lo, di, up;
-        stencil1d(*problem, c->hx, &lo, &di, &up);
-        const double dt = c->DT / m;
-        c->pl = (float)(dt * lo);
-        c->pu = (float)(dt * up);
+        // the FP32 step's stencil: diffusion, advection and reaction parts,
+        // each rounded once (their sums lo, up would carry the small
+        // advection part with the rounding error of the large diffusion part)
+        const double dt = c->DT / m, h = c->hx;
+        c->pd = (float)(dt * (problem->nu / (h * h)));
+        c->pa = (float)(dt * (problem->adv[0] / (2.0 * h)));
         c->pr = (float)(dt * problem->react);
     }
     c->ld = (long)sh.NT * sh.C;
@@ -1086,6 +1147,9 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
                           hipMemcpyHostToDevice));
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_ayc, ctx->ayc.data(), ctx->ayc.size() * sizeof(double),
                           hipMemcpyHostToDevice));
+        if (ctx->ycc)
+            PIT_HIP(hipMemcpy(ctx->ws + ctx->off_aycl, ctx->aycl.blob.data(), ctx->aycl.blob.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
         if (ctx->vel) {
             PIT_HIP(hipMemcpy(ctx->ws + ctx->off_vtf, ctx->vtf.data(), ctx->vtf.size() * sizeof(double),
                               hipMemcpyHostToDevice));
@@ -1181,17 +1245,11 @@ int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream)
     if (!ctx || !ctx->ws || !v || !z) return PIT_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (ctx->dim2()) {
-        PIT_HIP(op_sweep(ctx, v, z, false, st));
+        PIT_HIP(op_sweep(ctx, v, z, false, st));  // captured once, replayed as a graph
         return PIT_OK;
     }
-    // 1D: through the chunked layout (two of the context's block vectors),
-    // where every load and store of the sequential sweep is coalesced; the
-    // two layout passes cost far less than the strided accesses they replace.
-    const int NT = ctx->lc.sh.NT, C = ctx->lc.sh.C;
-    double *a = ctx->vec(0), *b = ctx->vec(1);
-    PIT_HIP(launch_to_chunked(v, a, ctx->N, ctx->npts, NT, C, st));
-    PIT_HIP(op_sweep(ctx, a, b, true, st));
-    PIT_HIP(launch_from_chunked(b, z, ctx->N, ctx->npts, NT, C, st));
+    // 1D: staged through two of the context's block vectors (contiguous)
+    PIT_HIP(sweep_staged(ctx, v, z, ctx->vec(0), st));
     return PIT_OK;
 }
 
@@ -1415,6 +1473,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
     double rho_dev = 0.0;
 
     for (;;) {
+        bool dr_zero = false;  // the one-sync iteration found <D, R~> = 0 for the current P
         if (info && info->history && hl < info->history_cap) info->history[hl++] = nrm;
         if (!std::isfinite(nrm)) {
             status = PIT_EBREAKDOWN;
@@ -1467,7 +1526,11 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             RedOut hs[kRedSlots];
             if ((rc = s.fetch(hs))) return rc;
             const double dr = hs[1].dot[0];
-            if (dr != 0.0) {  // (dr == 0: the iteration is redone below, restart first)
+            // dr == 0: the update kernels left X, R and P unchanged; the
+            // iteration is redone below from the restart (the products of D
+            // and K queued before the breakdown was known are spent)
+            dr_zero = dr == 0.0;
+            if (!dr_zero) {
                 const double alpha = rho / dr;
                 const double ks = hs[2].dot[0], kk = hs[2].dot[1], snorm = hs[2].nmax[2];
                 if (kk == 0.0) {  // S = 0: the half step solved the system
@@ -1508,10 +1571,10 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 continue;
             }
         }
-        // D = G^{-1} F P
-        if ((rc = s.matvec(s.P, s.D))) return rc;
-        double dr;
-        {
+        // D = G^{-1} F P (known already when the one-sync iteration broke down)
+        double dr = 0.0;
+        if (!dr_zero) {
+            if ((rc = s.matvec(s.P, s.D))) return rc;
             const double *a[1] = {s.D}, *b[1] = {s.Rt};
             if ((rc = s.reduce(1, a, b, h))) return rc;
             dr = h.dot[0];

@@ -212,9 +212,13 @@ def test_c4_full_batch():
     converges for most instances; a few strongly advection-dominated ones
     (cell Peclet up to 26) make no progress, as the FP64 oracle does on them
     (see the next test), and must end with PIT_ENOCONV from the stagnation
-    rule.  Every converged instance is within its FP32 bound of the FP64
-    serial trajectory on its first 4 slices, the six cheapest on all slices,
-    and three instances alone give the batch's bits."""
+    rule.  Every instance whose residual went below 1e-6 is compared on all
+    of its slices with the exact FP64 serial fine trajectory, computed by the
+    modal closed form of periodic CN (each Fourier mode of u0 is an exact grid
+    eigenvector; the form is pinned against the oracle's serial solve on the
+    CPU), and three instances alone give the batch's bits."""
+    import closed_forms as cf
+
     P = P_()
     say("c4 full batch")
     insts = wl.c4_batch()
@@ -233,24 +237,22 @@ def test_c4_full_batch():
     # FP32 rounding floor before reaching 1e-8)
     low = [i for i, inf in enumerate(infos) if inf.history.min() <= 1e-6]
     print(f"c4 batch: {dt * 1e3:.1f} ms, {len(conv)} of {len(probs)} reached tol, {len(low)} below 1e-6", flush=True)
+    errs = {}
     for i, inf in enumerate(infos):
-        print(f"  inst {i}: M={probs[i].M[0]} N={probs[i].N} m={probs[i].m} nu={probs[i].nu:.1e} "
-              f"a={probs[i].adv[0]:.2f} status={inf.status} iters={inf.iters} min res={inf.history.min():.1e}",
-              flush=True)
+        p = probs[i]
+        line = (f"  inst {i}: M={p.M[0]} N={p.N} m={p.m} nu={p.nu:.1e} a={p.adv[0]:.2f} status={inf.status} "
+                f"iters={inf.iters} min res={inf.history.min():.1e}")
         assert inf.status in (orc.OK, orc.ENOCONV), (i, inf.status)
-    cost = [probs[i].N * probs[i].m * probs[i].M[0] for i in low]
-    cheap = {low[j] for j in np.argsort(cost)[:6]}
-    for i in low:
-        p, X = probs[i], host(Xs[i]).reshape(probs[i].N, -1)
-        K = 4
-        head = orc.Oracle(**p.with_(N=K, T=p.T * K / p.N).oracle_kwargs()).serial(u0h[i]).reshape(K, -1)
-        e = relerr(X[:K], head)
-        assert e < fp32_bound(p), (i, e)
-        if i in cheap:
-            full = orc.Oracle(**p.oracle_kwargs()).serial(u0h[i]).reshape(p.N, -1)
-            ef = relerr(X, full)
-            print(f"inst {i}: full trajectory err {ef:.2e}", flush=True)
-            assert ef < fp32_bound(p), (i, ef)
+        if i in low:
+            exact = cf.fourier_serial(p, insts[i][1])
+            errs[i] = relerr(host(Xs[i]).reshape(p.N, -1), exact)
+            line += f" err vs exact {errs[i]:.2e}"
+        print(line, flush=True)
+    worst = max(errs, key=errs.get)
+    print(f"c4: {sum(e < 1e-5 for e in errs.values())} of {len(errs)} compared instances within 1e-5, "
+          f"worst {errs[worst]:.2e} (inst {worst})", flush=True)
+    for i, e in errs.items():
+        assert e < 1e-5, (i, e)
     for i in (0, 17, 42):
         Xa, ia = P.Batch(1).solve([ctxs[i]], [u0s[i]], tol=1e-8, stall_window=10)
         assert ia[0].iters == infos[i].iters

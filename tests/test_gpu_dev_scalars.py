@@ -139,3 +139,49 @@ def test_negative_timing_stride_is_rejected():
     c = P.Context(HEAT1D)
     with pytest.raises(P.PitError):
         c.solve(dev(u0_of(HEAT1D)), timing=-1)
+
+
+@pytest.mark.parametrize("case", ["omega_zero", "shadow_zero"])
+@pytest.mark.parametrize("flag", ["1", "0"])
+def test_breakdown_branches_on_exact_cases(case, flag, monkeypatch):
+    """Algorithm 1's omega = 0 and <D, R~> = 0 branches, reached in exact
+    arithmetic (dyadic data, factors that are powers of two; the CPU pins of
+    these cases fix the oracle's behaviour).  Both iteration forms follow the
+    oracle's status, iterations, restarts and residual history, and give its
+    iterate.  The one-sync iteration learns <D, R~> = 0 only after it has
+    queued the product of K, so each such breakdown costs it one product more
+    than the oracle and the read-back form."""
+    import exact_cases as ec
+    from paper_2203_10148_amd import pitsbicg as P
+
+    say(f"exact breakdown case {case}, one-sync={flag}")
+    if case == "omega_zero":
+        p = ec.OMEGA_ZERO
+        u0, X0, _ = ec.omega_zero_data()
+        kw = dict(tol=1e-12)
+        okw = dict(tol=1e-12)
+    else:
+        p = ec.SHADOW_ZERO
+        u0, X0, _ = ec.shadow_zero_data()
+        kw = dict(tol=1e-13, restart_tol=-1.0, max_iter=20)
+        okw = dict(tol=1e-13, eps0=-1.0, max_iter=20)
+    o = orc.Oracle(**p.oracle_kwargs())
+    Xo, io = o.pitsbicg(u0, x0_mode=orc.X0_GIVEN, X0=X0, **okw)
+    monkeypatch.setenv("PIT_DEV_SCALARS", flag)
+    c = P.Context(p)
+    Xd = dev(X0)
+    Xd, ig = c.solve(dev(u0), Xd, x0_mode=P.X0_GIVEN, **kw)
+    Xg = host(Xd)
+    print(f"gpu status {ig.status} iters {ig.iters} restarts {ig.restarts} matvecs {ig.matvecs}; oracle "
+          f"{io.status} {io.iters} {io.restarts} {io.matvecs}", flush=True)
+    assert (ig.status, ig.iters, ig.restarts) == (io.status, io.iters, io.restarts)
+    extra = 1 if flag == "1" else 0  # one <D, R~> = 0 breakdown in either case
+    assert ig.matvecs == io.matvecs + extra
+    if case == "omega_zero":
+        assert ig.status == orc.EBREAKDOWN
+        assert np.array_equal(Xg, Xo)
+        assert np.array_equal(ig.history[:2], io.history[:2])
+    else:
+        assert ig.status == orc.OK
+        assert np.array_equal(ig.history[:3], io.history[:3])  # exact through the restart
+        assert float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)) < 1e-12

@@ -517,6 +517,32 @@ def test_adi_other_y_shapes_on_a_short_column(yshape, reported, monkeypatch):
     assert relerr(host(c.coarse_sweep(dev(lam))), o.sweep(lam)) < 1e-12
 
 
+@pytest.mark.parametrize("yc", ["", "1", "4", "0"])
+@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3)])
+def test_adi_sweep_y_kernels(Mx, My, c, yc, monkeypatch):
+    """The coarse sweep's single-slice y half step, one column per wavefront
+    (the default for columns up to 512 rows, 2 columns per workgroup; 1 and 4
+    by PIT_ADI_YC) and the column-strip kernel (PIT_ADI_YC=0), in and out of
+    place, against the oracle's forward substitution; c coarse steps per
+    slice."""
+    if yc:
+        monkeypatch.setenv("PIT_ADI_YC", yc)
+    else:
+        monkeypatch.delenv("PIT_ADI_YC", raising=False)
+    p = adi_problem(Mx, My, 1.0, 1.1, 5, 2, c, wl.F64)
+    say(f"adi sweep y kernel yc={yc} {Mx}x{My} c={c}")
+    cx = ctx(p)
+    o = make_oracle(p)
+    lam = wl.random_block(p, 23)
+    ref = o.sweep(lam)
+    e1 = relerr(host(cx.coarse_sweep(dev(lam))), ref)
+    d = dev(lam)
+    cx.coarse_sweep(d, d)
+    e2 = relerr(host(d), ref)
+    print(f"sweep vs oracle {e1:.2e}, in place {e2:.2e}", flush=True)
+    assert e1 < 1e-12 and e2 < 1e-12
+
+
 def test_adi_shared_tables_on_a_small_fp64_slice(monkeypatch):
     """The shared-table kernels on a slice that would otherwise take the LDS
     path (PIT_VEL_LDS=0 at creation), against the oracle."""
