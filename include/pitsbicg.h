@@ -247,6 +247,30 @@ int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void 
  * overlap another call on the same context.  Errors as pit_apply_F. */
 int pit_coarse_sweep(pit_ctx *ctx, const double *v, double *z, void *stream);
 
+/* Size of the library's fixed device scratch array (one per GPU, held from
+ * the library's load until the process ends). */
+#define PIT_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* pit_coarse_sweep for callers that cannot allocate device memory (code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same z = G^{-1} v with the same kernels and the same bits,
+ * but every temporary lives in the library's fixed scratch array of
+ * PIT_NOALLOC_SCRATCH_BYTES on the current device instead of the context's
+ * workspace, and the launches are issued directly (never through a HIP
+ * graph the library instantiates).  The call allocates nothing: no hipMalloc,
+ * hipFree, graph instantiation or host allocation.
+ * Scratch needed: 1D 16*N*L bytes, L = NT*C >= M the line shape that
+ * pit_kernel_shape reports (the chunked copies of v and z); 2D 16*Mx*My
+ * bytes (two one-slice fields), 24*Mx*My with a velocity field, none when
+ * the whole-slice LDS kernels run.  The context's workspace must be bound on
+ * the current device (it holds the coefficient tables) and `stream` must
+ * belong to that device.  Every call on a GPU shares that GPU's scratch
+ * array, so calls that overlap on one GPU (any context, any stream) race;
+ * serialise them.  v == z is allowed.  Asynchronous on `stream`.
+ * Errors: PIT_EINVAL (NULL pointers, unbound workspace), PIT_ENOMEM (the
+ * problem needs more scratch than PIT_NOALLOC_SCRATCH_BYTES), PIT_EHIP. */
+int pit_coarse_sweep_noalloc(pit_ctx *ctx, const double *v, double *z, void *stream);
+
 /* ---- solver ---------------------------------------------------------------- */
 
 /* Algorithm 1 (Sec. 3) on  G^{-1} F X = G^{-1} B,  B = (u0, 0, .., 0):

@@ -942,7 +942,7 @@ const char *pit_strerror(int code)
     switch (code) {
     case PIT_OK: return "ok";
     case PIT_EINVAL: return "invalid argument or unsupported combination";
-    case PIT_ENOMEM: return "workspace too small or over the memory budget";
+    case PIT_ENOMEM: return "workspace or fixed scratch too small, or over the memory budget";
     case PIT_EHIP: return "HIP runtime error";
     case PIT_ENOCONV: return "not converged (max_iter or stagnation)";
     case PIT_EBREAKDOWN: return "breakdown (non-finite residual)";

@@ -25,6 +25,7 @@ F64, F32 = 0, 1
 ABS, REL = 0, 1
 X0_ZERO, X0_GIVEN, X0_COARSE = 0, 1, 2
 APPLY_RAW, APPLY_LAST = 1, 2
+NOALLOC_SCRATCH_BYTES = 32 << 20  # PIT_NOALLOC_SCRATCH_BYTES
 
 
 class PitError(RuntimeError):
@@ -83,7 +84,7 @@ EXPORTS = (
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
     "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
-    "pit_parareal", "pit_set_source", "pit_set_source_t",
+    "pit_parareal", "pit_set_source", "pit_set_source_t", "pit_coarse_sweep_noalloc",
 )
 
 _lib = None
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.pit_set_source_t.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     lib.pit_apply_F.argtypes = [vp, vp, vp, i32, vp]
     lib.pit_coarse_sweep.argtypes = [vp, vp, vp, vp]
+    lib.pit_coarse_sweep_noalloc.argtypes = [vp, vp, vp, vp]
     lib.pit_solve.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
     lib.pit_parareal.argtypes = [vp, vp, vp, ct.POINTER(pit_solve_opts), ct.POINTER(pit_solve_info), vp]
     lib.pit_strerror.argtypes = [ct.c_int]
@@ -291,6 +293,18 @@ class Context:
         nt = self.p.N * self.p.npts
         _check(load().pit_coarse_sweep(self._h, _ptr(v, nt), _ptr(z, nt), _stream(stream)),
                "pit_coarse_sweep")
+        return z
+
+    def coarse_sweep_noalloc(self, v, z=None, stream=None):
+        """pit_coarse_sweep_noalloc: the sweep with the library's fixed
+        scratch array (z must be given for a call that allocates nothing)."""
+        import torch
+
+        if z is None:
+            z = torch.empty_like(v)
+        nt = self.p.N * self.p.npts
+        _check(load().pit_coarse_sweep_noalloc(self._h, _ptr(v, nt), _ptr(z, nt), _stream(stream)),
+               "pit_coarse_sweep_noalloc")
         return z
 
     def solve(self, u0, X=None, *, tol=None, restart_tol=1e-30, max_iter=0, norm_mode=ABS,

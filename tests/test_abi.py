@@ -123,6 +123,8 @@ def test_unbound_context_and_null_pointers_are_rejected():
     _, h = create(wl.C1)
     assert lib.pit_apply_F(h, None, None, 0, None) == P.EINVAL
     assert lib.pit_coarse_sweep(h, None, None, None) == P.EINVAL
+    assert lib.pit_coarse_sweep_noalloc(h, None, None, None) == P.EINVAL
+    assert lib.pit_coarse_sweep_noalloc(None, None, None, None) == P.EINVAL
     assert lib.pit_solve(h, None, None, None, None, None) == P.EINVAL
     assert lib.pit_bind_workspace(h, None, 0) == P.EINVAL
     assert lib.pit_bind_workspace(h, ct.c_void_p(256 * 1000 + 8), 1 << 30) == P.EINVAL  # misaligned
