@@ -513,8 +513,18 @@ def main():
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         b = torch.empty_like(a)
         b.copy_(a)
+        # the library's own streaming copy: the achievable-bandwidth reference
+        P.stream_copy(b, a)
         torch.cuda.synchronize()
-        log(f"[bench] probe {args.probe} done")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            P.stream_copy(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / 5
+        log(f"[bench] probe {args.probe} done; pit_stream_copy of 1 GiB: {cms:.3f} ms = "
+            f"{2 * CAL_BYTES / cms / 1e6:.0f} GB/s read + write")
         return
     u0 = torch.as_tensor(u0h, dtype=torch.float64, device=dev)
     X = torch.empty(p.N * p.npts, dtype=torch.float64, device=dev)

@@ -302,14 +302,43 @@ int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_solve_opts *o
  * and the coarse substeps.  Later pit_create calls for matching problems use
  * the recorded shape (unless the PIT_LINE_SHAPE environment variable forces
  * one).  Host-synchronous on `stream`.  out = {NT, C}; *out_ms (may be NULL)
- * = the winner's time.  Errors: PIT_EINVAL (2D, bad arguments), PIT_ENOMEM
- * (no shape fits the scratch), PIT_EHIP. */
+ * = the winner's time.  Errors: PIT_EINVAL (2D: see pit_autotune_adi; bad
+ * arguments), PIT_ENOMEM (no shape fits the scratch), PIT_EHIP. */
 size_t pit_autotune_scratch_bytes(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine,
                                   pit_stepper coarse);
 int pit_autotune(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
                  void *scratch, size_t bytes, int32_t out[2], float *out_ms, void *stream);
+/* The same for 2D problems without a velocity field (PR-ADI or the
+ * backward-Euler splitting): the launch shapes of the half-step kernels.  It
+ * times the fine apply for every x strip height R (rows per wavefront of the
+ * x half step: 8, 16, 32, 64) and every y shape (waves, rows per segment,
+ * segments per wave) of the kernel menu that covers the column, and the
+ * coarse sweep for every number of columns per workgroup (1, 2, 4) of its
+ * one-column-per-wavefront y kernel (columns up to 512 rows; 0 otherwise),
+ * using `scratch` as the workspace (pit_autotune_scratch_bytes also answers
+ * for 2D).  The winners are recorded per size class of each axis (rounded up
+ * to a power of two), both steppers' schemes, the fine precision and the
+ * coarse substeps; pit_create uses them for matching problems unless the
+ * PIT_ADI_ROWS, PIT_ADI_YSHAPE or PIT_ADI_YC environment variables force a
+ * choice.  Host-synchronous on `stream`.  out = {R, wy, cy, seg, columns};
+ * out_ms (may be NULL) = {the apply's time, the sweep's time}.  Errors:
+ * PIT_EINVAL (1D, a velocity field or a small FP64 slice that runs the
+ * whole-slice kernels: nothing to choose; bad arguments), PIT_ENOMEM (no
+ * candidate fits the scratch), PIT_EHIP. */
+int pit_autotune_adi(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+                     void *scratch, size_t bytes, int32_t out[5], float out_ms[2], void *stream);
 /* Forget every recorded shape (pit_create falls back to its defaults). */
 int pit_autotune_reset(void);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Device-to-device copy of `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned) with 16-byte loads and stores, four in flight per thread, on
+ * enough workgroups to fill every CU: the achievable-bandwidth reference the
+ * HBM-bound half-step kernels are measured against (it reads and writes
+ * `bytes` each).  Asynchronous on `stream`.  Errors: PIT_EINVAL (NULL or
+ * misaligned), PIT_EHIP. */
+int pit_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* ---- batched solves --------------------------------------------------------- */
 

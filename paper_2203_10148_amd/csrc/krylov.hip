@@ -7,6 +7,7 @@
 // produces per-slice sums.
 #include <algorithm>
 #include "pit_internal.hpp"
+#include "ctx.hpp"
 
 namespace pit {
 
@@ -241,6 +242,29 @@ __global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src,
         dst[i] = src[i];
 }
 
+// Streaming copy for bandwidth reference: 16-byte accesses, four in flight
+// per thread (the loads of a group are issued before its stores), a
+// grid-stride loop over groups of 4 * blockDim 16-byte units.
+using U4 = __attribute__((ext_vector_type(4))) unsigned;
+__global__ __launch_bounds__(256) void k_stream_copy(U4 *__restrict__ dst, const U4 *__restrict__ src, long n16)
+{
+    constexpr int K = 4;
+    const long step = (long)gridDim.x * blockDim.x * K;
+    for (long base = (long)blockIdx.x * blockDim.x * K + threadIdx.x; base < n16; base += step) {
+        U4 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const long i = base + (long)k * blockDim.x;
+            if (i < n16) v[k] = src[i];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const long i = base + (long)k * blockDim.x;
+            if (i < n16) dst[i] = v[k];
+        }
+    }
+}
+
 __global__ void k_fill0(double *__restrict__ dst, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -439,3 +463,21 @@ hipError_t launch_fill0(double *dst, long n, hipStream_t st)
 }
 
 }  // namespace pit
+
+// 256 CUs x 8 workgroups of 256 threads: every SIMD holds 8 waves.
+extern "C" int pit_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+        return PIT_EINVAL;
+    const long n16 = (long)(bytes / 16);
+    if (n16 == 0) return PIT_OK;
+    const long blocks = std::min<long>(2048, (n16 + 1023) / 1024);
+    hipLaunchKernelGGL(pit::k_stream_copy, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<pit::U4 *>(dst), static_cast<const pit::U4 *>(src), n16);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        pit::set_last_hip((int)e);
+        return PIT_EHIP;
+    }
+    return PIT_OK;
+}

@@ -97,6 +97,39 @@ bool tuned_shape(const TuneKey &k, int M, LineShape &out)
     return true;
 }
 
+// 2D launch shapes: rows per wavefront of the fine x half step, the y
+// half step's (waves, rows per segment, segments per wave), and the columns
+// per workgroup of the coarse sweep's one-column y kernel (0: not used).
+struct AdiTune {
+    int R, wy, cy, seg, ycw;
+};
+// Shapes chosen by pit_autotune for 2D problems, per size class of each axis
+// and stepper kinds.
+struct TuneKey2 {
+    int mx, my, fine_scheme, fine_prec, coarse_scheme, c, vel;
+    bool operator<(const TuneKey2 &o) const
+    {
+        return std::tie(mx, my, fine_scheme, fine_prec, coarse_scheme, c, vel) <
+               std::tie(o.mx, o.my, o.fine_scheme, o.fine_prec, o.coarse_scheme, o.c, o.vel);
+    }
+};
+std::map<TuneKey2, AdiTune> g_tuned2;
+
+TuneKey2 tune_key2(const pit_problem &p, const pit_stepper &f, const pit_stepper &g)
+{
+    const int vel = p.adv[0] != 0.0 || p.adv[1] != 0.0 || p.rot != 0.0;
+    return TuneKey2{length_class(p.M[0]), length_class(p.M[1]), f.scheme, f.prec, g.scheme, g.substeps, vel};
+}
+
+bool tuned_adi(const TuneKey2 &k, AdiTune &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned2.find(k);
+    if (it == g_tuned2.end()) return false;
+    out = it->second;
+    return true;
+}
+
 LineShape shape_from_env(const char *name, int M)
 {
     const char *s = std::getenv(name);
@@ -319,7 +352,20 @@ double adi_theta(const pit_ctx &c, bool fine_step)
 // and coarse steps: theta = dt/2 with the explicit halves (I + theta L) for
 // PR-ADI, theta = dt with identity explicit parts for the backward-Euler
 // splitting.
-bool setup_2d(pit_ctx &c)
+// The y shapes the kernels in adi2d.hip are instantiated for, smallest
+// first (two segments of 32 rows beat one segment up to 512 rows: 32-column
+// blocks, twice as many workgroups and two resident per CU).
+const AdiShape kYMenu[] = {{0, 8, 16, 1, 0}, {0, 8, 32, 1, 0}, {0, 8, 32, 2, 0}, {0, 16, 32, 2, 0},
+                           {0, 16, 32, 1, 0}, {0, 8, 16, 2, 0}, {0, 16, 16, 2, 0}};
+int yshape_rows(const AdiShape &a) { return a.wy * a.cy * a.seg; }
+bool yshape_known(int wy, int cy, int seg)
+{
+    for (const auto &a : kYMenu)
+        if (a.wy == wy && a.cy == cy && a.seg == seg) return true;
+    return false;
+}
+
+bool setup_2d(pit_ctx &c, const AdiTune *force)
 {
     const int Mx = c.pb.M[0], My = c.pb.M[1];
     // rows up to 512 points on one wavefront (up to 8 points per lane), wider
@@ -327,29 +373,35 @@ bool setup_2d(pit_ctx &c)
     const int xw = Mx > 512 ? 2 : 1;
     int cx = 1;
     while (64 * xw * cx < Mx) cx *= 2;
-    // y shapes (waves, rows per segment, segments per wave), smallest first;
-    // the kernels in adi2d.hip are instantiated for exactly these
-    // (two segments of 32 rows beat one segment up to 512 rows: 32-column
-    // blocks, twice as many workgroups and two resident per CU)
-    const AdiShape menu[] = {{0, 8, 16, 1, 0}, {0, 8, 32, 1, 0}, {0, 8, 32, 2, 0}, {0, 16, 32, 2, 0},
-                             {0, 16, 32, 1, 0}, {0, 8, 16, 2, 0}, {0, 16, 16, 2, 0}};
-    auto rows = [](const AdiShape &a) { return a.wy * a.cy * a.seg; };
+    // y shape: the smallest of the menu that covers the column; then the
+    // autotuned choice for this size class, the PIT_ADI_YSHAPE override
+    // "wy,cy,seg", and an autotuning candidate, each if it covers the column
     AdiShape sh{cx, 0, 0, 0, xw};
-    for (const auto &a : menu)
-        if (rows(a) >= My) {
+    for (const auto &a : kYMenu)
+        if (yshape_rows(a) >= My) {
             sh = a;
             sh.cx = cx;
             sh.xw = xw;
             break;
         }
     if (!sh.wy || cx > 8) return false;
-    if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {  // tuning override "wy,cy,seg"
-        AdiShape o{cx, 0, 0, 0, xw};
-        if (std::sscanf(e, "%d,%d,%d", &o.wy, &o.cy, &o.seg) == 3 && rows(o) >= My)
-            for (const auto &a : menu)
-                if (a.wy == o.wy && a.cy == o.cy && a.seg == o.seg) sh = o;
+    AdiTune tuned{};
+    const bool have_tuned = tuned_adi(tune_key2(c.pb, c.fine, c.coarse), tuned);
+    auto take = [&](int wy, int cy, int seg) {
+        const AdiShape o{cx, wy, cy, seg, xw};
+        if (yshape_known(wy, cy, seg) && yshape_rows(o) >= My) sh = o;
+    };
+    if (have_tuned) take(tuned.wy, tuned.cy, tuned.seg);
+    if (const char *e = std::getenv("PIT_ADI_YSHAPE")) {
+        int wy = 0, cy = 0, seg = 0;
+        if (std::sscanf(e, "%d,%d,%d", &wy, &cy, &seg) == 3) take(wy, cy, seg);
     }
+    if (force) take(force->wy, force->cy, force->seg);
     c.ash = sh;
+    // rows per wavefront of the fine x half step
+    if (have_tuned && tuned.R > 0) c.adi_R = tuned.R;
+    if (const char *e = std::getenv("PIT_ADI_ROWS")) c.adi_R = std::max(1, std::atoi(e));
+    if (force && force->R > 0) c.adi_R = force->R;
     const double nu = c.pb.nu, r = c.pb.react;
     const double kx = nu / (c.hx * c.hx), ky = nu / (c.hy * c.hy);
     auto tables = [&](double th, bool pr, LineHost &ax, std::vector<double> &ay, double &xex, double &xed,
@@ -369,9 +421,13 @@ bool setup_2d(pit_ctx &c)
         return false;
     // the coarse sweep's single-slice y half steps: one column per wavefront
     // (PIT_ADI_YC=0 keeps the column-strip kernel; 1, 2, 4: columns per
-    // workgroup)
+    // workgroup, as is the autotuned value)
     const char *yc = std::getenv("PIT_ADI_YC");
-    if (My <= 512 && !(yc && yc[0] == '0')) {
+    int ycw = 2;  // columns per workgroup: 2 measured fastest at 512 x 512
+    if (have_tuned) ycw = tuned.ycw;
+    if (yc && (yc[0] == '0' || yc[0] == '1' || yc[0] == '2' || yc[0] == '4')) ycw = yc[0] - '0';
+    if (force) ycw = force->ycw;
+    if (My <= 512 && ycw > 0) {
         int cyc = 1;
         while (64 * cyc < My) cyc *= 2;
         const double th = adi_theta(c, false);
@@ -379,9 +435,7 @@ bool setup_2d(pit_ctx &c)
                         c.aycl))
             return false;
         c.ycc = cyc;
-        // columns per workgroup: 2 (measured fastest at 512 x 512), or 1 or 4
-        // by PIT_ADI_YC
-        c.ycw = (yc && (yc[0] == '1' || yc[0] == '4')) ? yc[0] - '0' : 2;
+        c.ycw = ycw;
     }
     return true;
 }
@@ -960,7 +1014,7 @@ namespace {
 // pit_create with the 1D line shape forced (autotuning) or chosen: an
 // environment override, else the tuned table, else the default.
 int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
-               const LineShape *force, pit_ctx **out)
+               const LineShape *force, pit_ctx **out, const AdiTune *force2 = nullptr)
 {
     if (!out) return PIT_EINVAL;
     *out = nullptr;
@@ -981,7 +1035,7 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
         c->hx = problem->length[0] / (problem->M[0] + 1);
         c->hy = problem->length[1] / (problem->M[1] + 1);
         c->w = c->hx * c->hy;
-        if (!setup_2d(*c)) {
+        if (!setup_2d(*c, force2)) {
             delete c;
             return PIT_EINVAL;
         }
@@ -999,7 +1053,6 @@ int create_ctx(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fin
             delete c;
             return PIT_EINVAL;
         }
-        if (const char *e = std::getenv("PIT_ADI_ROWS")) c->adi_R = std::max(1, std::atoi(e));
         c->ld = c->npts;
         c->bps = (int)std::min<long>(64, std::max<long>(1, (c->ld + 4095) / 4096));
         const size_t fs = c->fine32() ? sizeof(float) : sizeof(double);
@@ -1687,6 +1740,30 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
 // ---------------------------------------------------------------------------
 namespace {
 
+// 2D candidates: x strip heights x the y shapes that cover the column
+// (at most four times its length), and the coarse columns per workgroup
+// (columns up to 512 rows; otherwise the column-strip kernel, 0).  The
+// first candidate carries the first value of every axis, so the apply is
+// timed once per (R, y shape) and the sweep once per column count.
+std::vector<AdiTune> adi_candidates(const pit_problem &p)
+{
+    const int My = p.M[1];
+    std::vector<AdiTune> v;
+    std::vector<int> ycws = My <= 512 ? std::vector<int>{2, 1, 4} : std::vector<int>{0};
+    bool first = true;
+    for (int R : {32, 8, 16, 64})
+        for (const auto &a : kYMenu) {
+            if (yshape_rows(a) < My || yshape_rows(a) > std::max(4 * My, 256)) continue;
+            if (first) {
+                for (int w : ycws) v.push_back(AdiTune{R, a.wy, a.cy, a.seg, w});
+                first = false;
+            } else {
+                v.push_back(AdiTune{R, a.wy, a.cy, a.seg, ycws.front()});
+            }
+        }
+    return v;
+}
+
 std::vector<LineShape> tune_candidates(int M)
 {
     std::vector<LineShape> v;
@@ -1717,13 +1794,99 @@ extern "C" {
 size_t pit_autotune_scratch_bytes(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine,
                                   pit_stepper coarse)
 {
-    if (validate(problem, N, m, fine, coarse) != PIT_OK || problem->dim != 1) return 0;
+    if (validate(problem, N, m, fine, coarse) != PIT_OK) return 0;
     size_t mx = 0;
+    if (problem->dim == 2) {
+        for (const AdiTune &a : adi_candidates(*problem)) {
+            CtxGuard g;
+            if (create_ctx(problem, N, m, fine, coarse, nullptr, &g.c, &a) == PIT_OK && !g.c->vel)
+                mx = std::max(mx, g.c->total);
+        }
+        return mx;
+    }
     for (LineShape sh : tune_candidates(problem->M[0])) {
         CtxGuard g;
         if (create_ctx(problem, N, m, fine, coarse, &sh, &g.c) == PIT_OK) mx = std::max(mx, g.c->total);
     }
     return mx;
+}
+
+int pit_autotune_adi(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
+                     void *scratch, size_t bytes, int32_t out[5], float out_ms[2], void *stream)
+{
+    if (!problem || !out || !scratch || (reinterpret_cast<uintptr_t>(scratch) % kAlign) != 0) return PIT_EINVAL;
+    int rc = validate(problem, N, m, fine, coarse);
+    if (rc != PIT_OK) return rc;
+    if (problem->dim != 2) return PIT_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EventGuard ev;
+    PIT_HIP(hipEventCreate(&ev.a));
+    PIT_HIP(hipEventCreate(&ev.b));
+    // best apply shape (R, y shape) and best sweep shape (coarse columns per
+    // workgroup), each timed on its own operation
+    float best_apply = -1.0f, best_sweep = -1.0f;
+    AdiTune win{0, 0, 0, 0, 0};
+    bool shared_tables = false;
+    const std::vector<AdiTune> cands = adi_candidates(*problem);
+    if (cands.empty()) return PIT_EINVAL;
+    const AdiTune f0 = cands.front();
+    for (const AdiTune &a : cands) {
+        CtxGuard g;
+        if (create_ctx(problem, N, m, fine, coarse, nullptr, &g.c, &a) != PIT_OK) continue;
+        if (g.c->vel) {  // per-line or whole-slice kernels: no shape to choose
+            shared_tables = true;
+            break;
+        }
+        if (g.c->total > bytes) continue;
+        if ((rc = pit_bind_workspace(g.c, scratch, bytes)) != PIT_OK) return rc;
+        pit_ctx *c = g.c;
+        PIT_HIP(launch_fill0(c->vec(0), kSolveVectors * c->ntc(), st));
+        for (int op = 0; op < 2; ++op) {
+            // the apply depends on (R, y shape) only, the sweep on the coarse
+            // columns only: time each where the candidate varies it
+            const bool first_y = a.ycw == f0.ycw;
+            const bool first_ry = a.R == f0.R && a.wy == f0.wy && a.cy == f0.cy && a.seg == f0.seg;
+            if ((op == 0 && !first_y) || (op == 1 && !first_ry)) continue;
+            float t = 0.0f;
+            for (int rep = 0; rep < 3; ++rep) {  // the first is a warm-up (and the graph capture)
+                PIT_HIP(hipEventRecord(ev.a, st));
+                if (op == 0) PIT_HIP(op_apply(c, c->vec(2), c->vec(6), 0, 0, true, st));
+                else PIT_HIP(op_sweep(c, c->vec(6), c->vec(3), true, st));
+                PIT_HIP(hipEventRecord(ev.b, st));
+                PIT_HIP(hipEventSynchronize(ev.b));
+                float ms = 0.0f;
+                PIT_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                if (rep == 1 || (rep > 1 && ms < t)) t = ms;
+            }
+            if (op == 0 && (best_apply < 0.0f || t < best_apply)) {
+                best_apply = t;
+                win.R = c->adi_R;
+                win.wy = c->ash.wy;
+                win.cy = c->ash.cy;
+                win.seg = c->ash.seg;
+            }
+            if (op == 1 && (best_sweep < 0.0f || t < best_sweep)) {
+                best_sweep = t;
+                win.ycw = c->ycc ? c->ycw : 0;
+            }
+        }
+    }
+    if (shared_tables) return PIT_EINVAL;
+    if (best_apply < 0.0f || best_sweep < 0.0f) return PIT_ENOMEM;  // nothing fitted the scratch memory
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned2[tune_key2(*problem, fine, coarse)] = win;
+    }
+    out[0] = win.R;
+    out[1] = win.wy;
+    out[2] = win.cy;
+    out[3] = win.seg;
+    out[4] = win.ycw;
+    if (out_ms) {
+        out_ms[0] = best_apply;
+        out_ms[1] = best_sweep;
+    }
+    return PIT_OK;
 }
 
 int pit_autotune(const pit_problem *problem, int32_t N, int32_t m, pit_stepper fine, pit_stepper coarse,
@@ -1776,6 +1939,7 @@ int pit_autotune_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned.clear();
+    g_tuned2.clear();
     return PIT_OK;
 }
 

@@ -83,7 +83,7 @@ EXPORTS = (
     "pit_coarse_sweep", "pit_solve", "pit_strerror", "pit_last_hip_error", "pit_kernel_shape",
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
-    "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset",
+    "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset", "pit_autotune_adi", "pit_stream_copy",
     "pit_parareal", "pit_set_source", "pit_set_source_t", "pit_coarse_sweep_noalloc",
 )
 
@@ -131,6 +131,9 @@ def load(path: str = LIB_PATH):
     lib.pit_server_destroy.argtypes = [vp]
     lib.pit_autotune_scratch_bytes.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper]
     lib.pit_autotune_scratch_bytes.restype = sz
+    lib.pit_stream_copy.argtypes = [vp, vp, sz, vp]
+    lib.pit_autotune_adi.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper, vp, sz,
+                                     ct.POINTER(i32), ct.POINTER(ct.c_float), vp]
     lib.pit_autotune.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper, vp, sz,
                                  ct.POINTER(i32), ct.POINTER(ct.c_float), vp]
     _lib = lib
@@ -371,6 +374,34 @@ def autotune(p, device=None, stream=None):
            "pit_autotune")
     del buf
     return (int(out[0]), int(out[1])), float(ms.value)
+
+
+def autotune_adi(p, device=None, stream=None):
+    """Time the 2D half-step launch shapes for workloads.Problem p (2D, no
+    velocity field) and record the fastest for later contexts of the same
+    class; returns ((R, wy, cy, seg, columns), (apply ms, sweep ms))."""
+    lib = load()
+    pb = make_problem(p)
+    fine = pit_stepper(p.fine, p.m, p.prec, 0)
+    coarse = pit_stepper(p.coarse, p.c, F64, 0)
+    n = int(lib.pit_autotune_scratch_bytes(ct.byref(pb), p.N, p.m, fine, coarse))
+    if n == 0:
+        raise PitError(EINVAL, "pit_autotune_scratch_bytes")
+    buf, base = _aligned(n, device)
+    out = (ct.c_int32 * 5)()
+    ms = (ct.c_float * 2)()
+    _check(lib.pit_autotune_adi(ct.byref(pb), p.N, p.m, fine, coarse, base, n, out, ms, _stream(stream)),
+           "pit_autotune_adi")
+    del buf
+    return tuple(int(v) for v in out), (float(ms[0]), float(ms[1]))
+
+
+def stream_copy(dst, src, stream=None):
+    """pit_stream_copy of the tensor src into dst (same byte size)."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n
+    _check(load().pit_stream_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)), "pit_stream_copy")
+    return dst
 
 
 def autotune_reset():

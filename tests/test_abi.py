@@ -298,4 +298,21 @@ def test_autotune_scratch_covers_every_candidate_shape():
     p2 = wl.C3.with_(N=2, m=2)
     pb2 = P.make_problem(p2)
     f2, g2 = P.pit_stepper(p2.fine, p2.m, p2.prec, 0), P.pit_stepper(p2.coarse, p2.c, P.F64, 0)
-    assert lib.pit_autotune_scratch_bytes(ct.byref(pb2), p2.N, p2.m, f2, g2) == 0  # 1D only
+    n2 = lib.pit_autotune_scratch_bytes(ct.byref(pb2), p2.N, p2.m, f2, g2)  # 2D: every launch-shape candidate
+    _, h2 = create(p2)
+    assert n2 >= lib.pit_workspace_bytes(h2) > 0
+    lib.pit_destroy(h2)
+    out5 = (ct.c_int32 * 5)()
+    fake = ct.c_void_p(256 * 4096)  # never touched: the arguments are refused first
+    assert lib.pit_autotune_adi(ct.byref(pb), p.N, p.m, f, g, fake, n, out5, None, None) == P.EINVAL  # 1D
+    assert lib.pit_autotune_adi(ct.byref(pb2), p2.N, p2.m, f2, g2, None, n2, out5, None, None) == P.EINVAL
+    assert lib.pit_autotune_adi(ct.byref(pb2), p2.N, p2.m, f2, g2, fake, n2, None, None, None) == P.EINVAL
+
+
+def test_stream_copy_refuses_bad_arguments():
+    lib = P.load()
+    a = ct.c_void_p(256 * 4096)  # never touched: the arguments are refused first
+    assert lib.pit_stream_copy(None, a, 16, None) == P.EINVAL
+    assert lib.pit_stream_copy(a, None, 16, None) == P.EINVAL
+    assert lib.pit_stream_copy(a, a, 24, None) == P.EINVAL
+    assert lib.pit_stream_copy(ct.c_void_p(256 * 4096 + 8), a, 16, None) == P.EINVAL

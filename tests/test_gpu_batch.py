@@ -375,6 +375,32 @@ def test_autotuned_shape_is_used_and_correct():
     assert P.Context(p).kernel_shape()[:2] == default
 
 
+def test_autotuned_2d_shapes_are_used_and_correct():
+    """The 2D autotuner records launch shapes; the next context of that class
+    uses them, its apply and sweep still match the oracle, and after a reset
+    the defaults return."""
+    from paper_2203_10148_amd import pitsbicg as P
+
+    say("autotune 2d")
+    p = p2d(300, 200, 4, 3, wl.F32, c=2)
+    default = P.Context(p).kernel_shape()
+    (R, wy, cy, seg, cols), (ms_a, ms_s) = P.autotune_adi(p)
+    print(f"default {default} tuned R={R} y=({wy},{cy},{seg}) cols={cols}: apply {ms_a:.3f} ms sweep {ms_s:.3f} ms",
+          flush=True)
+    assert R in (8, 16, 32, 64) and wy * cy * seg >= 200 and cols in (1, 2, 4) and ms_a > 0 and ms_s > 0
+    c = P.Context(p)
+    assert c.kernel_shape()[2:] == (64 * wy, cy * seg)
+    o = orc.Oracle(**p.oracle_kwargs())
+    X, Y = wl.grid_2d(p)
+    lam = np.concatenate([(np.sin(np.pi * X) * np.sin((n + 1) * np.pi * Y)).reshape(-1) for n in range(p.N)])
+    assert relerr(host(c.apply_F(dev(lam))), o.apply(lam)) < 1e-5
+    assert relerr(host(c.coarse_sweep(dev(lam))), o.sweep(lam)) < 1e-12
+    P.autotune_reset()
+    assert P.Context(p).kernel_shape() == default
+    with pytest.raises(P.PitError):
+        P.autotune_adi(p1d(300, wl.PERIODIC, 4, 3))  # 1D: nothing for this tuner
+
+
 def test_batch_rejects_bad_requests_before_any_work():
     P = P_()
     say("batch argument checks")

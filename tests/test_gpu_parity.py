@@ -644,3 +644,19 @@ def test_c3_full_size_fp32():
     assert ig.res_norm <= 1e-6  # converged to tol or stopped at the FP32 floor, well below the data
     assert e_all < 1e-5 and errs.max() < 1e-5
     assert relerr(uT_g, uT) < 1e-5
+
+
+@pytest.mark.parametrize("nbytes", [16, 16 * 1023, 16 * 4096 * 4 + 48, 64 << 20])
+def test_stream_copy_copies_exactly(nbytes):
+    """pit_stream_copy (the bandwidth reference) copies every byte, also a
+    ragged tail of the grid-stride loop; misaligned sizes are refused."""
+    from paper_2203_10148_amd import pitsbicg as P
+
+    say(f"stream copy {nbytes} B")
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    P.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    with pytest.raises(P.PitError):
+        P.stream_copy(dst[:8], src[:8])
