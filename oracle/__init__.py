@@ -14,6 +14,8 @@ Bi-Conjugate Gradient Algorithm"):
   * ``pitsbicg``        -- Algorithm 1 (Sec. 3);
   * ``parareal_*``      -- Sec. 2, eqs. (pararealAlgebraic) and (pararealscheme);
   * ``serial``          -- the serial fine trajectory, the exact solution;
+  * ``set_nu_t``        -- a time-dependent operator, constant on each slice
+                           (nu s_n on slice n): per-slice F_n and G_n;
   * ``set_fine_f32``    -- the FP32-fine form of F, emulated (1D: FP32 increment
                            steps with a compensated float state; 2D: FP32 field
                            storage between half steps), to predict its accuracy;
@@ -79,6 +81,9 @@ def _load():
     lib.orc_set_source.argtypes = [ct.c_void_p, _D]
     lib.orc_set_source_t.argtypes = [ct.c_void_p, _D, _D]
     lib.orc_set_fine_f32.argtypes = [ct.c_void_p, ct.c_int]
+    lib.orc_set_nu_t.argtypes = [ct.c_void_p, _D]
+    lib.orc_set_nu_t.restype = ct.c_int
+    lib.orc_G_slice.argtypes = [ct.c_void_p, ct.c_int, _D, _D]
     lib.orc_set_fine_f32.restype = ct.c_int
     lib.orc_forced.argtypes = [ct.c_void_p, _D]
     lib.orc_forced_slice.argtypes = [ct.c_void_p, ct.c_int, _D]
@@ -153,7 +158,7 @@ class Oracle:
 
     def __init__(self, *, dim=1, M=(64, 1), bc=DIRICHLET, length=(1.0, 1.0), nu=1.0,
                  adv=(0.0, 0.0), react=0.0, T=1.0, N=4, m=4, fine=IE, c=1, coarse=IE, source=None, rot=0.0,
-                 fine_f32=False):
+                 fine_f32=False, nu_t=None):
         lib = _load()
         Mx, My = (M, 1) if isinstance(M, int) else (int(M[0]), int(M[1]))
         self.dim, self.Mx, self.My, self.N, self.m = dim, Mx, (My if dim == 2 else 1), N, m
@@ -169,6 +174,20 @@ class Oracle:
             self.set_source(source)
         if fine_f32:
             self.set_fine_f32(True)
+        if nu_t is not None:
+            self.set_nu_t(nu_t)
+
+    def set_nu_t(self, s):
+        """A time-dependent operator constant on each slice: the diffusion
+        coefficient on slice n is nu * s[n] (N positive values), or constant
+        again with None.  F, G, the apply, the sweep and Algorithm 1 all use
+        the slice's operator."""
+        if s is None:
+            _lib.orc_set_nu_t(self._h, None)
+            return
+        s = self._c(s)
+        if s.size != self.N or _lib.orc_set_nu_t(self._h, _p(s)) != OK:
+            raise ValueError("oracle: nu_t needs N finite positive factors")
 
     def set_fine_f32(self, on=True):
         """The fine propagator F as the emulated FP32-fine form (1D: FP32
@@ -224,9 +243,10 @@ class Oracle:
         u = self._c(u); out = self._slice()
         _lib.orc_F_slice(self._h, int(n), _p(u), _p(out)); return out
 
-    def G(self, u):
+    def G(self, u, n=0):
+        """The coarse propagator of slice n."""
         u = self._c(u); out = self._slice()
-        _lib.orc_G(self._h, _p(u), _p(out)); return out
+        _lib.orc_G_slice(self._h, int(n), _p(u), _p(out)); return out
 
     def step(self, scheme, dt, u):
         u = self._c(u); out = self._slice()

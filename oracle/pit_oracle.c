@@ -44,6 +44,10 @@
  *       advection-diffusion-reaction test of Sec. 4).  ux is constant along a
  *       row and uy along a column, so every line is a constant-stencil
  *       tridiagonal system, one per row or column.
+ * The operator may depend on time, constant on each slice: nu s_n on slice
+ * n (s_n > 0 given, orc_set_nu_t); F_n and G_n then differ from slice to
+ * slice, and the all-at-once operator carries F_{n-1} below the diagonal in
+ * row n and the preconditioner G_{n-1}.
  * f is an optional source (the source term of Sec. 2, eq. (Cauchy)); without
  * it f = 0.  It is either constant in time or separable, f(t, x) = g(t) h(x),
  * with g given at the fine step times t_j = j dt, j = 0..N m.  Fine step j
@@ -91,6 +95,8 @@ typedef struct {
     double *src;   /* source f, or its profile h (npts values, owned), or NULL */
     double *gt;    /* g(t_j), j = 0..N m (owned), or NULL: f constant in time */
     int fine_f32;  /* 1: the fine propagator is the FP32-fine form (emulated) */
+    double *nus;   /* per-slice diffusion factors s_n (N values, owned): nu on
+                      slice n is nu * s_n; NULL: nu constant in time */
 } orc_ctx;
 
 static int g_threads = 1;
@@ -567,6 +573,7 @@ void orc_destroy(orc_ctx *C)
     if (C) {
         free(C->src);
         free(C->gt);
+        free(C->nus);
     }
     free(C);
 }
@@ -606,17 +613,49 @@ int orc_set_fine_f32(orc_ctx *C, int on)
     return ORC_OK;
 }
 
-/* The linear part F0 of the fine propagator (no source). */
-static void F_lin(const orc_ctx *C, const double *in, double *out)
+/* A time-dependent operator, constant on each slice: L(t) = nu s_n D2 - a D1
+ * - r on [T_n, T_{n+1}) (the operator of the Cauchy problem restricted to
+ * slice n, Sec. 2, eq. (Cauchyn)).  Set (a copy of) the N factors s_n, or
+ * NULL for nu constant in time.  Returns -1 unless every s_n is finite and
+ * positive. */
+int orc_set_nu_t(orc_ctx *C, const double *s)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, NULL, -1, C->fine_f32);
+    if (s)
+        for (int n = 0; n < C->N; ++n)
+            if (!(s[n] > 0.0) || !isfinite(s[n])) return ORC_EINVAL;
+    free(C->nus);
+    C->nus = NULL;
+    if (s) {
+        C->nus = (double *)malloc(sizeof(double) * (size_t)C->N);
+        memcpy(C->nus, s, sizeof(double) * (size_t)C->N);
+    }
+    return ORC_OK;
+}
+
+/* The context of slice n: C itself, or a copy with nu * s_n. */
+static const orc_ctx *on_slice(const orc_ctx *C, int n, orc_ctx *tmp)
+{
+    if (!C->nus) return C;
+    *tmp = *C;
+    tmp->nu = C->nu * C->nus[n];
+    return tmp;
+}
+
+/* The linear part F0 of the fine propagator of slice n (no source). */
+static void F_lin(const orc_ctx *C, int n, const double *in, double *out)
+{
+    orc_ctx t;
+    const orc_ctx *S = on_slice(C, n, &t);
+    propagate(S, C->fine_scheme, C->m, C->DT, in, out, NULL, -1, C->fine_f32);
 }
 
 /* b_n = F_n(0): the forced response of slice n (0 without a source). */
 void orc_forced_slice(const orc_ctx *C, int n, double *b)
 {
+    orc_ctx t;
+    const orc_ctx *S = on_slice(C, n, &t);
     memset(b, 0, sizeof(double) * (size_t)C->npts);
-    if (C->src) propagate(C, C->fine_scheme, C->m, C->DT, b, b, C->src, n * C->m, 0);
+    if (C->src) propagate(S, C->fine_scheme, C->m, C->DT, b, b, C->src, n * C->m, 0);
 }
 
 /* The forced response of slice 0 (of every slice when f is constant). */
@@ -630,7 +669,7 @@ static void build_B(const orc_ctx *C, const double *u0, double *B)
     if (C->N > 1) {
         orc_forced_slice(C, 0, B + np);
         for (int n = 2; n < C->N; ++n) {
-            if (C->gt) orc_forced_slice(C, n - 1, B + (size_t)n * np);
+            if (C->gt || C->nus) orc_forced_slice(C, n - 1, B + (size_t)n * np);
             else memcpy(B + (size_t)n * np, B + np, sizeof(double) * np);
         }
     }
@@ -642,18 +681,26 @@ double orc_weight(const orc_ctx *C) { return C->w; }
  * source if one is set (affine). */
 void orc_F_slice(const orc_ctx *C, int n, const double *in, double *out)
 {
-    propagate(C, C->fine_scheme, C->m, C->DT, in, out, C->src, n * C->m, C->fine_f32);
+    orc_ctx t;
+    const orc_ctx *S = on_slice(C, n, &t);
+    propagate(S, C->fine_scheme, C->m, C->DT, in, out, C->src, n * C->m, C->fine_f32);
 }
 
 /* The fine propagator of slice 0 (of every slice when f is constant). */
 void orc_F(const orc_ctx *C, const double *in, double *out) { orc_F_slice(C, 0, in, out); }
 
-/* Coarse propagator over one slice: c steps of DT/c, linear (the
- * preconditioner's G; a source cancels from the parareal corrections). */
-void orc_G(const orc_ctx *C, const double *in, double *out)
+/* Coarse propagator over slice n: c steps of DT/c, linear (the
+ * preconditioner's G; a source cancels from the parareal corrections), with
+ * the slice's operator. */
+void orc_G_slice(const orc_ctx *C, int n, const double *in, double *out)
 {
-    propagate(C, C->coarse_scheme, C->c, C->DT, in, out, NULL, -1, 0);
+    orc_ctx t;
+    const orc_ctx *S = on_slice(C, n, &t);
+    propagate(S, C->coarse_scheme, C->c, C->DT, in, out, NULL, -1, 0);
 }
+
+/* The coarse propagator of slice 0 (of every slice when nu is constant). */
+void orc_G(const orc_ctx *C, const double *in, double *out) { orc_G_slice(C, 0, in, out); }
 
 /* One step of `scheme` with step dt and the source if set (exported for the
  * closed-form pins). */
@@ -677,7 +724,7 @@ void orc_apply(const orc_ctx *C, const double *lam, double *y)
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int n = 1; n < C->N; ++n) {
         double *f = (double *)malloc(sizeof(double) * np);
-        F_lin(C, lam + (size_t)(n - 1) * np, f);
+        F_lin(C, n - 1, lam + (size_t)(n - 1) * np, f);
         for (size_t j = 0; j < np; ++j) y[(size_t)n * np + j] = lam[(size_t)n * np + j] - f[j];
         free(f);
     }
@@ -700,7 +747,7 @@ void orc_sweep(const orc_ctx *C, const double *v, double *z)
     double *g = (double *)malloc(sizeof(double) * np);
     if (z != v) memcpy(z, v, sizeof(double) * np);
     for (int n = 1; n < C->N; ++n) {
-        orc_G(C, z + (size_t)(n - 1) * np, g);
+        orc_G_slice(C, n - 1, z + (size_t)(n - 1) * np, g);
         for (size_t j = 0; j < np; ++j) z[(size_t)n * np + j] = v[(size_t)n * np + j] + g[j];
     }
     free(g);
@@ -971,13 +1018,13 @@ void orc_parareal_pc(const orc_ctx *C, const double *u0, double *Lam, int iters)
         /* fine and old-coarse corrections of all slices (the parallel part) */
         for (int n = 0; n + 1 < C->N; ++n) {
             orc_F_slice(C, n, old + (size_t)n * np, f + (size_t)n * np);
-            orc_G(C, old + (size_t)n * np, g);
+            orc_G_slice(C, n, old + (size_t)n * np, g);
             for (size_t j = 0; j < np; ++j) f[(size_t)n * np + j] -= g[j];
         }
         /* sequential coarse prediction */
         memcpy(Lam, u0, sizeof(double) * np);
         for (int n = 0; n + 1 < C->N; ++n) {
-            orc_G(C, Lam + (size_t)n * np, g);
+            orc_G_slice(C, n, Lam + (size_t)n * np, g);
             for (size_t j = 0; j < np; ++j)
                 Lam[(size_t)(n + 1) * np + j] = g[j] + f[(size_t)n * np + j];
         }

@@ -1167,3 +1167,146 @@ def test_fp32_form_state_is_compensated(inst):
     x = o.serial(wl.u0_fourier(p, seed)).reshape(p.N, -1)
     e = relerr(x, fourier_serial(p, seed))
     assert e < 1e-6, e
+
+
+# ---------------------------------------------------------------------------
+# a time-dependent operator, constant on each slice (nu s_n on slice n)
+# ---------------------------------------------------------------------------
+
+NU_T = np.array([1.0, 2.5, 0.4, 1.7, 0.8, 3.0])
+
+
+def block_lower_slices(Ps):
+    """I on the diagonal, -P_{n-1} in block (n, n-1): the all-at-once operator
+    with a propagator per slice (Sec. 2, eq. (algebraiclinearsystem))."""
+    n, N = Ps[0].shape[0], len(Ps)
+    A = np.eye(N * n)
+    for i in range(1, N):
+        A[i * n:(i + 1) * n, (i - 1) * n:i * n] = -Ps[i - 1]
+    return A
+
+
+@pytest.mark.parametrize("p", TINY[:3], ids=["dir_ie", "per_cn", "adi"])
+def test_nu_t_operators_are_the_dense_slice_blocks(p):
+    """With nu s_n on slice n, the apply, the sweep and the slice propagators
+    equal the dense finite-difference blocks built with each slice's nu
+    (row n of the apply and of G carries slice n-1's propagator)."""
+    s = NU_T[: p.N]
+    o = make(p)
+    o.set_nu_t(s)
+    props = [dense_props(p.with_(nu=p.nu * sn)) for sn in s]
+    Fb = block_lower_slices([SF for SF, _ in props])
+    Gb = block_lower_slices([SG for _, SG in props])
+    v = wl.random_block(p, 12)
+    assert relerr(o.apply(v), Fb @ v) < 1e-13
+    assert relerr(o.sweep(v), np.linalg.solve(Gb, v)) < 1e-12
+    u = wl.random_block(p.with_(N=1), 3)
+    for n in range(p.N):
+        assert relerr(o.F(u, n), props[n][0] @ u) < 1e-13
+        assert relerr(o.G(u, n), props[n][1] @ u) < 1e-13
+    # and s = 1 on every slice is the constant operator, bit for bit
+    o1 = make(p)
+    o1.set_nu_t(np.ones(p.N))
+    assert np.array_equal(o1.apply(v), make(p).apply(v)) and np.array_equal(o1.sweep(v), make(p).sweep(v))
+
+
+@pytest.mark.parametrize("p", TINY[:3], ids=["dir_ie", "per_cn", "adi"])
+def test_nu_t_pitsbicg_is_textbook_bicgstab_on_the_slice_blocks(p):
+    """Algorithm 1 with per-slice operators: iterate by iterate the textbook
+    BiCGStab on the dense G^{-1} F of the slice blocks, and the serial
+    trajectory lambda_{n+1} = F_n(lambda_n) as the solution."""
+    s = NU_T[: p.N]
+    o = make(p)
+    o.set_nu_t(s)
+    props = [dense_props(p.with_(nu=p.nu * sn)) for sn in s]
+    Fb = block_lower_slices([SF for SF, _ in props])
+    Gb = block_lower_slices([SG for _, SG in props])
+    u0 = np.random.default_rng(21).standard_normal(p.npts)
+    B = np.zeros(p.N * p.npts); B[: p.npts] = u0
+    A, b = np.linalg.solve(Gb, Fb), np.linalg.solve(Gb, B)
+    X, info = o.pitsbicg(u0, tol=1e-13, eps0=0.0, max_iter=60)
+    assert info.status == orc.OK
+    xs, norms = bicgstab_textbook(A, b, o.weight, p.N, info.iters)
+    h = info.history
+    for k in range(len(h)):
+        if norms[k] < 1e-9 * norms[0]:
+            break
+        assert abs(h[k] - norms[k]) <= 1e-9 * norms[0], k
+    serial = o.serial(u0)
+    assert relerr(X, serial) < 1e-11 and relerr(serial, np.linalg.solve(Fb, B)) < 1e-12
+
+
+def test_nu_t_dirichlet_cn_modal_closed_form():
+    """CN, Dirichlet-0: sin(k pi x) is an exact grid eigenvector for every nu,
+    so lambda_n = prod_{j<n} rho_k(nu s_j)^m sin(k pi x); the closed form of
+    the slice-wise operator, 12 slices of 40 steps, modes 1 and 5."""
+    p = wl.C1.with_(fine=wl.CN, N=12, m=40)
+    s = 0.5 + np.abs(np.sin(np.arange(p.N) * 1.3)) * 2.0
+    o = make(p)
+    o.set_nu_t(s)
+    x = wl.grid_1d(p)
+    h, dt = 1.0 / (p.M[0] + 1), p.T / (p.N * p.m)
+    u0 = np.sin(np.pi * x) + 0.5 * np.sin(5 * np.pi * x)
+    lam = o.serial(u0).reshape(p.N, -1)
+    exact = np.zeros_like(lam)
+    for k, amp in ((1, 1.0), (5, 0.5)):
+        a = amp
+        for n in range(p.N):
+            exact[n] += a * np.sin(k * np.pi * x)
+            mu = -(4 * p.nu * s[n] / h ** 2) * math.sin(k * math.pi * h / 2) ** 2
+            a *= ((1 + 0.5 * dt * mu) / (1 - 0.5 * dt * mu)) ** p.m
+    assert relerr(lam, exact) < 1e-12
+
+
+def test_nu_t_periodic_advection_modal_closed_form():
+    """Periodic CN with advection and reaction, nu s_n on slice n: each
+    Fourier mode advances by its complex per-slice factor rho_k(nu s_n)^m."""
+    from closed_forms import periodic_cn_factor
+
+    p = wl.C2.with_(M=(256, 1), N=10, m=30, T=0.5, prec=wl.F64, react=0.3)
+    s = np.linspace(0.3, 4.0, p.N)
+    o = make(p)
+    o.set_nu_t(s)
+    f = wl.fourier_coeffs(7, 20)
+    x = wl.grid_1d(p)
+    k = f.k.astype(np.float64)
+    c = k ** -2 * (f.a - 1j * f.b)
+    u0 = (c[:, None] * np.exp(2j * np.pi * np.outer(k, x))).sum(0).real
+    lam = o.serial(u0).reshape(p.N, -1)
+    exact = []
+    for n in range(p.N):
+        exact.append((c[:, None] * np.exp(2j * np.pi * np.outer(k, x))).sum(0).real)
+        c = c * periodic_cn_factor(p.with_(nu=p.nu * s[n]), k) ** p.m
+    assert relerr(lam, np.array(exact)) < 1e-12
+
+
+def test_nu_t_adi_2d_modal_closed_form():
+    """2D PR-ADI, Dirichlet-0 on a rectangle: sin(k pi x) sin(l pi y) takes the
+    per-slice PR-ADI factor of nu s_n, m times per slice."""
+    p = wl.Problem(dim=2, M=(21, 17), length=(1.0, 0.8), nu=0.05, T=0.6, N=6, m=8, fine=wl.ADI, c=1,
+                   coarse=wl.ADI)
+    s = NU_T[: p.N]
+    o = make(p)
+    o.set_nu_t(s)
+    X, Y = wl.grid_2d(p)
+    hx, hy = 1.0 / 22, 0.8 / 18
+    th = 0.5 * p.T / (p.N * p.m)
+    k, l = 2, 3
+    mode = (np.sin(k * np.pi * X / 1.0) * np.sin(l * np.pi * Y / 0.8)).reshape(-1)
+    lam = o.serial(mode).reshape(p.N, -1)
+    a = 1.0
+    for n in range(p.N):
+        assert relerr(lam[n], a * mode) < 1e-12, n
+        nu = p.nu * s[n]
+        mx = -(4 * nu / hx ** 2) * math.sin(k * math.pi * hx / 2 / 1.0) ** 2
+        my = -(4 * nu / hy ** 2) * math.sin(l * math.pi * hy / 2 / 0.8) ** 2
+        a *= (((1 + th * mx) * (1 + th * my)) / ((1 - th * mx) * (1 - th * my))) ** p.m
+
+
+def test_nu_t_refuses_bad_factors():
+    o = make(wl.C1)
+    with pytest.raises(ValueError):
+        o.set_nu_t(np.ones(wl.C1.N - 1))
+    bad = np.ones(wl.C1.N); bad[3] = 0.0
+    with pytest.raises(ValueError):
+        o.set_nu_t(bad)
