@@ -393,9 +393,15 @@ def c2_summary(dev, reps=5):
         ms = float(np.median([i.ms_total for i in infos]))
         fine = sum(i.ms_fine for i in infos) / max(sum(i.n_fine_timed for i in infos), 1)
         sweep = sum(i.ms_coarse for i in infos) / max(sum(i.n_coarse_timed for i in infos), 1)
+        kry = sum(i.ms_krylov for i in infos) / max(sum(i.n_krylov_timed for i in infos), 1)
+        last = infos[-1]
         d = {"ms": ms, **solve_summary(infos, P),
-             "cell_updates_per_s": infos[-1].n_fine * p.cells_per_apply / (ms * 1e-3),
-             "fine_apply_avg_ms": fine, "coarse_sweep_avg_ms": sweep}
+             "cell_updates_per_s": last.n_fine * p.cells_per_apply / (ms * 1e-3),
+             "fine_apply_avg_ms": fine, "coarse_sweep_avg_ms": sweep, "krylov_per_iter_ms": kry,
+             # per-phase split of one solve from the sampled averages (the
+             # rest of the wall time is launch gaps and host round trips)
+             "phase_ms": {"fine": fine * last.n_fine, "sweep": sweep * last.n_coarse,
+                          "krylov": kry * last.iters}}
         if X64 is None:
             X64 = X.clone()
         else:
@@ -434,6 +440,9 @@ def main():
     ap.add_argument("--no-singles", action="store_true", help="c4: skip the single-instance baseline solves")
     ap.add_argument("--prec", default=None, choices=["f64", "f32"],
                     help="fine-propagator precision (default: the workload's)")
+    ap.add_argument("--nu-t", type=int, default=None, metavar="SEED",
+                    help="c1, c2: a time-dependent operator constant on each slice, nu s_n with seeded factors "
+                         "(pit_set_nu_t)")
     ap.add_argument("--source", type=int, default=None, metavar="SEED",
                     help="c1-c3, f2: add a seeded source term constant in time (pit_set_source)")
     ap.add_argument("--source-profile", action="store_true",
@@ -488,6 +497,10 @@ def main():
     log(f"[bench] workload {p.name} M={p.M} N={p.N} m={p.m} prec={args.prec}")
     ctx = P.Context(p, device=dev)
     source_f, source_g, src_ms = None, None, None
+    if args.nu_t is not None:
+        # the per-slice step tables are built and uploaded here (setup, not timed)
+        ctx.set_nu_t(wl.nu_factors(p, args.nu_t))
+        log(f"[bench] time-dependent operator: nu s_n per slice (seed {args.nu_t})")
     if args.source is not None:
         # the forced responses are computed at pit_set_source(_t) (setup, not timed)
         source_f = wl.source_bumps(p, args.source)
@@ -608,6 +621,11 @@ def main():
                              "timed_ms": ms_coarse, "timed_launches": n_coarse_timed, "bound": "hbm",
                              "work_per_launch": by_coarse, "unit": "GB/s", "peak": PEAK["hbm_GBs"]},
         }
+    # Algorithm 1's vector updates and inner products, sampled per iteration
+    n_kry_timed = sum(i.n_krylov_timed for i in infos)
+    kry_iter = sum(i.ms_krylov for i in infos) / max(n_kry_timed, 1)
+    phase_ms = {"fine": avg_fine * n_apply / args.steps, "sweep": avg_coarse * n_coarse / args.steps,
+                "krylov": kry_iter * sum(i.iters for i in infos) / args.steps}
     scale = {"TFLOP/s": 1e12, "GB/s": 1e9}
 
     def rate(v):
@@ -639,10 +657,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": p.name, "M": list(p.M[: p.dim]), "N": p.N, "m": p.m,
                    "fine": scheme, "coarse": f"{p.c}x{cscheme}", "bc": "periodic" if periodic else "dirichlet0",
-                   "tol": p.tol, "fine_prec": args.prec},
+                   "tol": p.tol, "fine_prec": args.prec,
+                   **({"nu_t_seed": args.nu_t} if args.nu_t is not None else {})},
         "roofline": roofline,
         "solve": solve_summary(infos, P),
         "kernels": {name: {**v, "achieved": rate(v)} for name, v in kern.items()},
+        "krylov_per_iter_ms": kry_iter, "phase_ms_per_solve": phase_ms,
         "fine_kernel_cell_updates_per_s": fine_cu_s,
         "kernel_shape": ctx.kernel_shape(),
     }
@@ -824,30 +844,60 @@ def bench_batch(args, dev):
     st = [i.status for i in infos]
     log(f"[bench] batch: {ms:.1f} ms per batched solve, {st.count(0)} of {len(st)} reached tol")
 
-    def singles(prec):
-        tot, its, mx = 0.0, 0, 0.0
-        for p, u in zip(probs, u0s):
+    # accuracy against the exact (serial fine FP64) trajectory of each
+    # instance, by the modal closed form of periodic CN (every Fourier mode of
+    # u0 is an exact grid eigenvector), for instances that reached tol
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from closed_forms import fourier_serial
+
+    exact = [fourier_serial(p, sd).reshape(-1) for p, sd in insts]
+
+    def err_of(i, X):
+        x = X.detach().cpu().numpy()
+        return float(np.linalg.norm(x - exact[i]) / np.linalg.norm(exact[i]))
+
+    batch_err = {i: err_of(i, Xs[i]) for i, inf in enumerate(infos) if inf.status == 0}
+
+    def singles(prec, tol=1e-8):
+        tot, its, mx, errs = 0.0, 0, 0.0, {}
+        for i, (p, u) in enumerate(zip(probs, u0s)):
             c = P.Context(p.with_(prec=prec), device=dev)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, inf = c.solve(u, tol=1e-8, stall_window=10)
+            X, inf = c.solve(u, tol=tol, stall_window=10)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             tot += dt
             mx = max(mx, dt)
             its += inf.iters
+            if inf.status == 0:
+                errs[i] = err_of(i, X)
             c.close()
-        return tot, its, mx
+        return tot, its, mx, errs
+
+    def err_stats(errs, among):
+        v = np.array([errs[i] for i in among if i in errs])
+        return {"n": int(v.size), "median": float(np.median(v)) if v.size else None,
+                "max": float(v.max()) if v.size else None}
 
     if args.no_singles:
         out = {"metric": "c4 batch only", "makespan_ms": ms, "value": cells * args.steps / elapsed,
                "reached_tol": st.count(0)}
         print(json.dumps(out), flush=True)
         return
-    s64, it64, m64 = singles(wl.F64)
+    s64, it64, m64, e64 = singles(wl.F64)
     log(f"[bench] single-instance plain FP64: {s64 * 1e3:.1f} ms summed, slowest {m64 * 1e3:.1f} ms")
-    s32, it32, m32 = singles(wl.F32)
+    s64b, it64b, m64b, e64b = singles(wl.F64, tol=1e-6)
+    log(f"[bench] single-instance plain FP64 at tol 1e-6: {s64b * 1e3:.1f} ms summed")
+    s32, it32, m32, _ = singles(wl.F32)
     log(f"[bench] single-instance FP32: {s32 * 1e3:.1f} ms summed, slowest {m32 * 1e3:.1f} ms")
+    both = sorted(set(batch_err) & set(e64) & set(e64b))
+    accuracy = {"against": "exact FP64 serial fine trajectory (modal closed form), every slice",
+                "instances": "those that reached tol in every form compared",
+                "batch_fp32_tol1e-8": err_stats(batch_err, both),
+                "single_fp64_tol1e-8": err_stats(e64, both),
+                "single_fp64_tol1e-6": err_stats(e64b, both)}
+    log(f"[bench] accuracy over {len(both)} instances: {json.dumps(accuracy)}")
     out = {
         "metric": "fine cell-updates/s, 64-instance batched PiTSBiCG (FP32 fine, tol 1e-8), 1 GPU",
         "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -861,7 +911,10 @@ def bench_batch(args, dev):
                   "sum_single_fp64_ms": s64 * 1e3, "sum_single_fp64_iters": it64,
                   "sum_single_fp32_ms": s32 * 1e3, "sum_single_fp32_iters": it32,
                   "slowest_single_fp64_ms": m64 * 1e3, "slowest_single_fp32_ms": m32 * 1e3,
-                  "speedup_vs_single_fp64": s64 * 1e3 / ms, "speedup_vs_single_fp32": s32 * 1e3 / ms},
+                  "sum_single_fp64_tol1e-6_ms": s64b * 1e3, "sum_single_fp64_tol1e-6_iters": it64b,
+                  "speedup_vs_single_fp64": s64 * 1e3 / ms, "speedup_vs_single_fp32": s32 * 1e3 / ms,
+                  "speedup_vs_single_fp64_tol1e-6": s64b * 1e3 / ms,
+                  "accuracy": accuracy},
     }
     print(json.dumps(out), flush=True)
 
@@ -877,7 +930,10 @@ def bench_serve(args, dev):
     from paper_2203_10148_amd import workloads as wl
 
     reqs = wl.c5_requests(rate=args.rate)[: args.requests]
-    log(f"[bench] c5: {len(reqs)} requests at {args.rate}/s, arena {args.arena_gib} GiB")
+    fprec = wl.F64 if args.prec == "f64" else wl.F32  # --prec f64: the same stream with plain FP64 fine
+    reqs = [(t, p.with_(prec=fprec), sd) for t, p, sd in reqs]
+    log(f"[bench] c5: {len(reqs)} requests at {args.rate}/s, arena {args.arena_gib} GiB, "
+        f"fine {'FP64' if fprec == wl.F64 else 'FP32'}")
     u0s, Xs = [], []
     for _, p, seed in reqs:
         u = wl.u0_bumps(p, seed) if p.dim == 2 else wl.u0_fourier(p, seed)
@@ -919,11 +975,13 @@ def bench_serve(args, dev):
         return float(np.percentile(a, q)) if len(a) else None
 
     out = {
-        "metric": "served PiTSBiCG solves/s with p50/p99 latency (FP32 fine, tol 1e-8), 1 GPU",
+        "metric": f"served PiTSBiCG solves/s with p50/p99 latency ({'FP64' if fprec == wl.F64 else 'FP32'} fine, "
+                  "tol 1e-8), 1 GPU",
         "value": len(reqs) / span, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f64" if fprec == wl.F64 else "f32", "data": "synthetic",
         "config": {"workload": "c5_serving", "requests": len(reqs), "rate_per_s": args.rate, "seed": 5,
+                   "fine_prec": "f64" if fprec == wl.F64 else "f32",
                    "arena_gib": args.arena_gib, "max_slots": 256, "tol": 1e-8},
         "roofline": None,
         "serving": {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": float(lat.max()),

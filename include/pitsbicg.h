@@ -122,10 +122,13 @@ typedef struct {
                                 many iterations (for FP32 fine propagators)         */
     int32_t timing;          /* >0: time launches with HIP events on `stream`: the
                                 first fine apply and coarse sweep and then every
-                                timing-th one of each (1: every launch).  Fills
-                                ms_fine / ms_coarse and n_fine_timed /
-                                n_coarse_timed.  Each timed launch adds two event
-                                records, and with them a gap, to the stream.
+                                timing-th one of each (1: every launch), and the
+                                vector updates and inner products of the first
+                                and every timing-th iteration.  Fills ms_fine /
+                                ms_coarse / ms_krylov and n_fine_timed /
+                                n_coarse_timed / n_krylov_timed.  Each timed
+                                launch or group adds two event records, and with
+                                them a gap, to the stream.
                                 <0 is PIT_EINVAL.                                   */
 } pit_solve_opts;
 
@@ -147,6 +150,10 @@ typedef struct {
     int32_t n_coarse; /* coarse-sweep launches in the call                    */
     int32_t n_fine_timed;   /* of those, timed (opts->timing); 0 in batches   */
     int32_t n_coarse_timed;
+    float ms_krylov;  /* summed duration of the vector updates and inner
+                         products of the timed iterations (the first and
+                         every timing-th; pit_solve only)                     */
+    int32_t n_krylov_timed; /* iterations whose Krylov launches were timed    */
 } pit_solve_info;
 
 typedef struct pit_ctx pit_ctx;
@@ -224,6 +231,24 @@ int pit_set_source(pit_ctx *ctx, const double *f);
  * replaces a separable source.  Errors: PIT_EINVAL (NULL ctx, non-finite
  * value), PIT_ENOMEM, PIT_EHIP. */
 int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g);
+
+/* A time-dependent operator, constant on each slice (1D): the Cauchy problem
+ * of Sec. 2, eq. (Cauchy), with its operator depending on time, restricted
+ * to slice n as in eq. (Cauchyn).  The diffusion coefficient on slice n is
+ * nu * s[n] (s: host, N positive finite values, copied; NULL: nu constant in
+ * time again), advection and reaction unchanged.  Slice n's fine propagator
+ * F_n and coarse propagator G_n then use that coefficient: row n of the
+ * all-at-once operator carries F_{n-1} (pit_apply_F: y_n = lam_n -
+ * F_{n-1}(lam_{n-1}); with PIT_APPLY_RAW y_n = F_n(lam_n)), the sweep
+ * z_n = v_n + G_{n-1}(z_{n-1}), and pit_solve, pit_parareal and batched
+ * solves follow.  Every slice gets its own step tables (N times the fine and
+ * coarse line tables, placed behind the rest of the workspace: call
+ * pit_workspace_bytes after this).  If the workspace is bound they are
+ * uploaded at once (synchronous, null stream); a bound workspace that is now
+ * too small is unbound and PIT_ENOMEM returned.  Errors: PIT_EINVAL (NULL
+ * ctx, 2D, a value not positive or not finite, a source set), PIT_ENOMEM,
+ * PIT_EHIP.  A source cannot be set while s is. */
+int pit_set_nu_t(pit_ctx *ctx, const double *s);
 
 /* ---- operators ------------------------------------------------------------ */
 

@@ -719,7 +719,7 @@ class Engine {
             for (Inst *in : T)
                 if (in->ph == PH_INIT || in->ph == PH_A || in->ph == PH_B) {
                     const pit_ctx *c = in->ctx;
-                    cls[{c->lc.sh.NT, c->lc.sh.C, c->coarse.scheme, 0}].push_back(in);
+                    cls[{c->lc.sh.NT, c->lc.sh.C, c->coarse.scheme, c->nu_t() ? 1 : 0}].push_back(in);
                 }
             for (auto &kv : cls) {
                 std::vector<int> list, first{0}, aux;
@@ -736,8 +736,8 @@ class Engine {
                 }
                 const Group g = group(list, first, aux, {});
                 const LineShape sh{kv.first.NT, kv.first.C};
-                const int sch = kv.first.a;
-                plan.push_back([=] { return launch_sweep1d_multi(sh, sch, g, st); });
+                const int sch = kv.first.a, per_slice = kv.first.b;
+                plan.push_back([=] { return launch_sweep1d_multi(sh, sch, per_slice != 0, g, st); });
             }
         }
         for (Inst *in : T)
@@ -873,6 +873,8 @@ void fill_info(const Inst *in, pit_solve_info *info)
     info->n_coarse = in->n_coarse;
     info->ms_fine = info->ms_coarse = 0.0f;
     info->n_fine_timed = info->n_coarse_timed = 0;
+    info->ms_krylov = 0.0f;
+    info->n_krylov_timed = 0;
     info->ms_total = (float)(in->t_done - in->t_admit);
 }
 

@@ -108,6 +108,16 @@ struct pit_ctx {
     bool src_t() const { return has_src() && !gt.empty(); }
     double *bft() const { return reinterpret_cast<double *>(ws + off_bft); }
     double *gw() const { return reinterpret_cast<double *>(ws + off_gw); }
+    // Time-dependent operator, constant on each slice (1D): the diffusion
+    // coefficient of slice n is nu * nus[n].  Per-slice fine, coarse and FP32
+    // fine tables (slice n at n times the stride) and per-slice scalars
+    // (kSliceScalars each) sit behind the rest of the workspace.
+    std::vector<double> nus;
+    bool nu_t() const { return !nus.empty(); }
+    std::vector<double> tft, tct, scf, scc;
+    std::vector<float> tf32t, scf32;
+    long str_f = 0, str_c = 0;
+    size_t off_tft = 0, off_tct = 0, off_tf32t = 0, off_scf = 0, off_scc = 0, off_scf32 = 0;
     // 2D with a velocity field: per-line tables of the fine and coarse PR-ADI
     // steps (layout of vel_tab_view), the y half-step's forward values for
     // all slices (wbuf) and for one slice (vwk).
@@ -158,6 +168,14 @@ struct pit_ctx {
     RedOut *red(int slot = 0) const { return reinterpret_cast<RedOut *>(ws + off_red) + slot; }
     LineTab<float> tab32(const LineHost &L, size_t off) const
     {
+        if (nu_t()) {  // per-slice tables: slice 0's view with the stride
+            LineTab<float> t = line_tab_view<float>(reinterpret_cast<const float *>(ws + off_tf32t), L.sh.NT, L.sh.C);
+            t.cyclic = L.cyclic;
+            t.M = L.M;
+            t.sstride = str_f;
+            t.sscal = reinterpret_cast<const float *>(ws + off_scf32);
+            return t;
+        }
         LineTab<float> t = line_tab_view<float>(reinterpret_cast<const float *>(ws + off), L.sh.NT, L.sh.C);
         t.inv_den = (float)L.inv_den;
         t.bg = (float)L.bg;
@@ -171,6 +189,16 @@ struct pit_ctx {
     bool fine32() const { return fine.prec == PIT_F32; }
     LineTab<double> tab(const LineHost &L, size_t off) const
     {
+        if (nu_t()) {  // per-slice tables: slice 0's view with the stride
+            const bool fine_tab = &L == &lf;
+            LineTab<double> t = line_tab_view<double>(
+                reinterpret_cast<const double *>(ws + (fine_tab ? off_tft : off_tct)), L.sh.NT, L.sh.C);
+            t.cyclic = L.cyclic;
+            t.M = L.M;
+            t.sstride = fine_tab ? str_f : str_c;
+            t.sscal = reinterpret_cast<const double *>(ws + (fine_tab ? off_scf : off_scc));
+            return t;
+        }
         LineTab<double> t = line_tab_view<double>(reinterpret_cast<const double *>(ws + off), L.sh.NT, L.sh.C);
         t.inv_den = L.inv_den;
         t.bg = L.bg;

@@ -98,7 +98,7 @@ __device__ __forceinline__ void fine1d_f64_slice(const LineTab<double> &tb, cons
         return;
     }
     LineSolver<double, NT, C> S;
-    S.load(tb, lds);
+    S.load(line_tab_slice(tb, raw ? n : n - 1), lds);  // the propagator of the slice it advances
     double u[C];
     load_chunk<NT, C, TR>(lam + (size_t)(raw ? n : n - 1) * ld, t, M, u);
     zero_pads<C>(t, M, u);
@@ -150,7 +150,9 @@ __device__ __forceinline__ void fine1d_f32_slice(const LineTab<float> &tb, const
         return;
     }
     LineSolver<float, NT, C> S;
-    S.load(tb, lds);
+    const int sl = raw ? n : n - 1;  // the slice whose propagator it applies
+    S.load(line_tab_slice(tb, sl), lds);
+    if (tb.sstride) pd = tb.sscal[kSliceScalars * sl + 5];
     double ud[C];
     load_chunk<NT, C, TR>(lam + (size_t)(raw ? n : n - 1) * ld, t, M, ud);
     zero_pads<C>(t, M, ud);
@@ -208,13 +210,25 @@ __device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double
 // loaded while slices n and n+1 are computed) and the prefetch index is
 // clamped instead of guarded, so the loaded registers are consumed where
 // they land.
-template <int NT, int C, int SCHEME, bool TR>
+template <int NT, int C, int SCHEME, bool TR, bool PS>
 __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, const double *v, double *z, int N,
                                                  int M, long ld, int c, double *lds)
 {
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
-    S.load(tb, lds);
+    S.load(PS ? line_tab_slice(tb, 0) : tb, lds);
+    // PS (an operator per slice): step n uses G_{n-1}, whose tables are
+    // loaded before the step (after a barrier, since the previous step's
+    // solves read the LDS slots that the load rewrites).  n is uniform.  A
+    // separate instantiation, so the constant operator's kernel keeps its
+    // registers.
+    auto tables_for = [&](int n) {
+        if constexpr (PS) {
+            if (n < 2) return;
+            if constexpr (LineSolver<double, NT, C>::W > 1) __syncthreads();
+            S.load(line_tab_slice(tb, n - 1), lds);
+        }
+    };
     if constexpr (line_compact(NT, C)) {
         // 16 FP64 points per lane at 1024 threads leave no registers for a
         // prefetch buffer.  Instead, while step n-1 runs, every thread touches
@@ -228,6 +242,7 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
         const long tofs = min(t * C, TR ? NT * C - 1 : M - 1);
         for (int n = 1; n < N; ++n) {
             const double touch = v[(size_t)n * ld + tofs];
+            tables_for(n);
             for (int s = 0; s < c; ++s) {
                 if constexpr (SCHEME == SCHEME_IE) {
                     S.solve(u);
@@ -267,6 +282,7 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
         const long tofs = min(t * C, TR ? NT * C - 1 : M - 1);
         for (int n = 1; n < N; ++n) {
             const double touch = v[(size_t)min(n + 2, N - 1) * ld + tofs];
+            tables_for(n);
             coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
             asm volatile("" ::"v"(touch));  // consumed a whole step after it was issued
             load_chunk<NT, C, TR>(v + (size_t)min(n + 1, N - 1) * ld, t, M, va);
@@ -277,22 +293,24 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
     double vb[C];
     load_chunk<NT, C, TR>(v + (size_t)min(2, N - 1) * ld, t, M, vb);
     for (int n = 1; n < N; n += 2) {
+        tables_for(n);
         coarse_step<NT, C, SCHEME>(S, u, va, c, t, M);
         load_chunk<NT, C, TR>(v + (size_t)min(n + 2, N - 1) * ld, t, M, va);
         store_chunk<NT, C, TR>(z + (size_t)n * ld, t, M, u);
         if (n + 1 >= N) break;
+        tables_for(n + 1);
         coarse_step<NT, C, SCHEME>(S, u, vb, c, t, M);
         load_chunk<NT, C, TR>(v + (size_t)min(n + 3, N - 1) * ld, t, M, vb);
         store_chunk<NT, C, TR>(z + (size_t)(n + 1) * ld, t, M, u);
     }
 }
 
-template <int NT, int C, int SCHEME, bool TR>
+template <int NT, int C, int SCHEME, bool TR, bool PS>
 __global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const double *v, double *z,
                                                     int N, int M, long ld, int c)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
-    sweep1d_f64_line<NT, C, SCHEME, TR>(tb, v, z, N, M, ld, c, lds);
+    sweep1d_f64_line<NT, C, SCHEME, TR, PS>(tb, v, z, N, M, ld, c, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,14 +343,15 @@ __global__ __launch_bounds__(NT) void k_fine1d_f32_multi(Group g)
                                   d.periodic, 0, blockIdx.x - g.first[k], lds);
 }
 
-template <int NT, int C, int SCHEME>
+template <int NT, int C, int SCHEME, bool PS>
 __global__ __launch_bounds__(NT) void k_sweep1d_f64_multi(Group g)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
     const Inst1d &d = g.inst[g.list[blockIdx.x]];
     const int vin = g.aux[2 * blockIdx.x], vout = g.aux[2 * blockIdx.x + 1];
     const long nv = (long)d.N * d.ld;
-    sweep1d_f64_line<NT, C, SCHEME, true>(d.tc, d.vec + vin * nv, d.vec + vout * nv, d.N, d.M, d.ld, d.c, lds);
+    sweep1d_f64_line<NT, C, SCHEME, true, PS>(d.tc, d.vec + vin * nv, d.vec + vout * nv, d.N, d.M, d.ld, d.c,
+                                              lds);
 }
 
 #define PIT_LINE_SHAPES(X)                                                                  \
@@ -391,17 +410,22 @@ hipError_t launch_fine1d_f32(LineShape sh, const LineTab<float> &tb, const doubl
 hipError_t launch_sweep1d_f64(LineShape sh, const LineTab<double> &tb, const double *v, double *z,
                               int N, int M, int c, int scheme, bool chunked, hipStream_t st)
 {
-#define LAUNCH(nt, cc, SCH, TR)                                                                    \
-    hipLaunchKernelGGL((k_sweep1d_f64<nt, cc, SCH, TR>), dim3(1), dim3(nt), 0, st, tb, v, z, N, M, \
+#define LAUNCH(nt, cc, SCH, TR, PS)                                                                    \
+    hipLaunchKernelGGL((k_sweep1d_f64<nt, cc, SCH, TR, PS>), dim3(1), dim3(nt), 0, st, tb, v, z, N, M, \
                        (long)(TR ? nt * cc : M), c)
+    // an operator per slice runs in the chunked layout only (pit_solve, the
+    // batch engine and pit_coarse_sweep all sweep there)
+    if (tb.sstride && !chunked) return hipErrorInvalidValue;
 #define X(nt, cc)                                                      \
     if (sh.NT == nt && sh.C == cc) {                                   \
         if (scheme == SCHEME_IE) {                                     \
-            if (chunked) LAUNCH(nt, cc, SCHEME_IE, true);              \
-            else LAUNCH(nt, cc, SCHEME_IE, false);                     \
+            if (tb.sstride) LAUNCH(nt, cc, SCHEME_IE, true, true);     \
+            else if (chunked) LAUNCH(nt, cc, SCHEME_IE, true, false);  \
+            else LAUNCH(nt, cc, SCHEME_IE, false, false);              \
         } else {                                                       \
-            if (chunked) LAUNCH(nt, cc, SCHEME_CN, true);              \
-            else LAUNCH(nt, cc, SCHEME_CN, false);                     \
+            if (tb.sstride) LAUNCH(nt, cc, SCHEME_CN, true, true);     \
+            else if (chunked) LAUNCH(nt, cc, SCHEME_CN, true, false);  \
+            else LAUNCH(nt, cc, SCHEME_CN, false, false);              \
         }                                                              \
         return hipGetLastError();                                      \
     }
@@ -430,18 +454,23 @@ hipError_t launch_fine1d_multi(LineShape sh, int fine32, int scheme, const Group
 }
 
 // grid: one block per listed instance
-hipError_t launch_sweep1d_multi(LineShape sh, int scheme, const Group &g, hipStream_t st)
+hipError_t launch_sweep1d_multi(LineShape sh, int scheme, bool per_slice, const Group &g, hipStream_t st)
 {
-#define X(nt, c)                                                                                             \
-    if (sh.NT == nt && sh.C == c) {                                                                          \
-        if (scheme == SCHEME_IE)                                                                             \
-            hipLaunchKernelGGL((k_sweep1d_f64_multi<nt, c, SCHEME_IE>), dim3(g.count), dim3(nt), 0, st, g);  \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_sweep1d_f64_multi<nt, c, SCHEME_CN>), dim3(g.count), dim3(nt), 0, st, g);  \
-        return hipGetLastError();                                                                            \
+#define L(nt, c, SCH, PS) hipLaunchKernelGGL((k_sweep1d_f64_multi<nt, c, SCH, PS>), dim3(g.count), dim3(nt), 0, st, g)
+#define X(nt, c)                                                                      \
+    if (sh.NT == nt && sh.C == c) {                                                   \
+        if (scheme == SCHEME_IE) {                                                    \
+            if (per_slice) L(nt, c, SCHEME_IE, true);                                 \
+            else L(nt, c, SCHEME_IE, false);                                          \
+        } else {                                                                      \
+            if (per_slice) L(nt, c, SCHEME_CN, true);                                 \
+            else L(nt, c, SCHEME_CN, false);                                          \
+        }                                                                             \
+        return hipGetLastError();                                                     \
     }
     PIT_LINE_SHAPES(X)
 #undef X
+#undef L
     return hipErrorInvalidValue;
 }
 

@@ -78,6 +78,36 @@ __device__ __forceinline__ T scan_down(T v, const T (&m)[7])
     return fma(m[4], t1, fma(m[5], t2, fma(m[6], t3, v)));
 }
 
+// The tables of slice n (a time-dependent operator, constant on each slice);
+// the shared table itself when there is one for every slice.  The branch is
+// uniform (a kernel argument).
+template <typename T>
+__device__ __forceinline__ LineTab<T> line_tab_slice(const LineTab<T> &tb, int n)
+{
+    if (tb.sstride == 0) return tb;
+    LineTab<T> t = tb;
+    const long o = (long)n * tb.sstride;
+    t.lm += o;
+    t.iu += o;
+    t.cm += o;
+    t.z += o;
+    t.wf += o;
+    t.wb += o;
+    t.qf += o;
+    t.qb += o;
+    t.pwf += o;
+    t.pwb += o;
+    t.rfw += o;
+    t.rf += o;
+    const T *sc = tb.sscal + (long)kSliceScalars * n;
+    t.inv_den = sc[0];
+    t.bg = sc[1];
+    t.iu_last = sc[2];
+    t.na = sc[3];
+    t.nc = sc[4];
+    return t;
+}
+
 // CYC = false drops the periodic (Sherman-Morrison) part: no z vector in
 // registers and no correction.  CP selects the compact tables (only iu per
 // point; see pit_internal.hpp), which the longest FP64 lines need.  FP32

@@ -71,7 +71,14 @@ struct LineTab {
     T na, nc;   // -a, -c: the negated off-diagonals (used by the compact form)
     int cyclic;
     int M;
+    // A time-dependent operator (constant on each slice): slice n's tables
+    // sit sstride elements after slice n-1's, and its scalars (inv_den, bg,
+    // iu_last, na, nc and the FP32 step's diffusion coefficient) at
+    // sscal[kSliceScalars * n ..].  sstride 0: one table for every slice.
+    long sstride;
+    const T *sscal;
 };
+constexpr int kSliceScalars = 6;
 
 inline size_t line_tab_elems(int NT, int C) { return (size_t)(4 * C + 2 * kScanConsts + 3) * NT + 3 * kMaxWaves; }
 
@@ -280,7 +287,7 @@ __device__ __forceinline__ int group_find(const int *first, int count, int b)
 // of their N.
 hipError_t launch_fine1d_multi(LineShape sh, int fine32, int scheme, const Group &g, int nblocks, hipStream_t st);
 // Coarse sweep of vector aux[2k] into aux[2k+1], one block per listed instance.
-hipError_t launch_sweep1d_multi(LineShape sh, int scheme, const Group &g, hipStream_t st);
+hipError_t launch_sweep1d_multi(LineShape sh, int scheme, bool per_slice, const Group &g, hipStream_t st);
 // Segmented dots of aux[9k] vector pairs (aux[9k+1+q], aux[9k+5+q]) per
 // listed instance; g.first is the prefix of bps*N; results into g.red[k].
 hipError_t launch_dots_multi(const Group &g, int nblocks, hipStream_t st);

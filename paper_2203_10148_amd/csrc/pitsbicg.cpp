@@ -331,12 +331,54 @@ bool build_col(int My, double a, double b, double c, int ns, int cy, std::vector
 }
 
 // Tables for A = I - theta*L with theta = dt (IE) or dt/2 (CN).
-bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &out)
+bool make_line(const pit_problem &pb, double h, int scheme, double dt, LineShape sh, LineHost &out)
 {
     double lo, di, up;
-    stencil1d(c.pb, c.hx, &lo, &di, &up);
+    stencil1d(pb, h, &lo, &di, &up);
     const double th = (scheme == PIT_IE) ? dt : 0.5 * dt;
-    return build_line(c.pb.M[0], c.pb.bc == PIT_PERIODIC, -th * lo, 1.0 - th * di, -th * up, sh, out);
+    return build_line(pb.M[0], pb.bc == PIT_PERIODIC, -th * lo, 1.0 - th * di, -th * up, sh, out);
+}
+bool make_line(const pit_ctx &c, int scheme, double dt, LineShape sh, LineHost &out)
+{
+    return make_line(c.pb, c.hx, scheme, dt, sh, out);
+}
+
+// Per-slice tables of a time-dependent operator (1D): slice n's fine and
+// coarse step matrices with nu * s[n], in the layout of line_tab_view, each
+// slice's block `stride` elements after the previous one, and its scalars.
+bool build_slice_tables(pit_ctx &c, const double *s)
+{
+    const int N = c.N;
+    c.tft.clear();
+    c.tct.clear();
+    c.tf32t.clear();
+    c.scf.assign((size_t)kSliceScalars * N, 0.0);
+    c.scc.assign((size_t)kSliceScalars * N, 0.0);
+    c.scf32.assign((size_t)kSliceScalars * N, 0.0f);
+    for (int n = 0; n < N; ++n) {
+        pit_problem pb = c.pb;
+        pb.nu = c.pb.nu * s[n];
+        LineHost f, g;
+        if (!make_line(pb, c.hx, c.fine.scheme, c.DT / c.m, c.lf.sh, f) ||
+            !make_line(pb, c.hx, c.coarse.scheme, c.DT / c.coarse.substeps, c.lc.sh, g))
+            return false;
+        if (n == 0) {
+            c.str_f = (long)f.blob.size();
+            c.str_c = (long)g.blob.size();
+        }
+        c.tft.insert(c.tft.end(), f.blob.begin(), f.blob.end());
+        c.tct.insert(c.tct.end(), g.blob.begin(), g.blob.end());
+        if (c.fine32()) c.tf32t.insert(c.tf32t.end(), f.blob32.begin(), f.blob32.end());
+        const double pd = (c.DT / c.m) * (pb.nu / (c.hx * c.hx));
+        const double vf[kSliceScalars] = {f.inv_den, f.bg, f.iu_last, -f.a, -f.c, pd};
+        const double vc[kSliceScalars] = {g.inv_den, g.bg, g.iu_last, -g.a, -g.c, 0.0};
+        for (int q = 0; q < kSliceScalars; ++q) {
+            c.scf[(size_t)kSliceScalars * n + q] = vf[q];
+            c.scc[(size_t)kSliceScalars * n + q] = vc[q];
+            c.scf32[(size_t)kSliceScalars * n + q] = (float)vf[q];
+        }
+    }
+    return true;
 }
 
 // theta of the fine or coarse 2D step: dt/2 (PR-ADI) or dt (backward-Euler
@@ -697,15 +739,44 @@ size_t source_slots(pit_ctx &c, size_t o)
 // base workspace.
 void size_source_t(pit_ctx *c)
 {
-    if (c->gt.empty()) {
-        c->total = c->base_total;
-        return;
-    }
     size_t o = align_up(c->base_total);
-    c->off_bft = o;
-    o = align_up(o + (size_t)c->N * c->npts * sizeof(double));
-    c->off_gw = o;
-    c->total = align_up(o + (size_t)c->N * c->m * sizeof(double));
+    if (!c->gt.empty()) {
+        c->off_bft = o;
+        o = align_up(o + (size_t)c->N * c->npts * sizeof(double));
+        c->off_gw = o;
+        o = align_up(o + (size_t)c->N * c->m * sizeof(double));
+    }
+    if (c->nu_t()) {  // per-slice tables of a time-dependent operator
+        c->off_tft = o;
+        o = align_up(o + c->tft.size() * sizeof(double));
+        c->off_tct = o;
+        o = align_up(o + c->tct.size() * sizeof(double));
+        c->off_tf32t = o;
+        o = align_up(o + c->tf32t.size() * sizeof(float));
+        c->off_scf = o;
+        o = align_up(o + c->scf.size() * sizeof(double));
+        c->off_scc = o;
+        o = align_up(o + c->scc.size() * sizeof(double));
+        c->off_scf32 = o;
+        o = align_up(o + c->scf32.size() * sizeof(float));
+    }
+    c->total = o;
+}
+
+// Upload the per-slice tables (synchronous, null stream).
+int upload_slice_tables(pit_ctx *c)
+{
+    if (!c->nu_t()) return PIT_OK;
+    auto up = [&](size_t off, const void *p, size_t bytes) {
+        return bytes ? hipMemcpy(c->ws + off, p, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    PIT_HIP(up(c->off_tft, c->tft.data(), c->tft.size() * sizeof(double)));
+    PIT_HIP(up(c->off_tct, c->tct.data(), c->tct.size() * sizeof(double)));
+    PIT_HIP(up(c->off_tf32t, c->tf32t.data(), c->tf32t.size() * sizeof(float)));
+    PIT_HIP(up(c->off_scf, c->scf.data(), c->scf.size() * sizeof(double)));
+    PIT_HIP(up(c->off_scc, c->scc.data(), c->scc.size() * sizeof(double)));
+    PIT_HIP(up(c->off_scf32, c->scf32.data(), c->scf32.size() * sizeof(float)));
+    return PIT_OK;
 }
 
 // One fine step of every slice: out_n = S in_n, n < N (natural layout,
@@ -1218,12 +1289,14 @@ int pit_bind_workspace(pit_ctx *ctx, void *dev_ptr, size_t bytes)
     if (ctx->fine32())
         PIT_HIP(hipMemcpy(ctx->ws + ctx->off_tf32, ctx->lf.blob32.data(), ctx->lf.blob32.size() * sizeof(float),
                           hipMemcpyHostToDevice));
+    if (int rc = upload_slice_tables(ctx)) return rc;
     return bind_source(ctx);
 }
 
 int pit_set_source(pit_ctx *ctx, const double *f)
 {
     if (!ctx) return PIT_EINVAL;
+    if (f && ctx->nu_t()) return PIT_EINVAL;  // not with a time-dependent operator
     if (f)
         for (int j = 0; j < ctx->npts; ++j)
             if (!std::isfinite(f[j])) return PIT_EINVAL;
@@ -1240,6 +1313,7 @@ int pit_set_source(pit_ctx *ctx, const double *f)
 int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g)
 {
     if (!ctx) return PIT_EINVAL;
+    if (h && ctx->nu_t()) return PIT_EINVAL;  // not with a time-dependent operator
     if (!h || !g) return pit_set_source(ctx, h);
     const size_t ng = (size_t)ctx->N * ctx->m + 1;
     for (int j = 0; j < ctx->npts; ++j)
@@ -1256,6 +1330,28 @@ int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g)
         return PIT_ENOMEM;
     }
     return ctx->ws ? bind_source(ctx) : PIT_OK;
+}
+
+int pit_set_nu_t(pit_ctx *ctx, const double *s)
+{
+    if (!ctx || ctx->dim2()) return PIT_EINVAL;
+    if (!s) {
+        ctx->nus.clear();
+        size_source_t(ctx);
+        return PIT_OK;
+    }
+    if (ctx->has_src()) return PIT_EINVAL;
+    for (int n = 0; n < ctx->N; ++n)
+        if (!(s[n] > 0.0) || !std::isfinite(s[n])) return PIT_EINVAL;
+    if (!build_slice_tables(*ctx, s)) return PIT_EINVAL;  // a factorisation that is not finite
+    ctx->nus.assign(s, s + ctx->N);
+    size_source_t(ctx);
+    if (ctx->ws && ctx->ws_bytes < ctx->total) {  // the bound workspace is too small: unbind
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+        return PIT_ENOMEM;
+    }
+    return ctx->ws ? upload_slice_tables(ctx) : PIT_OK;
 }
 
 int pit_apply_F(pit_ctx *ctx, const double *lam, double *y, int32_t flags, void *stream)
@@ -1325,12 +1421,30 @@ struct Solver {
     int matvecs = 0;
     int n_fine = 0, n_coarse = 0;
     int timing = 0;  // > 0: time the first launch of each kind and every timing-th after it
-    std::vector<EventPair> ev_fine, ev_coarse;
+    std::vector<EventPair> ev_fine, ev_coarse, ev_kry;
+    bool kry_timed = false;  // the current iteration's Krylov launches are timed
+    int n_kry_timed = 0;
 
     ~Solver()
     {
         for (auto &e : ev_fine) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (auto &e : ev_coarse) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        for (auto &e : ev_kry) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    }
+
+    // iteration k's Krylov launches are timed when timing > 0 and k is a
+    // multiple of the stride
+    void time_iteration(int k)
+    {
+        kry_timed = timing > 0 && k % timing == 0;
+        if (kry_timed) ++n_kry_timed;
+    }
+    // brackets around a group of Krylov launches of a timed iteration
+    int kopen() { return kry_timed ? begin(ev_kry) : PIT_OK; }
+    int kclose()
+    {
+        if (kry_timed) PIT_HIP(hipEventRecord(ev_kry.back().b, st));
+        return PIT_OK;
     }
 
     int begin(std::vector<EventPair> &v)
@@ -1395,7 +1509,9 @@ struct Solver {
             pr.a[q] = a[q];
             pr.b[q] = b[q];
         }
+        if (int e = kopen()) return e;
         PIT_HIP(launch_seg_dots(pr, nq, c->N, c->ld, c->bps, c->part(), c->w, c->red(), st));
+        if (int e = kclose()) return e;
         if (int e = pin()) return e;
         PIT_HIP(hipMemcpyAsync(c->red_pin, c->red(), sizeof(RedOut), hipMemcpyDeviceToHost, st));
         PIT_HIP(hipStreamSynchronize(st));
@@ -1549,6 +1665,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 break;
             }
         }
+        s.time_iteration(k);
         if (one_sync) {
             if (!rho_src || std::memcmp(&rho, &rho_dev, sizeof(double)) != 0) {
                 if ((rc = s.set_rho(rho))) return rc;
@@ -1560,12 +1677,15 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             RedOut *const Cn = ctx->red(rho_src == ctx->red(3) ? 4 : 3);
             const DevScalars ds{rho_src, rho_idx, A, Bq, Cn};
             if ((rc = s.matvec(s.P, s.D))) return rc;
+            if ((rc = s.kopen())) return rc;
             {
                 const double *a[1] = {s.D}, *b[1] = {s.Rt};
                 if ((rc = s.dots(1, a, b, A))) return rc;
             }
             PIT_HIP(launch_axpby_dev(s.S, s.R, s.D, ds, n, st));  // S = R - alpha D
+            if ((rc = s.kclose())) return rc;
             if ((rc = s.matvec(s.S, s.K))) return rc;
+            if ((rc = s.kopen())) return rc;
             {
                 const double *a[3] = {s.K, s.K, s.S}, *b[3] = {s.S, s.K, s.S};
                 if ((rc = s.dots(3, a, b, Bq))) return rc;
@@ -1576,6 +1696,7 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
                 if ((rc = s.dots(2, a, b, Cn))) return rc;
             }
             PIT_HIP(launch_update_p_dev(s.P, s.R, s.D, ds, n, st));
+            if ((rc = s.kclose())) return rc;
             RedOut hs[kRedSlots];
             if ((rc = s.fetch(hs))) return rc;
             const double dr = hs[1].dot[0];
@@ -1649,7 +1770,9 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             }
         }
         const double alpha = rho / dr;
+        if ((rc = s.kopen())) return rc;
         PIT_HIP(launch_axpby(s.S, s.R, 1.0, s.D, -alpha, n, st));  // S = R - alpha D
+        if ((rc = s.kclose())) return rc;
         if (o.half_step_check) {
             const double *a[1] = {s.S}, *b[1] = {s.S};
             if ((rc = s.reduce(1, a, b, h))) return rc;
@@ -1690,7 +1813,9 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
             continue;
         }
         // X and R updates
+        if ((rc = s.kopen())) return rc;
         PIT_HIP(launch_update_xr(X, s.R, s.P, s.S, s.K, alpha, omega, n, st));
+        if ((rc = s.kclose())) return rc;
         // beta (and the norm for the next stopping test)
         {
             const double *a[2] = {s.R, s.R}, *b[2] = {s.Rt, s.R};
@@ -1700,7 +1825,9 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         nrm = h.nmax[1];
         const double beta = (alpha / omega) * (rho_new / rho);
         // new direction P
+        if ((rc = s.kopen())) return rc;
         PIT_HIP(launch_update_p(s.P, s.R, s.D, beta, omega, n, st));
+        if ((rc = s.kclose())) return rc;
         // restart test with epsilon_0
         if (std::fabs(rho_new) <= o.restart_tol) {
             PIT_HIP(launch_copy(s.Rt, s.R, n, st));
@@ -1727,6 +1854,8 @@ extern "C" int pit_solve(pit_ctx *ctx, const double *u0, double *X, const pit_so
         info->ms_coarse = Solver::total_ms(s.ev_coarse);
         info->n_fine_timed = (int)s.ev_fine.size();
         info->n_coarse_timed = (int)s.ev_coarse.size();
+        info->ms_krylov = Solver::total_ms(s.ev_kry);
+        info->n_krylov_timed = s.n_kry_timed;
         info->ms_total =
             std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -2037,6 +2166,8 @@ extern "C" int pit_parareal(pit_ctx *ctx, const double *u0, double *X, const pit
         info->ms_coarse = Solver::total_ms(s.ev_coarse);
         info->n_fine_timed = (int)s.ev_fine.size();
         info->n_coarse_timed = (int)s.ev_coarse.size();
+        info->ms_krylov = Solver::total_ms(s.ev_kry);
+        info->n_krylov_timed = s.n_kry_timed;
         info->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;

@@ -58,7 +58,8 @@ class pit_solve_info(ct.Structure):
                 ("history", ct.POINTER(ct.c_double)), ("history_cap", ct.c_int32),
                 ("history_len", ct.c_int32), ("ms_total", ct.c_float),
                 ("ms_fine", ct.c_float), ("ms_coarse", ct.c_float), ("n_fine", ct.c_int32),
-                ("n_coarse", ct.c_int32), ("n_fine_timed", ct.c_int32), ("n_coarse_timed", ct.c_int32)]
+                ("n_coarse", ct.c_int32), ("n_fine_timed", ct.c_int32), ("n_coarse_timed", ct.c_int32),
+                ("ms_krylov", ct.c_float), ("n_krylov_timed", ct.c_int32)]
 
 
 class pit_server_cfg(ct.Structure):
@@ -83,7 +84,7 @@ EXPORTS = (
     "pit_coarse_sweep", "pit_solve", "pit_strerror", "pit_last_hip_error", "pit_kernel_shape",
     "pit_batch_create", "pit_batch_workspace_bytes", "pit_batch_bind_workspace", "pit_batch_destroy",
     "pit_batch_solve", "pit_server_create", "pit_submit", "pit_poll", "pit_server_load",
-    "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset", "pit_autotune_adi", "pit_stream_copy",
+    "pit_server_destroy", "pit_autotune_scratch_bytes", "pit_autotune", "pit_autotune_reset", "pit_autotune_adi", "pit_stream_copy", "pit_set_nu_t",
     "pit_parareal", "pit_set_source", "pit_set_source_t", "pit_coarse_sweep_noalloc",
 )
 
@@ -132,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.pit_autotune_scratch_bytes.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper]
     lib.pit_autotune_scratch_bytes.restype = sz
     lib.pit_stream_copy.argtypes = [vp, vp, sz, vp]
+    lib.pit_set_nu_t.argtypes = [vp, ct.POINTER(ct.c_double)]
     lib.pit_autotune_adi.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper, vp, sz,
                                      ct.POINTER(i32), ct.POINTER(ct.c_float), vp]
     lib.pit_autotune.argtypes = [ct.POINTER(pit_problem), i32, i32, pit_stepper, pit_stepper, vp, sz,
@@ -205,6 +207,8 @@ class SolveInfo:
     n_coarse: int = 0
     n_fine_timed: int = 0
     n_coarse_timed: int = 0
+    ms_krylov: float = 0.0
+    n_krylov_timed: int = 0
 
 
 class Context:
@@ -250,6 +254,23 @@ class Context:
             self.bind(self.ws.device)
             return
         _check(rc, "pit_set_source_t")
+
+    def set_nu_t(self, s):
+        """A time-dependent operator constant on each slice (1D): the
+        diffusion coefficient on slice n is nu * s[n] (N positive values), or
+        constant again with None.  A bound workspace that is too small for the
+        per-slice tables is replaced by one of the new size."""
+        if s is None:
+            _check(load().pit_set_nu_t(self._h, None), "pit_set_nu_t")
+            return
+        s = np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1))
+        if s.size != self.p.N:
+            raise ValueError("set_nu_t: N factors expected")
+        rc = load().pit_set_nu_t(self._h, s.ctypes.data_as(ct.POINTER(ct.c_double)))
+        if rc == ENOMEM and self.ws is not None:  # unbound: bind one of the new size
+            self.bind(self.ws.device)
+            return
+        _check(rc, "pit_set_nu_t")
 
     def kernel_shape(self):
         out = (ct.c_int32 * 4)()
@@ -333,7 +354,7 @@ class Context:
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
                             info.ms_coarse, info.n_fine, info.n_coarse, info.n_fine_timed,
-                            info.n_coarse_timed)
+                            info.n_coarse_timed, info.ms_krylov, info.n_krylov_timed)
 
     def parareal(self, u0, X=None, *, tol=0.0, max_iter=0, norm_mode=ABS, x0_mode=X0_ZERO, hist_cap=4096,
                  stream=None, timing=0):
@@ -354,7 +375,7 @@ class Context:
         return X, SolveInfo(info.status, info.iters, info.matvecs, info.restarts, info.res_norm,
                             hist[: info.history_len].copy(), info.ms_total, info.ms_fine,
                             info.ms_coarse, info.n_fine, info.n_coarse, info.n_fine_timed,
-                            info.n_coarse_timed)
+                            info.n_coarse_timed, info.ms_krylov, info.n_krylov_timed)
 
 
 def autotune(p, device=None, stream=None):

@@ -179,6 +179,18 @@ def source_profile(p: Problem, seed: int, nwaves: int = 3) -> np.ndarray:
     return g
 
 
+def nu_factors(p: Problem, seed: int) -> np.ndarray:
+    """Seeded per-slice diffusion factors s_n for a time-dependent operator
+    constant on each slice (nu s_n on slice n): a slow oscillation between
+    1/2 and 2 over the horizon, s_n = 2^sin(2 pi (n + 1/2)/N * f + phase),
+    with f ~ U[0.5, 2] periods and phase ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.5, 2.0)
+    ph = rng.uniform(0.0, 2.0 * np.pi)
+    n = np.arange(p.N) + 0.5
+    return 2.0 ** np.sin(2.0 * np.pi * f * n / p.N + ph)
+
+
 def random_block(p: Problem, seed: int) -> np.ndarray:
     """A seeded N x npts block vector of standard normals (operator parity inputs)."""
     return np.random.default_rng(seed).standard_normal(p.N * p.npts)

@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     assert ct.sizeof(P.pit_problem) == 4 * 4 + 8 * 8
     assert ct.sizeof(P.pit_stepper) == 16
     assert ct.sizeof(P.pit_solve_opts) == 8 * 2 + 4 * 6
-    assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 4 + 4  # + tail padding to 8
+    assert ct.sizeof(P.pit_solve_info) == 4 * 4 + 8 + 8 + 4 * 2 + 4 * 3 + 4 * 4 + 4 * 2 + 4  # + tail padding to 8
     assert ct.sizeof(P.pit_server_cfg) == 8 + 8 + 4 * 4
     assert ct.sizeof(P.pit_request) == ct.sizeof(P.pit_problem) + 4 * 2 + 16 * 2 + 8 * 2 + ct.sizeof(P.pit_solve_opts)
     assert ct.sizeof(P.pit_result) == 4 * 4 + 8 * 4 + 8 + 4 * 2
@@ -316,3 +316,29 @@ def test_stream_copy_refuses_bad_arguments():
     assert lib.pit_stream_copy(a, None, 16, None) == P.EINVAL
     assert lib.pit_stream_copy(a, a, 24, None) == P.EINVAL
     assert lib.pit_stream_copy(ct.c_void_p(256 * 4096 + 8), a, 16, None) == P.EINVAL
+
+
+def test_time_dependent_operator_validates_and_sizes_on_the_host():
+    """pit_set_nu_t: N positive finite factors on a 1D context; the per-slice
+    tables enlarge the workspace; 2D, bad values and a source are refused;
+    NULL restores the constant operator's size."""
+    lib = P.load()
+    p = wl.C2.with_(N=6, m=4)
+    _, h = create(p)
+    base = lib.pit_workspace_bytes(h)
+    s = (ct.c_double * p.N)(*[1.0, 2.0, 0.5, 1.5, 3.0, 0.7])
+    assert lib.pit_set_nu_t(h, s) == P.OK
+    assert lib.pit_workspace_bytes(h) > base
+    bad = (ct.c_double * p.N)(*[1.0, 2.0, 0.0, 1.5, 3.0, 0.7])
+    assert lib.pit_set_nu_t(h, bad) == P.EINVAL
+    f = (ct.c_double * p.npts)(*([0.1] * p.npts))
+    assert lib.pit_set_source(h, f) == P.EINVAL  # not with a time-dependent operator
+    assert lib.pit_set_nu_t(h, None) == P.OK
+    assert lib.pit_workspace_bytes(h) == base
+    assert lib.pit_set_source(h, f) == P.OK
+    assert lib.pit_set_nu_t(h, s) == P.EINVAL  # not with a source
+    lib.pit_destroy(h)
+    _, h2 = create(wl.C3.with_(N=2, m=2))
+    assert lib.pit_set_nu_t(h2, (ct.c_double * 2)(1.0, 2.0)) == P.EINVAL  # 1D only
+    lib.pit_destroy(h2)
+    assert lib.pit_set_nu_t(None, s) == P.EINVAL

@@ -126,11 +126,14 @@ def test_timing_stride_counts_and_averages(stride):
     X, info = c.solve(u0, tol=p.tol, timing=stride)
     assert np.array_equal(host(X), host(X0)) and info.iters == i0.iters
     if stride == 0:
-        assert info.n_fine_timed == info.n_coarse_timed == 0 and info.ms_fine == info.ms_coarse == 0.0
+        assert info.n_fine_timed == info.n_coarse_timed == info.n_krylov_timed == 0
+        assert info.ms_fine == info.ms_coarse == info.ms_krylov == 0.0
         return
     assert info.n_fine_timed == -(-info.n_fine // stride)
     assert info.n_coarse_timed == -(-info.n_coarse // stride)
     assert info.ms_fine > 0.0 and info.ms_coarse > 0.0
+    # the vector updates and inner products of iterations 0, stride, 2 stride, ..
+    assert info.n_krylov_timed == -(-info.iters // stride) and info.ms_krylov > 0.0
 
 
 def test_negative_timing_stride_is_rejected():
