@@ -156,6 +156,8 @@ __global__ __launch_bounds__(XW == 1 ? 256 : 128) void k_adi_x(LineTab<double> t
                                                                double ed)
 {
     constexpr int NT = kWave * XW;
+    __shared__ double lds[XW == 1 ? 1 : LineSolver<double, NT, C, false>::kLds];
+    poison_lds(lds, (int)(sizeof(lds) / sizeof(double)));
     const int lane = threadIdx.x & (NT - 1);  // thread of the row group
     const int strips = (My + R - 1) / R;
     // group-uniform indices in scalar registers, so row addresses stay scalar
@@ -168,7 +170,6 @@ __global__ __launch_bounds__(XW == 1 ? 256 : 128) void k_adi_x(LineTab<double> t
     SOUT *oslice = out + (size_t)(s + out_off) * npts;
     // 16-byte accesses when the row length keeps every thread's chunk aligned
     const bool vec = (Mx == NT * C) && (Mx * sizeof(SIN)) % 16 == 0 && (Mx * sizeof(SOUT)) % 16 == 0;
-    __shared__ double lds[XW == 1 ? 1 : LineSolver<double, NT, C, false>::kLds];
     LineSolver<double, NT, C, false> LS;
     LS.load(tb, XW == 1 ? nullptr : lds);
     // Five rotating row buffers: row r uses the buffers of rows r-1, r, r+1
@@ -214,6 +215,12 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     __shared__ double s_lm[NR], s_iu[NR], s_cm[NR];
     __shared__ double s_pf[NS], s_pb[NS];
     __shared__ double s_agg[2][NS][CW];
+    poison_lds(s_lm, NR);
+    poison_lds(s_iu, NR);
+    poison_lds(s_cm, NR);
+    poison_lds(s_pf, NS);
+    poison_lds(s_pb, NS);
+    poison_lds(&s_agg[0][0][0], 2 * NS * CW);
     const int t = threadIdx.x, lane = t & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform (scalar)
     const int cl = lane % CW, sg = lane / CW;
@@ -403,6 +410,7 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
 {
     constexpr int L = kWave * C, TW = CW + 2, NTH = CW * kWave;
     __shared__ double tile[TW * L];
+    poison_lds(tile, TW * L);
     const int t = threadIdx.x, lane = t & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(t / kWave);
     const int bx = (Mx + CW - 1) / CW;

@@ -38,7 +38,10 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "ctx.hpp"
+
+static_assert(pit::kArenaAlign == pit::kAlign, "arena granules keep workspaces aligned");
 
 using namespace pit;
 
@@ -806,55 +809,7 @@ pit_solve_opts default_opts()
     return o;
 }
 
-// First-fit allocator over the server's arena (offsets, 256-byte granules).
-struct Arena {
-    std::map<size_t, size_t> free;  // offset -> size
-    size_t used = 0;
-    void init(size_t off, size_t size)
-    {
-        free.clear();
-        if (size) free[off] = size;
-        used = 0;
-    }
-    bool alloc(size_t bytes, size_t &off)
-    {
-        bytes = align_up(bytes);
-        for (auto it = free.begin(); it != free.end(); ++it) {
-            if (it->second < bytes) continue;
-            off = it->first;
-            const size_t rest = it->second - bytes;
-            free.erase(it);
-            if (rest) free[off + bytes] = rest;
-            used += bytes;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = align_up(bytes);
-        used -= bytes;
-        auto it = free.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free.erase(nx);
-        }
-        if (it != free.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free.erase(it);
-            }
-        }
-    }
-    size_t largest() const
-    {
-        size_t m = 0;
-        for (auto &kv : free) m = std::max(m, kv.second);
-        return m;
-    }
-};
+
 
 void fill_info(const Inst *in, pit_solve_info *info)
 {

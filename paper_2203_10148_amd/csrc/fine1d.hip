@@ -130,6 +130,7 @@ __global__ __launch_bounds__(NT) void k_fine1d_f64(LineTab<double> tb, const dou
                                                    int raw, int n0)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    poison_lds(lds, LineSolver<double, NT, C>::kLds);
     fine1d_f64_slice<NT, C, SCHEME, TR>(tb, lam, y, M, ld, m, raw, n0 + blockIdx.x, lds);
 }
 
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(NT) void k_fine1d_f32(LineTab<float> tb, const doub
                                                    float pd, float pa, float pr, int periodic, int raw, int n0)
 {
     __shared__ float lds[LineSolver<float, NT, C>::kLds];
+    poison_lds(lds, LineSolver<float, NT, C>::kLds);
     fine1d_f32_slice<NT, C, TR>(tb, lam, y, M, ld, m, pd, pa, pr, periodic, raw, n0 + blockIdx.x, lds);
 }
 
@@ -310,6 +312,7 @@ __global__ __launch_bounds__(NT) void k_sweep1d_f64(LineTab<double> tb, const do
                                                     int N, int M, long ld, int c)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    poison_lds(lds, LineSolver<double, NT, C>::kLds);
     sweep1d_f64_line<NT, C, SCHEME, TR, PS>(tb, v, z, N, M, ld, c, lds);
 }
 
@@ -323,6 +326,7 @@ template <int NT, int C, int SCHEME>
 __global__ __launch_bounds__(NT) void k_fine1d_f64_multi(Group g)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    poison_lds(lds, LineSolver<double, NT, C>::kLds);
     const int k = group_find(g.first, g.count, blockIdx.x);
     const int vin = g.aux[2 * k], vout = g.aux[2 * k + 1];
     const Inst1d &d = g.inst[g.list[k]];
@@ -335,6 +339,7 @@ template <int NT, int C>
 __global__ __launch_bounds__(NT) void k_fine1d_f32_multi(Group g)
 {
     __shared__ float lds[LineSolver<float, NT, C>::kLds];
+    poison_lds(lds, LineSolver<float, NT, C>::kLds);
     const int k = group_find(g.first, g.count, blockIdx.x);
     const int vin = g.aux[2 * k], vout = g.aux[2 * k + 1];
     const Inst1d &d = g.inst[g.list[k]];
@@ -347,6 +352,7 @@ template <int NT, int C, int SCHEME, bool PS>
 __global__ __launch_bounds__(NT) void k_sweep1d_f64_multi(Group g)
 {
     __shared__ double lds[LineSolver<double, NT, C>::kLds];
+    poison_lds(lds, LineSolver<double, NT, C>::kLds);
     const Inst1d &d = g.inst[g.list[blockIdx.x]];
     const int vin = g.aux[2 * blockIdx.x], vout = g.aux[2 * blockIdx.x + 1];
     const long nv = (long)d.N * d.ld;

@@ -6,6 +6,7 @@
 // maximum over slices of the discrete L2 norm.  Both come out of one pass that
 // produces per-slice sums.
 #include <algorithm>
+#include "check.hpp"
 #include "pit_internal.hpp"
 #include "ctx.hpp"
 
@@ -26,6 +27,7 @@ __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N
                                                double *__restrict__ part, int b, int s)
 {
     __shared__ double sh[4][kRedThreads / kWave];
+    poison_lds(&sh[0][0], 4 * (kRedThreads / kWave));
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     const size_t base = (size_t)s * npts;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -64,6 +66,8 @@ __device__ __forceinline__ void seg_finalize_block(const double *__restrict__ pa
 {
     __shared__ double sd[kRedThreads];
     __shared__ double sm[kRedThreads];
+    poison_lds(sd, kRedThreads);
+    poison_lds(sm, kRedThreads);
     const int t = threadIdx.x;
     for (int q = 0; q < nq; ++q) {
         double tot = 0.0, mx = 0.0;

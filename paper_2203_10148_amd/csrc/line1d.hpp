@@ -16,6 +16,7 @@
 // costs no extra barrier.
 #pragma once
 
+#include "check.hpp"
 #include "pit_internal.hpp"
 
 namespace pit {

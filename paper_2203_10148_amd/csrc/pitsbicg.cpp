@@ -1334,13 +1334,13 @@ int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g)
 
 int pit_set_nu_t(pit_ctx *ctx, const double *s)
 {
-    if (!ctx || ctx->dim2()) return PIT_EINVAL;
+    if (!ctx) return PIT_EINVAL;
     if (!s) {
         ctx->nus.clear();
         size_source_t(ctx);
         return PIT_OK;
     }
-    if (ctx->has_src()) return PIT_EINVAL;
+    if (ctx->dim2() || ctx->has_src()) return PIT_EINVAL;
     for (int n = 0; n < ctx->N; ++n)
         if (!(s[n] > 0.0) || !std::isfinite(s[n])) return PIT_EINVAL;
     if (!build_slice_tables(*ctx, s)) return PIT_EINVAL;  // a factorisation that is not finite

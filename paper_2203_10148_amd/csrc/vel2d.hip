@@ -10,6 +10,7 @@
 // reuse each fetched 128-byte line over the next 15 steps from L1.  The walks
 // are unrolled so that the loads of several points (which depend on the
 // index only) are in flight at once.
+#include "check.hpp"
 #include "vel2d.hpp"
 
 namespace pit {
@@ -367,6 +368,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_apply_lds(VelTab t, const 
 {
     extern __shared__ double sh[];
     const VelLds L = vel_lds_layout(Mx, My, TAB);
+    poison_lds(sh, (int)L.total);
     double *U = sh, *S = sh + L.s, *W = sh + L.w;
     const VelView v = vel_stage<TAB>(t, sh, Mx, My, L);
     const int np = Mx * My;
@@ -394,6 +396,7 @@ __global__ __launch_bounds__(kVelLdsLines) void k_vel_sweep_lds(VelTab t, const 
 {
     extern __shared__ double sh[];
     const VelLds L = vel_lds_layout(Mx, My, TAB);
+    poison_lds(sh, (int)L.total);
     const int P = L.P;
     double *U = sh, *S = sh + L.s, *W = sh + L.w;
     const VelView w = vel_stage<TAB>(t, sh, Mx, My, L);

@@ -16,6 +16,7 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpitsbicg.so")
+CHECK_LIB_PATH = os.path.join(_PKG, "libpitsbicg_check.so")
 
 # status codes
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, EAGAIN = 0, -1, -2, -3, -4, -5, 1
@@ -91,11 +92,15 @@ EXPORTS = (
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libpitsbicg.so (raises if it has not been built)."""
+def load(path: str | None = None):
+    """Load libpitsbicg.so (raises if it has not been built).  The
+    environment variable PIT_LIBRARY=check loads the checking build
+    libpitsbicg_check.so instead (LDS poisoned with NaN before first use)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = CHECK_LIB_PATH if os.environ.get("PIT_LIBRARY") == "check" else LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2203_10148_amd.build`")
     lib = ct.CDLL(path)
