@@ -246,8 +246,9 @@ int pit_set_source_t(pit_ctx *ctx, const double *h, const double *g);
  * pit_workspace_bytes after this).  If the workspace is bound they are
  * uploaded at once (synchronous, null stream); a bound workspace that is now
  * too small is unbound and PIT_ENOMEM returned.  Errors: PIT_EINVAL (NULL
- * ctx, 2D, a value not positive or not finite, a source set), PIT_ENOMEM,
- * PIT_EHIP.  A source cannot be set while s is. */
+ * ctx; s given for a 2D context, with a value not positive or not finite, or
+ * while a source is set), PIT_ENOMEM, PIT_EHIP.  A source cannot be set
+ * while s is. */
 int pit_set_nu_t(pit_ctx *ctx, const double *s);
 
 /* ---- operators ------------------------------------------------------------ */
