@@ -208,6 +208,83 @@ __device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double
     for (int k = 0; k < C; ++k) u[k] = (j0 + k < M) ? u[k] + vn[k] : 0.0;
 }
 
+// Implicit-Euler sweep with the slice's global traffic spread over the
+// solves (chunked layout, point pairs).  The first solve of slice n runs out
+// of place, so u keeps z_{n-1} through it and z_{n-1} is stored from u at its
+// hook points; v_n is then loaded into u at the second solve's hook points
+// (c >= 2; with c = 1 after the stores, in the backward half of the one
+// solve), and z_n = w + v_n.  The same registers as a one-buffer prefetch,
+// but no wave issues sixteen 1 KiB accesses back to back.  A touch of v_{n+2}
+// (one element per 128-byte line) makes the loads L2 hits.  Hook plans
+// (measured on the 4096-point line, 256 threads): stores of pair slot s at
+// hook s + (s > 0) + (s > 3) of the first solve, loads at the same hooks of the
+// second, the touch at hook 10 of the first; with c = 1 stores at hook s,
+// loads at hook 8 + s/2, the touch at the start of the slice.
+template <int NT, int C, bool ONE>
+__device__ __forceinline__ void sweep1d_ie_spread(const LineTab<double> &tb, const double *v, double *z, int N,
+                                                  int M, long ld, int c, double *lds)
+{
+    static_assert(chunk_width(C) == 2, "point pairs");
+    constexpr int P = C / 2;  // pairs per thread
+    const int t = threadIdx.x;
+    LineSolver<double, NT, C> S;
+    S.load(tb, lds);
+    double u[C], w[C];
+    load_chunk<NT, C, true>(v, t, M, u);
+    zero_pads<C>(t, M, u);
+    const long tofs = min(t * C, NT * C - 1);
+    for (int n = 1; n < N; ++n) {
+        pit_d2 *zp = reinterpret_cast<pit_d2 *>(z + (size_t)(n - 1) * ld);
+        const pit_d2 *vn = reinterpret_cast<const pit_d2 *>(v + (size_t)n * ld);
+        const double *vt = v + (size_t)min(n + 2, N - 1) * ld + tofs;
+        auto store_pair = [&](int g) {
+            pit_d2 x;
+            x.x = u[2 * g];
+            x.y = u[2 * g + 1];
+            zp[g * NT + t] = x;
+        };
+        auto load_pair = [&](int g) {
+            const pit_d2 x = vn[g * NT + t];
+            u[2 * g] = x.x;
+            u[2 * g + 1] = x.y;
+        };
+        double touch = 0.0;
+        if constexpr (ONE) {
+            touch = *vt;
+            S.solve_to(u, w, make_hook([&](int h) {
+#pragma unroll
+                for (int g = 0; g < P; ++g) {
+                    const int s = g * 8 / P;
+                    if (h == s) store_pair(g);
+                    if (h == 8 + s / 2) load_pair(g);
+                }
+            }));
+        } else {
+            S.solve_to(u, w, make_hook([&](int h) {
+#pragma unroll
+                for (int g = 0; g < P; ++g) {
+                    const int s = g * 8 / P;
+                    if (h == s + (s > 0) + (s > 3)) store_pair(g);
+                }
+                if (h == 10) touch = *vt;
+            }));
+            S.solve_to(w, w, make_hook([&](int h) {
+#pragma unroll
+                for (int g = 0; g < P; ++g) {
+                    const int s = g * 8 / P;
+                    if (h == s + (s > 0) + (s > 3)) load_pair(g);
+                }
+            }));
+            for (int s = 2; s < c; ++s) S.solve(w);
+        }
+        asm volatile("" ::"v"(touch));  // the touched value, consumed long after it landed
+        const int j0 = t * C;
+#pragma unroll
+        for (int k = 0; k < C; ++k) u[k] = (j0 + k < M) ? w[k] + u[k] : 0.0;
+    }
+    store_chunk<NT, C, true>(z + (size_t)(N - 1) * ld, t, M, u);
+}
+
 // The slice loop is unrolled by two with two prefetch buffers (v_{n+2} is
 // loaded while slices n and n+1 are computed) and the prefetch index is
 // clamped instead of guarded, so the loaded registers are consumed where
@@ -216,6 +293,20 @@ template <int NT, int C, int SCHEME, bool TR, bool PS>
 __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, const double *v, double *z, int N,
                                                  int M, long ld, int c, double *lds)
 {
+    // A second prefetch buffer does not fit in the registers at 16 points per
+    // thread (with the solver's four per-point tables the compiler parks the
+    // buffers in AGPRs, and its copies then wait on loads just issued), nor
+    // at 1024 threads (128 registers per lane).
+    constexpr bool kTwoBuffers = C <= 8 && NT * C <= 4096;
+    // The interleaved implicit-Euler path where it fits the registers: one
+    // constant operator (reloading a slice's tables keeps more values live),
+    // 16-point chunks of lines up to 4096 points (at 8 and 16 waves the
+    // one-buffer forms already spill, and spill more with it).
+    if constexpr (!PS && !kTwoBuffers && NT * C <= 4096 && SCHEME == SCHEME_IE && TR && chunk_width(C) == 2) {
+        if (c == 1) sweep1d_ie_spread<NT, C, true>(tb, v, z, N, M, ld, c, lds);
+        else sweep1d_ie_spread<NT, C, false>(tb, v, z, N, M, ld, c, lds);
+        return;
+    }
     const int t = threadIdx.x;
     LineSolver<double, NT, C> S;
     S.load(PS ? line_tab_slice(tb, 0) : tb, lds);
@@ -267,14 +358,11 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
         }
         return;
     }
-    // A second prefetch buffer does not fit in the registers at 16 points per
-    // thread (with the solver's four per-point tables the compiler parks the
-    // buffers in AGPRs, and its copies then wait on loads just issued), nor
-    // at 1024 threads (128 registers per lane).  One buffer is enough there:
+    // Where a second prefetch buffer does not fit (see above), one is enough:
     // v_{n+1} is loaded at the end of step n and needed only after the c
     // solves of step n+1, and a touch of v_{n+2} (one element per 128-byte
-    // line, as above) a step earlier makes that load an L2 hit.
-    constexpr bool kTwoBuffers = C <= 8 && NT * C <= 4096;
+    // line, as above) a step earlier makes that load an L2 hit.  (Implicit
+    // Euler in the chunked layout takes the interleaved path instead.)
     double u[C], va[C];
     load_chunk<NT, C, TR>(v, t, M, u);
     zero_pads<C>(t, M, u);

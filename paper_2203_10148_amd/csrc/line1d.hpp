@@ -109,6 +109,47 @@ __device__ __forceinline__ LineTab<T> line_tab_slice(const LineTab<T> &tb, int n
     return t;
 }
 
+// Hook points of a solve.  A caller that has global memory instructions to
+// issue while a line is being solved (a sweep writing the previous slice and
+// reading the next one) passes a callable, run at twelve fixed points of
+// solve_to: 0 at the start, 1 halfway through the forward local pass, 2 after
+// the in-wave forward scan, 3 after posting the wave aggregate (before the
+// barrier), 4 after the cross-wave combination, 5 halfway through and 6 after
+// the forward second pass, 7 halfway through the backward local pass, 8 after
+// the in-wave backward scan, 9 after posting (before the barrier), 10 after
+// the combination and 11 after the backward second pass (before the periodic
+// correction).  Every point is reached exactly once per solve, whatever the
+// shape.  Spread over those points, a wave's 1 KiB loads and stores drain
+// through the compute unit's memory pipeline while the wave waits on its FMA
+// chains and barriers; issued back to back (sixteen per wave at the end of a
+// slice) they stall every wave until the pipeline has taken them all.  The
+// scheduling fences keep the compiler from bunching them again.  NoHook
+// compiles to nothing.
+struct NoHook {
+    static constexpr bool kActive = false;
+    __device__ void operator()(int) const {}
+};
+template <class F>
+struct Hook {
+    static constexpr bool kActive = true;
+    F f;
+    __device__ __forceinline__ void operator()(int p) { f(p); }
+};
+template <class F>
+__device__ __forceinline__ Hook<F> make_hook(F f)
+{
+    return Hook<F>{f};
+}
+template <class H>
+__device__ __forceinline__ void at(H &h, int p)
+{
+    if constexpr (H::kActive) {
+        __builtin_amdgcn_sched_barrier(0);
+        h(p);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // CYC = false drops the periodic (Sherman-Morrison) part: no z vector in
 // registers and no correction.  CP selects the compact tables (only iu per
 // point; see pit_internal.hpp), which the longest FP64 lines need.  FP32
@@ -237,11 +278,16 @@ struct LineSolver {
     }
 
     // ---- forward elimination y_j = d_j + lm_j y_{j-1}: local pass + in-wave scan ----
-    __device__ __forceinline__ T fwd_scan(const T (&d)[C]) const
+    template <class H = NoHook>
+    __device__ __forceinline__ T fwd_scan(const T (&d)[C], H h = H{}) const
     {
         T e = d[0];
 #pragma unroll
-        for (int k = 1; k < C; ++k) e = CP ? fma(na, iu[k - 1] * e, d[k]) : fma(lm[k], e, d[k]);
+        for (int k = 1; k < C; ++k) {
+            e = CP ? fma(na, iu[k - 1] * e, d[k]) : fma(lm[k], e, d[k]);
+            if (k == C / 2) at(h, 1);
+        }
+        if constexpr (C < 2) at(h, 1);
         return scan_up(e, wf);
     }
 
@@ -257,6 +303,20 @@ struct LineSolver {
         }
     }
 
+    // the same out of place: out = y from in (in may be out)
+    template <class H>
+    __device__ __forceinline__ void fwd_pass2_to(const T (&in)[C], T (&out)[C], T c, H &h) const
+    {
+        T y = c;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            if constexpr (CP) y = fma(na, (k == 0 ? iup : iu[k - 1]) * y, in[k]);
+            else y = fma(lm[k], y, in[k]);
+            out[k] = y;
+            if (k == C / 2) at(h, 5);
+        }
+    }
+
     // one backward step x = iu_k y + cm_k x_next
     __device__ __forceinline__ T bstep(int k, T x, T y) const
     {
@@ -266,15 +326,21 @@ struct LineSolver {
 
     // ---- back substitution x_j = iu_j y_j + cm_j x_{j+1}, then the periodic
     // correction; ytot is the forward value at point M-1 ----
-    __device__ __forceinline__ void backward(T (&d)[C], T ytot)
+    template <class H = NoHook>
+    __device__ __forceinline__ void backward(T (&d)[C], T ytot, H h = H{})
     {
         const int t = threadIdx.x;
         const int lane = t & (kWave - 1);
         const int w = t / kWave;
         T b = iu[C - 1] * d[C - 1];
 #pragma unroll
-        for (int k = C - 2; k >= 0; --k) b = bstep(k, b, d[k]);
+        for (int k = C - 2; k >= 0; --k) {
+            b = bstep(k, b, d[k]);
+            if (k == C / 2 - 1) at(h, 7);
+        }
+        if constexpr (C < 2) at(h, 7);
         T v = scan_down(b, wb);
+        at(h, 8);
         T cb = T(0), xtot;
         if constexpr (W > 1) {
             if (lane == 0) sh[kAggB + w] = v;
@@ -286,6 +352,7 @@ struct LineSolver {
                         if (j0 + k == M - 1) sh[kYLast] = d[k];
                 }
             }
+            at(h, 9);
             __syncthreads();
             if constexpr (CP && CYC) ytot = sh[kYLast];
             if constexpr (kLaneComb) {
@@ -304,8 +371,10 @@ struct LineSolver {
                 xtot = acc;
             }
         } else {
+            at(h, 9);
             xtot = readlane(v, 0);
         }
+        at(h, 10);
         const T next = dpp<0x130>(v);  // wave_shl:1, lane 63 reads 0
         T x = fma(qb, cb, next);
 #pragma unroll
@@ -313,6 +382,7 @@ struct LineSolver {
             x = bstep(k, x, d[k]);
             d[k] = x;
         }
+        at(h, 11);
         if (CYC && cyclic) {  // Sherman-Morrison correction
             const T xlast = iu_last * ytot;  // x_{M-1} = iu_{M-1} y_{M-1}: nothing lies beyond it
             const T phi = (xtot + bg * xlast) * inv_den;
@@ -322,15 +392,23 @@ struct LineSolver {
     }
 
     // Solve A x = d; d is overwritten by x.
-    __device__ __forceinline__ void solve(T (&d)[C])
+    __device__ __forceinline__ void solve(T (&d)[C]) { solve_to(d, d); }
+
+    // Solve A out = in (in may be out; otherwise in is left as it was), with
+    // the caller's hook run at the twelve points listed above NoHook.
+    template <class H = NoHook>
+    __device__ __forceinline__ void solve_to(const T (&in)[C], T (&out)[C], H h = H{})
     {
         const int t = threadIdx.x;
         const int lane = t & (kWave - 1);
         const int w = t / kWave;
-        const T v = fwd_scan(d);
+        at(h, 0);
+        const T v = fwd_scan(in, h);
+        at(h, 2);
         T cw = T(0), ytot;
         if constexpr (W > 1) {
             if (lane == kWave - 1) sh[kAggF + w] = v;
+            at(h, 3);
             __syncthreads();
             if constexpr (kLaneComb) {
                 const T S = lane_scan_up(sh[kAggF + (lane & (W - 1))], lane);
@@ -348,11 +426,14 @@ struct LineSolver {
                 ytot = acc;
             }
         } else {
+            at(h, 3);
             ytot = readlane(v, kWave - 1);
         }
+        at(h, 4);
         const T prev = dpp<0x138>(v);  // wave_shr:1, lane 0 reads 0
-        fwd_pass2(d, fma(qf, cw, prev));
-        backward(d, ytot);
+        fwd_pass2_to(in, out, fma(qf, cw, prev), h);
+        at(h, 6);
+        backward(out, ytot, h);
     }
 
     // One step in increment form:  u <- u + A^{-1} r,  with

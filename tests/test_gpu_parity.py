@@ -166,6 +166,53 @@ def test_solve_every_layout(shape, monkeypatch):
     assert relerr(Xg, o.serial(u0)) < 1e-9
 
 
+IE_SPREAD = [
+    # (c, bc, M, N): the 256 x 16 implicit-Euler sweep, one solve per slice and more
+    (1, wl.PERIODIC, 4096, 6),
+    (1, wl.DIRICHLET, 4001, 5),
+    (2, wl.DIRICHLET, 4096, 6),
+    (3, wl.PERIODIC, 3001, 5),
+    (4, wl.DIRICHLET, 2049, 4),
+    (2, wl.PERIODIC, 4090, 2),   # one slice step
+    (1, wl.PERIODIC, 4096, 1),   # no slice step: z_0 = v_0 only
+]
+
+
+@pytest.mark.parametrize("case", IE_SPREAD, ids=lambda c: f"c{c[0]}_bc{c[1]}_M{c[2]}_N{c[3]}")
+def test_ie_sweep_with_interleaved_traffic(case, monkeypatch):
+    """The implicit-Euler sweep at 256 threads x 16 points stores z_{n-1} and
+    loads v_n between the phases of slice n's solves (out of place first
+    solve; the loads in the second solve, or after the stores in the one
+    solve when c = 1).  Against the oracle's sweep, out of place and in place,
+    ragged lines and both boundary conditions; then Algorithm 1 through
+    pit_solve and through the batch engine's multi-instance kernel."""
+    from paper_2203_10148_amd import pitsbicg as P
+
+    cc, bc, M, N = case
+    monkeypatch.setenv("PIT_LINE_SHAPE", "256,16")
+    p = op_problem(M, bc, wl.CN, wl.IE, cc, N, 2)
+    say(f"ie interleaved sweep {case}")
+    c = ctx(p)
+    assert c.kernel_shape() == (256, 16, 256, 16)
+    o = make_oracle(p)
+    lam = wl.random_block(p, 99 + cc)
+    ref = o.sweep(lam)
+    assert relerr(host(c.coarse_sweep(dev(lam))), ref) < 1e-12
+    d2 = dev(lam)
+    c.coarse_sweep(d2, d2)
+    assert relerr(host(d2), ref) < 1e-12
+    if N < 4:
+        return
+    u0 = wl.u0_fourier(p, 3)
+    Xo, io = o.pitsbicg(u0, tol=1e-10)
+    X, ig = c.solve(dev(u0), tol=1e-10)
+    assert ig.status == io.status == orc.OK and ig.iters == io.iters
+    assert relerr(host(X), Xo) < 1e-10
+    Xb, ib = P.Batch(1).solve([c], [dev(u0)], tol=1e-10)
+    assert ib[0].iters == ig.iters
+    assert relerr(host(Xb[0]), Xo) < 1e-10
+
+
 def test_serial_trajectory_is_annihilated():
     """F applied to the serial fine trajectory gives (u0, 0, .., 0)."""
     p = wl.C1
