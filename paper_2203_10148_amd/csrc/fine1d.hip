@@ -215,11 +215,12 @@ __device__ __forceinline__ void coarse_step(LineSolver<double, NT, C> &S, double
 // (c >= 2; with c = 1 after the stores, in the backward half of the one
 // solve), and z_n = w + v_n.  The same registers as a one-buffer prefetch,
 // but no wave issues sixteen 1 KiB accesses back to back.  A touch of v_{n+2}
-// (one element per 128-byte line) makes the loads L2 hits.  Hook plans
-// (measured on the 4096-point line, 256 threads): stores of pair slot s at
-// hook s + (s > 0) + (s > 3) of the first solve, loads at the same hooks of the
-// second, the touch at hook 10 of the first; with c = 1 stores at hook s,
-// loads at hook 8 + s/2, the touch at the start of the slice.
+// (one element of each thread's chunk) makes the loads L2 hits.  Hook plans
+// (measured on the 4096-point line, 256 threads): pair g of the P pairs a
+// thread holds takes slot s = 8g/P; its store goes at hook s + (s > 0) +
+// (s > 3) of the first solve, its load at the same hook of the second, the
+// touch at hook 10 of the first; with c = 1 stores at hook s, loads at hook
+// 8 + s/2, the touch at the start of the slice.
 template <int NT, int C, bool ONE>
 __device__ __forceinline__ void sweep1d_ie_spread(const LineTab<double> &tb, const double *v, double *z, int N,
                                                   int M, long ld, int c, double *lds)
@@ -298,11 +299,13 @@ __device__ __forceinline__ void sweep1d_f64_line(const LineTab<double> &tb, cons
     // buffers in AGPRs, and its copies then wait on loads just issued), nor
     // at 1024 threads (128 registers per lane).
     constexpr bool kTwoBuffers = C <= 8 && NT * C <= 4096;
-    // The interleaved implicit-Euler path where it fits the registers: one
-    // constant operator (reloading a slice's tables keeps more values live),
-    // 16-point chunks of lines up to 4096 points (at 8 and 16 waves the
-    // one-buffer forms already spill, and spill more with it).
-    if constexpr (!PS && !kTwoBuffers && NT * C <= 4096 && SCHEME == SCHEME_IE && TR && chunk_width(C) == 2) {
+    // The interleaved implicit-Euler path for one constant operator (with a
+    // table per slice the reloads keep more values live and it spilled), in
+    // the register form, at 8 or 16 points per lane and two or more waves:
+    // there it measured faster than both prefetch forms at one and at two
+    // solves per slice (512x8 and 1024x8 lines 15-50% faster, the 4096-point
+    // line 18%).  At 4 points or one wave it was slower at one solve per slice.
+    if constexpr (!PS && !line_compact(NT, C) && C >= 8 && NT >= 128 && SCHEME == SCHEME_IE && TR) {
         if (c == 1) sweep1d_ie_spread<NT, C, true>(tb, v, z, N, M, ld, c, lds);
         else sweep1d_ie_spread<NT, C, false>(tb, v, z, N, M, ld, c, lds);
         return;

@@ -167,33 +167,43 @@ def test_solve_every_layout(shape, monkeypatch):
 
 
 IE_SPREAD = [
-    # (c, bc, M, N): the 256 x 16 implicit-Euler sweep, one solve per slice and more
-    (1, wl.PERIODIC, 4096, 6),
-    (1, wl.DIRICHLET, 4001, 5),
-    (2, wl.DIRICHLET, 4096, 6),
-    (3, wl.PERIODIC, 3001, 5),
-    (4, wl.DIRICHLET, 2049, 4),
-    (2, wl.PERIODIC, 4090, 2),   # one slice step
-    (1, wl.PERIODIC, 4096, 1),   # no slice step: z_0 = v_0 only
+    # (NT, C, c, bc, M, N): the implicit-Euler sweep with interleaved traffic
+    # (8 or 16 points per lane, two or more waves), one solve per slice and more
+    (256, 16, 1, wl.PERIODIC, 4096, 6),
+    (256, 16, 1, wl.DIRICHLET, 4001, 5),
+    (256, 16, 2, wl.DIRICHLET, 4096, 6),
+    (256, 16, 3, wl.PERIODIC, 3001, 5),
+    (256, 16, 4, wl.DIRICHLET, 2049, 4),
+    (256, 16, 2, wl.PERIODIC, 4090, 2),   # one slice step
+    (256, 16, 1, wl.PERIODIC, 4096, 1),   # no slice step: z_0 = v_0 only
+    (128, 8, 1, wl.PERIODIC, 1000, 5),
+    (128, 8, 2, wl.DIRICHLET, 1024, 4),
+    (256, 8, 3, wl.PERIODIC, 2047, 4),
+    (512, 8, 1, wl.DIRICHLET, 4000, 4),
+    (512, 16, 2, wl.PERIODIC, 8000, 4),
+    (512, 16, 1, wl.DIRICHLET, 7001, 4),
+    (1024, 8, 2, wl.PERIODIC, 8192, 4),
+    (1024, 8, 1, wl.PERIODIC, 5003, 4),
 ]
 
 
-@pytest.mark.parametrize("case", IE_SPREAD, ids=lambda c: f"c{c[0]}_bc{c[1]}_M{c[2]}_N{c[3]}")
+@pytest.mark.parametrize("case", IE_SPREAD, ids=lambda c: f"NT{c[0]}_C{c[1]}_c{c[2]}_bc{c[3]}_M{c[4]}_N{c[5]}")
 def test_ie_sweep_with_interleaved_traffic(case, monkeypatch):
-    """The implicit-Euler sweep at 256 threads x 16 points stores z_{n-1} and
-    loads v_n between the phases of slice n's solves (out of place first
-    solve; the loads in the second solve, or after the stores in the one
-    solve when c = 1).  Against the oracle's sweep, out of place and in place,
-    ragged lines and both boundary conditions; then Algorithm 1 through
-    pit_solve and through the batch engine's multi-instance kernel."""
+    """The implicit-Euler sweep at 8 or 16 points per lane and two or more
+    waves stores z_{n-1} and loads v_n between the phases of slice n's solves
+    (out of place first solve; the loads in the second solve, or after the
+    stores in the one solve when c = 1).  Against the oracle's sweep, out of
+    place and in place, ragged lines and both boundary conditions; then
+    Algorithm 1 through pit_solve and through the batch engine's
+    multi-instance kernel."""
     from paper_2203_10148_amd import pitsbicg as P
 
-    cc, bc, M, N = case
-    monkeypatch.setenv("PIT_LINE_SHAPE", "256,16")
+    NT, C, cc, bc, M, N = case
+    monkeypatch.setenv("PIT_LINE_SHAPE", f"{NT},{C}")
     p = op_problem(M, bc, wl.CN, wl.IE, cc, N, 2)
     say(f"ie interleaved sweep {case}")
     c = ctx(p)
-    assert c.kernel_shape() == (256, 16, 256, 16)
+    assert c.kernel_shape() == (NT, C, NT, C)
     o = make_oracle(p)
     lam = wl.random_block(p, 99 + cc)
     ref = o.sweep(lam)
