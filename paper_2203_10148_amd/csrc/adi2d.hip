@@ -93,10 +93,15 @@ __device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, i
     for (int k = 0; k < C; ++k) r[k] = row[min(lane * C + k, Mx - 1)];
 }
 
-template <int NT, int C, typename SIN, typename SOUT>
+// PRE (one wave per row, FP64 out): the row is stored as the next y half
+// step's right-hand side (I + theta Lx) u* (ex2, ed2) instead of u*, formed
+// from the solved row with the same operations, in the same order, as the
+// y kernel would form it from the stored u* (left + right neighbour, zero
+// outside the row), so the result is the same to the bit.
+template <int NT, int C, typename SIN, typename SOUT, bool PRE = false>
 __device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
                                       const SIN (&nx)[C], int j, int My, int Mx, int lane, bool vec, double ex,
-                                      double ed, SOUT *__restrict__ oslice)
+                                      double ed, SOUT *__restrict__ oslice, double ex2 = 0.0, double ed2 = 0.0)
 {
     const double fp = (j > 0) ? 1.0 : 0.0, fn = (j + 1 < My) ? 1.0 : 0.0;
     double d[C];
@@ -106,6 +111,20 @@ __device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, cons
         d[k] = (lane * C + k < Mx) ? v : 0.0;
     }
     LS.solve(d);
+    if constexpr (PRE) {
+        static_assert(NT == kWave && sizeof(SOUT) == sizeof(double), "one wave per row, FP64 out");
+        const double dl = dpp<0x138>(d[C - 1]);  // lane-1's last point (lane 0 reads 0: the boundary)
+        const double dr = dpp<0x130>(d[0]);      // lane+1's first point (lane 63 reads 0)
+        double rr[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const double left = (k == 0) ? dl : d[k - 1];
+            const double right = (lane * C + k + 1 < Mx) ? ((k == C - 1) ? dr : d[k + 1]) : 0.0;
+            rr[k] = fma(ed2, d[k], ex2 * (left + right));
+        }
+#pragma unroll
+        for (int k = 0; k < C; ++k) d[k] = rr[k];
+    }
     SOUT *row = oslice + (size_t)j * Mx;
     constexpr int V = 16 / sizeof(SOUT);
     if constexpr (C % V == 0) {
@@ -149,19 +168,24 @@ __device__ __forceinline__ int xcd_block(int b, int n)
 // (rows wider than 512 points): blocks of one wave pair, block g handles strip
 // g, and the pair's line solves exchange their carries through LDS.  in/out
 // slice s sits at in + (s + in_off)*npts.
-template <int XW, int C, typename SIN, typename SOUT>
-__global__ __launch_bounds__(XW == 1 ? 256 : 128) void k_adi_x(LineTab<double> tb, const SIN *__restrict__ in,
-                                                               long in_off, SOUT *__restrict__ out, long out_off,
-                                                               int nslices, int Mx, int My, int R, double ex,
-                                                               double ed)
+// XW = 1 launches carry WPB independent waves per block: 4 over many
+// slices, 1 for a single slice, where 4 would leave half the CUs without a
+// row (512 rows: 128 blocks of 4 waves; 512 blocks of one measured 9% faster
+// per coarse step).
+template <int XW, int C, typename SIN, typename SOUT, int WPB = 4, bool PRE = false>
+__global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<double> tb, const SIN *__restrict__ in,
+                                                                    long in_off, SOUT *__restrict__ out,
+                                                                    long out_off, int nslices, int Mx, int My, int R,
+                                                                    double ex, double ed, double ex2, double ed2)
 {
+    static_assert(!PRE || XW == 1, "the pre-formed right-hand side needs the whole row in one wave");
     constexpr int NT = kWave * XW;
     __shared__ double lds[XW == 1 ? 1 : LineSolver<double, NT, C, false>::kLds];
     poison_lds(lds, (int)(sizeof(lds) / sizeof(double)));
     const int lane = threadIdx.x & (NT - 1);  // thread of the row group
     const int strips = (My + R - 1) / R;
     // group-uniform indices in scalar registers, so row addresses stay scalar
-    const int g = XW == 1 ? __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + threadIdx.x / kWave)
+    const int g = XW == 1 ? __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * WPB + threadIdx.x / kWave)
                           : xcd_block(blockIdx.x, gridDim.x);
     if (g >= nslices * strips) return;  // the whole group exits (a block for XW = 2); no barriers skipped
     const int s = g / strips, j0 = (g % strips) * R, j1 = min(j0 + R, My);
@@ -186,7 +210,8 @@ __global__ __launch_bounds__(XW == 1 ? 256 : 128) void k_adi_x(LineTab<double> t
     {                                                                                                          \
         const int r = j + (u);                                                                                 \
         if (r >= j1) break;                                                                                    \
-        x_row<NT, C>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, ex, ed, oslice); \
+        x_row<NT, C, SIN, SOUT, PRE>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, \
+                                     ex, ed, oslice, ex2, ed2);                                                 \
         load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                    \
     }
         PIT_XSTEP(0) PIT_XSTEP(1) PIT_XSTEP(2) PIT_XSTEP(3) PIT_XSTEP(4)
@@ -402,13 +427,17 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
 // solve), and the solution goes back through LDS so that the stores and the
 // epilogue's base reads are row-wise again.  In LDS a column keeps row r at
 // (r % C)*64 + r / C: the 64 lanes of one access read consecutive slots.
-template <int CW, int C, typename SIN, typename SOUT, int EPI>
+// PRE: `in` already holds the right-hand side (I + theta Lx) u* (formed by
+// the x half step), so only the block's own CW columns are staged and no
+// neighbour column is read.
+template <int CW, int C, typename SIN, typename SOUT, int EPI, bool PRE = false>
 __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SIN *__restrict__ in, long in_off,
                                                     SOUT *__restrict__ out, long out_off,
                                                     const double *__restrict__ base, long base_off, double sign,
                                                     int nslices, int Mx, int My, double ex, double ed)
 {
-    constexpr int L = kWave * C, TW = CW + 2, NTH = CW * kWave;
+    constexpr int H = PRE ? 0 : 1;  // halo columns on each side
+    constexpr int L = kWave * C, TW = CW + 2 * H, NTH = CW * kWave;
     __shared__ double tile[TW * L];
     poison_lds(tile, TW * L);
     const int t = threadIdx.x, lane = t & (kWave - 1);
@@ -420,13 +449,13 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     const long npts = (long)Mx * My;
     const SIN *islice = in + (size_t)(s + in_off) * npts;
     auto slot = [](int r) { return (r % C) * kWave + r / C; };
-    // stage the CW + 2 columns (zeros left and right of the slice and below
-    // its last row: the Dirichlet values and the solver's pad rows)
+    // stage the CW (+ 2 halo) columns (zeros left and right of the slice and
+    // below its last row: the Dirichlet values and the solver's pad rows)
     constexpr int kIn = (TW * L + NTH - 1) / NTH;
     double v[kIn];
 #pragma unroll
     for (int q = 0; q < kIn; ++q) {
-        const int i = q * NTH + t, r = i / TW, col = col0 - 1 + i % TW;
+        const int i = q * NTH + t, r = i / TW, col = col0 - H + i % TW;
         v[q] = (i < TW * L && r < My && col >= 0 && col < Mx) ? to_d(islice[(size_t)r * Mx + col]) : 0.0;
     }
 #pragma unroll
@@ -452,11 +481,13 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     __syncthreads();
     // right-hand side (I + theta Lx) u* of column col0 + w, then the solve
     double d[C];
-    const int cc = w + 1;
+    const int cc = w + H;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int q = k * kWave + lane;  // slot of row lane*C + k
-        const double u = fma(ed, tile[cc * L + q], ex * (tile[(cc - 1) * L + q] + tile[(cc + 1) * L + q]));
+        double u;
+        if constexpr (PRE) u = tile[cc * L + q];
+        else u = fma(ed, tile[cc * L + q], ex * (tile[(cc - 1) * L + q] + tile[(cc + 1) * L + q]));
         d[k] = (lane * C + k < My) ? u : 0.0;
     }
     LS.solve(d);
@@ -468,7 +499,7 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     for (int q = 0; q < kOut; ++q) {
         const int i = q * NTH + t, r = i / CW, c = i % CW, col = col0 + c;
         if (r < My && col < Mx) {
-            double x = tile[(c + 1) * L + slot(r)];
+            double x = tile[(c + H) * L + slot(r)];
             if constexpr (EPI) x = fma(sign, x, bq[q]);
             oslice[(size_t)r * Mx + col] = (SOUT)x;
         }
@@ -486,11 +517,16 @@ static hipError_t adi_x_t(const AdiShape &sh, const LineTab<double> &tb, const S
                           long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
 {
     const int strips = (My + R - 1) / R;
-    const int blocks = sh.xw == 1 ? (nslices * strips + 3) / 4 : nslices * strips;
+    const bool one = nslices == 1;  // one wave per block over a single slice
+    const int blocks = sh.xw == 1 ? (one ? strips : (nslices * strips + 3) / 4) : nslices * strips;
 #define X(XW_, C_)                                                                                              \
     if (sh.xw == XW_ && sh.cx == C_) {                                                                          \
-        hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT>), dim3(blocks), dim3(XW_ == 1 ? 256 : 128), 0, st, tb,   \
-                           in, in_off, out, out_off, nslices, Mx, My, R, ex, ed);                               \
+        if (XW_ == 1 && one)                                                                                    \
+            hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT, 1>), dim3(blocks), dim3(64), 0, st, tb, in, in_off,  \
+                               out, out_off, nslices, Mx, My, R, ex, ed, 0.0, 0.0);                             \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT>), dim3(blocks), dim3(XW_ == 1 ? 256 : 128), 0, st,   \
+                               tb, in, in_off, out, out_off, nslices, Mx, My, R, ex, ed, 0.0, 0.0);             \
         return hipGetLastError();                                                                               \
     }
     PIT_ADI_XC(X)
@@ -516,7 +552,7 @@ static hipError_t adi_y_t(const AdiShape &sh, const ColTab &tb, const SIN *in, l
     return hipErrorInvalidValue;
 }
 
-template <int CW, typename SIN, typename SOUT, int EPI>
+template <int CW, typename SIN, typename SOUT, int EPI, bool PRE>
 static hipError_t adi_yc_t(int cy, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out, long out_off,
                            const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
                            double ed, hipStream_t st)
@@ -524,7 +560,7 @@ static hipError_t adi_yc_t(int cy, const LineTab<double> &tb, const SIN *in, lon
     const int blocks = nslices * ((Mx + CW - 1) / CW);
 #define X(C_)                                                                                                  \
     if (cy == C_) {                                                                                            \
-        hipLaunchKernelGGL((k_adi_yc<CW, C_, SIN, SOUT, EPI>), dim3(blocks), dim3(CW * 64), 0, st, tb, in,     \
+        hipLaunchKernelGGL((k_adi_yc<CW, C_, SIN, SOUT, EPI, PRE>), dim3(blocks), dim3(CW * 64), 0, st, tb, in, \
                            in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);               \
         return hipGetLastError();                                                                              \
     }
@@ -535,19 +571,35 @@ static hipError_t adi_yc_t(int cy, const LineTab<double> &tb, const SIN *in, lon
 
 hipError_t launch_adi_yc(int cw, int cy, const LineTab<double> &tb, const double *in, long in_off, double *out,
                          long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
-                         double ex, double ed, hipStream_t st)
+                         double ex, double ed, hipStream_t st, bool pre)
 {
     if (64 * cy < My) return hipErrorInvalidValue;
-#define Y(CW_)                                                                                                 \
-    if (cw == CW_) {                                                                                           \
+#define Y(CW_, PRE_)                                                                                           \
+    if (cw == CW_ && pre == PRE_) {                                                                            \
         if (base)                                                                                              \
-            return adi_yc_t<CW_, double, double, 1>(cy, tb, in, in_off, out, out_off, base, base_off, sign,     \
-                                                    nslices, Mx, My, ex, ed, st);                              \
-        return adi_yc_t<CW_, double, double, 0>(cy, tb, in, in_off, out, out_off, nullptr, 0, 0.0, nslices, Mx, \
-                                                My, ex, ed, st);                                               \
+            return adi_yc_t<CW_, double, double, 1, PRE_>(cy, tb, in, in_off, out, out_off, base, base_off,     \
+                                                          sign, nslices, Mx, My, ex, ed, st);                  \
+        return adi_yc_t<CW_, double, double, 0, PRE_>(cy, tb, in, in_off, out, out_off, nullptr, 0, 0.0,        \
+                                                      nslices, Mx, My, ex, ed, st);                            \
     }
-    Y(1) Y(2) Y(4)
+    Y(1, false) Y(2, false) Y(4, false) Y(1, true) Y(2, true) Y(4, true)
 #undef Y
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adi_x_pre(const AdiShape &sh, const LineTab<double> &tb, const double *in, long in_off,
+                            double *out, int Mx, int My, double ex, double ed, double ex2, double ed2,
+                            hipStream_t st)
+{
+    if (sh.xw != 1) return hipErrorInvalidValue;
+#define X(XW_, C_)                                                                                              \
+    if (XW_ == 1 && sh.cx == C_) {                                                                              \
+        hipLaunchKernelGGL((k_adi_x<1, C_, double, double, 1, true>), dim3(My), dim3(64), 0, st, tb, in, in_off, \
+                           out, 0, 1, Mx, My, 1, ex, ed, ex2, ed2);                                             \
+        return hipGetLastError();                                                                               \
+    }
+    PIT_ADI_XC(X)
+#undef X
     return hipErrorInvalidValue;
 }
 

@@ -178,9 +178,17 @@ hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in
 // FP64 y half step with one column per wavefront (columns of at most 512
 // rows, 64*cy >= My; tb: the line tables of a column, shape {64, cy}), for
 // the single-slice steps of the coarse sweep; cw (1, 2 or 4) columns per block.
+// pre: `in` holds the right-hand side (I + theta Lx) u*, as launch_adi_x_pre
+// stores it (no neighbour columns are read).
 hipError_t launch_adi_yc(int cw, int cy, const LineTab<double> &tb, const double *in, long in_off, double *out,
                          long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
-                         double ex, double ed, hipStream_t st);
+                         double ex, double ed, hipStream_t st, bool pre = false);
+// FP64 x half step of one slice (rows of at most 512 points, one wave per
+// row) that stores the next y half step's right-hand side (I + theta Lx) u*
+// (coefficients ex2, ed2) instead of u*.
+hipError_t launch_adi_x_pre(const AdiShape &sh, const LineTab<double> &tb, const double *in, long in_off,
+                            double *out, int Mx, int My, double ex, double ed, double ex2, double ed2,
+                            hipStream_t st);
 hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
                         const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
                         double ed, hipStream_t st);

@@ -478,6 +478,10 @@ bool setup_2d(pit_ctx &c, const AdiTune *force)
             return false;
         c.ycc = cyc;
         c.ycw = ycw;
+        // the x half step hands it the right-hand side (PIT_ADI_PRE=0: the
+        // y kernel forms it from u* and its neighbour columns)
+        const char *pe = std::getenv("PIT_ADI_PRE");
+        c.ypre = !(pe && pe[0] == '0');
     }
     return true;
 }
@@ -703,18 +707,27 @@ hipError_t sweep_2d(const pit_ctx *c, const double *v, double *z, double *tmpa, 
     const AdiBuf zb{nullptr, z, false};
     const AdiBuf ta{nullptr, tmpa, false}, tb{nullptr, tmpb, false};
     const int cs = c->coarse.substeps;
+    // With the one-column y kernel and rows that fit one wave, the x half
+    // step stores the y half step's right-hand side (I + theta Lx) u* itself
+    // (bitwise what the y kernel would form), so the y kernel stages only
+    // its own columns.
+    const bool pre = c->ycc && c->ypre && c->ash.xw == 1;
     // y half step of slice n: one column per wavefront where the tables exist
     auto yhalf = [&](const AdiBuf &out, long out_off, const double *base, long base_off, double sign) {
         if (c->ycc)
             return launch_adi_yc(c->ycw, c->ycc, tyc, tmpa, 0, out.d, out_off, base, base_off, sign, 1, Mx, My,
-                                 c->cy_ex, c->cy_ed, st);
+                                 c->cy_ex, c->cy_ed, st, pre);
         return launch_adi_y(c->ash, ty, ta, 0, out, out_off, base, base_off, sign, 1, Mx, My, c->cy_ex, c->cy_ed, st);
     };
     for (int n = 1; n < c->N; ++n) {
         for (int s = 0; s < cs; ++s) {
-            if ((e = launch_adi_x(c->ash, tx, s == 0 ? zb : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, c->cx_ex,
-                                  c->cx_ed, st)) != hipSuccess)
-                return e;
+            if (pre)
+                e = launch_adi_x_pre(c->ash, tx, s == 0 ? z : tmpb, s == 0 ? n - 1 : 0, tmpa, Mx, My, c->cx_ex,
+                                     c->cx_ed, c->cy_ex, c->cy_ed, st);
+            else
+                e = launch_adi_x(c->ash, tx, s == 0 ? zb : tb, s == 0 ? n - 1 : 0, ta, 0, 1, Mx, My, 1, c->cx_ex,
+                                 c->cx_ed, st);
+            if (e != hipSuccess) return e;
             e = (s == cs - 1) ? yhalf(zb, n, v, n, 1.0) : yhalf(tb, 0, nullptr, 0, 0.0);
             if (e != hipSuccess) return e;
         }

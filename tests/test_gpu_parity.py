@@ -600,6 +600,35 @@ def test_adi_sweep_y_kernels(Mx, My, c, yc, monkeypatch):
     assert e1 < 1e-12 and e2 < 1e-12
 
 
+@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3), (64, 512, 1)])
+def test_adi_sweep_preformed_rhs_is_bitwise(Mx, My, c, monkeypatch):
+    """With the one-column y kernel the coarse sweep's x half step stores the
+    y half step's right-hand side (I + theta Lx) u* itself: the same bits as
+    the y kernel forming it from u* and its neighbour columns
+    (PIT_ADI_PRE=0), in and out of place, one and several coarse steps per
+    slice, and the same solve."""
+    monkeypatch.delenv("PIT_ADI_YC", raising=False)
+    p = adi_problem(Mx, My, 1.0, 1.1, 5, 2, c, wl.F64)
+    say(f"adi sweep pre-formed rhs {Mx}x{My} c={c}")
+    monkeypatch.delenv("PIT_ADI_PRE", raising=False)
+    c1 = ctx(p)
+    monkeypatch.setenv("PIT_ADI_PRE", "0")
+    c0 = ctx(p)
+    lam = dev(wl.random_block(p, 29))
+    z1 = c1.coarse_sweep(lam)
+    z0 = c0.coarse_sweep(lam)
+    torch.cuda.synchronize()
+    assert torch.equal(z0, z1)
+    d = lam.clone()
+    c1.coarse_sweep(d, d)
+    torch.cuda.synchronize()
+    assert torch.equal(d, z1)
+    u0 = dev(wl.u0_for(p))
+    X1, i1 = c1.solve(u0, tol=1e-10)
+    X0, i0 = c0.solve(u0, tol=1e-10)
+    assert i1.iters == i0.iters and torch.equal(X0, X1)
+
+
 def test_adi_shared_tables_on_a_small_fp64_slice(monkeypatch):
     """The shared-table kernels on a slice that would otherwise take the LDS
     path (PIT_VEL_LDS=0 at creation), against the oracle."""
