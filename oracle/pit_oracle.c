@@ -246,7 +246,9 @@ static double stored(double v, int rnd) { return rnd ? (double)(float)v : v; }
 
 /* out = one step of `scheme` with time step dt applied to u (no aliasing);
  * the source of the step is wf * f (f NULL: none).  2D only: rnd bit 1 rounds
- * the intermediate field to float, bit 2 the output. */
+ * to float what the first half step hands to the second (PR-ADI: the second
+ * half's right-hand side; the backward-Euler splitting: the intermediate
+ * field), bit 2 the output. */
 static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, double *out,
                      double *work, const double *f, double wf, int rnd)
 {
@@ -336,10 +338,12 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
             }
             op1d(C->nu, ux_at(C, j), 0.5 * C->react, C->hx, &xlo, &xdi, &xup);
             implicit_line(nx, ORC_DIRICHLET, th, xlo, xdi, xup, line, sol, lw);
-            for (int i = 0; i < nx; ++i) star[j * nx + i] = stored(sol[i], rnd & 1);
+            for (int i = 0; i < nx; ++i) star[j * nx + i] = sol[i];
         }
         /* half-step 2: rhs = (I + th*Lx) u* + th*f, then (I - th*Ly) u' = rhs column by column
-         * (the implicit barrier of the loop above orders the two halves) */
+         * (the implicit barrier of the loop above orders the two halves).  What the
+         * first half hands to the second is this right-hand side: in the FP32-fine
+         * form (rnd bit 1) it is the value stored in FP32. */
 #pragma omp for schedule(static)
         for (int i = 0; i < nx; ++i) {
             for (int j = 0; j < ny; ++j) {
@@ -349,6 +353,7 @@ static void one_step(const orc_ctx *C, int scheme, double dt, const double *u, d
                 double cq = (i < nx - 1) ? star[j * nx + i + 1] : 0.0;
                 line[j] = c0 + th * (xlo * cm + xdi * c0 + xup * cq);
                 if (f) line[j] += th * (wf * f[j * nx + i]);
+                line[j] = stored(line[j], rnd & 1);
             }
             op1d(C->nu, uy_at(C, i), 0.5 * C->react, C->hy, &ylo, &ydi, &yup);
             implicit_line(ny, ORC_DIRICHLET, th, ylo, ydi, yup, line, sol, lw);

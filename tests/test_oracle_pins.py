@@ -1121,11 +1121,9 @@ def test_fp32_form_dirichlet_ie_sine_mode():
 
 
 def test_fp32_form_2d_rounds_the_fields_between_half_steps():
-    """2D PR-ADI: FP64 arithmetic with the fields between half steps stored in
-    FP32: the slice output differs from FP64 at the FP32 level, and equals the
-    FP64 propagator when there is only one half-step pair to round (m = 1: the
-    intermediate field is rounded, so not even then bit-equal, but within
-    FP32 rounding)."""
+    """2D PR-ADI: FP64 arithmetic with what crosses between the half steps (the
+    second half's right-hand side) and the step's output stored in FP32: the
+    slice output differs from FP64 at the FP32 level, within FP32 rounding."""
     p = wl.Problem(dim=2, M=(40, 30), bc=wl.DIRICHLET, nu=0.05, T=0.2, N=4, m=8, fine=wl.ADI, c=1,
                    coarse=wl.ADI, prec=wl.F64)
     o64 = make(p)
