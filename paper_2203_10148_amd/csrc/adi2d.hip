@@ -98,10 +98,13 @@ __device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, i
 // from the solved row with the same operations, in the same order, as the
 // y kernel would form it from the stored u* (left + right neighbour, zero
 // outside the row), so the result is the same to the bit.
+// A row on two wavefronts (NT = 128) swaps the points beside the wave edge
+// through xch (two LDS slots) and one barrier.
 template <int NT, int C, typename SIN, typename SOUT, bool PRE = false>
 __device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
                                       const SIN (&nx)[C], int j, int My, int Mx, int lane, bool vec, double ex,
-                                      double ed, SOUT *__restrict__ oslice, double ex2 = 0.0, double ed2 = 0.0)
+                                      double ed, SOUT *__restrict__ oslice, double ex2 = 0.0, double ed2 = 0.0,
+                                      double *xch = nullptr)
 {
     const double fp = (j > 0) ? 1.0 : 0.0, fn = (j + 1 < My) ? 1.0 : 0.0;
     double d[C];
@@ -112,9 +115,19 @@ __device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, cons
     }
     LS.solve(d);
     if constexpr (PRE) {
-        static_assert(NT == kWave && sizeof(SOUT) == sizeof(double), "one wave per row, FP64 out");
-        const double dl = dpp<0x138>(d[C - 1]);  // lane-1's last point (lane 0 reads 0: the boundary)
-        const double dr = dpp<0x130>(d[0]);      // lane+1's first point (lane 63 reads 0)
+        static_assert(NT == kWave || NT == 2 * kWave, "one or two waves per row");
+        double dl = dpp<0x138>(d[C - 1]);  // lane-1's last point (lane 0 reads 0: the boundary)
+        double dr = dpp<0x130>(d[0]);      // lane+1's first point (lane 63 reads 0)
+        if constexpr (NT == 2 * kWave) {
+            // wave 0's last point and wave 1's first cross through LDS; the
+            // previous row's reads finished before this row's solve passed
+            // its barriers
+            if (lane == kWave - 1) xch[0] = d[C - 1];
+            if (lane == kWave) xch[1] = d[0];
+            __syncthreads();
+            if (lane == kWave) dl = xch[0];
+            if (lane == kWave - 1) dr = xch[1];
+        }
         double rr[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -178,9 +191,9 @@ __global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<doub
                                                                     long out_off, int nslices, int Mx, int My, int R,
                                                                     double ex, double ed, double ex2, double ed2)
 {
-    static_assert(!PRE || XW == 1, "the pre-formed right-hand side needs the whole row in one wave");
     constexpr int NT = kWave * XW;
     __shared__ double lds[XW == 1 ? 1 : LineSolver<double, NT, C, false>::kLds];
+    __shared__ double xch[XW == 2 && PRE ? 2 : 1];  // the wave-edge points of a pre-formed row
     poison_lds(lds, (int)(sizeof(lds) / sizeof(double)));
     const int lane = threadIdx.x & (NT - 1);  // thread of the row group
     const int strips = (My + R - 1) / R;
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<doub
         const int r = j + (u);                                                                                 \
         if (r >= j1) break;                                                                                    \
         x_row<NT, C, SIN, SOUT, PRE>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, \
-                                     ex, ed, oslice, ex2, ed2);                                                 \
+                                     ex, ed, oslice, ex2, ed2, xch);                                            \
         load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                    \
     }
         PIT_XSTEP(0) PIT_XSTEP(1) PIT_XSTEP(2) PIT_XSTEP(3) PIT_XSTEP(4)
@@ -227,8 +240,9 @@ __global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<doub
 // col0 + l % CW, segment g = SEG*w + l / CW (rows g*CY .. g*CY+CY-1), so
 // WY*SEG*CY rows in all.  Epilogue EPI: 0 stores u', 1 stores base +
 // sign*u' (FP64) -- the all-at-once apply's lam_n - F(...) and the coarse
-// sweep's v_n + G(...).
-template <int WY, int CY, int SEG, typename SIN, typename SOUT, int EPI>
+// sweep's v_n + G(...).  PRE: `in` already holds the right-hand side
+// (I + theta Lx) u* (formed by the x half step), so no halo column is read.
+template <int WY, int CY, int SEG, typename SIN, typename SOUT, int EPI, bool PRE = false>
 __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restrict__ in, long in_off,
                                                    SOUT *__restrict__ out, long out_off,
                                                    const double *__restrict__ base, long base_off, double sign,
@@ -317,6 +331,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     // speculatable, so inside a conditional they would become a divergent
     // branch); the strip-edge lanes then select the halo values.
     auto rhs = [&](SIN v, int r) {
+        if constexpr (PRE) return to_d(v);
         SIN hl, hr;
         if constexpr (SEG == 1) {
             hl = readlane(hv, r);
@@ -343,14 +358,14 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
         // place (a separate copy of the rows would not fit in registers)
 #pragma unroll
         for (int r = 0; r < CY; ++r) d[r] = in_row(r);
-        load_halos();
+        if constexpr (!PRE) load_halos();
 #pragma unroll
         for (int r = 0; r < CY; ++r) d[r] = rhs(d[r], r);
     } else {
         SIN raw[CY];
 #pragma unroll
         for (int r = 0; r < CY; ++r) raw[r] = in_row(r);
-        load_halos();
+        if constexpr (!PRE) load_halos();
 #pragma unroll
         for (int r = 0; r < CY; ++r) d[r] = rhs(raw[r], r);
     }
@@ -365,11 +380,15 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
         const double n = fma(s_pf[q], cw, s_agg[0][q][cl]);
         cw = (q < g) ? n : cw;
     }
+    // FP32 fields: d[r] then holds y_r / u_r, the term both backward passes
+    // add, formed once (the same product, so the same bits).  With FP64 fields
+    // the extra live products cost the 8-wave block its second slot on a CU.
+    constexpr bool PS = sizeof(SIN) == sizeof(float);
     double y = cw;
 #pragma unroll
     for (int r = 0; r < CY; ++r) {
         y = fma(s_lm[r0 + r], y, d[r]);
-        d[r] = y;
+        d[r] = PS ? s_iu[r0 + r] * y : y;
     }
     // back substitution along y
     const Rsrc rout = make_rsrc(out + (size_t)(s + out_off) * npts, (unsigned)(npts * zo));
@@ -391,7 +410,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     }
     double bsum = 0.0;
 #pragma unroll
-    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, s_iu[r0 + r] * d[r]);
+    for (int r = CY - 1; r >= 0; --r) bsum = fma(s_cm[r0 + r], bsum, PS ? d[r] : s_iu[r0 + r] * d[r]);
     s_agg[1][g][cl] = bsum;
     __syncthreads();
     double cb = 0.0;
@@ -403,7 +422,7 @@ __global__ __launch_bounds__(WY * 64) void k_adi_y(ColTab tb, const SIN *__restr
     double x = cb;
 #pragma unroll
     for (int r = CY - 1; r >= 0; --r) {
-        x = fma(s_cm[r0 + r], x, s_iu[r0 + r] * d[r]);
+        x = fma(s_cm[r0 + r], x, PS ? d[r] : s_iu[r0 + r] * d[r]);
         double o = x;
         if constexpr (EPI) {
             const int q = (CY - 1 - r) % PB;
@@ -519,13 +538,24 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
 
 template <typename SIN, typename SOUT>
 static hipError_t adi_x_t(const AdiShape &sh, const LineTab<double> &tb, const SIN *in, long in_off, SOUT *out,
-                          long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
+                          long out_off, int nslices, int Mx, int My, int R, double ex, double ed, bool pre,
+                          double ex2, double ed2, hipStream_t st)
 {
     const int strips = (My + R - 1) / R;
     const bool one = nslices == 1;  // one wave per block over a single slice
     const int blocks = sh.xw == 1 ? (one ? strips : (nslices * strips + 3) / 4) : nslices * strips;
 #define X(XW_, C_)                                                                                              \
     if (sh.xw == XW_ && sh.cx == C_) {                                                                          \
+        if (pre) {                                                                                              \
+            if (XW_ == 1 && one)                                                                                \
+                hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT, 1, true>), dim3(blocks), dim3(64), 0, st, tb,   \
+                                   in, in_off, out, out_off, nslices, Mx, My, R, ex, ed, ex2, ed2);             \
+            else                                                                                                \
+                hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT, 4, true>), dim3(blocks),                        \
+                                   dim3(XW_ == 1 ? 256 : 128), 0, st, tb, in, in_off, out, out_off, nslices, Mx, \
+                                   My, R, ex, ed, ex2, ed2);                                                     \
+            return hipGetLastError();                                                                           \
+        }                                                                                                       \
         if (XW_ == 1 && one)                                                                                    \
             hipLaunchKernelGGL((k_adi_x<XW_, C_, SIN, SOUT, 1>), dim3(blocks), dim3(64), 0, st, tb, in, in_off,  \
                                out, out_off, nslices, Mx, My, R, ex, ed, 0.0, 0.0);                             \
@@ -539,7 +569,7 @@ static hipError_t adi_x_t(const AdiShape &sh, const LineTab<double> &tb, const S
     return hipErrorInvalidValue;
 }
 
-template <typename SIN, typename SOUT, int EPI>
+template <typename SIN, typename SOUT, int EPI, bool PRE>
 static hipError_t adi_y_t(const AdiShape &sh, const ColTab &tb, const SIN *in, long in_off, SOUT *out,
                           long out_off, const double *base, long base_off, double sign, int nslices, int Mx, int My,
                           double ex, double ed, hipStream_t st)
@@ -548,8 +578,8 @@ static hipError_t adi_y_t(const AdiShape &sh, const ColTab &tb, const SIN *in, l
     const int blocks = nslices * ((Mx + cw - 1) / cw);
 #define X(WY_, CY_, SG_)                                                                                         \
     if (sh.wy == WY_ && sh.cy == CY_ && sh.seg == SG_) {                                                        \
-        hipLaunchKernelGGL((k_adi_y<WY_, CY_, SG_, SIN, SOUT, EPI>), dim3(blocks), dim3(WY_ * 64), 0, st, tb,   \
-                           in, in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);              \
+        hipLaunchKernelGGL((k_adi_y<WY_, CY_, SG_, SIN, SOUT, EPI, PRE>), dim3(blocks), dim3(WY_ * 64), 0, st,  \
+                           tb, in, in_off, out, out_off, base, base_off, sign, nslices, Mx, My, ex, ed);          \
         return hipGetLastError();                                                                                \
     }
     PIT_ADI_YSHAPES(X)
@@ -609,37 +639,53 @@ hipError_t launch_adi_x_pre(const AdiShape &sh, const LineTab<double> &tb, const
 }
 
 hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in, long in_off, AdiBuf out,
-                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st)
+                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st,
+                        bool pre, double ex2, double ed2)
 {
     if (in.f32 && out.f32)
-        return adi_x_t<float, float>(sh, tb, in.f, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<float, float>(sh, tb, in.f, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, pre, ex2, ed2,
+                                     st);
     if (!in.f32 && out.f32)
-        return adi_x_t<double, float>(sh, tb, in.d, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<double, float>(sh, tb, in.d, in_off, out.f, out_off, nslices, Mx, My, R, ex, ed, pre, ex2,
+                                      ed2, st);
     if (!in.f32 && !out.f32)
-        return adi_x_t<double, double>(sh, tb, in.d, in_off, out.d, out_off, nslices, Mx, My, R, ex, ed, st);
+        return adi_x_t<double, double>(sh, tb, in.d, in_off, out.d, out_off, nslices, Mx, My, R, ex, ed, pre, ex2,
+                                       ed2, st);
     return hipErrorInvalidValue;
+}
+
+template <typename SIN, typename SOUT, int EPI>
+static hipError_t adi_y_pre(bool pre, const AdiShape &sh, const ColTab &tb, const SIN *in, long in_off, SOUT *out,
+                            long out_off, const double *base, long base_off, double sign, int nslices, int Mx,
+                            int My, double ex, double ed, hipStream_t st)
+{
+    if (pre)
+        return adi_y_t<SIN, SOUT, EPI, true>(sh, tb, in, in_off, out, out_off, base, base_off, sign, nslices, Mx,
+                                             My, ex, ed, st);
+    return adi_y_t<SIN, SOUT, EPI, false>(sh, tb, in, in_off, out, out_off, base, base_off, sign, nslices, Mx, My,
+                                          ex, ed, st);
 }
 
 hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
                         const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
-                        double ed, hipStream_t st)
+                        double ed, hipStream_t st, bool pre)
 {
     const bool epi = base != nullptr;
     if (in.f32 && out.f32 && !epi)
-        return adi_y_t<float, float, 0>(sh, tb, in.f, in_off, out.f, out_off, nullptr, 0, 0.0, nslices,
-                                        Mx, My, ex, ed, st);
+        return adi_y_pre<float, float, 0>(pre, sh, tb, in.f, in_off, out.f, out_off, nullptr, 0, 0.0, nslices, Mx,
+                                          My, ex, ed, st);
     if (in.f32 && !out.f32 && epi)
-        return adi_y_t<float, double, 1>(sh, tb, in.f, in_off, out.d, out_off, base, base_off, sign,
-                                         nslices, Mx, My, ex, ed, st);
+        return adi_y_pre<float, double, 1>(pre, sh, tb, in.f, in_off, out.d, out_off, base, base_off, sign,
+                                           nslices, Mx, My, ex, ed, st);
     if (in.f32 && !out.f32 && !epi)
-        return adi_y_t<float, double, 0>(sh, tb, in.f, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
-                                         Mx, My, ex, ed, st);
+        return adi_y_pre<float, double, 0>(pre, sh, tb, in.f, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
+                                           Mx, My, ex, ed, st);
     if (!in.f32 && !out.f32 && epi)
-        return adi_y_t<double, double, 1>(sh, tb, in.d, in_off, out.d, out_off, base, base_off, sign,
-                                          nslices, Mx, My, ex, ed, st);
+        return adi_y_pre<double, double, 1>(pre, sh, tb, in.d, in_off, out.d, out_off, base, base_off, sign,
+                                            nslices, Mx, My, ex, ed, st);
     if (!in.f32 && !out.f32 && !epi)
-        return adi_y_t<double, double, 0>(sh, tb, in.d, in_off, out.d, out_off, nullptr, 0, 0.0,
-                                          nslices, Mx, My, ex, ed, st);
+        return adi_y_pre<double, double, 0>(pre, sh, tb, in.d, in_off, out.d, out_off, nullptr, 0, 0.0, nslices,
+                                            Mx, My, ex, ed, st);
     return hipErrorInvalidValue;
 }
 

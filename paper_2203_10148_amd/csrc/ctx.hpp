@@ -90,6 +90,7 @@ struct pit_ctx {
     int ycc = 0;  // 0: not built (taller columns, or PIT_ADI_YC=0)
     int ycw = 4;  // columns per workgroup of that kernel
     bool ypre = false;  // its right-hand side formed by the x half step
+    bool fpre = false;  // the same in the fine apply
     size_t off_aycl = 0;
     // Source constant in time (host copy; empty: none) and, in the workspace,
     // the source (natural layout) and the forced response b = F(0) of one

@@ -173,8 +173,12 @@ struct AdiBuf {
     double *d;
     bool f32;
 };
+// pre: each solved row is stored as the y half step's
+// right-hand side (I + theta Lx) u* (ex2, ed2: that step's explicit
+// coefficients) instead of u*; the y launch then takes pre as well.
 hipError_t launch_adi_x(const AdiShape &sh, const LineTab<double> &tb, AdiBuf in, long in_off, AdiBuf out,
-                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st);
+                        long out_off, int nslices, int Mx, int My, int R, double ex, double ed, hipStream_t st,
+                        bool pre = false, double ex2 = 0.0, double ed2 = 0.0);
 // FP64 y half step with one column per wavefront (columns of at most 512
 // rows, 64*cy >= My; tb: the line tables of a column, shape {64, cy}), for
 // the single-slice steps of the coarse sweep; cw (1, 2 or 4) columns per block.
@@ -189,9 +193,11 @@ hipError_t launch_adi_yc(int cw, int cy, const LineTab<double> &tb, const double
 hipError_t launch_adi_x_pre(const AdiShape &sh, const LineTab<double> &tb, const double *in, long in_off,
                             double *out, int Mx, int My, double ex, double ed, double ex2, double ed2,
                             hipStream_t st);
+// pre: `in` holds the right-hand side stored by a pre launch of the x half
+// step, so no neighbour column is read.
 hipError_t launch_adi_y(const AdiShape &sh, const ColTab &tb, AdiBuf in, long in_off, AdiBuf out, long out_off,
                         const double *base, long base_off, double sign, int nslices, int Mx, int My, double ex,
-                        double ed, hipStream_t st);
+                        double ed, hipStream_t st, bool pre = false);
 
 // Krylov block-vector kernels (krylov.hip).  n = total number of doubles.
 // Segmented dot products: for each slice s and pair q < nq,

@@ -483,6 +483,10 @@ bool setup_2d(pit_ctx &c, const AdiTune *force)
         const char *pe = std::getenv("PIT_ADI_PRE");
         c.ypre = !(pe && pe[0] == '0');
     }
+    // the same hand-over in the fine apply (PIT_ADI_FPRE=0: the y kernel
+    // forms its right-hand side from u* and two halo columns)
+    const char *fe = std::getenv("PIT_ADI_FPRE");
+    c.fpre = !(fe && fe[0] == '0');
     return true;
 }
 
@@ -605,16 +609,19 @@ hipError_t apply_2d(const pit_ctx *c, const double *lam, double *y, int raw, int
     const ColTab ty = col_tab_view(reinterpret_cast<const double *>(c->ws + c->off_ayf), c->ash.wy * c->ash.cy * c->ash.seg);
     const AdiBuf lamb{nullptr, const_cast<double *>(lam), false}, yb{nullptr, y, false};
     const AdiBuf ub = c->fbuf(c->off_ubuf), sb = c->fbuf(c->off_sbuf);
+    // the x half step stores the y half step's right-hand side, so the y
+    // kernel reads no halo columns
+    const bool pre = c->fpre;
     for (int step = 0; step < c->m; ++step) {
         const bool first = step == 0, fin = step == c->m - 1;
         if ((e = launch_adi_x(c->ash, tx, first ? lamb : ub, first ? in_off : 0, sb, 0, ns, Mx, My, c->adi_R,
-                              c->fx_ex, c->fx_ed, st)) != hipSuccess)
+                              c->fx_ex, c->fx_ed, st, pre, c->fy_ex, c->fy_ed)) != hipSuccess)
             return e;
         if (fin)
             e = launch_adi_y(c->ash, ty, sb, 0, yb, out_off, raw ? nullptr : lam, out_off, -1.0, ns, Mx, My,
-                             c->fy_ex, c->fy_ed, st);
+                             c->fy_ex, c->fy_ed, st, pre);
         else
-            e = launch_adi_y(c->ash, ty, sb, 0, ub, 0, nullptr, 0, 0.0, ns, Mx, My, c->fy_ex, c->fy_ed, st);
+            e = launch_adi_y(c->ash, ty, sb, 0, ub, 0, nullptr, 0, 0.0, ns, Mx, My, c->fy_ex, c->fy_ed, st, pre);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -629,6 +629,47 @@ def test_adi_sweep_preformed_rhs_is_bitwise(Mx, My, c, monkeypatch):
     assert i1.iters == i0.iters and torch.equal(X0, X1)
 
 
+@pytest.mark.parametrize("Mx,My,prec", [(130, 257, wl.F64), (512, 512, wl.F64), (150, 90, wl.F64),
+                                         (700, 130, wl.F64), (100, 70, wl.F32), (512, 512, wl.F32),
+                                         (700, 130, wl.F32)])
+def test_adi_apply_preformed_rhs(Mx, My, prec, monkeypatch):
+    """The fine apply's x half step stores the y half step's right-hand side
+    (I + theta Lx) u* itself (PIT_ADI_FPRE=0: it stores u* and the y kernel
+    forms the right-hand side from u* and two halo columns); rows of 700
+    points run on two wavefronts, whose edge points cross through LDS.  FP64
+    fields: the same bits in every apply form and the same solve.  FP32
+    fields: the right-hand side is rounded to FP32 where u* was, so the bits
+    differ; both forms hold the FP32 bound against the oracle."""
+    p = adi_problem(Mx, My, 1.0, 1.1, 4, 3, 1, prec)
+    say(f"adi apply pre-formed rhs {Mx}x{My} prec={prec}")
+    monkeypatch.delenv("PIT_ADI_FPRE", raising=False)
+    c1 = ctx(p)
+    monkeypatch.setenv("PIT_ADI_FPRE", "0")
+    c0 = ctx(p)
+    lam = wl.random_block(p, 31)
+    d = dev(lam)
+    forms = [dict(), dict(raw=True), dict(last=True)]
+    ys = [(host(c1.apply_F(d, **kw)), host(c0.apply_F(d, **kw))) for kw in forms]
+    if prec == wl.F64:
+        for y1, y0 in ys:
+            assert np.array_equal(y1, y0)
+        u0 = dev(wl.u0_for(p))
+        X1, i1 = c1.solve(u0, tol=1e-10)
+        X0, i0 = c0.solve(u0, tol=1e-10)
+        assert i1.iters == i0.iters and torch.equal(X0, X1)
+        return
+    assert not np.array_equal(ys[0][0], ys[0][1])  # the pre-formed path ran
+    o = make_oracle(p)
+    X, Y = wl.grid_2d(p)
+    smooth = np.concatenate([(np.sin(np.pi * X / p.length[0]) * np.sin((n + 1) * np.pi * Y / p.length[1])).reshape(-1)
+                             for n in range(p.N)])
+    ref = o.apply(smooth)
+    for cc in (c1, c0):
+        e = relerr(host(cc.apply_F(dev(smooth))), ref)
+        print(f"FP32 apply vs oracle {e:.2e}", flush=True)
+        assert e < 1e-5
+
+
 def test_adi_shared_tables_on_a_small_fp64_slice(monkeypatch):
     """The shared-table kernels on a slice that would otherwise take the LDS
     path (PIT_VEL_LDS=0 at creation), against the oracle."""
