@@ -93,13 +93,14 @@ __device__ __forceinline__ void load_row(const SIN *__restrict__ slice, int j, i
     for (int k = 0; k < C; ++k) r[k] = row[min(lane * C + k, Mx - 1)];
 }
 
-// PRE (one wave per row, FP64 out): the row is stored as the next y half
-// step's right-hand side (I + theta Lx) u* (ex2, ed2) instead of u*, formed
-// from the solved row with the same operations, in the same order, as the
-// y kernel would form it from the stored u* (left + right neighbour, zero
-// outside the row), so the result is the same to the bit.
-// A row on two wavefronts (NT = 128) swaps the points beside the wave edge
-// through xch (two LDS slots) and one barrier.
+// PRE: the row is stored as the next y half step's right-hand side
+// (I + theta Lx) u* (ex2, ed2) instead of u*, formed from the solved row with
+// the same operations, in the same order, as the y kernel would form it from
+// the stored u* (left + right neighbour, zero outside the row).  With FP64
+// fields the result is the same to the bit; with FP32 fields this value is
+// the one rounded to FP32 in place of u*.  A row on two wavefronts
+// (NT = 128) swaps the points beside the wave edge through xch (two LDS
+// slots) and one barrier.
 template <int NT, int C, typename SIN, typename SOUT, bool PRE = false>
 __device__ __forceinline__ void x_row(LineSolver<double, NT, C, false> &LS, const SIN (&pv)[C], const SIN (&cu)[C],
                                       const SIN (&nx)[C], int j, int My, int Mx, int lane, bool vec, double ex,
