@@ -476,29 +476,61 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     auto slot = [](int r) { return (r % C) * kWave + r / C; };
     // stage the CW (+ 2 halo) columns (zeros left and right of the slice and
     // below its last row: the Dirichlet values and the solver's pad rows)
-    constexpr int kIn = (TW * L + NTH - 1) / NTH;
-    double v[kIn];
-#pragma unroll
-    for (int q = 0; q < kIn; ++q) {
-        const int i = q * NTH + t, r = i / TW, col = col0 - H + i % TW;
-        v[q] = (i < TW * L && r < My && col >= 0 && col < Mx) ? to_d(islice[(size_t)r * Mx + col]) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kIn; ++q) {
-        const int i = q * NTH + t;
-        if (i < TW * L) tile[(i % TW) * L + slot(i / TW)] = v[q];
-    }
-    // the epilogue's base values, read now so that their latency hides
-    // behind the staging and the solve
+    // Two FP64 columns of an even-width slice (PAIR): one 16-byte access per
+    // row for the staging, the epilogue's base values and the stores.
+    constexpr bool PAIR2 = TW == 2 && CW == 2 && sizeof(SIN) == 8 && sizeof(SOUT) == 8;
+    const bool pair = PAIR2 && (Mx % 2) == 0;
+    using D2 = __attribute__((ext_vector_type(2))) double;
+    constexpr int kRow = (L + NTH - 1) / NTH;  // rows per thread in the pair form
     SOUT *oslice = out + (size_t)(s + out_off) * npts;
     const double *bslice = EPI ? base + (size_t)(s + base_off) * npts : nullptr;
+    constexpr int kIn = (TW * L + NTH - 1) / NTH;
     constexpr int kOut = (CW * L + NTH - 1) / NTH;
-    double bq[EPI ? kOut : 1];
-    if constexpr (EPI) {
+    double bq[EPI ? (kOut > 2 * kRow ? kOut : 2 * kRow) : 1];
+    if (PAIR2 && pair) {
+        D2 v2[kRow];
 #pragma unroll
-        for (int q = 0; q < kOut; ++q) {
-            const int i = q * NTH + t, r = i / CW, col = col0 + i % CW;
-            bq[q] = (r < My && col < Mx) ? bslice[(size_t)r * Mx + col] : 0.0;
+        for (int q = 0; q < kRow; ++q) {
+            const int r = q * NTH + t;
+            v2[q] = (r < L && r < My) ? *reinterpret_cast<const D2 *>(islice + (size_t)r * Mx + col0) : D2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < kRow; ++q) {
+            const int r = q * NTH + t;
+            if (r < L) {
+                tile[slot(r)] = v2[q].x;
+                tile[L + slot(r)] = v2[q].y;
+            }
+        }
+        if constexpr (EPI) {
+#pragma unroll
+            for (int q = 0; q < kRow; ++q) {
+                const int r = q * NTH + t;
+                const D2 b2 = (r < My) ? *reinterpret_cast<const D2 *>(bslice + (size_t)r * Mx + col0) : D2{0.0, 0.0};
+                bq[2 * q] = b2.x;
+                bq[2 * q + 1] = b2.y;
+            }
+        }
+    } else {
+        double v[kIn];
+#pragma unroll
+        for (int q = 0; q < kIn; ++q) {
+            const int i = q * NTH + t, r = i / TW, col = col0 - H + i % TW;
+            v[q] = (i < TW * L && r < My && col >= 0 && col < Mx) ? to_d(islice[(size_t)r * Mx + col]) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kIn; ++q) {
+            const int i = q * NTH + t;
+            if (i < TW * L) tile[(i % TW) * L + slot(i / TW)] = v[q];
+        }
+        // the epilogue's base values, read now so that their latency hides
+        // behind the staging and the solve
+        if constexpr (EPI) {
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) {
+                const int i = q * NTH + t, r = i / CW, col = col0 + i % CW;
+                bq[q] = (r < My && col < Mx) ? bslice[(size_t)r * Mx + col] : 0.0;
+            }
         }
     }
     LineSolver<double, kWave, C, false> LS;
@@ -520,6 +552,21 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
 #pragma unroll
     for (int k = 0; k < C; ++k) tile[cc * L + k * kWave + lane] = d[k];
     __syncthreads();
+    if (PAIR2 && pair) {
+#pragma unroll
+        for (int q = 0; q < kRow; ++q) {
+            const int r = q * NTH + t;
+            if (r < My) {
+                double x0 = tile[slot(r)], x1 = tile[L + slot(r)];
+                if constexpr (EPI) {
+                    x0 = fma(sign, x0, bq[2 * q]);
+                    x1 = fma(sign, x1, bq[2 * q + 1]);
+                }
+                *reinterpret_cast<D2 *>(oslice + (size_t)r * Mx + col0) = D2{x0, x1};
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < kOut; ++q) {
         const int i = q * NTH + t, r = i / CW, c = i % CW, col = col0 + c;

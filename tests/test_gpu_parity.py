@@ -575,7 +575,7 @@ def test_adi_other_y_shapes_on_a_short_column(yshape, reported, monkeypatch):
 
 
 @pytest.mark.parametrize("yc", ["", "1", "4", "0"])
-@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3)])
+@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3), (151, 90, 2)])
 def test_adi_sweep_y_kernels(Mx, My, c, yc, monkeypatch):
     """The coarse sweep's single-slice y half step, one column per wavefront
     (the default for columns up to 512 rows, 2 columns per workgroup; 1 and 4
@@ -600,13 +600,16 @@ def test_adi_sweep_y_kernels(Mx, My, c, yc, monkeypatch):
     assert e1 < 1e-12 and e2 < 1e-12
 
 
-@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3), (64, 512, 1)])
+@pytest.mark.parametrize("Mx,My,c", [(130, 257, 2), (512, 512, 1), (150, 90, 3), (64, 512, 1), (151, 90, 2),
+                                    (130, 40, 2)])
 def test_adi_sweep_preformed_rhs_is_bitwise(Mx, My, c, monkeypatch):
     """With the one-column y kernel the coarse sweep's x half step stores the
     y half step's right-hand side (I + theta Lx) u* itself: the same bits as
     the y kernel forming it from u* and its neighbour columns
     (PIT_ADI_PRE=0), in and out of place, one and several coarse steps per
-    slice, and the same solve."""
+    slice, and the same solve.  Even widths move the two columns of a
+    workgroup with one 16-byte access per row, odd widths (151) one value at
+    a time; 40 rows take one point per lane."""
     monkeypatch.delenv("PIT_ADI_YC", raising=False)
     p = adi_problem(Mx, My, 1.0, 1.1, 5, 2, c, wl.F64)
     say(f"adi sweep pre-formed rhs {Mx}x{My} c={c}")
