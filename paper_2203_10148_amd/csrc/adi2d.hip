@@ -211,14 +211,23 @@ __global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<doub
     LineSolver<double, NT, C, false> LS;
     LS.load(tb, XW == 1 ? nullptr : lds);
     // Five rotating row buffers: row r uses the buffers of rows r-1, r, r+1
-    // while rows r+2 .. r+4 are in flight.  Reads past the strip are clamped
-    // to its last halo row (a cache hit), so no row is fetched from HBM twice.
+    // while rows r+2 .. r+4 are in flight.  Rows past the strip's last halo
+    // row jl are not read: a buffer that would hold one is only ever the
+    // neighbour below the slice's last row, which enters with weight 0, so
+    // it starts as zeros (a strip of one row reads three rows, not five).
     // Every thread of a group runs the same rows, so the solver's barriers
     // (XW = 2) match.
     SIN B[5][C];
     const int jl = min(j1, My - 1);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) load_row<C>(islice, min(j0 - 1 + q, jl), My, Mx, lane, vec, B[q]);
+    for (int q = 0; q < 5; ++q) {
+        if (j0 - 1 + q <= jl) {
+            load_row<C>(islice, j0 - 1 + q, My, Mx, lane, vec, B[q]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) B[q][k] = SIN(0);
+        }
+    }
     for (int j = j0; j < j1; j += 5) {
 #define PIT_XSTEP(u)                                                                                           \
     {                                                                                                          \
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(XW == 1 ? 64 * WPB : 128) void k_adi_x(LineTab<doub
         if (r >= j1) break;                                                                                    \
         x_row<NT, C, SIN, SOUT, PRE>(LS, B[(u) % 5], B[((u) + 1) % 5], B[((u) + 2) % 5], r, My, Mx, lane, vec, \
                                      ex, ed, oslice, ex2, ed2, xch);                                            \
-        load_row<C>(islice, min(r + 4, jl), My, Mx, lane, vec, B[(u) % 5]);                                    \
+        if (r + 4 <= jl) load_row<C>(islice, r + 4, My, Mx, lane, vec, B[(u) % 5]);                            \
     }
         PIT_XSTEP(0) PIT_XSTEP(1) PIT_XSTEP(2) PIT_XSTEP(3) PIT_XSTEP(4)
 #undef PIT_XSTEP
