@@ -485,12 +485,14 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     auto slot = [](int r) { return (r % C) * kWave + r / C; };
     // stage the CW (+ 2 halo) columns (zeros left and right of the slice and
     // below its last row: the Dirichlet values and the solver's pad rows)
-    // Two FP64 columns of an even-width slice (PAIR): one 16-byte access per
-    // row for the staging, the epilogue's base values and the stores.
-    constexpr bool PAIR2 = TW == 2 && CW == 2 && sizeof(SIN) == 8 && sizeof(SOUT) == 8;
+    // FP64 columns of an even-width slice (PAIR2, an even CW): a row's CW
+    // values are CW/2 aligned pairs, each moved with one 16-byte access, for
+    // the staging, the epilogue's base values and the stores.
+    constexpr bool PAIR2 = TW == CW && CW % 2 == 0 && sizeof(SIN) == 8 && sizeof(SOUT) == 8;
+    constexpr int NP = CW / 2 > 0 ? CW / 2 : 1;  // pairs per row
     const bool pair = PAIR2 && (Mx % 2) == 0;
     using D2 = __attribute__((ext_vector_type(2))) double;
-    constexpr int kRow = (L + NTH - 1) / NTH;  // rows per thread in the pair form
+    constexpr int kRow = (L * NP + NTH - 1) / NTH;  // pairs per thread in the pair form
     SOUT *oslice = out + (size_t)(s + out_off) * npts;
     const double *bslice = EPI ? base + (size_t)(s + base_off) * npts : nullptr;
     constexpr int kIn = (TW * L + NTH - 1) / NTH;
@@ -500,22 +502,27 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
         D2 v2[kRow];
 #pragma unroll
         for (int q = 0; q < kRow; ++q) {
-            const int r = q * NTH + t;
-            v2[q] = (r < L && r < My) ? *reinterpret_cast<const D2 *>(islice + (size_t)r * Mx + col0) : D2{0.0, 0.0};
+            const int i = q * NTH + t, r = i / NP, c = 2 * (i % NP);
+            // with Mx even a pair is inside the row or wholly past it
+            v2[q] = (r < L && r < My && col0 + c < Mx)
+                        ? *reinterpret_cast<const D2 *>(islice + (size_t)r * Mx + col0 + c)
+                        : D2{0.0, 0.0};
         }
 #pragma unroll
         for (int q = 0; q < kRow; ++q) {
-            const int r = q * NTH + t;
+            const int i = q * NTH + t, r = i / NP, c = 2 * (i % NP);
             if (r < L) {
-                tile[slot(r)] = v2[q].x;
-                tile[L + slot(r)] = v2[q].y;
+                tile[c * L + slot(r)] = v2[q].x;
+                tile[(c + 1) * L + slot(r)] = v2[q].y;
             }
         }
         if constexpr (EPI) {
 #pragma unroll
             for (int q = 0; q < kRow; ++q) {
-                const int r = q * NTH + t;
-                const D2 b2 = (r < My) ? *reinterpret_cast<const D2 *>(bslice + (size_t)r * Mx + col0) : D2{0.0, 0.0};
+                const int i = q * NTH + t, r = i / NP, c = 2 * (i % NP);
+                const D2 b2 = (r < My && col0 + c < Mx)
+                                  ? *reinterpret_cast<const D2 *>(bslice + (size_t)r * Mx + col0 + c)
+                                  : D2{0.0, 0.0};
                 bq[2 * q] = b2.x;
                 bq[2 * q + 1] = b2.y;
             }
@@ -564,14 +571,14 @@ __global__ __launch_bounds__(CW * 64) void k_adi_yc(LineTab<double> tb, const SI
     if (PAIR2 && pair) {
 #pragma unroll
         for (int q = 0; q < kRow; ++q) {
-            const int r = q * NTH + t;
-            if (r < My) {
-                double x0 = tile[slot(r)], x1 = tile[L + slot(r)];
+            const int i = q * NTH + t, r = i / NP, c = 2 * (i % NP);
+            if (r < My && col0 + c < Mx) {
+                double x0 = tile[c * L + slot(r)], x1 = tile[(c + 1) * L + slot(r)];
                 if constexpr (EPI) {
                     x0 = fma(sign, x0, bq[2 * q]);
                     x1 = fma(sign, x1, bq[2 * q + 1]);
                 }
-                *reinterpret_cast<D2 *>(oslice + (size_t)r * Mx + col0) = D2{x0, x1};
+                *reinterpret_cast<D2 *>(oslice + (size_t)r * Mx + col0 + c) = D2{x0, x1};
             }
         }
         return;
