@@ -4,20 +4,24 @@
 //   x half step:  (I - theta Lx) u* = (I + theta Ly) u     solved along rows
 //   y half step:  (I - theta Ly) u' = (I + theta Lx) u*    solved along columns
 // Every slice of a block vector is independent, so each launch covers all the
-// slices it is given.  The fields between half steps are stored in S (float
-// for the FP32 fine propagator, double otherwise); the arithmetic is FP64.
+// slices it is given.  What passes between the half steps is stored in S
+// (float for the FP32 fine propagator, double otherwise); the arithmetic is
+// FP64.  In the fine apply and the coarse sweep the x half step stores the y
+// half step's right-hand side (I + theta Lx) u* rather than u* (PRE).
 //
-// x half step: one wavefront per strip of R rows, lane l owns the x-points
-// l*C .. l*C+C-1 of the row, the row solve is the register-resident in-wave
-// line solver (no LDS, no barrier).  The y stencil uses a rolling window of
-// three rows held in rotating registers (no copies, so the row loaded ahead
-// stays in flight while the current row is solved).
+// x half step: one wavefront per strip of R rows (rows of more than 512
+// points: a wavefront pair), lane l owns the x-points l*C .. l*C+C-1 of the
+// row, the row solve is the register-resident in-wave line solver (no LDS, no
+// barrier on one wave).  The y stencil uses a rolling window of three rows
+// held in rotating registers (no copies, so the row loaded ahead stays in
+// flight while the current row is solved).
 //
-// y half step: a workgroup owns 64 columns of one slice; wave w holds rows
-// w*CY .. w*CY+CY-1 of them, one column per lane.  Each lane's tridiagonal
+// y half step: a workgroup owns 64/SEG columns of one slice; each wave holds
+// SEG row segments of CY rows, one column per lane.  Each lane's tridiagonal
 // recurrence along y runs locally with one LDS exchange of the per-lane
 // carries per direction (two barriers per half step); the row constants are
-// the same for every column and are read from LDS.
+// the same for every column and are read from LDS.  The coarse sweep's
+// single slice uses a one-column-per-wavefront form (k_adi_yc).
 #include "line1d.hpp"
 
 namespace pit {
