@@ -633,8 +633,8 @@ def test_adi_sweep_preformed_rhs_is_bitwise(Mx, My, c, monkeypatch):
 
 
 @pytest.mark.parametrize("Mx,My,prec", [(130, 257, wl.F64), (512, 512, wl.F64), (150, 90, wl.F64),
-                                         (700, 130, wl.F64), (100, 70, wl.F32), (512, 512, wl.F32),
-                                         (700, 130, wl.F32)])
+                                         (700, 130, wl.F64), (777, 65, wl.F64), (100, 70, wl.F32),
+                                         (512, 512, wl.F32), (700, 130, wl.F32), (520, 33, wl.F32)])
 def test_adi_apply_preformed_rhs(Mx, My, prec, monkeypatch):
     """The fine apply's x half step stores the y half step's right-hand side
     (I + theta Lx) u* itself (PIT_ADI_FPRE=0: it stores u* and the y kernel
