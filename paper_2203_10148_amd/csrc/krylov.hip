@@ -356,56 +356,112 @@ __device__ __forceinline__ bool dev_scalars(const DevScalars &s, double &alpha, 
 // `one` is 1.0, passed at run time as k_axpby's coefficient is: with a
 // literal 1 the compiler folds fma(1, R, b D) into R + b D and may then
 // contract that into one fma, which rounds b D differently.
+//
+// V = 2 (every vector 16-byte aligned): two elements per access, the odd
+// last element, if any, on its own; the same operations per element, so the
+// same bits as V = 1.
+using Dv2 = __attribute__((ext_vector_type(2))) double;
+template <int V>
 __global__ void k_axpby_dev(double *__restrict__ S, const double *__restrict__ R, const double *__restrict__ D,
                             DevScalars s, double one, long n)
 {
     const double dr = s.A->dot[0];
     const double alpha = s.rho->dot[s.rho_idx] / dr;  // dr == 0: S is not used
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        S[i] = axpby_elem(one, R[i], -alpha, D[i]);
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, st = (long)gridDim.x * blockDim.x;
+    if constexpr (V == 2) {
+        for (long i = t0; i < n / 2; i += st) {
+            const Dv2 r = reinterpret_cast<const Dv2 *>(R)[i], d = reinterpret_cast<const Dv2 *>(D)[i];
+            reinterpret_cast<Dv2 *>(S)[i] = Dv2{axpby_elem(one, r.x, -alpha, d.x), axpby_elem(one, r.y, -alpha, d.y)};
+        }
+        if ((n & 1) && t0 == 0) S[n - 1] = axpby_elem(one, R[n - 1], -alpha, D[n - 1]);
+    } else {
+        for (long i = t0; i < n; i += st) S[i] = axpby_elem(one, R[i], -alpha, D[i]);
+    }
 }
 
+template <int V>
 __global__ void k_update_xr_dev(double *__restrict__ X, double *__restrict__ R, const double *__restrict__ P,
                                 const double *__restrict__ S, const double *__restrict__ K, DevScalars s, long n)
 {
     double alpha, omega;
     if (!dev_scalars(s, alpha, omega)) return;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        double x = X[i], r;
-        update_xr_elem(x, r, P[i], S[i], K[i], alpha, omega);
-        X[i] = x;
-        R[i] = r;
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, st = (long)gridDim.x * blockDim.x;
+    if constexpr (V == 2) {
+        for (long i = t0; i < n / 2; i += st) {
+            const Dv2 x = reinterpret_cast<const Dv2 *>(X)[i], p = reinterpret_cast<const Dv2 *>(P)[i];
+            const Dv2 sv = reinterpret_cast<const Dv2 *>(S)[i], k = reinterpret_cast<const Dv2 *>(K)[i];
+            double x0 = x.x, x1 = x.y, r0, r1;
+            update_xr_elem(x0, r0, p.x, sv.x, k.x, alpha, omega);
+            update_xr_elem(x1, r1, p.y, sv.y, k.y, alpha, omega);
+            reinterpret_cast<Dv2 *>(X)[i] = Dv2{x0, x1};
+            reinterpret_cast<Dv2 *>(R)[i] = Dv2{r0, r1};
+        }
+        if ((n & 1) && t0 == 0) {
+            double x = X[n - 1], r;
+            update_xr_elem(x, r, P[n - 1], S[n - 1], K[n - 1], alpha, omega);
+            X[n - 1] = x;
+            R[n - 1] = r;
+        }
+    } else {
+        for (long i = t0; i < n; i += st) {
+            double x = X[i], r;
+            update_xr_elem(x, r, P[i], S[i], K[i], alpha, omega);
+            X[i] = x;
+            R[i] = r;
+        }
     }
 }
 
+template <int V>
 __global__ void k_update_p_dev(double *__restrict__ P, const double *__restrict__ R, const double *__restrict__ D,
                                DevScalars s, long n)
 {
     double alpha, omega;
     if (!dev_scalars(s, alpha, omega)) return;
     const double beta = (alpha / omega) * (s.C->dot[0] / s.rho->dot[s.rho_idx]);
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        P[i] = update_p_elem(P[i], R[i], D[i], beta, omega);
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, st = (long)gridDim.x * blockDim.x;
+    if constexpr (V == 2) {
+        for (long i = t0; i < n / 2; i += st) {
+            const Dv2 p = reinterpret_cast<const Dv2 *>(P)[i], r = reinterpret_cast<const Dv2 *>(R)[i];
+            const Dv2 d = reinterpret_cast<const Dv2 *>(D)[i];
+            reinterpret_cast<Dv2 *>(P)[i] =
+                Dv2{update_p_elem(p.x, r.x, d.x, beta, omega), update_p_elem(p.y, r.y, d.y, beta, omega)};
+        }
+        if ((n & 1) && t0 == 0) P[n - 1] = update_p_elem(P[n - 1], R[n - 1], D[n - 1], beta, omega);
+    } else {
+        for (long i = t0; i < n; i += st) P[i] = update_p_elem(P[i], R[i], D[i], beta, omega);
+    }
 }
+
+static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 hipError_t launch_axpby_dev(double *S, const double *R, const double *D, const DevScalars &s, long n,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_axpby_dev, vec_grid(n), dim3(kVecThreads), 0, st, S, R, D, s, 1.0, n);
+    if (aligned16(S) && aligned16(R) && aligned16(D))
+        hipLaunchKernelGGL(k_axpby_dev<2>, vec_grid(n / 2), dim3(kVecThreads), 0, st, S, R, D, s, 1.0, n);
+    else
+        hipLaunchKernelGGL(k_axpby_dev<1>, vec_grid(n), dim3(kVecThreads), 0, st, S, R, D, s, 1.0, n);
     return hipGetLastError();
 }
 
 hipError_t launch_update_xr_dev(double *X, double *R, const double *P, const double *S, const double *K,
                                 const DevScalars &s, long n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_update_xr_dev, vec_grid(n), dim3(kVecThreads), 0, st, X, R, P, S, K, s, n);
+    if (aligned16(X) && aligned16(R) && aligned16(P) && aligned16(S) && aligned16(K))
+        hipLaunchKernelGGL(k_update_xr_dev<2>, vec_grid(n / 2), dim3(kVecThreads), 0, st, X, R, P, S, K, s, n);
+    else
+        hipLaunchKernelGGL(k_update_xr_dev<1>, vec_grid(n), dim3(kVecThreads), 0, st, X, R, P, S, K, s, n);
     return hipGetLastError();
 }
 
 hipError_t launch_update_p_dev(double *P, const double *R, const double *D, const DevScalars &s, long n,
                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_update_p_dev, vec_grid(n), dim3(kVecThreads), 0, st, P, R, D, s, n);
+    if (aligned16(P) && aligned16(R) && aligned16(D))
+        hipLaunchKernelGGL(k_update_p_dev<2>, vec_grid(n / 2), dim3(kVecThreads), 0, st, P, R, D, s, n);
+    else
+        hipLaunchKernelGGL(k_update_p_dev<1>, vec_grid(n), dim3(kVecThreads), 0, st, P, R, D, s, n);
     return hipGetLastError();
 }
 
