@@ -21,6 +21,35 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// A thread's strided share of a slice, elements i0, i0 + stride, ...: each
+// accumulator takes them in that order, one fma each, as a one-element loop
+// would, with the loads of U elements issued before their fmas (a loop that
+// waited for each element's loads kept two loads in flight per thread).
+template <int NQ>
+__device__ __forceinline__ void dots_accumulate(const DotPairs &pr, size_t base, long i0, long stride, long npts,
+                                                double (&acc)[4])
+{
+    constexpr int U = 4;
+    long i = i0;
+    for (; i + (U - 1) * stride < npts; i += U * stride) {
+        double av[NQ][U], bv[NQ][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                av[q][u] = pr.a[q][base + i + u * stride];
+                bv[q][u] = pr.b[q][base + i + u * stride];
+            }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[q] = fma(av[q][u], bv[q][u], acc[q]);
+    }
+    for (; i < npts; i += stride)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = fma(pr.a[q][base + i], pr.b[q][base + i], acc[q]);
+}
+
 // Block b of slice s sums a strided part of the slice for nq pairs (shared
 // by the single- and multi-instance kernels).
 __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N, long npts, int bps,
@@ -31,10 +60,13 @@ __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     const size_t base = (size_t)s * npts;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long i = (long)b * kRedThreads + t; i < npts; i += (long)bps * kRedThreads) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < nq) acc[q] = fma(pr.a[q][base + i], pr.b[q][base + i], acc[q]);
+    const long i0 = (long)b * kRedThreads + t, stride = (long)bps * kRedThreads;
+    switch (nq) {  // uniform
+    case 0: break;
+    case 1: dots_accumulate<1>(pr, base, i0, stride, npts, acc); break;
+    case 2: dots_accumulate<2>(pr, base, i0, stride, npts, acc); break;
+    case 3: dots_accumulate<3>(pr, base, i0, stride, npts, acc); break;
+    default: dots_accumulate<4>(pr, base, i0, stride, npts, acc); break;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
