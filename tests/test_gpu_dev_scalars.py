@@ -6,8 +6,8 @@ the residual history and the counters must agree bit for bit.  The cases
 cover the regular path, the half step that solves the system (one slice:
 S = 0 exactly, kk = 0), the restart test of Algorithm 1 firing at the end of
 every iteration (rho then comes from the second inner product), an FP32 fine
-propagator, a 2D problem and a source term, and one oracle check of the
-solution.
+propagator, 2D problems (one of odd vector length) and a source term, and
+one oracle check of the solution.
 """
 import os
 import sys
@@ -59,6 +59,10 @@ CASES = {
     "heat2d": (wl.Problem(dim=2, M=(40, 30), bc=wl.DIRICHLET, nu=0.05, T=0.3, N=8, m=6, fine=wl.ADI, c=1,
                           coarse=wl.ADI, prec=wl.F64, tol=1e-10, name="heat2d_40x30"), {}),
     "f2_short": (wl.F2.with_(T=0.4, N=4, m=25), {}),
+    # 7 slices of 41 x 31 points: an odd vector length, so the paired updates
+    # take their last element on its own
+    "heat2d_odd": (wl.Problem(dim=2, M=(41, 31), bc=wl.DIRICHLET, nu=0.05, T=0.3, N=7, m=6, fine=wl.ADI, c=1,
+                              coarse=wl.ADI, prec=wl.F64, tol=1e-10, name="heat2d_41x31"), {}),
 }
 
 
