@@ -50,6 +50,35 @@ __device__ __forceinline__ void dots_accumulate(const DotPairs &pr, size_t base,
         for (int q = 0; q < NQ; ++q) acc[q] = fma(pr.a[q][base + i], pr.b[q][base + i], acc[q]);
 }
 
+// The same when every operand is one of two vectors x = a[0], y = b[0] (as in
+// <K,S>, <K,K>, <S,S> and <R,R~>, <R,R>): each element of x and y is loaded
+// once; bit 2q of sel picks y for a[q], bit 2q+1 for b[q].
+template <int NQ>
+__device__ __forceinline__ void dots_accumulate_xy(const double *__restrict__ x, const double *__restrict__ y,
+                                                   unsigned sel, long i0, long stride, long npts, double (&acc)[4])
+{
+    constexpr int U = 4;
+    long i = i0;
+    auto add = [&](double xv, double yv) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double av = (sel >> (2 * q)) & 1 ? yv : xv, bv = (sel >> (2 * q + 1)) & 1 ? yv : xv;
+            acc[q] = fma(av, bv, acc[q]);
+        }
+    };
+    for (; i + (U - 1) * stride < npts; i += U * stride) {
+        double xv[U], yv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xv[u] = x[i + u * stride];
+            yv[u] = y[i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add(xv[u], yv[u]);
+    }
+    for (; i < npts; i += stride) add(x[i], y[i]);
+}
+
 // Block b of slice s sums a strided part of the slice for nq pairs (shared
 // by the single- and multi-instance kernels).
 __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N, long npts, int bps,
@@ -61,12 +90,30 @@ __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N
     const size_t base = (size_t)s * npts;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const long i0 = (long)b * kRedThreads + t, stride = (long)bps * kRedThreads;
-    switch (nq) {  // uniform
-    case 0: break;
-    case 1: dots_accumulate<1>(pr, base, i0, stride, npts, acc); break;
-    case 2: dots_accumulate<2>(pr, base, i0, stride, npts, acc); break;
-    case 3: dots_accumulate<3>(pr, base, i0, stride, npts, acc); break;
-    default: dots_accumulate<4>(pr, base, i0, stride, npts, acc); break;
+    // operands drawn from the two vectors a[0], b[0] only? (uniform)
+    const double *x = pr.a[0], *y = pr.b[0];
+    bool two = nq >= 2 && x != y;
+    unsigned sel = 0;
+    for (int q = 0; q < 4 && q < nq; ++q) {
+        const double *ops[2] = {pr.a[q], pr.b[q]};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (ops[k] == y) sel |= 1u << (2 * q + k);
+            else if (ops[k] != x) two = false;
+        }
+    }
+    if (two) {
+        if (nq == 2) dots_accumulate_xy<2>(x + base, y + base, sel, i0, stride, npts, acc);
+        else if (nq == 3) dots_accumulate_xy<3>(x + base, y + base, sel, i0, stride, npts, acc);
+        else dots_accumulate_xy<4>(x + base, y + base, sel, i0, stride, npts, acc);
+    } else {
+        switch (nq) {  // uniform
+        case 0: break;
+        case 1: dots_accumulate<1>(pr, base, i0, stride, npts, acc); break;
+        case 2: dots_accumulate<2>(pr, base, i0, stride, npts, acc); break;
+        case 3: dots_accumulate<3>(pr, base, i0, stride, npts, acc); break;
+        default: dots_accumulate<4>(pr, base, i0, stride, npts, acc); break;
+        }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
