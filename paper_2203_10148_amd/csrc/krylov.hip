@@ -127,7 +127,7 @@ __device__ __forceinline__ void seg_dots_block(const DotPairs &pr, int nq, int N
         double v = 0.0;
 #pragma unroll
         for (int i = 0; i < kRedThreads / kWave; ++i) v += sh[t][i];
-        part[((size_t)t * N + s) * bps + b] = v;
+        part[((size_t)t * bps + b) * N + s] = v;  // [q][b][s]: the finalize reads each b across slices
     }
 }
 
@@ -151,9 +151,19 @@ __device__ __forceinline__ void seg_finalize_block(const double *__restrict__ pa
     for (int q = 0; q < nq; ++q) {
         double tot = 0.0, mx = 0.0;
         for (int s = t; s < N; s += kRedThreads) {
-            const double *p = part + ((size_t)q * N + s) * bps;
+            // the slice's partials in block order; consecutive threads read
+            // consecutive slices, and eight loads go out before their adds
+            const double *p = part + (size_t)q * bps * N + s;
             double ss = 0.0;
-            for (int b = 0; b < bps; ++b) ss += p[b];
+            int b = 0;
+            for (; b + 8 <= bps; b += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(b + u) * N];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) ss += v[u];
+            }
+            for (; b < bps; ++b) ss += p[(size_t)b * N];
             tot += ss;
             double nrm = sqrt(w * ss);
             mx = (nrm > mx || nrm != nrm) ? nrm : mx;  // NaN propagates
