@@ -471,7 +471,7 @@ def main():
         print(json.dumps(summarize_pmc(fc, wc, out, p, prec, unit, rx, int(units), [cf, cw])))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
